@@ -1,0 +1,153 @@
+"""Plain CPU oracle for the DM stray-field method -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The product library never does.
+
+The arithmetic lives in ``demag_oracle.c`` (FP64 direct O(N^2) sums over all
+cell pairs; Newell f/g lattice in binary128).  This module only loads the
+shared object with ctypes and marshals numpy arrays.
+
+Functions and the passages they follow (Abert et al., arXiv:1204.4302):
+
+* ``tensor``      -- cell-averaged demagnetization tensor N for homogeneously
+                     magnetized cells (Sec. 4.1, "Homogeneously Magnetized
+                     Cube"; closed forms of Newell et al. 1993, which the paper
+                     cites only by property).
+* ``field``       -- H = -Ms N * m as a plain sum, Sec. 3.1 eq. (demag).
+* ``field_targets`` -- the same sum evaluated at selected cells only.
+* ``field_T``     -- the transposed operator as its own loop.
+* ``energy``      -- E = -(mu0/2) Ms V sum m.H, Sec. 2 (stray-field energy).
+* ``matrix``      -- the explicit 3N x 3N operator for tiny grids.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "demag_oracle.c")
+_LIB = os.path.join(_HERE, "_demag_oracle.so")
+_lib = None
+
+MU0 = 4.0e-7 * np.pi
+
+
+def build(force: bool = False, extra_flags: list[str] | None = None,
+          out: str | None = None) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, libquadmath)."""
+    out = out or _LIB
+    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(_SRC):
+        return out
+    cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=gnu11",
+           _SRC, "-o", out + ".tmp", "-lquadmath", "-lm"]
+    if extra_flags:
+        cmd[1:1] = list(extra_flags)
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def load(path: str | None = None):
+    """Load (building first if needed) and declare the C signatures."""
+    global _lib
+    if path is None and _lib is not None:
+        return _lib
+    lib = ctypes.CDLL(path or build())
+    d, i, l, p = ctypes.c_double, ctypes.c_int, ctypes.c_long, ctypes.c_void_p
+    lib.oracle_tensor.argtypes = [i, i, i, d, d, d, p]
+    lib.oracle_tensor.restype = i
+    lib.oracle_tensor_at.argtypes = [i, l, l, l, d, d, d]
+    lib.oracle_tensor_at.restype = d
+    lib.oracle_f.argtypes = [d, d, d]
+    lib.oracle_f.restype = d
+    lib.oracle_g.argtypes = [d, d, d]
+    lib.oracle_g.restype = d
+    lib.oracle_field.argtypes = [i, i, i, p, p, d, p]
+    lib.oracle_field.restype = i
+    lib.oracle_field_targets.argtypes = [i, i, i, p, p, d, p, l, p]
+    lib.oracle_field_targets.restype = i
+    lib.oracle_field_T.argtypes = [i, i, i, p, p, d, p]
+    lib.oracle_field_T.restype = i
+    lib.oracle_energy.argtypes = [i, i, i, d, d, d, p, p, d]
+    lib.oracle_energy.restype = d
+    lib.oracle_matrix.argtypes = [i, i, i, p, d, p]
+    lib.oracle_matrix.restype = i
+    lib.oracle_mu0.argtypes = []
+    lib.oracle_mu0.restype = d
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _vec(m: np.ndarray, shape) -> np.ndarray:
+    nx, ny, nz = shape
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    if m.shape != (3, nz, ny, nx):
+        raise ValueError(f"expected a [3][nz][ny][nx] field, got {m.shape}")
+    return m
+
+
+class Oracle:
+    """One grid (shape (nx, ny, nz), cell (dx, dy, dz)) with its FP64 tensor."""
+
+    def __init__(self, shape, cell, lib=None):
+        self.lib = lib or load()
+        self.shape = tuple(int(v) for v in shape)
+        self.cell = tuple(float(v) for v in cell)
+        nx, ny, nz = self.shape
+        self.Noct = np.empty((6, nz, ny, nx), dtype=np.float64)
+        rc = self.lib.oracle_tensor(nx, ny, nz, *self.cell, _ptr(self.Noct))
+        if rc != 0:
+            raise ValueError(f"oracle_tensor failed ({rc})")
+
+    @property
+    def volume(self) -> float:
+        dx, dy, dz = self.cell
+        return dx * dy * dz
+
+    def field(self, m, Ms):
+        m = _vec(m, self.shape)
+        H = np.empty_like(m)
+        self.lib.oracle_field(*self.shape, _ptr(self.Noct), _ptr(m), float(Ms), _ptr(H))
+        return H
+
+    def field_targets(self, m, Ms, targets):
+        m = _vec(m, self.shape)
+        t = np.ascontiguousarray(targets, dtype=np.int64)
+        out = np.empty((3, t.size), dtype=np.float64)
+        rc = self.lib.oracle_field_targets(*self.shape, _ptr(self.Noct), _ptr(m),
+                                           float(Ms), _ptr(t), t.size, _ptr(out))
+        if rc != 0:
+            raise ValueError("target index out of range")
+        return out
+
+    def field_T(self, g, Ms):
+        g = _vec(g, self.shape)
+        out = np.empty_like(g)
+        self.lib.oracle_field_T(*self.shape, _ptr(self.Noct), _ptr(g), float(Ms), _ptr(out))
+        return out
+
+    def energy(self, m, H, Ms) -> float:
+        m = _vec(m, self.shape)
+        H = _vec(H, self.shape)
+        return self.lib.oracle_energy(*self.shape, *self.cell, _ptr(m), _ptr(H), float(Ms))
+
+    def matrix(self, Ms):
+        n = 3 * int(np.prod(self.shape))
+        A = np.empty((n, n), dtype=np.float64)
+        if self.lib.oracle_matrix(*self.shape, _ptr(self.Noct), float(Ms), _ptr(A)) != 0:
+            raise ValueError("grid too large for an explicit matrix")
+        return A
+
+
+def tensor_at(comp: int, offset, cell) -> float:
+    """N_comp at one signed integer offset, straight from f/g (binary128)."""
+    ox, oy, oz = (int(v) for v in offset)
+    return load().oracle_tensor_at(int(comp), ox, oy, oz, *(float(c) for c in cell))
