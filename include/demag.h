@@ -1,0 +1,133 @@
+/*
+ * demag.h -- C ABI of the MI355X (gfx950) demagnetization-tensor (DM) stray
+ * field library.
+ *
+ * The operation (Abert et al., "Numerical Methods for the Stray-Field
+ * Calculation: A Comparison of recently developed Algorithms", Sec. 3.1,
+ * eq. (demag)): for a cell-wise constant magnetization M = Ms m on a regular
+ * nx x ny x nz grid of dx x dy x dz cuboid cells, the cell-averaged stray
+ * field is the discrete matrix-vector convolution
+ *
+ *      H_i = -Ms * sum_j N(r_i - r_j) m_j ,
+ *
+ * N the demagnetization tensor of homogeneously magnetized cells averaged over
+ * the target cell (Sec. 5.1).  The convolution is evaluated with the
+ * convolution theorem (eq. (convolution)) on a grid zero-padded to P = 2L
+ * points per axis (L >= n), as an element-wise 3x3 matrix-vector product in
+ * Fourier space (Sec. 3.1).  The energy is the stray-field energy of Sec. 2,
+ *
+ *      E = -(mu0/2) * Ms * V * sum_i m_i . H_i ,   V = dx dy dz, mu0 = 4 pi 1e-7.
+ *
+ * Conventions for every call:
+ *  - Vector fields (m, H, gH, gm) are DEVICE pointers owned by the caller,
+ *    contiguous structure-of-arrays [3][nz][ny][nx] (x fastest), in the plan's
+ *    precision (float for DEMAG_F32, double for DEMAG_F64).  Input and output
+ *    buffers must not overlap.
+ *  - m is used as given (not renormalised).  NaN/Inf in m propagate.
+ *  - Ms in A/m; H in A/m; E in J.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Field calls only enqueue work and return; they do not synchronise.
+ *  - Every function returns DEMAG_OK (0) or a negative demag_status; the text
+ *    of the last error of the calling thread is demag_last_error().
+ *  - A plan owns its scratch (two spectrum buffers) and must not be used on
+ *    two streams at the same time; a call on another stream while work of the
+ *    plan is still pending returns DEMAG_ESTATE.
+ */
+#ifndef DEMAG_H
+#define DEMAG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct demag_plan_s* demag_plan_t;
+typedef struct demag_batch_s* demag_batch_t;
+
+typedef enum { DEMAG_F32 = 0, DEMAG_F64 = 1 } demag_dtype;
+
+typedef enum {
+    DEMAG_OK = 0,
+    DEMAG_EINVAL = -1,      /* bad argument (shape, cell size, pointer, option) */
+    DEMAG_ENOMEM = -2,      /* device allocation failed */
+    DEMAG_EHIP = -3,        /* a HIP runtime call failed */
+    DEMAG_EUNSUPPORTED = -4,/* shape beyond what the kernels handle */
+    DEMAG_ESTATE = -5       /* plan busy on another stream, or wrong object state */
+} demag_status;
+
+/* Create a plan for an nx x ny x nz grid of dx x dy x dz cells (metres, > 0,
+ * finite).  Computes the tensor N in FP64 on the current device and stores
+ * the real, symmetric spectrum of N on its non-redundant octant in `dtype`
+ * (Sec. 4: the constants depend on the geometry only and are computed once).
+ * Runs on `setup_stream` and synchronises it.  Padded length per axis:
+ * 2L, L the smallest 2^a 3^b 5^c >= n; 2L <= 4096 per axis, else
+ * DEMAG_EUNSUPPORTED.  *out receives the plan (caller destroys it once). */
+int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, double dy, double dz,
+                      demag_dtype dtype, void* setup_stream);
+
+/* Tensor-setup options; the spectrum is recomputed at once (synchronous).
+ *  "far_cut": offsets with |o (.) d| / max(d) >= far_cut (cell-size units) use
+ *             the moment series of the dipole kernel (default 40; 0 < v).
+ *  "fg_cut":  offsets with Chebyshev distance <= fg_cut use the Newell f/g
+ *             closed form (default 1; integer >= 0); the rest of the near field
+ *             uses Gauss-Legendre quadrature of the cell-average integral. */
+int demag_plan_set_option(demag_plan_t plan, const char* key, double value);
+int demag_plan_destroy(demag_plan_t plan);
+
+/* Plan facts, written to info[0..15] (host):
+ * nx ny nz Px Py Pz Kx dtype scratch_bytes tensor_bytes setup_us 0... */
+int demag_plan_info(demag_plan_t plan, int64_t* info);
+
+/* H = -Ms N * m  (Sec. 3.1 eq. (demag)); asynchronous on `stream`. */
+int demag_field(demag_plan_t plan, const void* m, double Ms, void* H, void* stream);
+
+/* Adjoint (transpose) of m -> H applied to a cotangent gH:
+ * gm (+)= A^T gH with A = -Ms N * (restricted to the grid).  N(o) is symmetric
+ * and even under o -> -o, so A^T = A and the same passes run on gH.
+ * accumulate = 0 overwrites gm, 1 adds to it.  Asynchronous. */
+int demag_field_adjoint(demag_plan_t plan, const void* gH, double Ms, void* gm, int accumulate, void* stream);
+
+/* Field and energy in one evaluation: H (may be NULL: energy only) and
+ * E_dev, a DEVICE double receiving E = -(mu0/2) Ms V sum m.H (Sec. 2).
+ * FP32 plans form m.H in FP32 and accumulate in FP64.  Asynchronous. */
+int demag_field_energy(demag_plan_t plan, const void* m, double Ms, void* H, double* E_dev, void* stream);
+
+/* Energy only, result to a HOST double; synchronises `stream`. */
+int demag_energy(demag_plan_t plan, const void* m, double Ms, double* E_host, void* stream);
+/* Energy only, result to a DEVICE double; asynchronous. */
+int demag_energy_async(demag_plan_t plan, const void* m, double Ms, double* E_dev, void* stream);
+
+/* Copy the stored tensor spectrum (plan precision) to HOST memory `out`,
+ * layout [Py/2+1][6][Kx][Pz/2+1], components xx yy zz xy xz yz, with the
+ * factor -1/(Px Py Pz) folded in.  Synchronous. */
+int demag_plan_spectrum(demag_plan_t plan, void* out);
+
+/* Recompute the FP64 real-space tensor octant N(o), o in [0,n), to HOST
+ * memory `out` [6][nz][ny][nx] (components xx yy zz xy xz yz).  Synchronous. */
+int demag_plan_tensor(demag_plan_t plan, double* out);
+
+/* Time the candidate launch shapes of every pass on this plan's buffers,
+ * keep the fastest, and update the cache file named by $DEMAG_AUTOTUNE_CACHE
+ * (if set).  Synchronous; clobbers the plan's scratch. */
+int demag_autotune(demag_plan_t plan, void* stream);
+
+/* Batch: `count` independent field evaluations (one per plan, plans may have
+ * different shapes but one precision) with their m / H device buffers; the
+ * whole batch is recorded once into a HIP graph and replayed by
+ * demag_batch_launch.  The batch references (does not own) plans and buffers;
+ * all must stay alive and unchanged until demag_batch_destroy.  Plans must be
+ * distinct (each owns the scratch its evaluation uses). */
+int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans, int count, const void* const* m,
+                       void* const* H, double Ms, void* stream);
+int demag_batch_launch(demag_batch_t batch, void* stream);
+int demag_batch_destroy(demag_batch_t batch);
+
+/* Last error message of the calling thread ("" if none). */
+const char* demag_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEMAG_H */

@@ -1,0 +1,871 @@
+// Plan runtime and C ABI of the DM stray-field library (host side).
+//
+// A plan fixes one grid (n, d) and precision.  Creating it computes the
+// demagnetization-tensor spectrum once (the paper's "setup" column: the
+// auxiliary constants depend only on geometry and discretization, Sec. 4) and
+// allocates the two spectrum scratch buffers; each field evaluation then
+// enqueues five pass kernels and, for the energy, one reduction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/demag.h"
+#include "internal.hpp"
+
+using namespace demag;
+
+// ---------------------------------------------------------------------------
+// errors
+namespace {
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(DEMAG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                                       \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);   \
+    } while (0)
+
+constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846264338327950288;
+constexpr int kMaxLen = 4096;
+constexpr size_t kMaxLdsBytes = 65536;  // dynamic LDS per workgroup
+
+// ---------------------------------------------------------------------------
+// lengths, radices, twiddles
+bool is_smooth(long v) {
+    for (int p : {2, 3, 5})
+        while (v % p == 0) v /= p;
+    return v == 1;
+}
+
+int smooth_at_least(int n) {
+    long v = n;
+    while (!is_smooth(v)) ++v;
+    return (int)v;
+}
+
+FftPlanDev make_fft_plan(int P) {
+    FftPlanDev pl{};
+    pl.P = P;
+    int v = P, ns = 0;
+    while (v % 8 == 0) { pl.radix[ns++] = 8; v /= 8; }
+    while (v % 4 == 0) { pl.radix[ns++] = 4; v /= 4; }
+    while (v % 2 == 0) { pl.radix[ns++] = 2; v /= 2; }
+    while (v % 5 == 0) { pl.radix[ns++] = 5; v /= 5; }
+    while (v % 3 == 0) { pl.radix[ns++] = 3; v /= 3; }
+    pl.nstages = ns;
+    return pl;
+}
+
+// tw[t] = exp(-2 pi i t / P), evaluated in long double and rounded once.
+template <typename T>
+std::vector<cx<T>> twiddles(int P) {
+    std::vector<cx<T>> tw(P);
+    const long double twopi = 6.283185307179586476925286766559005768L;
+    for (int t = 0; t < P; ++t) {
+        long double a = twopi * (long double)t / (long double)P;
+        tw[t].re = (T)cosl(a);
+        tw[t].im = (T)(-sinl(a));
+    }
+    return tw;
+}
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_q, long double).
+void gauss_legendre(int q, std::vector<double>& x, std::vector<double>& w) {
+    x.resize(q);
+    w.resize(q);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < q; ++i) {
+        long double z = cosl(pi * (i + 0.75L) / (q + 0.5L)), dp = 1;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1, p1 = z;
+            for (int k = 2; k <= q; ++k) {
+                long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = q * (z * p1 - p0) / (z * z - 1);
+            long double dz = p1 / dp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        long double p0 = 1, p1 = z;
+        for (int k = 2; k <= q; ++k) {
+            long double p2 = ((2 * k - 1) * z * p1 - (k - 1) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = q * (z * p1 - p0) / (z * z - 1);
+        x[i] = (double)z;
+        w[i] = (double)(2 / ((1 - z * z) * dp * dp));
+    }
+}
+
+int pick_E(long elems, int threads) {
+    for (int E : {4, 8, 16, 32})
+        if ((long)threads * E >= elems) return E;
+    return -1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct PassCfgs {
+    LaunchCfg xf, yf, zc, yi, xi;
+};
+
+struct demag_plan_s {
+    int n[3];
+    double d[3];
+    demag_dtype dtype;
+    int L[3], P[3], Kx;
+    FftPlanDev fp[3];
+    void* tw[3] = {nullptr, nullptr, nullptr};
+    void* nhat = nullptr;
+    void* B1 = nullptr;
+    void* B2 = nullptr;
+    double* partials = nullptr;
+    double* e_dev = nullptr;
+    int npartials = 0;
+    size_t scratch_bytes = 0, tensor_bytes = 0;
+    TensorBands bands;
+    PassCfgs cfg;
+    double setup_us = 0;
+    int device = 0;
+    hipEvent_t done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool used = false;
+    bool capturing = false;
+};
+
+struct demag_batch_s {
+    std::vector<demag_plan_t> plans;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+size_t csize(demag_dtype t) { return t == DEMAG_F32 ? sizeof(cx<float>) : sizeof(cx<double>); }
+
+// Default launch shapes: about `target` complex elements per workgroup, tiles
+// rounded to what the pass needs, E the smallest instance that covers them.
+LaunchCfg cfg_rows(int P, int rows, size_t cbytes) {
+    LaunchCfg c;
+    long target = (long)(32768 / cbytes);  // 32 KB of LDS
+    int pencils = (int)std::max<long>(1, target / P);
+    int Ty = std::min(2 * pencils, rows + (rows & 1));
+    Ty = std::max(2, Ty & ~1);
+    c.t0 = Ty;
+    c.E = pick_E((long)(Ty / 2) * P, c.threads);
+    return c;
+}
+
+LaunchCfg cfg_pencils(int P, int Kx, int nzr, size_t cbytes) {
+    LaunchCfg c;
+    long target = (long)(32768 / cbytes);
+    int B = (int)std::max<long>(1, target / P);
+    int Tz = std::min(B, nzr);
+    int Tx = std::max(1, std::min(B / Tz, Kx));
+    c.t0 = Tx;
+    c.t1 = Tz;
+    c.E = pick_E((long)Tx * Tz * P, c.threads);
+    return c;
+}
+
+LaunchCfg cfg_zconv(int P, int Kx, size_t cbytes) {
+    LaunchCfg c;
+    long target = (long)(32768 / cbytes);
+    int Tx = (int)std::max<long>(1, target / (6L * P));
+    Tx = std::min(Tx, Kx);
+    c.t0 = Tx;
+    c.E = pick_E(6L * Tx * P, c.threads);
+    return c;
+}
+
+bool cfg_ok(const LaunchCfg& c, long pencils, int P, size_t cbytes) {
+    return c.E > 0 && c.threads > 0 && c.threads <= kMaxThreads && c.threads % 64 == 0 &&
+           (long)c.threads * c.E >= pencils * P && (size_t)pencils * P * cbytes <= kMaxLdsBytes;
+}
+
+bool plan_cfgs_ok(const demag_plan_s* p, const PassCfgs& c) {
+    size_t cb = csize(p->dtype);
+    return cfg_ok(c.xf, (c.xf.t0 + 1) / 2, p->P[0], cb) && c.xf.t0 % 2 == 0 &&
+           cfg_ok(c.yf, (long)c.yf.t0 * c.yf.t1, p->P[1], cb) && cfg_ok(c.zc, 6L * c.zc.t0, p->P[2], cb) &&
+           cfg_ok(c.yi, (long)c.yi.t0 * c.yi.t1, p->P[1], cb) && cfg_ok(c.xi, (c.xi.t0 + 1) / 2, p->P[0], cb) &&
+           c.xi.t0 % 2 == 0;
+}
+
+PassCfgs default_cfgs(const demag_plan_s* p) {
+    size_t cb = csize(p->dtype);
+    PassCfgs c;
+    c.xf = cfg_rows(p->P[0], p->n[1], cb);
+    c.xi = c.xf;
+    c.yf = cfg_pencils(p->P[1], p->Kx, p->n[2], cb);
+    c.yi = c.yf;
+    c.zc = cfg_zconv(p->P[2], p->Kx, cb);
+    return c;
+}
+
+template <typename T>
+int upload(void** dst, const std::vector<T>& v) {
+    HIP_TRY(hipMalloc(dst, v.size() * sizeof(T)));
+    HIP_TRY(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return DEMAG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tensor setup (FP64 throughout, cast at the end)
+struct SetupBufs {
+    double* Noct = nullptr;
+    double* A = nullptr;
+    cx<double>* B1 = nullptr;
+    cx<double>* B2 = nullptr;
+    void* tw[3] = {nullptr, nullptr, nullptr};
+    double* glx = nullptr;
+    double* glw = nullptr;
+    ~SetupBufs() {
+        hipFree(Noct);
+        hipFree(A);
+        hipFree(B1);
+        hipFree(B2);
+        for (auto t : tw) hipFree(t);
+        hipFree(glx);
+        hipFree(glw);
+    }
+};
+
+void reduced_cell(const double d[3], double dt[3]) {
+    double h = std::max(d[0], std::max(d[1], d[2]));
+    for (int k = 0; k < 3; ++k) dt[k] = d[k] / h;
+}
+
+int compute_octant(demag_plan_s* p, hipStream_t st, SetupBufs& sb) {
+    const size_t ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
+    HIP_TRY(hipMalloc(&sb.Noct, 6 * ncell * sizeof(double)));
+    std::vector<double> gx, gw;
+    gauss_legendre(p->bands.gl_q, gx, gw);
+    int rc = upload((void**)&sb.glx, gx);
+    if (rc) return rc;
+    rc = upload((void**)&sb.glw, gw);
+    if (rc) return rc;
+    double dt[3];
+    reduced_cell(p->d, dt);
+    HIP_TRY(launch_tensor_octant(st, p->n[0], p->n[1], p->n[2], dt, p->bands, sb.glx, sb.glw, sb.Noct));
+    return DEMAG_OK;
+}
+
+template <typename T>
+int setup_spectrum(demag_plan_s* p, hipStream_t st) {
+    SetupBufs sb;
+    int rc = compute_octant(p, st, sb);
+    if (rc) return rc;
+    const int Px = p->P[0], Py = p->P[1], Pz = p->P[2], Kx = p->Kx;
+    const size_t nA = (size_t)Px * Py * Pz, nS = (size_t)Pz * Kx * Py;
+    HIP_TRY(hipMalloc(&sb.A, nA * sizeof(double)));
+    HIP_TRY(hipMalloc(&sb.B1, nS * sizeof(cx<double>)));
+    HIP_TRY(hipMalloc(&sb.B2, nS * sizeof(cx<double>)));
+    for (int k = 0; k < 3; ++k) {
+        rc = upload(&sb.tw[k], twiddles<double>(p->P[k]));
+        if (rc) return rc;
+    }
+    const size_t cb = sizeof(cx<double>);
+    LaunchCfg xf = cfg_rows(Px, Py, cb), yf = cfg_pencils(Py, Kx, Pz, cb), zf;
+    zf.t0 = (int)std::max<long>(1, std::min<long>(Kx, 2048 / Pz));
+    zf.E = pick_E((long)zf.t0 * Pz, zf.threads);
+    const double scale = -1.0 / ((double)Px * Py * Pz);
+    for (int comp = 0; comp < 6; ++comp) {
+        HIP_TRY(launch_tensor_embed(st, comp, p->n[0], p->n[1], p->n[2], Px, Py, Pz, sb.Noct, sb.A));
+        HIP_TRY(launch_x_fwd<double>(xf, st, sb.A, sb.B1, Px, Py, Pz, Kx, 1, p->fp[0], (const cx<double>*)sb.tw[0]));
+        HIP_TRY(launch_y_fwd<double>(yf, st, sb.B1, sb.B2, Py, Pz, Kx, Pz, 1, p->fp[1], (const cx<double>*)sb.tw[1]));
+        HIP_TRY(launch_z_fwd<double>(zf, st, sb.B2, Py, Kx, p->fp[2], (const cx<double>*)sb.tw[2]));
+        HIP_TRY(launch_tensor_extract<T>(st, comp, Px, Py, Pz, Kx, scale, sb.B2, (T*)p->nhat));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return DEMAG_OK;
+}
+
+int run_setup(demag_plan_s* p, hipStream_t st) {
+    auto t0 = std::chrono::steady_clock::now();
+    int rc = p->dtype == DEMAG_F32 ? setup_spectrum<float>(p, st) : setup_spectrum<double>(p, st);
+    p->setup_us = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+    return rc;
+}
+
+void free_plan(demag_plan_s* p) {
+    for (auto t : p->tw) hipFree(t);
+    hipFree(p->nhat);
+    hipFree(p->B1);
+    hipFree(p->B2);
+    hipFree(p->partials);
+    hipFree(p->e_dev);
+    if (p->done) hipEventDestroy(p->done);
+    delete p;
+}
+
+// ---------------------------------------------------------------------------
+// one evaluation: X-R2C -> Y -> Z (x N) -> Y^-1 -> X-C2R (+ energy)
+template <typename T>
+int run_field(demag_plan_s* p, const PassCfgs& c, const T* m, double Ms, T* H, const T* m_energy, double* E_dev,
+              int accumulate, hipStream_t st) {
+    const int nx = p->n[0], ny = p->n[1], nz = p->n[2], Kx = p->Kx;
+    auto* B1 = (cx<T>*)p->B1;
+    auto* B2 = (cx<T>*)p->B2;
+    const auto* twx = (const cx<T>*)p->tw[0];
+    const auto* twy = (const cx<T>*)p->tw[1];
+    const auto* twz = (const cx<T>*)p->tw[2];
+    HIP_TRY(launch_x_fwd<T>(c.xf, st, m, B1, nx, ny, nz, Kx, 3, p->fp[0], twx));
+    HIP_TRY(launch_y_fwd<T>(c.yf, st, B1, B2, ny, nz, Kx, nz, 3, p->fp[1], twy));
+    HIP_TRY(launch_z_conv<T>(c.zc, st, B2, (const T*)p->nhat, (T)Ms, nz, p->P[1], Kx, p->fp[2], twz));
+    HIP_TRY(launch_y_inv<T>(c.yi, st, B2, B1, ny, nz, Kx, 3, p->fp[1], twy));
+    double* partials = E_dev ? p->partials : nullptr;
+    HIP_TRY(launch_x_inv<T>(c.xi, st, B1, H, E_dev ? m_energy : nullptr, partials, nx, ny, nz, Kx, 3, accumulate,
+                            p->fp[0], twx));
+    if (E_dev) {
+        const int nparts = ((ny + c.xi.t0 - 1) / c.xi.t0) * nz * 3;
+        const double V = p->d[0] * p->d[1] * p->d[2];
+        HIP_TRY(launch_energy_reduce(st, p->partials, nparts, -0.5 * kMu0 * Ms * V, E_dev));
+    }
+    return DEMAG_OK;
+}
+
+int dispatch_field(demag_plan_s* p, const void* m, double Ms, void* H, double* E_dev, int accumulate,
+                   hipStream_t st) {
+    if (p->dtype == DEMAG_F32)
+        return run_field<float>(p, p->cfg, (const float*)m, Ms, (float*)H, (const float*)m, E_dev, accumulate, st);
+    return run_field<double>(p, p->cfg, (const double*)m, Ms, (double*)H, (const double*)m, E_dev, accumulate, st);
+}
+
+// One plan on one stream at a time: refuse a call on another stream while
+// the plan's previous work is still pending.
+int enter(demag_plan_s* p, hipStream_t st) {
+    if (p->capturing) return DEMAG_OK;
+    int cur = 0;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != p->device) return fail(DEMAG_ESTATE, "plan was created on device %d, current device is %d", p->device, cur);
+    if (p->used && st != p->last_stream) {
+        hipError_t q = hipEventQuery(p->done);
+        if (q == hipErrorNotReady)
+            return fail(DEMAG_ESTATE, "plan is still busy on another stream");
+        if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
+    }
+    return DEMAG_OK;
+}
+
+int leave(demag_plan_s* p, hipStream_t st) {
+    if (p->capturing) return DEMAG_OK;
+    HIP_TRY(hipEventRecord(p->done, st));
+    p->last_stream = st;
+    p->used = true;
+    return DEMAG_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+extern "C" {
+
+const char* demag_last_error(void) { return g_last_error.c_str(); }
+
+int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, double dy, double dz,
+                      demag_dtype dtype, void* setup_stream) {
+    if (!out) return fail(DEMAG_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(DEMAG_EINVAL, "grid must be at least 1x1x1 (got %d x %d x %d)", nx, ny, nz);
+    if (!finite_pos(dx) || !finite_pos(dy) || !finite_pos(dz))
+        return fail(DEMAG_EINVAL, "cell sizes must be finite and > 0");
+    if (dtype != DEMAG_F32 && dtype != DEMAG_F64) return fail(DEMAG_EINVAL, "unknown dtype %d", (int)dtype);
+    const int n[3] = {nx, ny, nz};
+    int L[3], P[3];
+    for (int k = 0; k < 3; ++k) {
+        if (n[k] > kMaxLen / 2) return fail(DEMAG_EUNSUPPORTED, "axis %d: n = %d exceeds %d", k, n[k], kMaxLen / 2);
+        L[k] = smooth_at_least(n[k]);
+        P[k] = 2 * L[k];
+        if (P[k] > kMaxLen) return fail(DEMAG_EUNSUPPORTED, "axis %d: padded length %d exceeds %d", k, P[k], kMaxLen);
+        const size_t cb = dtype == DEMAG_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
+        if ((size_t)P[k] * cb > kMaxLdsBytes || (size_t)P[k] * sizeof(cx<double>) > kMaxLdsBytes)
+            return fail(DEMAG_EUNSUPPORTED, "axis %d: padded length %d does not fit one LDS pencil in FP64", k, P[k]);
+    }
+    const int Kx = P[0] / 2 + 1;
+    // all device buffers are indexed with 64-bit bases; per-dimension extents fit in int
+    const long double big = (long double)P[0] * P[1] * P[2];
+    if (big > 4.0e12L) return fail(DEMAG_EINVAL, "padded grid too large");
+
+    auto* p = new demag_plan_s();
+    for (int k = 0; k < 3; ++k) {
+        p->n[k] = n[k];
+        p->L[k] = L[k];
+        p->P[k] = P[k];
+        p->fp[k] = make_fft_plan(P[k]);
+    }
+    p->d[0] = dx;
+    p->d[1] = dy;
+    p->d[2] = dz;
+    p->dtype = dtype;
+    p->Kx = Kx;
+    hipError_t he = hipGetDevice(&p->device);
+    if (he != hipSuccess) {
+        delete p;
+        return hip_fail(he, "hipGetDevice");
+    }
+    hipStream_t st = (hipStream_t)setup_stream;
+    const size_t cb = csize(dtype), rb = dtype == DEMAG_F32 ? 4 : 8;
+    const size_t nB1 = 3ull * nz * Kx * ny, nB2 = 3ull * P[1] * Kx * nz;
+    const size_t nH = (size_t)(P[1] / 2 + 1) * 6 * Kx * (P[2] / 2 + 1);
+    p->cfg = default_cfgs(p);
+    int rc = DEMAG_OK;
+    auto alloc = [&](void** ptr, size_t bytes, const char* what) {
+        if (rc) return;
+        if (hipMalloc(ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *ptr = nullptr;
+            rc = fail(DEMAG_ENOMEM, "cannot allocate %zu bytes for %s", bytes, what);
+        }
+    };
+    alloc(&p->B1, nB1 * cb, "spectrum scratch B1");
+    alloc(&p->B2, nB2 * cb, "spectrum scratch B2");
+    alloc(&p->nhat, nH * rb, "tensor spectrum");
+    p->npartials = 3 * nz * ((ny + 1) / 2);  // upper bound: X-inverse tiles of >= 2 rows
+    alloc((void**)&p->partials, (size_t)p->npartials * sizeof(double), "energy partials");
+    alloc((void**)&p->e_dev, sizeof(double), "energy scalar");
+    p->scratch_bytes = (nB1 + nB2) * cb;
+    p->tensor_bytes = nH * rb;
+    if (!rc) {
+        for (int k = 0; k < 3 && !rc; ++k)
+            rc = dtype == DEMAG_F32 ? upload(&p->tw[k], twiddles<float>(P[k])) : upload(&p->tw[k], twiddles<double>(P[k]));
+    }
+    if (!rc && hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess)
+        rc = fail(DEMAG_EHIP, "hipEventCreate failed");
+    if (!rc) rc = run_setup(p, st);
+    if (rc) {
+        free_plan(p);
+        return rc;
+    }
+    *out = p;
+    return DEMAG_OK;
+}
+
+int demag_plan_set_option(demag_plan_t p, const char* key, double value) {
+    if (!p || !key) return fail(DEMAG_EINVAL, "NULL plan or key");
+    TensorBands b = p->bands;
+    if (!strcmp(key, "far_cut")) {
+        if (!(value > 0) || std::isnan(value)) return fail(DEMAG_EINVAL, "far_cut must be > 0");
+        b.far_cut = value;
+    } else if (!strcmp(key, "fg_cut")) {
+        if (!(value >= 0) || value != std::floor(value) || value > 1e9)
+            return fail(DEMAG_EINVAL, "fg_cut must be a non-negative integer");
+        b.fg_cut = (int)value;
+    } else {
+        return fail(DEMAG_EINVAL, "unknown option '%s'", key);
+    }
+    HIP_TRY(hipDeviceSynchronize());
+    p->bands = b;
+    return run_setup(p, nullptr);
+}
+
+int demag_plan_destroy(demag_plan_t p) {
+    if (!p) return fail(DEMAG_EINVAL, "NULL plan");
+    hipDeviceSynchronize();
+    free_plan(p);
+    return DEMAG_OK;
+}
+
+int demag_plan_info(demag_plan_t p, int64_t* info) {
+    if (!p || !info) return fail(DEMAG_EINVAL, "NULL argument");
+    int64_t v[16] = {p->n[0], p->n[1], p->n[2], p->P[0], p->P[1], p->P[2], p->Kx, (int64_t)p->dtype,
+                     (int64_t)p->scratch_bytes, (int64_t)p->tensor_bytes, (int64_t)p->setup_us, 0, 0, 0, 0, 0};
+    memcpy(info, v, sizeof v);
+    return DEMAG_OK;
+}
+
+int demag_field(demag_plan_t p, const void* m, double Ms, void* H, void* stream) {
+    if (!p || !m || !H) return fail(DEMAG_EINVAL, "NULL plan, m or H");
+    if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    rc = dispatch_field(p, m, Ms, H, nullptr, 0, st);
+    if (rc) return rc;
+    return leave(p, st);
+}
+
+int demag_field_adjoint(demag_plan_t p, const void* gH, double Ms, void* gm, int accumulate, void* stream) {
+    if (!p || !gH || !gm) return fail(DEMAG_EINVAL, "NULL plan, gH or gm");
+    if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
+    if (accumulate != 0 && accumulate != 1) return fail(DEMAG_EINVAL, "accumulate must be 0 or 1");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    rc = dispatch_field(p, gH, Ms, gm, nullptr, accumulate, st);
+    if (rc) return rc;
+    return leave(p, st);
+}
+
+int demag_field_energy(demag_plan_t p, const void* m, double Ms, void* H, double* E_dev, void* stream) {
+    if (!p || !m || !E_dev) return fail(DEMAG_EINVAL, "NULL plan, m or E_dev");
+    if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    rc = dispatch_field(p, m, Ms, H, E_dev, 0, st);
+    if (rc) return rc;
+    return leave(p, st);
+}
+
+int demag_energy_async(demag_plan_t p, const void* m, double Ms, double* E_dev, void* stream) {
+    return demag_field_energy(p, m, Ms, nullptr, E_dev, stream);
+}
+
+int demag_energy(demag_plan_t p, const void* m, double Ms, double* E_host, void* stream) {
+    if (!E_host) return fail(DEMAG_EINVAL, "E_host is NULL");
+    if (!p) return fail(DEMAG_EINVAL, "NULL plan");
+    int rc = demag_field_energy(p, m, Ms, nullptr, p->e_dev, stream);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipMemcpyAsync(E_host, p->e_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return DEMAG_OK;
+}
+
+int demag_plan_spectrum(demag_plan_t p, void* out) {
+    if (!p || !out) return fail(DEMAG_EINVAL, "NULL argument");
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(out, p->nhat, p->tensor_bytes, hipMemcpyDeviceToHost));
+    return DEMAG_OK;
+}
+
+int demag_plan_tensor(demag_plan_t p, double* out) {
+    if (!p || !out) return fail(DEMAG_EINVAL, "NULL argument");
+    HIP_TRY(hipDeviceSynchronize());
+    SetupBufs sb;
+    int rc = compute_octant(p, nullptr, sb);
+    if (rc) return rc;
+    const size_t ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
+    HIP_TRY(hipMemcpy(out, sb.Noct, 6 * ncell * sizeof(double), hipMemcpyDeviceToHost));
+    return DEMAG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuner
+namespace {
+
+std::vector<LaunchCfg> candidates_rows(const demag_plan_s* p) {
+    std::vector<LaunchCfg> out;
+    const size_t cb = csize(p->dtype);
+    for (int threads : {128, 256})
+        for (int Ty : {2, 4, 8, 16, 32, 64}) {
+            if (Ty > p->n[1] + (p->n[1] & 1) && Ty != 2) continue;
+            LaunchCfg c;
+            c.threads = threads;
+            c.t0 = Ty;
+            c.E = pick_E((long)(Ty / 2) * p->P[0], threads);
+            if (cfg_ok(c, Ty / 2, p->P[0], cb)) out.push_back(c);
+        }
+    return out;
+}
+
+std::vector<LaunchCfg> candidates_pencils(const demag_plan_s* p) {
+    std::vector<LaunchCfg> out;
+    const size_t cb = csize(p->dtype);
+    for (int threads : {128, 256})
+        for (int Tz : {1, 2, 4, 8, 16, 32, 64})
+            for (int Tx : {1, 2, 4, 8, 16}) {
+                if (Tz > p->n[2] && Tz != 1) continue;
+                if (Tx > p->Kx && Tx != 1) continue;
+                LaunchCfg c;
+                c.threads = threads;
+                c.t0 = Tx;
+                c.t1 = Tz;
+                c.E = pick_E((long)Tx * Tz * p->P[1], threads);
+                if (cfg_ok(c, (long)Tx * Tz, p->P[1], cb)) out.push_back(c);
+            }
+    return out;
+}
+
+std::vector<LaunchCfg> candidates_z(const demag_plan_s* p) {
+    std::vector<LaunchCfg> out;
+    const size_t cb = csize(p->dtype);
+    for (int threads : {128, 256})
+        for (int Tx : {1, 2, 3, 4, 6, 8, 12, 16}) {
+            if (Tx > p->Kx && Tx != 1) continue;
+            LaunchCfg c;
+            c.threads = threads;
+            c.t0 = Tx;
+            c.E = pick_E(6L * Tx * p->P[2], threads);
+            if (cfg_ok(c, 6L * Tx, p->P[2], cb)) out.push_back(c);
+        }
+    return out;
+}
+
+std::string cfg_str(const LaunchCfg& c) {
+    char b[64];
+    snprintf(b, sizeof b, "%d,%d,%d,%d", c.threads, c.E, c.t0, c.t1);
+    return b;
+}
+
+bool cfg_parse(const std::string& s, LaunchCfg& c) {
+    return sscanf(s.c_str(), "%d,%d,%d,%d", &c.threads, &c.E, &c.t0, &c.t1) == 4;
+}
+
+std::string cache_key(const demag_plan_s* p) {
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    char b[160];
+    snprintf(b, sizeof b, "v1|%s|%s|%d,%d,%d", arch.c_str(), p->dtype == DEMAG_F32 ? "f32" : "f64", p->n[0],
+             p->n[1], p->n[2]);
+    return b;
+}
+
+// Cache file: one line per plan key, "key xf yf zc yi xi" (each a,b,c,d).
+std::map<std::string, std::string> read_cache(const char* path) {
+    std::map<std::string, std::string> m;
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+        auto sp = line.find(' ');
+        if (sp == std::string::npos || line.rfind("v1|", 0) != 0) continue;
+        m[line.substr(0, sp)] = line.substr(sp + 1);
+    }
+    return m;
+}
+
+bool parse_cfgs(const std::string& s, PassCfgs& c) {
+    std::istringstream is(s);
+    std::string a[5];
+    for (auto& x : a)
+        if (!(is >> x)) return false;
+    return cfg_parse(a[0], c.xf) && cfg_parse(a[1], c.yf) && cfg_parse(a[2], c.zc) && cfg_parse(a[3], c.yi) &&
+           cfg_parse(a[4], c.xi);
+}
+
+template <typename T>
+int time_pass(demag_plan_s* p, int which, const LaunchCfg& lc, hipStream_t st, const T* m, T* H, float* ms_out) {
+    PassCfgs c = p->cfg;
+    LaunchCfg* slot[5] = {&c.xf, &c.yf, &c.zc, &c.yi, &c.xi};
+    *slot[which] = lc;
+    const int nx = p->n[0], ny = p->n[1], nz = p->n[2], Kx = p->Kx;
+    auto* B1 = (cx<T>*)p->B1;
+    auto* B2 = (cx<T>*)p->B2;
+    auto launch = [&]() -> hipError_t {
+        switch (which) {
+        case 0: return launch_x_fwd<T>(c.xf, st, m, B1, nx, ny, nz, Kx, 3, p->fp[0], (const cx<T>*)p->tw[0]);
+        case 1: return launch_y_fwd<T>(c.yf, st, B1, B2, ny, nz, Kx, nz, 3, p->fp[1], (const cx<T>*)p->tw[1]);
+        case 2: return launch_z_conv<T>(c.zc, st, B2, (const T*)p->nhat, T(1), nz, p->P[1], Kx, p->fp[2], (const cx<T>*)p->tw[2]);
+        case 3: return launch_y_inv<T>(c.yi, st, B2, B1, ny, nz, Kx, 3, p->fp[1], (const cx<T>*)p->tw[1]);
+        default: return launch_x_inv<T>(c.xi, st, B1, H, nullptr, nullptr, nx, ny, nz, Kx, 3, 0, p->fp[0], (const cx<T>*)p->tw[0]);
+        }
+    };
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipError_t err = launch();
+    const int reps = 5;
+    if (err == hipSuccess) err = hipEventRecord(e0, st);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
+    if (err == hipSuccess) err = hipEventRecord(e1, st);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_fail(err, "autotune timing");
+    *ms_out = ms / reps;
+    return DEMAG_OK;
+}
+
+template <typename T>
+int autotune_impl(demag_plan_s* p, hipStream_t st) {
+    const size_t nvec = 3ull * p->n[0] * p->n[1] * p->n[2];
+    T *m = nullptr, *H = nullptr;
+    HIP_TRY(hipMalloc(&m, nvec * sizeof(T)));
+    HIP_TRY(hipMalloc(&H, nvec * sizeof(T)));
+    HIP_TRY(hipMemsetAsync(m, 0, nvec * sizeof(T), st));
+    int rc = DEMAG_OK;
+    std::vector<LaunchCfg> cand[5] = {candidates_rows(p), candidates_pencils(p), candidates_z(p),
+                                      candidates_pencils(p), candidates_rows(p)};
+    LaunchCfg* slot[5] = {&p->cfg.xf, &p->cfg.yf, &p->cfg.zc, &p->cfg.yi, &p->cfg.xi};
+    for (int which = 0; which < 5 && !rc; ++which) {
+        float best = 1e30f;
+        LaunchCfg bestc = *slot[which];
+        for (const auto& lc : cand[which]) {
+            float ms = 0;
+            rc = time_pass<T>(p, which, lc, st, m, H, &ms);
+            if (rc) break;
+            if (ms < best) {
+                best = ms;
+                bestc = lc;
+            }
+        }
+        *slot[which] = bestc;
+    }
+    hipFree(m);
+    hipFree(H);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" int demag_autotune(demag_plan_t p, void* stream) {
+    if (!p) return fail(DEMAG_EINVAL, "NULL plan");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    const char* path = getenv("DEMAG_AUTOTUNE_CACHE");
+    const std::string key = cache_key(p);
+    if (path) {
+        auto cache = read_cache(path);
+        auto it = cache.find(key);
+        PassCfgs c;
+        if (it != cache.end() && parse_cfgs(it->second, c) && plan_cfgs_ok(p, c)) {
+            p->cfg = c;  // a valid cached entry; a corrupt one falls through to tuning
+            return DEMAG_OK;
+        }
+    }
+    rc = p->dtype == DEMAG_F32 ? autotune_impl<float>(p, st) : autotune_impl<double>(p, st);
+    if (rc) {
+        p->cfg = default_cfgs(p);
+        return rc;
+    }
+    if (path) {
+        auto cache = read_cache(path);
+        cache[key] = cfg_str(p->cfg.xf) + " " + cfg_str(p->cfg.yf) + " " + cfg_str(p->cfg.zc) + " " +
+                     cfg_str(p->cfg.yi) + " " + cfg_str(p->cfg.xi);
+        std::string tmp = std::string(path) + ".tmp";
+        std::ofstream f(tmp);
+        for (auto& kv : cache) f << kv.first << " " << kv.second << "\n";
+        f.close();
+        if (f) std::rename(tmp.c_str(), path);
+    }
+    return leave(p, st);
+}
+
+// ---------------------------------------------------------------------------
+// batch: every plan's evaluation recorded once into one HIP graph.  Plans are
+// spread over up to kBranches forked capture streams, so small grids run side
+// by side; one replay of the graph is one evaluation of the whole batch.
+namespace {
+constexpr int kBranches = 8;
+}
+
+extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans, int count, const void* const* m,
+                                  void* const* H, double Ms, void* stream) {
+    if (!out || !plans || !m || !H || count < 1) return fail(DEMAG_EINVAL, "bad batch arguments");
+    *out = nullptr;
+    if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
+    for (int i = 0; i < count; ++i) {
+        if (!plans[i] || !m[i] || !H[i]) return fail(DEMAG_EINVAL, "NULL plan or buffer at batch index %d", i);
+        if (plans[i]->dtype != plans[0]->dtype) return fail(DEMAG_EINVAL, "mixed precisions in one batch");
+        for (int j = 0; j < i; ++j)
+            if (plans[j] == plans[i]) return fail(DEMAG_EINVAL, "plan repeated at batch indices %d and %d", j, i);
+    }
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    auto* b = new demag_batch_s();
+    b->plans.assign(plans, plans + count);
+    hipStream_t cs[kBranches] = {};
+    hipEvent_t ev[kBranches + 1] = {};
+    const int nb = std::min(kBranches, count);
+    int rc = DEMAG_OK;
+    for (int k = 0; k < nb && !rc; ++k)
+        if (hipStreamCreateWithFlags(&cs[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess)
+            rc = fail(DEMAG_EHIP, "cannot create capture streams");
+    if (!rc && hipEventCreateWithFlags(&ev[kBranches], hipEventDisableTiming) != hipSuccess)
+        rc = fail(DEMAG_EHIP, "cannot create capture event");
+    bool capturing = false;
+    if (!rc) {
+        if (hipStreamBeginCapture(cs[0], hipStreamCaptureModeThreadLocal) != hipSuccess)
+            rc = fail(DEMAG_EHIP, "hipStreamBeginCapture failed");
+        else
+            capturing = true;
+    }
+    if (!rc) {
+        hipEventRecord(ev[kBranches], cs[0]);
+        for (int k = 1; k < nb; ++k) hipStreamWaitEvent(cs[k], ev[kBranches], 0);
+        for (int i = 0; i < count && !rc; ++i) {
+            demag_plan_s* p = plans[i];
+            p->capturing = true;
+            rc = dispatch_field(p, m[i], Ms, H[i], nullptr, 0, cs[i % nb]);
+            p->capturing = false;
+        }
+        for (int k = 1; k < nb; ++k) {
+            hipEventRecord(ev[k], cs[k]);
+            hipStreamWaitEvent(cs[0], ev[k], 0);
+        }
+    }
+    if (capturing) {
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cs[0], &g);
+        if (!rc && e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
+        b->graph = g;
+        if (!rc && hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess)
+            rc = fail(DEMAG_EHIP, "hipGraphInstantiate failed");
+    }
+    for (int k = 0; k < nb; ++k) {
+        if (cs[k]) hipStreamDestroy(cs[k]);
+        if (ev[k]) hipEventDestroy(ev[k]);
+    }
+    if (ev[kBranches]) hipEventDestroy(ev[kBranches]);
+    if (rc) {
+        if (b->exec) hipGraphExecDestroy(b->exec);
+        if (b->graph) hipGraphDestroy(b->graph);
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return DEMAG_OK;
+}
+
+extern "C" int demag_batch_launch(demag_batch_t b, void* stream) {
+    if (!b || !b->exec) return fail(DEMAG_EINVAL, "NULL batch");
+    hipStream_t st = (hipStream_t)stream;
+    for (auto p : b->plans) {
+        int rc = enter(p, st);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipGraphLaunch(b->exec, st));
+    for (auto p : b->plans) {
+        int rc = leave(p, st);
+        if (rc) return rc;
+    }
+    return DEMAG_OK;
+}
+
+extern "C" int demag_batch_destroy(demag_batch_t b) {
+    if (!b) return fail(DEMAG_EINVAL, "NULL batch");
+    hipDeviceSynchronize();
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    delete b;
+    return DEMAG_OK;
+}

@@ -1,0 +1,213 @@
+"""Python face of the DM stray-field library: Plan, Batch, autograd Functions.
+
+Torch supplies device memory and streams only; each method hands raw device
+pointers and the current HIP stream to the C ABI (include/demag.h).
+
+Conventions (Abert et al., Sec. 2 and Sec. 3.1): a magnetization direction
+field m has shape (3, nz, ny, nx) on the GPU; H = -Ms N * m in A/m;
+E = -(mu0/2) Ms V sum m.H in J.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+MU0 = 4.0e-7 * np.pi
+_DT = {torch.float32: _lib.DEMAG_F32, torch.float64: _lib.DEMAG_F64}
+
+
+def _stream_ptr():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """One grid (shape (nx, ny, nz), cell (dx, dy, dz) in metres) and precision.
+
+    Creating a plan computes the tensor spectrum on the current CUDA device
+    (FP64 setup, stored in `dtype`)."""
+
+    def __init__(self, shape, cell, dtype=torch.float32, far_cut=None, fg_cut=None):
+        if dtype not in _DT:
+            raise TypeError("dtype must be torch.float32 or torch.float64")
+        self.shape = tuple(int(v) for v in shape)
+        self.cell = tuple(float(v) for v in cell)
+        self.dtype = dtype
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = ctypes.c_void_p()
+        nx, ny, nz = self.shape
+        _lib.call("demag_plan_create", ctypes.byref(h), nx, ny, nz, *self.cell, _DT[dtype], _stream_ptr())
+        self._h = h
+        if far_cut is not None:
+            self.set_option("far_cut", far_cut)
+        if fg_cut is not None:
+            self.set_option("fg_cut", fg_cut)
+
+    # -- lifetime -------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.call("demag_plan_destroy", self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- facts ------------------------------------------------------------
+    @property
+    def volume(self) -> float:
+        dx, dy, dz = self.cell
+        return dx * dy * dz
+
+    @property
+    def vec_shape(self):
+        nx, ny, nz = self.shape
+        return (3, nz, ny, nx)
+
+    def info(self) -> dict:
+        v = (ctypes.c_int64 * 16)()
+        _lib.call("demag_plan_info", self._h, v)
+        keys = ["nx", "ny", "nz", "Px", "Py", "Pz", "Kx", "dtype", "scratch_bytes", "tensor_bytes", "setup_us"]
+        return {k: int(v[i]) for i, k in enumerate(keys)}
+
+    def set_option(self, key: str, value: float):
+        _lib.call("demag_plan_set_option", self._h, key.encode(), float(value))
+
+    def autotune(self):
+        _lib.call("demag_autotune", self._h, _stream_ptr())
+
+    def spectrum(self) -> np.ndarray:
+        """Stored tensor spectrum, [Py/2+1][6][Kx][Pz/2+1], -1/(PxPyPz) folded in."""
+        i = self.info()
+        a = np.empty((i["Py"] // 2 + 1, 6, i["Kx"], i["Pz"] // 2 + 1),
+                     dtype=np.float32 if self.dtype == torch.float32 else np.float64)
+        _lib.call("demag_plan_spectrum", self._h, a.ctypes.data_as(ctypes.c_void_p))
+        return a
+
+    def tensor(self) -> np.ndarray:
+        """FP64 real-space tensor octant N(o), [6][nz][ny][nx]."""
+        nx, ny, nz = self.shape
+        a = np.empty((6, nz, ny, nx), dtype=np.float64)
+        _lib.call("demag_plan_tensor", self._h, a.ctypes.data_as(ctypes.c_void_p))
+        return a
+
+    # -- evaluation -------------------------------------------------------
+    def _check(self, t: torch.Tensor, name: str):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} has dtype {t.dtype}, plan has {self.dtype}")
+        if tuple(t.shape) != self.vec_shape:
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {self.vec_shape}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def _ptr(self, t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    def field(self, m: torch.Tensor, Ms: float, out: torch.Tensor | None = None) -> torch.Tensor:
+        self._check(m, "m")
+        H = torch.empty_like(m) if out is None else out
+        self._check(H, "out")
+        _lib.call("demag_field", self._h, self._ptr(m), float(Ms), self._ptr(H), _stream_ptr())
+        return H
+
+    def adjoint(self, gH: torch.Tensor, Ms: float, out: torch.Tensor | None = None,
+                accumulate: bool = False) -> torch.Tensor:
+        self._check(gH, "gH")
+        gm = torch.empty_like(gH) if out is None else out
+        self._check(gm, "out")
+        _lib.call("demag_field_adjoint", self._h, self._ptr(gH), float(Ms), self._ptr(gm),
+                  1 if accumulate else 0, _stream_ptr())
+        return gm
+
+    def field_energy(self, m: torch.Tensor, Ms: float, with_field: bool = True):
+        """(H or None, E) with E a 0-dim float64 CUDA tensor."""
+        self._check(m, "m")
+        H = torch.empty_like(m) if with_field else None
+        E = torch.empty((), dtype=torch.float64, device=m.device)
+        _lib.call("demag_field_energy", self._h, self._ptr(m), float(Ms),
+                  self._ptr(H) if H is not None else None, ctypes.c_void_p(E.data_ptr()), _stream_ptr())
+        return H, E
+
+    def energy(self, m: torch.Tensor, Ms: float) -> float:
+        self._check(m, "m")
+        e = ctypes.c_double()
+        _lib.call("demag_energy", self._h, self._ptr(m), float(Ms), ctypes.byref(e), _stream_ptr())
+        return e.value
+
+
+class Batch:
+    """Field evaluations of several plans recorded into one HIP graph."""
+
+    def __init__(self, plans, ms, hs, Ms: float):
+        n = len(plans)
+        self._keep = (list(plans), list(ms), list(hs))
+        for p, m, h in zip(plans, ms, hs):
+            p._check(m, "m")
+            p._check(h, "H")
+        arr_p = (ctypes.c_void_p * n)(*[p._h.value for p in plans])
+        arr_m = (ctypes.c_void_p * n)(*[m.data_ptr() for m in ms])
+        arr_h = (ctypes.c_void_p * n)(*[h.data_ptr() for h in hs])
+        b = ctypes.c_void_p()
+        _lib.call("demag_batch_create", ctypes.byref(b), arr_p, n, arr_m, arr_h, float(Ms), _stream_ptr())
+        self._h = b
+
+    def launch(self):
+        _lib.call("demag_batch_launch", self._h, _stream_ptr())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.call("demag_batch_destroy", self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DemagField(torch.autograd.Function):
+    """H = -Ms N * m with the hand-written adjoint as its backward:
+    dL/dm = A^T dL/dH, A = -Ms N * (A = A^T; same passes on the cotangent)."""
+
+    @staticmethod
+    def forward(ctx, m, plan: Plan, Ms: float):
+        ctx.plan, ctx.Ms = plan, float(Ms)
+        return plan.field(m.contiguous(), Ms)
+
+    @staticmethod
+    def backward(ctx, gH):
+        gm = ctx.plan.adjoint(gH.contiguous(), ctx.Ms)
+        return gm, None, None
+
+
+class DemagEnergy(torch.autograd.Function):
+    """E = -(mu0/2) Ms V sum m.H; dE/dm = -mu0 Ms V H (the operator is
+    symmetric), so the backward needs no further convolution."""
+
+    @staticmethod
+    def forward(ctx, m, plan: Plan, Ms: float):
+        H, E = plan.field_energy(m.contiguous(), Ms)
+        ctx.save_for_backward(H)
+        ctx.scale = -MU0 * float(Ms) * plan.volume
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        (H,) = ctx.saved_tensors
+        return (gE.to(H.dtype) * ctx.scale) * H, None, None
+
+
+def demag_field(m, plan: Plan, Ms: float):
+    return DemagField.apply(m, plan, Ms)
+
+
+def demag_energy(m, plan: Plan, Ms: float):
+    return DemagEnergy.apply(m, plan, Ms)

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP path against the CPU oracle, element by element.
+
+Bars (relative max-norm, eps = max|H - H_ref| / max|H_ref|): FP64 <= 1e-12,
+FP32 <= 1e-5.  Shapes span several workgroup tiles and ragged tails, padded
+lengths with radix-3/5 factors, degenerate axes of length 1 and non-cubic
+cells.  FP32 inputs are compared against the oracle evaluated on the same
+FP32-rounded m promoted to FP64, so input quantisation is not counted.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1204_4302_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32_TOL = 1e-5
+
+
+def rel_err(a, ref):
+    return float(np.max(np.abs(a - ref)) / np.max(np.abs(ref)))
+
+
+def to_gpu(m, dtype):
+    return torch.from_numpy(np.ascontiguousarray(m)).to(device="cuda", dtype=dtype)
+
+
+def quantised(m, dtype):
+    return m.astype(np.float32).astype(np.float64) if dtype == torch.float32 else m
+
+
+_ORACLES = {}
+
+
+def get_oracle(shape, cell):
+    key = (tuple(shape), tuple(cell))
+    if key not in _ORACLES:
+        _ORACLES[key] = oracle.Oracle(shape, cell)
+    return _ORACLES[key]
+
+
+_PLANS = {}
+
+
+def get_plan(shape, cell, dtype):
+    from paper_1204_4302_amd import Plan
+    key = (tuple(shape), tuple(cell), dtype)
+    if key not in _PLANS:
+        _PLANS[key] = Plan(shape, cell, dtype)
+    return _PLANS[key]
+
+
+SHAPES = [
+    ((8, 8, 8), (2e-9, 2e-9, 2e-9), 8e5),          # the plain FP64 DM case
+    ((1, 1, 1), (2e-9, 2e-9, 3e-9), 1.4e6),        # single cell
+    ((5, 1, 1), (2e-9, 2e-9, 2e-9), 8e5),          # chain
+    ((1, 1, 7), (1.95e-9, 1.95e-9, 0.75e-9), 8e5),  # column
+    ((13, 7, 5), (2e-9, 2e-9, 3e-9), 1.4e6),       # non-smooth n -> padded 30, 14, 10
+    ((24, 17, 3), (1.95e-9, 1.95e-9, 0.75e-9), 8e5),
+    ((33, 20, 9), (2.5e-9, 2.5e-9, 2.5e-9), 8e5),  # padded 72 (8*9) ragged tiles
+    ((48, 12, 6), (2e-9, 2e-9, 2e-9), 8e5),        # 96 = 8*4*3
+    ((70, 9, 2), (2e-9, 3e-9, 1e-9), 8e5),         # far band reached along x
+]
+
+
+@pytest.mark.parametrize("shape,cell,Ms", SHAPES, ids=lambda v: str(v))
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_field_random_vs_oracle(shape, cell, Ms, dtype):
+    o = get_oracle(shape, cell)
+    plan = get_plan(shape, cell, dtype)
+    m = inputs.random_unit(shape, 1)
+    H = plan.field(to_gpu(m, dtype), Ms).double().cpu().numpy()
+    ref = o.field(quantised(m, dtype), Ms)
+    err = rel_err(H, ref)
+    print(f"shape={shape} dtype={dtype} rel_err={err:.3e}")
+    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_uniform_cube_state(dtype):
+    shape, cell, Ms = (8, 8, 8), (2e-9,) * 3, 8e5
+    o = get_oracle(shape, cell)
+    plan = get_plan(shape, cell, dtype)
+    m = inputs.uniform(shape, (1, 1, 1))
+    H = plan.field(to_gpu(m, dtype), Ms).double().cpu().numpy()
+    ref = o.field(quantised(m, dtype), Ms)
+    assert rel_err(H, ref) <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+
+
+@pytest.mark.parametrize("shape,cell", [((8, 8, 8), (2e-9,) * 3), ((70, 9, 2), (2e-9, 3e-9, 1e-9)),
+                                        ((60, 60, 4), (1.95e-9, 1.95e-9, 0.75e-9)),
+                                        ((64, 10, 6), (2e-9, 2e-9, 3e-9))])
+def test_tensor_octant_per_band(shape, cell):
+    """FP64 setup tensor vs the binary128 f/g oracle, offset by offset."""
+    o = get_oracle(shape, cell)
+    plan = get_plan(shape, cell, torch.float64)
+    N = plan.tensor()
+    ref = o.Noct
+    scale = np.max(np.abs(ref), axis=0)  # per offset
+    err = np.max(np.abs(N - ref), axis=0) / scale
+    nx, ny, nz = shape
+    h = max(cell)
+    oz, oy, ox = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    rho = np.sqrt((ox * cell[0]) ** 2 + (oy * cell[1]) ** 2 + (oz * cell[2]) ** 2) / h
+    cheb = np.maximum(np.maximum(ox, oy), oz)
+    for name, mask in [("near", cheb <= 1), ("mid", (cheb > 1) & (rho < 40)), ("far", rho >= 40)]:
+        if mask.any():
+            print(f"{shape} {name}: max rel err {err[mask].max():.2e} over {mask.sum()} offsets")
+            assert err[mask].max() <= 1e-12
+
+
+def test_spectrum_matches_fft_of_oracle_tensor():
+    """The stored FP64 spectrum equals -1/(PxPyPz) x DFT of the P-periodic
+    embedding of the oracle tensor (numpy FFT), on the stored octant."""
+    shape, cell = (12, 10, 6), (2e-9, 2e-9, 3e-9)
+    o = get_oracle(shape, cell)
+    plan = get_plan(shape, cell, torch.float64)
+    info = plan.info()
+    Px, Py, Pz, Kx = info["Px"], info["Py"], info["Pz"], info["Kx"]
+    nx, ny, nz = shape
+    par = [(0, 0, 0), (0, 0, 0), (0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+    S = plan.spectrum()
+    for c in range(6):
+        A = np.zeros((Pz, Py, Px))
+        for sz in (1, -1):
+            for sy in (1, -1):
+                for sx in (1, -1):
+                    sign = (sx if par[c][0] else 1) * (sy if par[c][1] else 1) * (sz if par[c][2] else 1)
+                    zi = (sz * np.arange(nz)) % Pz
+                    yi = (sy * np.arange(ny)) % Py
+                    xi = (sx * np.arange(nx)) % Px
+                    A[np.ix_(zi, yi, xi)] = sign * o.Noct[c]
+        F = np.fft.fftn(A)  # axes (z, y, x)
+        ref = (-F.real / (Px * Py * Pz))[: Pz // 2 + 1, : Py // 2 + 1, :Kx]  # [kz][ky][kx]
+        got = S[:, c, :, :].transpose(2, 0, 1)  # [ky][kx][kz] -> [kz][ky][kx]
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_energy_vs_oracle(dtype):
+    shape, cell, Ms = (24, 17, 3), (1.95e-9, 1.95e-9, 0.75e-9), 8e5
+    o = get_oracle(shape, cell)
+    plan = get_plan(shape, cell, dtype)
+    for m in [inputs.uniform(shape, (1, 0.2, 0.1)), inputs.gaussian_vortex(shape, cell, 10e-9),
+              inputs.random_unit(shape, 5)]:
+        mq = quantised(m, dtype)
+        ref = o.energy(mq, o.field(mq, Ms), Ms)
+        H, E = plan.field_energy(to_gpu(m, dtype), Ms)
+        E = float(E.cpu())
+        # scale for states whose energy nearly cancels: (mu0/2) Ms V sum |m||H|
+        Href = o.field(mq, Ms)
+        scale = 0.5 * oracle.MU0 * Ms * o.volume * np.sum(np.abs(mq * Href))
+        tol = 1e-12 if dtype == torch.float64 else 1e-5
+        assert abs(E - ref) <= tol * scale
+        assert abs(plan.energy(to_gpu(m, dtype), Ms) - E) <= 1e-15 * scale
+        assert rel_err(H.double().cpu().numpy(), Href) <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_adjoint_vs_oracle_transpose(dtype):
+    shape, cell, Ms = (16, 8, 2), (1.95e-9, 1.95e-9, 0.75e-9), 8e5
+    o = get_oracle(shape, cell)
+    plan = get_plan(shape, cell, dtype)
+    g = np.random.default_rng(6).standard_normal((3, 2, 8, 16))
+    ref = o.field_T(quantised(g, dtype), Ms)
+    got = plan.adjoint(to_gpu(g, dtype), Ms).double().cpu().numpy()
+    assert rel_err(got, ref) <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    # accumulate flag: gm += A^T gH
+    base = np.random.default_rng(7).standard_normal(g.shape)
+    acc = to_gpu(base, dtype)
+    plan.adjoint(to_gpu(g, dtype), Ms, out=acc, accumulate=True)
+    assert rel_err(acc.double().cpu().numpy(), quantised(base, dtype) + ref) <= (
+        FP64_TOL if dtype == torch.float64 else FP32_TOL)
+
+
+def test_repeatable_bitwise():
+    shape, cell, Ms = (33, 20, 9), (2.5e-9,) * 3, 8e5
+    plan = get_plan(shape, cell, torch.float32)
+    m = to_gpu(inputs.random_unit(shape, 9), torch.float32)
+    a = plan.field(m, Ms).cpu()
+    b = plan.field(m, Ms).cpu()
+    assert torch.equal(a, b)
+    _, e1 = plan.field_energy(m, Ms)
+    _, e2 = plan.field_energy(m, Ms)
+    assert float(e1) == float(e2)
+
+
+def test_sentinels_around_output():
+    """Writes stay inside H: guard bands before and after it are untouched."""
+    shape, cell, Ms = (13, 7, 5), (2e-9, 2e-9, 3e-9), 1.4e6
+    plan = get_plan(shape, cell, torch.float32)
+    n = 3 * 13 * 7 * 5
+    buf = torch.full((n + 2048,), 12345.0, device="cuda", dtype=torch.float32)
+    H = buf[1024:1024 + n].view(3, 5, 7, 13)
+    plan.field(to_gpu(inputs.random_unit(shape, 2), torch.float32), Ms, out=H)
+    torch.cuda.synchronize()
+    assert torch.all(buf[:1024] == 12345.0) and torch.all(buf[1024 + n:] == 12345.0)
