@@ -1,0 +1,303 @@
+#!/usr/bin/env python3
+"""Throughput of the DM stray-field path on one MI355X.
+
+Workload: 256 x 256 x 64 cells of 2 x 2 x 3 nm, Ms = 1.4e6 A/m, seeded i.i.d.
+random unit magnetization, FP32 bulk path (tensor set up in FP64).  One step
+is one forward field evaluation with the fused energy (H = -Ms N * m and
+E = -(mu0/2) Ms V sum m.H) plus one adjoint evaluation (gm = A^T gH) of a
+fixed cotangent: two field evaluations.  `value` counts field evaluations per
+second (forward and adjoint each count one); inputs are resident in HBM.
+
+Also reported: the same step in FP64 on the GPU, the FP32 error against the
+FP64 oracle at sampled cells, the roofline of the dominant pass (live HIP
+events over the timed region) and the CPU oracle timed on a bounded sample.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W]
+  python bench.py --summarize-profile DIR --out FILE   (rocprofv3 output -> text)
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+SHAPE = (256, 256, 64)
+CELL = (2e-9, 2e-9, 3e-9)
+MS = 1.4e6
+SEED_M, SEED_G, SEED_T = 3, 33, 7
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_z_conv_256x256x64_f32.txt")
+KERNEL_SOURCES = ["paper_1204_4302_amd/csrc/passes.hip", "paper_1204_4302_amd/csrc/fft_lds.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def pass_bytes(shape, Px, Py, Pz, Kx, real_bytes):
+    """Algorithmic HBM bytes per launch of each pass (read + write, each byte
+    of every array a pass must touch once)."""
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    c = 2 * real_bytes
+    vec = 3 * N * real_bytes
+    B1 = 3 * nz * Kx * ny * c
+    B2 = 3 * Py * Kx * nz * c
+    nhat = (Py // 2 + 1) * 6 * Kx * (Pz // 2 + 1) * real_bytes
+    return {
+        "x_r2c": vec + B1,
+        "y_fwd": B1 + B2,
+        "z_conv": 2 * B2 + nhat,
+        "y_inv": B2 + B1,
+        "x_c2r": B1 + vec,          # + another vec when the energy reads m
+    }
+
+
+def read_traffic():
+    """HBM bytes per z_conv launch from the committed --pmc summary, or None if
+    the kernels changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_steps(step, k, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(k):
+        step()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(m, target_seconds, Href32, Href64):
+    import numpy as np
+    import oracle
+    from paper_1204_4302_amd import inputs
+
+    o = oracle.Oracle(SHAPE, CELL, cache_dir=os.environ.get("DEMAG_ORACLE_CACHE"))
+    N = SHAPE[0] * SHAPE[1] * SHAPE[2]
+    # calibrate the per-target cost, then size the sample to ~target_seconds
+    probe = inputs.sample_targets(SHAPE, 32, SEED_T)
+    t0 = time.perf_counter()
+    o.field_targets(m, MS, probe)
+    per = (time.perf_counter() - t0) / probe.size
+    count = int(max(64, min(20000, target_seconds / max(per, 1e-9))))
+    targets = inputs.sample_targets(SHAPE, count, SEED_T + 1)
+    t0 = time.perf_counter()
+    Ht = o.field_targets(m, MS, targets)
+    dt = time.perf_counter() - t0
+    flat32 = Href32.reshape(3, -1)[:, targets]
+    flat64 = Href64.reshape(3, -1)[:, targets]
+    scale = np.max(np.abs(Ht))
+    err = {"f32": float(np.max(np.abs(flat32 - Ht)) / scale),
+           "f64": float(np.max(np.abs(flat64 - Ht)) / scale),
+           "targets": int(targets.size)}
+    base = {
+        "value": targets.size / dt / N,
+        "unit": "evals/s",
+        "cores": oracle.threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 direct O(N^2) field at {targets.size} seeded target cells of the "
+                   f"256x256x64 grid ({dt:.1f} s), scaled to whole-grid evaluations; "
+                   f"binary128 tensor setup {o.tensor_seconds:.1f} s not counted"),
+    }
+    return base, err
+
+
+def bench(args):
+    import numpy as np
+    import torch
+
+    from paper_1204_4302_amd import Plan, inputs
+
+    torch.cuda.set_device(0)
+    nx, ny, nz = SHAPE
+    # FP32-representable directions, so the FP32 and FP64 paths and the oracle see one input
+    m_np = inputs.random_unit(SHAPE, SEED_M).astype(np.float32).astype(np.float64)
+    g_np = np.random.default_rng(SEED_G).standard_normal((3, nz, ny, nx))
+
+    results = {}
+    for dtype, steps in [(torch.float32, args.steps), (torch.float64, args.fp64_steps)]:
+        if steps <= 0:
+            continue
+        plan = Plan(SHAPE, CELL, dtype)
+        if args.autotune:
+            plan.autotune()
+        m = torch.from_numpy(m_np).to("cuda", dtype)
+        gH = torch.from_numpy(g_np).to("cuda", dtype)
+        H = torch.empty_like(m)
+        gm = torch.empty_like(m)
+        E = torch.empty((), dtype=torch.float64, device="cuda")
+
+        def step():
+            plan.field_energy(m, MS, out=H, E_out=E)
+            plan.adjoint(gH, MS, out=gm)
+
+        for _ in range(args.warmup):
+            step()
+        timing = dtype == torch.float32 and not args.no_pass_timing
+        if timing:
+            plan.set_option("pass_timing", 2 * steps)
+        secs = run_steps(step, steps, torch)
+        passes, nrec = plan.pass_times() if timing else ({}, 0)
+        results[dtype] = {"plan": plan, "secs": secs, "steps": steps, "H": H.double().cpu().numpy(),
+                          "E": float(E.cpu()), "passes": passes, "nrec": nrec, "info": plan.info()}
+        print(f"# {dtype}: {steps} steps in {secs:.3f} s ({1e3 * secs / steps:.3f} ms/step)", file=sys.stderr,
+              flush=True)
+
+    r32 = results[torch.float32]
+    info = r32["info"]
+    ms_step = 1e3 * r32["secs"] / r32["steps"]
+    value = 2 * r32["steps"] / r32["secs"]
+
+    # roofline of the dominant pass, from the live per-pass events
+    pb = pass_bytes(SHAPE, info["Px"], info["Py"], info["Pz"], info["Kx"], 4)
+    passes = r32["passes"]
+    roofline = None
+    if passes:
+        dom = max(pb, key=lambda k: passes.get(k, 0.0))
+        achieved = pb[dom] / (passes[dom] * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": read_traffic() if dom == "z_conv" else None,
+                    "bytes_per_launch": pb[dom], "avg_launch_ms": round(passes[dom], 5),
+                    "pass_ms": {k: round(v, 5) for k, v in passes.items()}}
+        # the whole step against HBM: modelled bytes of all passes of both evaluations
+        step_bytes = 2 * sum(pb.values()) + 3 * nx * ny * nz * 4  # + m read by the energy epilogue
+        roofline["step_achieved_GBs"] = round(step_bytes / (ms_step * 1e-3) / 1e9, 1)
+
+    out = {
+        "metric": "demag field evals/s at 256x256x64 FP32 (fwd+adjoint), achieved HBM GB/s, vs FP64",
+        "value": round(value, 2),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": r32["steps"],
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256x256x64 cells, 2x2x3 nm, Ms=1.4e6 A/m, seeded random unit m; "
+                               "step = forward field+energy and adjoint (2 field evaluations)",
+                   "padded": [info["Px"], info["Py"], info["Pz"]], "parallelism": "none (1 GPU)"},
+        "roofline": roofline,
+    }
+    if torch.float64 in results:
+        r64 = results[torch.float64]
+        v64 = 2 * r64["steps"] / r64["secs"]
+        out["fp64"] = {"value": round(v64, 2), "unit": "evals/s",
+                       "ms_per_step": round(1e3 * r64["secs"] / r64["steps"], 4),
+                       "speedup_fp32_over_fp64": round(value / v64, 3)}
+        H64 = r64["H"]
+        out["accuracy"] = {"f32_vs_f64_gpu_field": float(np.max(np.abs(r32["H"] - H64)) / np.max(np.abs(H64))),
+                           "f32_vs_f64_gpu_energy": abs(r32["E"] - r64["E"]) / abs(r64["E"])}
+    if not args.no_cpu_baseline:
+        H64 = results[torch.float64]["H"] if torch.float64 in results else r32["H"]
+        base, err = cpu_baseline(m_np, args.cpu_seconds, r32["H"], H64)
+        out["cpu_baseline"] = base
+        out.setdefault("accuracy", {})["vs_oracle_sampled"] = err
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# rocprofv3 output -> short text summaries for profiles/
+def _find(d, pattern):
+    hits = glob.glob(os.path.join(d, "**", pattern), recursive=True)
+    return sorted(hits)
+
+
+def summarize_profile(d, out_path, command):
+    lines = [f"# command: {command}", f"# kernel_source_hash = {kernel_source_hash()}"]
+    stats = _find(d, "*kernel_stats.csv")
+    if stats:
+        lines.append("# kernel stats (rocprofv3 --kernel-trace --stats)")
+        lines.append(f"{'kernel':60s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}")
+        with open(stats[0]) as f:
+            for row in csv.DictReader(f):
+                name = row.get("Name", "")[:60]
+                lines.append(f"{name:60s} {row.get('Calls', ''):>7s} "
+                             f"{float(row.get('AverageNs', 0)) / 1e3:10.2f} "
+                             f"{float(row.get('TotalDurationNs', 0)) / 1e6:10.3f} "
+                             f"{float(row.get('Percentage', 0)):6.2f}")
+    counters = _find(d, "*counter_collection.csv")
+    if counters:
+        agg = {}
+        with open(counters[0]) as f:
+            for row in csv.DictReader(f):
+                key = (row.get("Kernel_Name", "")[:60], row.get("Counter_Name", ""))
+                agg.setdefault(key, []).append(float(row.get("Counter_Value", 0)))
+        lines.append("# counters per dispatch (mean over dispatches), rocprofv3 --pmc")
+        for (k, c), v in sorted(agg.items()):
+            lines.append(f"{k:60s} {c:12s} n={len(v):5d} mean={sum(v) / len(v):.6g}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--fp64-steps", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample budget")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-pass-timing", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="tune launch shapes before timing")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of 256 MiB (counter calibration)")
+    ap.add_argument("--summarize-profile", metavar="DIR")
+    ap.add_argument("--out", metavar="FILE")
+    ap.add_argument("--command", default="", help="command line recorded in the summary")
+    args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile, args.out or "/dev/stdout", args.command)
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(this build measures the one-GPU path only)", file=sys.stderr)
+        return 2
+    if args.copy_calibration:
+        import torch
+        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print("# copy calibration: 3 x 256 MiB device copies", file=sys.stderr)
+    bench(args)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

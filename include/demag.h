@@ -71,7 +71,10 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
  *             the moment series of the dipole kernel (default 40; 0 < v).
  *  "fg_cut":  offsets with Chebyshev distance <= fg_cut use the Newell f/g
  *             closed form (default 1; integer >= 0); the rest of the near field
- *             uses Gauss-Legendre quadrature of the cell-average integral. */
+ *             uses Gauss-Legendre quadrature of the cell-average integral.
+ *  "pass_timing": K > 0 records HIP events around every pass of the next
+ *             evaluations on their own stream (a ring of K evaluations; 0 turns
+ *             it off); read the averages with demag_plan_pass_times. */
 int demag_plan_set_option(demag_plan_t plan, const char* key, double value);
 int demag_plan_destroy(demag_plan_t plan);
 
@@ -106,6 +109,13 @@ int demag_plan_spectrum(demag_plan_t plan, void* out);
 /* Recompute the FP64 real-space tensor octant N(o), o in [0,n), to HOST
  * memory `out` [6][nz][ny][nx] (components xx yy zz xy xz yz).  Synchronous. */
 int demag_plan_tensor(demag_plan_t plan, double* out);
+
+/* Average duration in ms of each pass over the evaluations recorded since the
+ * last call (at most the ring size), from the events of "pass_timing":
+ * ms[0..5] = X-R2C, Y, fused Z, Y-inverse, X-C2R, energy reduction (0 when the
+ * evaluations had no energy).  *count = evaluations averaged.  Synchronises
+ * the device and empties the ring. */
+int demag_plan_pass_times(demag_plan_t plan, double* ms, int64_t* count);
 
 /* Time the candidate launch shapes of every pass on this plan's buffers,
  * keep the fastest, and update the cache file named by $DEMAG_AUTOTUNE_CACHE

@@ -15,7 +15,8 @@ Functions and the passages they follow (Abert et al., arXiv:1204.4302):
                      cites only by property).
 * ``field``       -- H = -Ms N * m as a plain sum, Sec. 3.1 eq. (demag).
 * ``field_targets`` -- the same sum evaluated at selected cells only.
-* ``field_T``     -- the transposed operator as its own loop.
+* ``field_T``     -- the transposed operator as its own loop (also at
+                     selected cells: ``field_T_targets``).
 * ``energy``      -- E = -(mu0/2) Ms V sum m.H, Sec. 2 (stray-field energy).
 * ``matrix``      -- the explicit 3N x 3N operator for tiny grids.
 """
@@ -71,12 +72,16 @@ def load(path: str | None = None):
     lib.oracle_field_targets.restype = i
     lib.oracle_field_T.argtypes = [i, i, i, p, p, d, p]
     lib.oracle_field_T.restype = i
+    lib.oracle_field_T_targets.argtypes = [i, i, i, p, p, d, p, l, p]
+    lib.oracle_field_T_targets.restype = i
     lib.oracle_energy.argtypes = [i, i, i, d, d, d, p, p, d]
     lib.oracle_energy.restype = d
     lib.oracle_matrix.argtypes = [i, i, i, p, d, p]
     lib.oracle_matrix.restype = i
     lib.oracle_mu0.argtypes = []
     lib.oracle_mu0.restype = d
+    lib.oracle_threads.argtypes = []
+    lib.oracle_threads.restype = i
     if path is None:
         _lib = lib
     return lib
@@ -97,15 +102,32 @@ def _vec(m: np.ndarray, shape) -> np.ndarray:
 class Oracle:
     """One grid (shape (nx, ny, nz), cell (dx, dy, dz)) with its FP64 tensor."""
 
-    def __init__(self, shape, cell, lib=None):
+    def __init__(self, shape, cell, lib=None, cache_dir: str | None = None):
+        """cache_dir: optional folder where the tensor this oracle computed is
+        kept (.npy, keyed by shape and cell) and reused by later instances."""
         self.lib = lib or load()
         self.shape = tuple(int(v) for v in shape)
         self.cell = tuple(float(v) for v in cell)
         nx, ny, nz = self.shape
+        path = None
+        if cache_dir:
+            key = "noct_%dx%dx%d_%s_%s_%s.npy" % (nx, ny, nz, *(v.hex() for v in self.cell))
+            path = os.path.join(cache_dir, key)
+            if os.path.exists(path):
+                self.Noct = np.load(path)
+                self.tensor_seconds = 0.0
+                return
+        import time
+        t0 = time.perf_counter()
         self.Noct = np.empty((6, nz, ny, nx), dtype=np.float64)
         rc = self.lib.oracle_tensor(nx, ny, nz, *self.cell, _ptr(self.Noct))
         if rc != 0:
             raise ValueError(f"oracle_tensor failed ({rc})")
+        self.tensor_seconds = time.perf_counter() - t0
+        if path:
+            os.makedirs(cache_dir, exist_ok=True)
+            np.save(path + ".tmp.npy", self.Noct)
+            os.replace(path + ".tmp.npy", path)
 
     @property
     def volume(self) -> float:
@@ -134,6 +156,16 @@ class Oracle:
         self.lib.oracle_field_T(*self.shape, _ptr(self.Noct), _ptr(g), float(Ms), _ptr(out))
         return out
 
+    def field_T_targets(self, g, Ms, targets):
+        g = _vec(g, self.shape)
+        t = np.ascontiguousarray(targets, dtype=np.int64)
+        out = np.empty((3, t.size), dtype=np.float64)
+        rc = self.lib.oracle_field_T_targets(*self.shape, _ptr(self.Noct), _ptr(g),
+                                             float(Ms), _ptr(t), t.size, _ptr(out))
+        if rc != 0:
+            raise ValueError("target index out of range")
+        return out
+
     def energy(self, m, H, Ms) -> float:
         m = _vec(m, self.shape)
         H = _vec(H, self.shape)
@@ -145,6 +177,11 @@ class Oracle:
         if self.lib.oracle_matrix(*self.shape, _ptr(self.Noct), float(Ms), _ptr(A)) != 0:
             raise ValueError("grid too large for an explicit matrix")
         return A
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(load().oracle_threads())
 
 
 def tensor_at(comp: int, offset, cell) -> float:

@@ -35,6 +35,7 @@
  * components in the order xx, yy, zz, xy, xz, yz.
  */
 #include <math.h>
+#include <omp.h>
 #include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -303,6 +304,40 @@ int oracle_field_T(int nx, int ny, int nz, const double *Noct, const double *g,
     return 0;
 }
 
+/* The transposed operator at a list of flat source indices only; out_t is
+ * [3][ntarget].  Same loop as oracle_field_T for each listed j.            */
+int oracle_field_T_targets(int nx, int ny, int nz, const double *Noct, const double *g,
+                           double Ms, const int64_t *targets, long ntarget, double *out_t)
+{
+    tensor_view tv = {Noct, nx, ny, nz, (long)nx * ny * nz};
+    const long N = tv.ncell;
+    for (long k = 0; k < ntarget; ++k)
+        if (targets[k] < 0 || targets[k] >= N) return -1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long k = 0; k < ntarget; ++k) {
+        long j = targets[k];
+        long jx = j % nx, jy = (j / nx) % ny, jz = j / ((long)nx * ny);
+        double ax = 0, ay = 0, az = 0, Nv[6];
+        for (long iz = 0; iz < nz; ++iz)
+            for (long iy = 0; iy < ny; ++iy)
+                for (long ix = 0; ix < nx; ++ix) {
+                    long i = (iz * ny + iy) * nx + ix;
+                    tensor_signed(&tv, ix - jx, iy - jy, iz - jz, Nv);
+                    double B[3][3] = {{Nv[0], Nv[3], Nv[4]},
+                                      {Nv[3], Nv[1], Nv[5]},
+                                      {Nv[4], Nv[5], Nv[2]}};
+                    double gx = g[i], gy = g[N + i], gz = g[2 * N + i];
+                    ax += B[0][0] * gx + B[1][0] * gy + B[2][0] * gz;
+                    ay += B[0][1] * gx + B[1][1] * gy + B[2][1] * gz;
+                    az += B[0][2] * gx + B[1][2] * gy + B[2][2] * gz;
+                }
+        out_t[k] = -Ms * ax;
+        out_t[ntarget + k] = -Ms * ay;
+        out_t[2 * ntarget + k] = -Ms * az;
+    }
+    return 0;
+}
+
 /* E = -(mu0/2) Ms V sum_i m_i . H_i  (Sec. 2, SI units). */
 double oracle_energy(int nx, int ny, int nz, double dx, double dy, double dz,
                      const double *m, const double *H, double Ms)
@@ -336,3 +371,15 @@ int oracle_matrix(int nx, int ny, int nz, const double *Noct, double Ms, double 
 }
 
 double oracle_mu0(void) { return ORACLE_MU0; }
+
+/* Threads an OpenMP loop of this library runs on (reporting only). */
+int oracle_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
+}

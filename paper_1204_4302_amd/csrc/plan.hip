@@ -50,6 +50,7 @@ int hip_fail(hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail(e_, #call);   \
     } while (0)
 
+constexpr int kPassMarks = 7;  // before X, Y, Z, Y^-1, X^-1, energy; end
 constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846264338327950288;
 constexpr int kMaxLen = 4096;
 constexpr size_t kMaxLdsBytes = 65536;  // dynamic LDS per workgroup
@@ -160,6 +161,10 @@ struct demag_plan_s {
     hipStream_t last_stream = nullptr;
     bool used = false;
     bool capturing = false;
+    // optional pass timing: kPassMarks events per evaluation in a ring of tcap slots
+    std::vector<hipEvent_t> tev;
+    int tcap = 0;
+    long tcount = 0;
 };
 
 struct demag_batch_s {
@@ -324,6 +329,7 @@ void free_plan(demag_plan_s* p) {
     hipFree(p->partials);
     hipFree(p->e_dev);
     if (p->done) hipEventDestroy(p->done);
+    for (auto e : p->tev) hipEventDestroy(e);
     delete p;
 }
 
@@ -338,18 +344,29 @@ int run_field(demag_plan_s* p, const PassCfgs& c, const T* m, double Ms, T* H, c
     const auto* twx = (const cx<T>*)p->tw[0];
     const auto* twy = (const cx<T>*)p->tw[1];
     const auto* twz = (const cx<T>*)p->tw[2];
+    hipEvent_t* mark = nullptr;
+    if (p->tcap > 0 && !p->capturing) mark = &p->tev[(size_t)(p->tcount % p->tcap) * kPassMarks];
+    auto stamp = [&](int k) -> hipError_t { return mark ? hipEventRecord(mark[k], st) : hipSuccess; };
+    HIP_TRY(stamp(0));
     HIP_TRY(launch_x_fwd<T>(c.xf, st, m, B1, nx, ny, nz, Kx, 3, p->fp[0], twx));
+    HIP_TRY(stamp(1));
     HIP_TRY(launch_y_fwd<T>(c.yf, st, B1, B2, ny, nz, Kx, nz, 3, p->fp[1], twy));
+    HIP_TRY(stamp(2));
     HIP_TRY(launch_z_conv<T>(c.zc, st, B2, (const T*)p->nhat, (T)Ms, nz, p->P[1], Kx, p->fp[2], twz));
+    HIP_TRY(stamp(3));
     HIP_TRY(launch_y_inv<T>(c.yi, st, B2, B1, ny, nz, Kx, 3, p->fp[1], twy));
+    HIP_TRY(stamp(4));
     double* partials = E_dev ? p->partials : nullptr;
     HIP_TRY(launch_x_inv<T>(c.xi, st, B1, H, E_dev ? m_energy : nullptr, partials, nx, ny, nz, Kx, 3, accumulate,
                             p->fp[0], twx));
+    HIP_TRY(stamp(5));
     if (E_dev) {
         const int nparts = ((ny + c.xi.t0 - 1) / c.xi.t0) * nz * 3;
         const double V = p->d[0] * p->d[1] * p->d[2];
         HIP_TRY(launch_energy_reduce(st, p->partials, nparts, -0.5 * kMu0 * Ms * V, E_dev));
     }
+    HIP_TRY(stamp(6));
+    if (mark) ++p->tcount;
     return DEMAG_OK;
 }
 
@@ -482,6 +499,16 @@ int demag_plan_set_option(demag_plan_t p, const char* key, double value) {
         if (!(value >= 0) || value != std::floor(value) || value > 1e9)
             return fail(DEMAG_EINVAL, "fg_cut must be a non-negative integer");
         b.fg_cut = (int)value;
+    } else if (!strcmp(key, "pass_timing")) {
+        if (!(value >= 0) || value != std::floor(value) || value > 1e6)
+            return fail(DEMAG_EINVAL, "pass_timing must be an integer in [0, 1e6]");
+        HIP_TRY(hipDeviceSynchronize());
+        for (auto e : p->tev) hipEventDestroy(e);
+        p->tev.assign((size_t)value * kPassMarks, nullptr);
+        for (auto& e : p->tev) HIP_TRY(hipEventCreate(&e));
+        p->tcap = (int)value;
+        p->tcount = 0;
+        return DEMAG_OK;
     } else {
         return fail(DEMAG_EINVAL, "unknown option '%s'", key);
     }
@@ -569,6 +596,24 @@ int demag_plan_tensor(demag_plan_t p, double* out) {
     if (rc) return rc;
     const size_t ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
     HIP_TRY(hipMemcpy(out, sb.Noct, 6 * ncell * sizeof(double), hipMemcpyDeviceToHost));
+    return DEMAG_OK;
+}
+
+int demag_plan_pass_times(demag_plan_t p, double* ms, int64_t* count) {
+    if (!p || !ms || !count) return fail(DEMAG_EINVAL, "NULL argument");
+    for (int k = 0; k < kPassMarks - 1; ++k) ms[k] = 0.0;
+    const long n = std::min<long>(p->tcount, p->tcap);
+    *count = n;
+    if (n == 0) return DEMAG_OK;
+    HIP_TRY(hipDeviceSynchronize());
+    for (long s = 0; s < n; ++s)
+        for (int k = 0; k < kPassMarks - 1; ++k) {
+            float t = 0;
+            HIP_TRY(hipEventElapsedTime(&t, p->tev[s * kPassMarks + k], p->tev[s * kPassMarks + k + 1]));
+            ms[k] += t;
+        }
+    for (int k = 0; k < kPassMarks - 1; ++k) ms[k] /= (double)n;
+    p->tcount = 0;
     return DEMAG_OK;
 }
 

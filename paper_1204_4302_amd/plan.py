@@ -78,6 +78,15 @@ class Plan:
     def set_option(self, key: str, value: float):
         _lib.call("demag_plan_set_option", self._h, key.encode(), float(value))
 
+    PASSES = ("x_r2c", "y_fwd", "z_conv", "y_inv", "x_c2r", "energy")
+
+    def pass_times(self) -> tuple[dict, int]:
+        """Average ms per pass over the evaluations recorded by "pass_timing"."""
+        ms = (ctypes.c_double * 6)()
+        n = ctypes.c_int64()
+        _lib.call("demag_plan_pass_times", self._h, ms, ctypes.byref(n))
+        return {k: ms[i] for i, k in enumerate(self.PASSES)}, int(n.value)
+
     def autotune(self):
         _lib.call("demag_autotune", self._h, _stream_ptr())
 
@@ -126,11 +135,16 @@ class Plan:
                   1 if accumulate else 0, _stream_ptr())
         return gm
 
-    def field_energy(self, m: torch.Tensor, Ms: float, with_field: bool = True):
+    def field_energy(self, m: torch.Tensor, Ms: float, with_field: bool = True,
+                     out: torch.Tensor | None = None, E_out: torch.Tensor | None = None):
         """(H or None, E) with E a 0-dim float64 CUDA tensor."""
         self._check(m, "m")
-        H = torch.empty_like(m) if with_field else None
-        E = torch.empty((), dtype=torch.float64, device=m.device)
+        H = (torch.empty_like(m) if out is None else out) if with_field else None
+        if H is not None:
+            self._check(H, "out")
+        E = torch.empty((), dtype=torch.float64, device=m.device) if E_out is None else E_out
+        if E.dtype != torch.float64 or E.device.type != "cuda" or E.numel() != 1:
+            raise TypeError("E_out must be a one-element float64 CUDA tensor")
         _lib.call("demag_field_energy", self._h, self._ptr(m), float(Ms),
                   self._ptr(H) if H is not None else None, ctypes.c_void_p(E.data_ptr()), _stream_ptr())
         return H, E
