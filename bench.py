@@ -130,6 +130,46 @@ def cpu_baseline(m, target_seconds, Href32, Href64):
     return base, err
 
 
+BATCH_SIZES = [(32, 32, 32), (64, 64, 16), (96, 48, 8), (128, 128, 4), (48, 48, 48)]
+
+
+def bench_batch(args, torch, np):
+    """96 independent grids of seeded uneven shapes (2 nm cubes, Ms = 8e5, FP32):
+    one replay of the recorded batch graph vs 96 single-grid calls."""
+    from paper_1204_4302_amd import Batch, Plan, inputs
+    rng = np.random.default_rng(4)
+    shapes = [BATCH_SIZES[i] for i in rng.integers(0, len(BATCH_SIZES), size=96)]
+    cell, Ms = (2e-9, 2e-9, 2e-9), 8e5
+    plans = [Plan(s, cell, torch.float32) for s in shapes]
+    ms = [torch.from_numpy(inputs.random_unit(s, 4000 + g)).to("cuda", torch.float32) for g, s in enumerate(shapes)]
+    hs = [torch.empty_like(m) for m in ms]
+    batch = Batch(plans, ms, hs, Ms)
+
+    def seq():
+        for p, m, h in zip(plans, ms, hs):
+            p.field(m, Ms, out=h)
+
+    k = args.batch_steps
+    for _ in range(3):
+        seq()
+        batch.launch()
+    t_seq = run_steps(seq, k, torch)
+    t_graph = run_steps(batch.launch, k, torch)
+    nbytes = 0
+    for p in plans:
+        i = p.info()
+        nbytes += sum(pass_bytes(p.shape, i["Px"], i["Py"], i["Pz"], i["Kx"], 4).values())
+    cells = sum(a * b * c for a, b, c in shapes)
+    out = {"grids": len(shapes), "cells": cells, "distinct_shapes": len(set(shapes)),
+           "graph_batches_per_s": round(k / t_graph, 2), "graph_grid_evals_per_s": round(96 * k / t_graph, 1),
+           "sequential_batches_per_s": round(k / t_seq, 2), "speedup_graph_over_sequential": round(t_seq / t_graph, 3),
+           "modelled_bytes_per_batch": nbytes, "graph_achieved_GBs": round(nbytes * k / t_graph / 1e9, 1)}
+    batch.close()
+    for p in plans:
+        p.close()
+    return out
+
+
 def bench(args):
     import numpy as np
     import torch
@@ -166,6 +206,7 @@ def bench(args):
             plan.set_option("pass_timing", 2 * steps)
         secs = run_steps(step, steps, torch)
         passes, nrec = plan.pass_times() if timing else ({}, 0)
+        print(f"# {dtype} launch: {plan.describe()}", file=sys.stderr, flush=True)
         results[dtype] = {"plan": plan, "secs": secs, "steps": steps, "H": H.double().cpu().numpy(),
                           "E": float(E.cpu()), "passes": passes, "nrec": nrec, "info": plan.info()}
         print(f"# {dtype}: {steps} steps in {secs:.3f} s ({1e3 * secs / steps:.3f} ms/step)", file=sys.stderr,
@@ -207,7 +248,8 @@ def bench(args):
         "data": "synthetic",
         "config": {"workload": "256x256x64 cells, 2x2x3 nm, Ms=1.4e6 A/m, seeded random unit m; "
                                "step = forward field+energy and adjoint (2 field evaluations)",
-                   "padded": [info["Px"], info["Py"], info["Pz"]], "parallelism": "none (1 GPU)"},
+                   "padded": [info["Px"], info["Py"], info["Pz"]], "parallelism": "none (1 GPU)",
+                   "launch": r32["plan"].describe()},
         "roofline": roofline,
     }
     if torch.float64 in results:
@@ -219,6 +261,9 @@ def bench(args):
         H64 = r64["H"]
         out["accuracy"] = {"f32_vs_f64_gpu_field": float(np.max(np.abs(r32["H"] - H64)) / np.max(np.abs(H64))),
                            "f32_vs_f64_gpu_energy": abs(r32["E"] - r64["E"]) / abs(r64["E"])}
+    if args.batch_steps > 0:
+        out["batch"] = bench_batch(args, torch, np)
+        print(f"# batch: {out['batch']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         H64 = results[torch.float64]["H"] if torch.float64 in results else r32["H"]
         base, err = cpu_baseline(m_np, args.cpu_seconds, r32["H"], H64)
@@ -264,6 +309,52 @@ def summarize_profile(d, out_path, command):
     print("\n".join(lines))
 
 
+def _counter_means(d):
+    """{(kernel, counter): (mean per dispatch, dispatches)} from a --pmc run."""
+    files = _find(d, "*counter_collection.csv")
+    agg = {}
+    if files:
+        with open(files[0]) as f:
+            for row in csv.DictReader(f):
+                key = (row.get("Kernel_Name", ""), row.get("Counter_Name", ""))
+                agg.setdefault(key, []).append(float(row.get("Counter_Value", 0)))
+    return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
+
+
+def traffic_summary(fetch_dir, write_dir, out_path, command):
+    """HBM bytes per launch of every pass kernel from FETCH_SIZE / WRITE_SIZE
+    (KiB per dispatch), each scaled by what the same counter reads for the
+    plain 256 MiB device copy of --copy-calibration."""
+    fetch, write = _counter_means(fetch_dir), _counter_means(write_dir)
+    copy_bytes = 256 * 1024 * 1024
+
+    def calib(tab, counter):
+        cands = [(v, k) for (k, c), (v, n) in tab.items() if c == counter and "copy" in k.lower()]
+        cands = [x for x in cands if x[0] > 0.5 * copy_bytes / 1024]
+        return (copy_bytes / 1024.0) / max(cands)[0] if cands else None
+
+    f_fetch, f_write = calib(fetch, "FETCH_SIZE"), calib(write, "WRITE_SIZE")
+    lines = [f"# command: {command}", f"kernel_source_hash = {kernel_source_hash()}",
+             f"copy_calibration_fetch_factor = {f_fetch}", f"copy_calibration_write_factor = {f_write}",
+             "# kernel  FETCH_KiB/dispatch  WRITE_KiB/dispatch  scaled_bytes/dispatch"]
+    zconv = None
+    names = sorted({k for (k, c) in fetch} | {k for (k, c) in write})
+    for k in names:
+        fv = fetch.get((k, "FETCH_SIZE"), (0.0, 0))[0]
+        wv = write.get((k, "WRITE_SIZE"), (0.0, 0))[0]
+        scaled = None
+        if f_fetch and f_write:
+            scaled = (fv * f_fetch + wv * f_write) * 1024.0
+        lines.append(f"{k[:90]}  {fv:.1f}  {wv:.1f}  {scaled}")
+        if "kz_conv" in k and "IfLi128" in k:
+            zconv = scaled
+    if zconv is not None:
+        lines.append(f"traffic_bytes_per_launch = {zconv}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -271,15 +362,20 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--fp64-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample budget")
+    ap.add_argument("--batch-steps", type=int, default=50, help="replays of the 96-grid batch (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune launch shapes before timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (counter calibration)")
     ap.add_argument("--summarize-profile", metavar="DIR")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--out", metavar="FILE")
     ap.add_argument("--command", default="", help="command line recorded in the summary")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(*args.traffic_summary, args.out or "/dev/stdout", args.command)
+        return 0
     if args.summarize_profile:
         summarize_profile(args.summarize_profile, args.out or "/dev/stdout", args.command)
         return 0

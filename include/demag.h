@@ -72,6 +72,10 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
  *  "fg_cut":  offsets with Chebyshev distance <= fg_cut use the Newell f/g
  *             closed form (default 1; integer >= 0); the rest of the near field
  *             uses Gauss-Legendre quadrature of the cell-average integral.
+ *  "generic_kernels": 1 runs every pass on the generic (any-length)
+ *             kernels, 0 (default) uses the compile-time power-of-two kernels
+ *             on the axes whose padded length allows them; resets the launch
+ *             shapes to their defaults.
  *  "pass_timing": K > 0 records HIP events around every pass of the next
  *             evaluations on their own stream (a ring of K evaluations; 0 turns
  *             it off); read the averages with demag_plan_pass_times. */
@@ -110,6 +114,10 @@ int demag_plan_spectrum(demag_plan_t plan, void* out);
  * memory `out` [6][nz][ny][nx] (components xx yy zz xy xz yz).  Synchronous. */
 int demag_plan_tensor(demag_plan_t plan, double* out);
 
+/* Text description of the launch shape of every pass (kernel family, threads,
+ * tiles) into `buf` (len bytes, NUL-terminated); DEMAG_EINVAL if too small. */
+int demag_plan_describe(demag_plan_t plan, char* buf, int len);
+
 /* Average duration in ms of each pass over the evaluations recorded since the
  * last call (at most the ring size), from the events of "pass_timing":
  * ms[0..5] = X-R2C, Y, fused Z, Y-inverse, X-C2R, energy reduction (0 when the
@@ -122,12 +130,15 @@ int demag_plan_pass_times(demag_plan_t plan, double* ms, int64_t* count);
  * (if set).  Synchronous; clobbers the plan's scratch. */
 int demag_autotune(demag_plan_t plan, void* stream);
 
-/* Batch: `count` independent field evaluations (one per plan, plans may have
- * different shapes but one precision) with their m / H device buffers; the
- * whole batch is recorded once into a HIP graph and replayed by
- * demag_batch_launch.  The batch references (does not own) plans and buffers;
- * all must stay alive and unchanged until demag_batch_destroy.  Plans must be
- * distinct (each owns the scratch its evaluation uses). */
+/* Batch: `count` independent field evaluations H_i = -Ms N_i * m_i (one per
+ * plan; plans may have different grids and cells but one precision) with their
+ * m / H device buffers.  Plans of equal geometry form a group that runs each
+ * pass as one launch over all its members (and uses the first member's
+ * tensor spectrum and launch shapes); all groups' launches are recorded once
+ * into a HIP graph, replayed by demag_batch_launch (asynchronous).  The batch
+ * references (does not own) plans and buffers; all must stay alive and
+ * unchanged until demag_batch_destroy.  Plans must be distinct (each owns the
+ * scratch its evaluation uses).  demag_batch_create synchronises `stream`. */
 int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans, int count, const void* const* m,
                        void* const* H, double Ms, void* stream);
 int demag_batch_launch(demag_batch_t batch, void* stream);

@@ -32,6 +32,7 @@ SIGNATURES = {
     "demag_energy_async": (_I, [_P, _P, _D, _P, _P]),
     "demag_plan_spectrum": (_I, [_P, _P]),
     "demag_plan_tensor": (_I, [_P, _P]),
+    "demag_plan_describe": (_I, [_P, ctypes.c_char_p, _I]),
     "demag_plan_pass_times": (_I, [_P, ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int64)]),
     "demag_autotune": (_I, [_P, _P]),
     "demag_batch_create": (_I, [ctypes.POINTER(_P), ctypes.POINTER(_P), _I, ctypes.POINTER(_P),

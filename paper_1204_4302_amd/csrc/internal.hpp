@@ -15,32 +15,71 @@ constexpr int kMaxThreads = 256;  // workgroup size bound of every pass kernel
 //   X fwd / X inv : t0 = rows per workgroup (Ty)
 //   Y fwd / Y inv : t0 = kx per workgroup (Tx), t1 = z per workgroup (Tz)
 //   Z conv / fwd  : t0 = kx per workgroup (Tx)
+//
+// p2 = 1 selects the compile-time power-of-two kernels (passes_p2.hip); then
+// t0, t1 are log2 of the tile extents (X: Ty; Y: Tx, Tz; Z: Tx) and the
+// workgroup size follows from them (pencils x threads per pencil).
 struct LaunchCfg {
     int threads = 256;
     int E = 16;
     int t0 = 1;
     int t1 = 1;
+    int p2 = 0;
+};
+
+// Several grids of one shape in one launch: per-grid device pointers of the
+// pass's input and output (arrays of `count` pointers in device memory).
+// in == nullptr: a single grid, whose pointers are the launcher's arguments.
+struct BatchIO {
+    const void* const* in = nullptr;
+    void* const* out = nullptr;
+    int count = 1;
 };
 
 template <typename T>
 hipError_t launch_x_fwd(const LaunchCfg&, hipStream_t, const T* in, cx<T>* out, int Xin, int Yr, int Zr, int Kx,
-                        int C, const FftPlanDev&, const cx<T>* tw);
+                        int C, const FftPlanDev&, const cx<T>* tw, const BatchIO& bio = BatchIO());
 template <typename T>
 hipError_t launch_y_fwd(const LaunchCfg&, hipStream_t, const cx<T>* in, cx<T>* out, int Yin, int Zr, int Kx, int Zs,
-                        int C, const FftPlanDev&, const cx<T>* tw);
+                        int C, const FftPlanDev&, const cx<T>* tw, const BatchIO& bio = BatchIO());
 template <typename T>
 hipError_t launch_z_conv(const LaunchCfg&, hipStream_t, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx,
-                         const FftPlanDev&, const cx<T>* tw);
+                         const FftPlanDev&, const cx<T>* tw, const BatchIO& bio = BatchIO());
 template <typename T>
 hipError_t launch_z_fwd(const LaunchCfg&, hipStream_t, cx<T>* B2, int Py, int Kx, const FftPlanDev&,
                         const cx<T>* tw);
 template <typename T>
 hipError_t launch_y_inv(const LaunchCfg&, hipStream_t, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx, int C,
-                        const FftPlanDev&, const cx<T>* tw);
+                        const FftPlanDev&, const cx<T>* tw, const BatchIO& bio = BatchIO());
 template <typename T>
 hipError_t launch_x_inv(const LaunchCfg&, hipStream_t, const cx<T>* in, T* out, const T* m, double* partials, int nx,
-                        int ny, int nz, int Kx, int C, int accumulate, const FftPlanDev&, const cx<T>* tw);
+                        int ny, int nz, int Kx, int C, int accumulate, const FftPlanDev&, const cx<T>* tw,
+                        const BatchIO& bio = BatchIO());
 hipError_t launch_energy_reduce(hipStream_t, const double* partials, int n, double scale, double* out);
+
+// power-of-two lengths (2 <= P <= 4096): compile-time instances
+bool p2_supported(int P);
+int p2_threads_per_pencil(int P);
+int p2_slab_elems(int P);
+extern int kXcds;                       // XCDs of the device: 8 on MI355X; 1 turns the swizzle off
+constexpr int kP2MaxThreads = 1024;     // X and Y passes
+constexpr int kP2MaxThreadsZ = 512;     // fused Z pass (three pencils per thread)
+template <typename T>
+hipError_t launch_x_fwd_p2(int lgTy, hipStream_t, const T* in, cx<T>* out, int nx, int ny, int nz, int C, int P,
+                           const cx<T>* tw, const BatchIO& bio = BatchIO());
+template <typename T>
+hipError_t launch_x_inv_p2(int lgTy, hipStream_t, const cx<T>* in, T* out, const T* m, double* partials, int nx,
+                           int ny, int nz, int C, int accumulate, int P, const cx<T>* tw,
+                           const BatchIO& bio = BatchIO());
+template <typename T>
+hipError_t launch_y_fwd_p2(int lgTz, int lgTx, hipStream_t, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
+                           int C, int P, const cx<T>* tw, const BatchIO& bio = BatchIO());
+template <typename T>
+hipError_t launch_y_inv_p2(int lgTz, int lgTx, hipStream_t, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
+                           int C, int P, const cx<T>* tw, const BatchIO& bio = BatchIO());
+template <typename T>
+hipError_t launch_z_conv_p2(int lgTx, hipStream_t, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx, int P,
+                            const cx<T>* tw, const BatchIO& bio = BatchIO());
 
 // ---- tensor setup (FP64) ----------------------------------------------------
 struct TensorBands {

@@ -36,11 +36,15 @@ __device__ __forceinline__ cx<T>* lds_buf() {
 // grid (ceil(Yr/Ty), Zr, C); in [C][Zr][Yr][Xin]; out [C][Zr][Kx][Yr].
 template <typename T, int E>
 __global__ void __launch_bounds__(kMaxThreads) k_x_fwd(const T* __restrict__ in, cx<T>* __restrict__ out,
-                                                     int Xin, int Yr, int Zr, int Kx, int Ty, FftPlanDev pl,
-                                                     const cx<T>* __restrict__ tw) {
+                                                     int Xin, int Yr, int Zr, int Kx, int Ty, int C, FftPlanDev pl,
+                                                     const cx<T>* __restrict__ tw, BatchIO bio) {
     cx<T>* buf = lds_buf<T>();
     const int P = pl.P, tid = threadIdx.x, nthr = blockDim.x;
-    const int y0 = blockIdx.x * Ty, z = blockIdx.y, c = blockIdx.z;
+    const int y0 = blockIdx.x * Ty, z = blockIdx.y, c = blockIdx.z % C, g = blockIdx.z / C;
+    if (bio.in) {
+        in = (const T*)bio.in[g];
+        out = (cx<T>*)bio.out[g];
+    }
     const int ty = min(Ty, Yr - y0);
     const int B = (ty + 1) >> 1;
     const T* src = in + (((size_t)c * Zr + z) * Yr + y0) * (size_t)Xin;
@@ -73,11 +77,15 @@ __global__ void __launch_bounds__(kMaxThreads) k_x_fwd(const T* __restrict__ in,
 // grid (ceil(Kx/Tx), ceil(Zr/Tz), C); in [C][Zr][Kx][Yin]; out [C][Py][Kx][Zs].
 template <typename T, int E>
 __global__ void __launch_bounds__(kMaxThreads) k_y_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                                     int Yin, int Zr, int Kx, int Zs, int Tx, int Tz,
-                                                     FftPlanDev pl, const cx<T>* __restrict__ tw) {
+                                                     int Yin, int Zr, int Kx, int Zs, int Tx, int Tz, int C,
+                                                     FftPlanDev pl, const cx<T>* __restrict__ tw, BatchIO bio) {
     cx<T>* buf = lds_buf<T>();
     const int P = pl.P, tid = threadIdx.x, nthr = blockDim.x;
-    const int kx0 = blockIdx.x * Tx, z0 = blockIdx.y * Tz, c = blockIdx.z;
+    const int kx0 = blockIdx.x * Tx, z0 = blockIdx.y * Tz, c = blockIdx.z % C, g = blockIdx.z / C;
+    if (bio.in) {
+        in = (const cx<T>*)bio.in[g];
+        out = (cx<T>*)bio.out[g];
+    }
     const int tx = min(Tx, Kx - kx0), tz = min(Tz, Zr - z0);
     const int B = tx * tz;
     for (int e = tid; e < B * Yin; e += nthr) {
@@ -110,10 +118,11 @@ __global__ void __launch_bounds__(kMaxThreads) k_y_fwd(const cx<T>* __restrict__
 template <typename T, int E>
 __global__ void __launch_bounds__(kMaxThreads) k_z_conv(cx<T>* __restrict__ B2, const T* __restrict__ nhat, T Ms,
                                                       int nz, int Py, int Kx, int Tx, FftPlanDev pl,
-                                                      const cx<T>* __restrict__ tw) {
+                                                      const cx<T>* __restrict__ tw, BatchIO bio) {
     cx<T>* buf = lds_buf<T>();
     const int P = pl.P, Lz = P >> 1, Ly = Py >> 1, tid = threadIdx.x, nthr = blockDim.x;
     const int kx0 = blockIdx.x * Tx, kyp = blockIdx.y;
+    if (bio.in) B2 = (cx<T>*)bio.out[blockIdx.z];
     const int tx = min(Tx, Kx - kx0);
     const int ns = (kyp == 0 || kyp == Ly) ? 1 : 2;
     const int B = ns * 3 * tx;
@@ -183,11 +192,15 @@ __global__ void __launch_bounds__(kMaxThreads) k_z_fwd(cx<T>* __restrict__ B2, i
 // grid (ceil(Kx/Tx), ceil(nz/Tz), C); in [C][Py][Kx][nz]; out [C][nz][Kx][ny].
 template <typename T, int E>
 __global__ void __launch_bounds__(kMaxThreads) k_y_inv(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
-                                                     int ny, int nz, int Kx, int Tx, int Tz, FftPlanDev pl,
-                                                     const cx<T>* __restrict__ tw) {
+                                                     int ny, int nz, int Kx, int Tx, int Tz, int C, FftPlanDev pl,
+                                                     const cx<T>* __restrict__ tw, BatchIO bio) {
     cx<T>* buf = lds_buf<T>();
     const int P = pl.P, tid = threadIdx.x, nthr = blockDim.x;
-    const int kx0 = blockIdx.x * Tx, z0 = blockIdx.y * Tz, c = blockIdx.z;
+    const int kx0 = blockIdx.x * Tx, z0 = blockIdx.y * Tz, c = blockIdx.z % C, g = blockIdx.z / C;
+    if (bio.in) {
+        in = (const cx<T>*)bio.in[g];
+        out = (cx<T>*)bio.out[g];
+    }
     const int tx = min(Tx, Kx - kx0), tz = min(Tz, nz - z0);
     const int B = tx * tz;
     for (int e = tid; e < P * B; e += nthr) {
@@ -213,11 +226,17 @@ __global__ void __launch_bounds__(kMaxThreads) k_y_inv(const cx<T>* __restrict__
 template <typename T, int E>
 __global__ void __launch_bounds__(kMaxThreads) k_x_inv(const cx<T>* __restrict__ in, T* __restrict__ out,
                                                      const T* __restrict__ m, double* __restrict__ partials,
-                                                     int nx, int ny, int nz, int Kx, int Ty, int accumulate,
-                                                     FftPlanDev pl, const cx<T>* __restrict__ tw) {
+                                                     int nx, int ny, int nz, int Kx, int Ty, int accumulate, int C,
+                                                     FftPlanDev pl, const cx<T>* __restrict__ tw, BatchIO bio) {
     cx<T>* buf = lds_buf<T>();
     const int P = pl.P, Lx = P >> 1, tid = threadIdx.x, nthr = blockDim.x;
-    const int y0 = blockIdx.x * Ty, z = blockIdx.y, c = blockIdx.z;
+    const int y0 = blockIdx.x * Ty, z = blockIdx.y, c = blockIdx.z % C, g = blockIdx.z / C;
+    if (bio.in) {  // batches carry no energy
+        in = (const cx<T>*)bio.in[g];
+        out = (T*)bio.out[g];
+        m = nullptr;
+        partials = nullptr;
+    }
     const int ty = min(Ty, ny - y0);
     const int B = (ty + 1) >> 1;
     const cx<T>* src = in + ((size_t)c * nz + z) * (size_t)Kx * ny + y0;
@@ -288,10 +307,10 @@ __global__ void __launch_bounds__(256) k_energy_reduce(const double* __restrict_
 
 template <typename T>
 hipError_t launch_x_fwd(const LaunchCfg& lc, hipStream_t st, const T* in, cx<T>* out, int Xin, int Yr, int Zr,
-                        int Kx, int C, const FftPlanDev& pl, const cx<T>* tw) {
-    dim3 grid((Yr + lc.t0 - 1) / lc.t0, Zr, C);
+                        int Kx, int C, const FftPlanDev& pl, const cx<T>* tw, const BatchIO& bio) {
+    dim3 grid((Yr + lc.t0 - 1) / lc.t0, Zr, C * bio.count);
     size_t lds = (size_t)((lc.t0 + 1) / 2) * pl.P * sizeof(cx<T>);
-#define CALL(EE) hipLaunchKernelGGL((k_x_fwd<T, EE>), grid, dim3(lc.threads), lds, st, in, out, Xin, Yr, Zr, Kx, lc.t0, pl, tw)
+#define CALL(EE) hipLaunchKernelGGL((k_x_fwd<T, EE>), grid, dim3(lc.threads), lds, st, in, out, Xin, Yr, Zr, Kx, lc.t0, C, pl, tw, bio)
     DEMAG_E_SWITCH(lc.E, CALL)
 #undef CALL
     return hipGetLastError();
@@ -299,10 +318,10 @@ hipError_t launch_x_fwd(const LaunchCfg& lc, hipStream_t st, const T* in, cx<T>*
 
 template <typename T>
 hipError_t launch_y_fwd(const LaunchCfg& lc, hipStream_t st, const cx<T>* in, cx<T>* out, int Yin, int Zr, int Kx,
-                        int Zs, int C, const FftPlanDev& pl, const cx<T>* tw) {
-    dim3 grid((Kx + lc.t0 - 1) / lc.t0, (Zr + lc.t1 - 1) / lc.t1, C);
+                        int Zs, int C, const FftPlanDev& pl, const cx<T>* tw, const BatchIO& bio) {
+    dim3 grid((Kx + lc.t0 - 1) / lc.t0, (Zr + lc.t1 - 1) / lc.t1, C * bio.count);
     size_t lds = (size_t)lc.t0 * lc.t1 * pl.P * sizeof(cx<T>);
-#define CALL(EE) hipLaunchKernelGGL((k_y_fwd<T, EE>), grid, dim3(lc.threads), lds, st, in, out, Yin, Zr, Kx, Zs, lc.t0, lc.t1, pl, tw)
+#define CALL(EE) hipLaunchKernelGGL((k_y_fwd<T, EE>), grid, dim3(lc.threads), lds, st, in, out, Yin, Zr, Kx, Zs, lc.t0, lc.t1, C, pl, tw, bio)
     DEMAG_E_SWITCH(lc.E, CALL)
 #undef CALL
     return hipGetLastError();
@@ -310,10 +329,10 @@ hipError_t launch_y_fwd(const LaunchCfg& lc, hipStream_t st, const cx<T>* in, cx
 
 template <typename T>
 hipError_t launch_z_conv(const LaunchCfg& lc, hipStream_t st, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx,
-                         const FftPlanDev& pl, const cx<T>* tw) {
-    dim3 grid((Kx + lc.t0 - 1) / lc.t0, Py / 2 + 1, 1);
+                         const FftPlanDev& pl, const cx<T>* tw, const BatchIO& bio) {
+    dim3 grid((Kx + lc.t0 - 1) / lc.t0, Py / 2 + 1, bio.count);
     size_t lds = (size_t)6 * lc.t0 * pl.P * sizeof(cx<T>);
-#define CALL(EE) hipLaunchKernelGGL((k_z_conv<T, EE>), grid, dim3(lc.threads), lds, st, B2, nhat, Ms, nz, Py, Kx, lc.t0, pl, tw)
+#define CALL(EE) hipLaunchKernelGGL((k_z_conv<T, EE>), grid, dim3(lc.threads), lds, st, B2, nhat, Ms, nz, Py, Kx, lc.t0, pl, tw, bio)
     DEMAG_E_SWITCH(lc.E, CALL)
 #undef CALL
     return hipGetLastError();
@@ -332,10 +351,10 @@ hipError_t launch_z_fwd(const LaunchCfg& lc, hipStream_t st, cx<T>* B2, int Py, 
 
 template <typename T>
 hipError_t launch_y_inv(const LaunchCfg& lc, hipStream_t st, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
-                        int C, const FftPlanDev& pl, const cx<T>* tw) {
-    dim3 grid((Kx + lc.t0 - 1) / lc.t0, (nz + lc.t1 - 1) / lc.t1, C);
+                        int C, const FftPlanDev& pl, const cx<T>* tw, const BatchIO& bio) {
+    dim3 grid((Kx + lc.t0 - 1) / lc.t0, (nz + lc.t1 - 1) / lc.t1, C * bio.count);
     size_t lds = (size_t)lc.t0 * lc.t1 * pl.P * sizeof(cx<T>);
-#define CALL(EE) hipLaunchKernelGGL((k_y_inv<T, EE>), grid, dim3(lc.threads), lds, st, in, out, ny, nz, Kx, lc.t0, lc.t1, pl, tw)
+#define CALL(EE) hipLaunchKernelGGL((k_y_inv<T, EE>), grid, dim3(lc.threads), lds, st, in, out, ny, nz, Kx, lc.t0, lc.t1, C, pl, tw, bio)
     DEMAG_E_SWITCH(lc.E, CALL)
 #undef CALL
     return hipGetLastError();
@@ -344,11 +363,11 @@ hipError_t launch_y_inv(const LaunchCfg& lc, hipStream_t st, const cx<T>* in, cx
 template <typename T>
 hipError_t launch_x_inv(const LaunchCfg& lc, hipStream_t st, const cx<T>* in, T* out, const T* m, double* partials,
                         int nx, int ny, int nz, int Kx, int C, int accumulate, const FftPlanDev& pl,
-                        const cx<T>* tw) {
-    dim3 grid((ny + lc.t0 - 1) / lc.t0, nz, C);
+                        const cx<T>* tw, const BatchIO& bio) {
+    dim3 grid((ny + lc.t0 - 1) / lc.t0, nz, C * bio.count);
     size_t lds = (size_t)((lc.t0 + 1) / 2) * pl.P * sizeof(cx<T>);
     lds = std::max(lds, (size_t)(kMaxThreads / 64) * sizeof(double));  // the epilogue reduction reuses it
-#define CALL(EE) hipLaunchKernelGGL((k_x_inv<T, EE>), grid, dim3(lc.threads), lds, st, in, out, m, partials, nx, ny, nz, Kx, lc.t0, accumulate, pl, tw)
+#define CALL(EE) hipLaunchKernelGGL((k_x_inv<T, EE>), grid, dim3(lc.threads), lds, st, in, out, m, partials, nx, ny, nz, Kx, lc.t0, accumulate, C, pl, tw, bio)
     DEMAG_E_SWITCH(lc.E, CALL)
 #undef CALL
     return hipGetLastError();
@@ -361,17 +380,17 @@ hipError_t launch_energy_reduce(hipStream_t st, const double* partials, int n, d
 
 #define DEMAG_INSTANTIATE(T)                                                                                      \
     template hipError_t launch_x_fwd<T>(const LaunchCfg&, hipStream_t, const T*, cx<T>*, int, int, int, int, int, \
-                                        const FftPlanDev&, const cx<T>*);                                         \
+                                        const FftPlanDev&, const cx<T>*, const BatchIO&);                         \
     template hipError_t launch_y_fwd<T>(const LaunchCfg&, hipStream_t, const cx<T>*, cx<T>*, int, int, int, int,  \
-                                        int, const FftPlanDev&, const cx<T>*);                                    \
+                                        int, const FftPlanDev&, const cx<T>*, const BatchIO&);                    \
     template hipError_t launch_z_conv<T>(const LaunchCfg&, hipStream_t, cx<T>*, const T*, T, int, int, int,       \
-                                         const FftPlanDev&, const cx<T>*);                                        \
+                                         const FftPlanDev&, const cx<T>*, const BatchIO&);                        \
     template hipError_t launch_z_fwd<T>(const LaunchCfg&, hipStream_t, cx<T>*, int, int, const FftPlanDev&,       \
                                         const cx<T>*);                                                            \
     template hipError_t launch_y_inv<T>(const LaunchCfg&, hipStream_t, const cx<T>*, cx<T>*, int, int, int, int,  \
-                                        const FftPlanDev&, const cx<T>*);                                         \
+                                        const FftPlanDev&, const cx<T>*, const BatchIO&);                         \
     template hipError_t launch_x_inv<T>(const LaunchCfg&, hipStream_t, const cx<T>*, T*, const T*, double*, int,  \
-                                        int, int, int, int, int, const FftPlanDev&, const cx<T>*);
+                                        int, int, int, int, int, const FftPlanDev&, const cx<T>*, const BatchIO&);
 
 DEMAG_INSTANTIATE(float)
 DEMAG_INSTANTIATE(double)

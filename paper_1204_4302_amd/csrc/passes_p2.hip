@@ -1,0 +1,486 @@
+// The five passes of one field evaluation for power-of-two padded lengths
+// (compile-time P), on the register-resident FFT of fft_reg.hpp.  Same data
+// layouts and arithmetic as the generic passes (passes.hip):
+//   m [C][nz][ny][nx] -> B1 [C][nz][Kx][ny] -> B2 [C][Py][Kx][nz] -> (x Nhat)
+//   -> B2 -> B1 -> H [C][nz][ny][nx].
+// The side of a pass whose pencils are contiguous in memory moves directly
+// between HBM and registers (input positions of the first stage, output
+// positions of the last); the transposed side goes through the padded LDS
+// slabs.  Tile extents are powers of two, passed as log2.
+#include <algorithm>
+
+#include "fft_reg.hpp"
+#include "internal.hpp"
+
+namespace demag {
+namespace {
+
+template <typename T>
+__device__ __forceinline__ cx<T>* lds_base() {
+    extern __shared__ __align__(16) unsigned char smem_p2[];
+    return reinterpret_cast<cx<T>*>(smem_p2);
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> czero() { return mk(T(0), T(0)); }
+
+// Several grids per launch (BatchIO): the tiles of grid g are the logical
+// tiles [g T, (g+1) T), T = gridDim.x / count.  Returns the tile within the
+// grid and sets g.
+__device__ __forceinline__ int batch_tile(int L, const BatchIO& bio, int* g) {
+    *g = 0;
+    if (!bio.in) return L;
+    const int tiles = gridDim.x / bio.count;
+    *g = L / tiles;
+    return L - *g * tiles;
+}
+
+// Logical tile index of this workgroup.  The hardware hands consecutive
+// workgroups of a 1-D grid to the XCDs in turn (workgroup b to XCD b mod
+// nxcd); renumbering so that XCD x runs one contiguous range of logical tiles
+// keeps neighbouring tiles -- which share 128-byte lines of the strided side
+// of a pass -- in the same L2.  A bijection on [0, gridDim.x).
+__device__ __forceinline__ int xcd_tile(int nxcd) {
+    const int b = blockIdx.x, nb = gridDim.x;
+    if (nxcd <= 1 || nb < nxcd) return b;
+    const int x = b % nxcd, q = b / nxcd;
+    const int per = nb / nxcd, rem = nb % nxcd;
+    return x * per + min(x, rem) + q;
+}
+
+// register slot of the last stage whose position equals the first-stage input
+// position of slot j (forward output -> inverse input hand-over in registers)
+template <int P>
+__host__ __device__ constexpr int out_slot_for_in(int j) {
+    using F = p2::Fft<P>;
+    for (int jj = 0; jj < F::EPT; ++jj)
+        if (F::slot_out(jj) == F::slot_in(j)) return jj;
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// X forward (R2C of two rows per complex pencil).  grid (ceil(ny/Ty), nz, C),
+// block (Ty/2) * TP threads.
+template <typename T, int P>
+__global__ void __launch_bounds__(1024) kx_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, int nx, int ny,
+                                               int nz, int lgTy, int nxcd, const cx<T>* __restrict__ tw,
+                                               BatchIO bio) {
+    using F = p2::Fft<P>;
+    constexpr int Kx = P / 2 + 1;
+    cx<T>* lds = lds_base<T>();
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int p = tid >> F::LOG_TP, t = tid & (F::TP - 1);
+    const int Ty = 1 << lgTy;
+    const int nyt = (ny + Ty - 1) >> lgTy;
+    int g;
+    const int L = batch_tile(xcd_tile(nxcd), bio, &g), yt = L % nyt, zc = L / nyt;
+    if (bio.in) {
+        in = (const T*)bio.in[g];
+        out = (cx<T>*)bio.out[g];
+    }
+    const int y0 = yt << lgTy, z = zc % nz, c = zc / nz;
+    const int ty = min(Ty, ny - y0);
+    const T* src = in + (((size_t)c * nz + z) * ny + y0) * (size_t)nx;
+    const bool ok0 = 2 * p < ty, ok1 = 2 * p + 1 < ty;
+    cx<T> v[F::EPT];
+#pragma unroll
+    for (int j = 0; j < F::EPT; ++j) {
+        const int k = F::slot_in(j);
+        const int x = t + k * F::TP;
+        T a = T(0), b = T(0);
+        if (k < F::EPT / 2 && x < nx) {  // the padded half is never read
+            if (ok0) a = src[(size_t)(2 * p) * nx + x];
+            if (ok1) b = src[(size_t)(2 * p + 1) * nx + x];
+        }
+        v[j] = mk(a, b);
+    }
+    cx<T>* slab = lds + p * F::PS;
+    p2::fft<P, -1>(v, slab, t, tw);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < F::EPT; ++j) slab[F::pad(t + F::slot_out(j) * F::TP)] = v[j];
+    __syncthreads();
+    cx<T>* dst = out + ((size_t)c * nz + z) * (size_t)Kx * ny + y0;
+    for (int e = tid; e < (Kx << lgTy); e += nthr) {
+        const int y = e & (Ty - 1), k = e >> lgTy;
+        if (y < ty) {
+            const cx<T>* pen = lds + (y >> 1) * F::PS;
+            const cx<T> a = pen[F::pad(k)], b = pen[F::pad((P - k) & (P - 1))];
+            const cx<T> r = (y & 1) ? mk(T(0.5) * (a.im + b.im), T(0.5) * (b.re - a.re))
+                                    : mk(T(0.5) * (a.re + b.re), T(0.5) * (a.im - b.im));
+            dst[(size_t)k * ny + y] = r;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// X inverse (C2R of two rows per pencil), first nx outputs, optional
+// accumulate and energy partial (one FP64 value per workgroup).
+template <typename T, int P>
+__global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* __restrict__ out,
+                                               const T* __restrict__ m, double* __restrict__ partials, int nx,
+                                               int ny, int nz, int lgTy, int accumulate, int nxcd,
+                                               const cx<T>* __restrict__ tw, BatchIO bio) {
+    using F = p2::Fft<P>;
+    constexpr int Kx = P / 2 + 1, Lx = P / 2;
+    __shared__ double red[16];
+    cx<T>* lds = lds_base<T>();
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int p = tid >> F::LOG_TP, t = tid & (F::TP - 1);
+    const int Ty = 1 << lgTy, lgB = lgTy - 1, Bp = Ty >> 1;
+    const int nyt = (ny + Ty - 1) >> lgTy;
+    int g;
+    const int L = batch_tile(xcd_tile(nxcd), bio, &g), yt = L % nyt, zc = L / nyt;
+    if (bio.in) {  // batches carry no energy
+        in = (const cx<T>*)bio.in[g];
+        out = (T*)bio.out[g];
+        m = nullptr;
+        partials = nullptr;
+    }
+    const int y0 = yt << lgTy, z = zc % nz, c = zc / nz;
+    const int ty = min(Ty, ny - y0);
+    const cx<T>* src = in + ((size_t)c * nz + z) * (size_t)Kx * ny + y0;
+    for (int e = tid; e < (Kx << lgB); e += nthr) {
+        const int q = e & (Bp - 1), k = e >> lgB;
+        cx<T> xe = 2 * q < ty ? src[(size_t)k * ny + 2 * q] : czero<T>();
+        cx<T> xo = 2 * q + 1 < ty ? src[(size_t)k * ny + 2 * q + 1] : czero<T>();
+        if (k == 0 || k == Lx) {  // C2R ignores the imaginary parts of DC and Nyquist
+            xe.im = T(0);
+            xo.im = T(0);
+        }
+        cx<T>* pen = lds + q * F::PS;
+        pen[F::pad(k)] = mk(xe.re - xo.im, xe.im + xo.re);                           // xe + i xo
+        if (k > 0 && k < Lx) pen[F::pad(P - k)] = mk(xe.re + xo.im, xo.re - xe.im);  // conj(xe) + i conj(xo)
+    }
+    __syncthreads();
+    cx<T>* slab = lds + p * F::PS;
+    cx<T> v[F::EPT];
+#pragma unroll
+    for (int j = 0; j < F::EPT; ++j) v[j] = slab[F::pad(t + F::slot_in(j) * F::TP)];
+    p2::fft<P, +1>(v, slab, t, tw);
+    const size_t rowbase = (((size_t)c * nz + z) * ny + y0) * (size_t)nx;
+    T* dst = out ? out + rowbase : nullptr;
+    const T* msrc = m ? m + rowbase : nullptr;
+    const bool ok0 = 2 * p < ty, ok1 = 2 * p + 1 < ty;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < F::EPT; ++j) {
+        const int k = F::slot_out(j);
+        const int x = t + k * F::TP;
+        if (k < F::EPT / 2 && x < nx) {  // the discarded half is never written
+            const size_t i0 = (size_t)(2 * p) * nx + x, i1 = i0 + nx;
+            if (ok0) {
+                const T h = v[j].re;
+                if (msrc) acc += (double)(msrc[i0] * h);
+                if (dst) dst[i0] = accumulate ? dst[i0] + h : h;
+            }
+            if (ok1) {
+                const T h = v[j].im;
+                if (msrc) acc += (double)(msrc[i1] * h);
+                if (dst) dst[i1] = accumulate ? dst[i1] + h : h;
+            }
+        }
+    }
+    if (partials) {
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if ((tid & 63) == 0) red[tid >> 6] = acc;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < (nthr + 63) / 64; ++w) s += red[w];
+            partials[L] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Y forward.  Tile Tz x Tx pencils (z, kx); pencil p = zi * Tx + xi.
+// grid (ceil(Kx/Tx), ceil(nz/Tz), C), block Tz * Tx * TP.
+template <typename T, int P>
+__global__ void __launch_bounds__(1024) ky_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
+                                               int nz, int Kx, int lgTz, int lgTx, int nxcd,
+                                               const cx<T>* __restrict__ tw, BatchIO bio) {
+    using F = p2::Fft<P>;
+    cx<T>* lds = lds_base<T>();
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int p = tid >> F::LOG_TP, t = tid & (F::TP - 1);
+    const int Tx = 1 << lgTx, Tz = 1 << lgTz;
+    const int nzt = (nz + Tz - 1) >> lgTz, nxt = (Kx + Tx - 1) >> lgTx;
+    int g;
+    const int L = batch_tile(xcd_tile(nxcd), bio, &g), zt = L % nzt, xc = L / nzt;
+    if (bio.in) {
+        in = (const cx<T>*)bio.in[g];
+        out = (cx<T>*)bio.out[g];
+    }
+    const int kx0 = (xc % nxt) << lgTx, z0 = zt << lgTz, c = xc / nxt;
+    const int tx = min(Tx, Kx - kx0), tz = min(Tz, nz - z0);
+    const int xi = p & (Tx - 1), zi = p >> lgTx;
+    const bool ok = xi < tx && zi < tz;
+    const cx<T>* src = in + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny;
+    cx<T> v[F::EPT];
+#pragma unroll
+    for (int j = 0; j < F::EPT; ++j) {
+        const int k = F::slot_in(j);
+        const int y = t + k * F::TP;
+        v[j] = (k < F::EPT / 2 && ok && y < ny) ? src[y] : czero<T>();
+    }
+    cx<T>* slab = lds + p * F::PS;
+    p2::fft<P, -1>(v, slab, t, tw);
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < F::EPT; ++j) slab[F::pad(t + F::slot_out(j) * F::TP)] = v[j];
+    __syncthreads();
+    const int lgB = lgTz + lgTx;
+    for (int e = tid; e < (P << lgB); e += nthr) {
+        const int zj = e & (Tz - 1), xj = (e >> lgTz) & (Tx - 1), ky = e >> lgB;
+        if (zj < tz && xj < tx)
+            out[(((size_t)c * P + ky) * Kx + kx0 + xj) * (size_t)nz + z0 + zj] =
+                lds[((zj << lgTx) + xj) * F::PS + F::pad(ky)];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Y inverse: first ny outputs, written y-contiguous.
+template <typename T, int P>
+__global__ void __launch_bounds__(1024) ky_inv(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
+                                               int nz, int Kx, int lgTz, int lgTx, int nxcd,
+                                               const cx<T>* __restrict__ tw, BatchIO bio) {
+    using F = p2::Fft<P>;
+    cx<T>* lds = lds_base<T>();
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int p = tid >> F::LOG_TP, t = tid & (F::TP - 1);
+    const int Tx = 1 << lgTx, Tz = 1 << lgTz;
+    const int nzt = (nz + Tz - 1) >> lgTz, nxt = (Kx + Tx - 1) >> lgTx;
+    int g;
+    const int L = batch_tile(xcd_tile(nxcd), bio, &g), zt = L % nzt, xc = L / nzt;
+    if (bio.in) {
+        in = (const cx<T>*)bio.in[g];
+        out = (cx<T>*)bio.out[g];
+    }
+    const int kx0 = (xc % nxt) << lgTx, z0 = zt << lgTz, c = xc / nxt;
+    const int tx = min(Tx, Kx - kx0), tz = min(Tz, nz - z0);
+    const int lgB = lgTz + lgTx;
+    for (int e = tid; e < (P << lgB); e += nthr) {
+        const int zj = e & (Tz - 1), xj = (e >> lgTz) & (Tx - 1), ky = e >> lgB;
+        lds[((zj << lgTx) + xj) * F::PS + F::pad(ky)] =
+            (zj < tz && xj < tx) ? in[(((size_t)c * P + ky) * Kx + kx0 + xj) * (size_t)nz + z0 + zj] : czero<T>();
+    }
+    __syncthreads();
+    cx<T>* slab = lds + p * F::PS;
+    cx<T> v[F::EPT];
+#pragma unroll
+    for (int j = 0; j < F::EPT; ++j) v[j] = slab[F::pad(t + F::slot_in(j) * F::TP)];
+    p2::fft<P, +1>(v, slab, t, tw);
+    const int xi = p & (Tx - 1), zi = p >> lgTx;
+    if (xi < tx && zi < tz) {
+        cx<T>* dst = out + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny;
+#pragma unroll
+        for (int j = 0; j < F::EPT; ++j) {
+            const int k = F::slot_out(j);
+            const int y = t + k * F::TP;
+            if (k < F::EPT / 2 && y < ny) dst[y] = v[j];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused Z pass.  Group g = s * Tx + xi handles the three component pencils
+// at (kx0 + xi, ky_s), ky_0 = ky', ky_1 = Py - ky'; each thread keeps all
+// three components in registers, so the tensor product needs no exchange and
+// the forward output slots are the inverse input slots.
+// grid (ceil(Kx/Tx), Py/2 + 1), block 2 * Tx * TP.
+template <typename T, int P>
+__global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2, const T* __restrict__ nhat, T Ms, int nz,
+                                                int Py, int Kx, int lgTx, int nxcd, const cx<T>* __restrict__ tw,
+                                                BatchIO bio) {
+    using F = p2::Fft<P>;
+    constexpr int Lz = P / 2;
+    cx<T>* lds = lds_base<T>();
+    const int tid = threadIdx.x;
+    const int g = tid >> F::LOG_TP, t = tid & (F::TP - 1);
+    const int Tx = 1 << lgTx, Ly = Py >> 1;
+    const int xi = g & (Tx - 1), s = g >> lgTx;
+    const int nxt = (Kx + Tx - 1) >> lgTx;
+    int gb;
+    const int L = batch_tile(xcd_tile(nxcd), bio, &gb);
+    if (bio.in) B2 = (cx<T>*)bio.out[gb];
+    const int kx0 = (L % nxt) << lgTx, kyp = L / nxt;
+    const int tx = min(Tx, Kx - kx0);
+    const int ns = (kyp == 0 || kyp == Ly) ? 1 : 2;
+    const bool ok = s < ns && xi < tx;
+    const int ky = s ? Py - kyp : kyp;
+    cx<T> v[3][F::EPT];
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        const cx<T>* src = B2 + (((size_t)comp * Py + ky) * Kx + kx0 + xi) * (size_t)nz;
+#pragma unroll
+        for (int j = 0; j < F::EPT; ++j) {
+            const int k = F::slot_in(j);
+            const int zz = t + k * F::TP;
+            v[comp][j] = (k < F::EPT / 2 && ok && zz < nz) ? src[zz] : czero<T>();
+        }
+    }
+    cx<T>* slab = lds + g * F::PS;
+    p2::Twiddles<P, T> tws;  // one load of this thread's twiddles for all six transforms
+    tws.load(t, tw);
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) p2::fft<P, -1>(v[comp], slab, t, tws);
+    // H^ = Ms * Nhat(kx, ky, kz) M^ ; octant lookup with parity signs
+    const size_t cs = (size_t)Kx * (Lz + 1);
+    const T* nh0 = nhat + ((size_t)kyp * 6 * Kx + kx0 + xi) * (Lz + 1);
+    const T sy = s ? T(-1) : T(1);
+#pragma unroll
+    for (int j = 0; j < F::EPT; ++j) {
+        const int kz = t + F::slot_out(j) * F::TP;
+        const int kzp = kz <= Lz ? kz : P - kz;
+        const T sz = kz > Lz ? T(-1) : T(1);
+        T nxx = T(0), nyy = T(0), nzz = T(0), nxy = T(0), nxz = T(0), nyz = T(0);
+        if (ok) {
+            const T* nh = nh0 + kzp;
+            nxx = nh[0];
+            nyy = nh[cs];
+            nzz = nh[2 * cs];
+            nxy = sy * nh[3 * cs];
+            nxz = sz * nh[4 * cs];
+            nyz = sy * sz * nh[5 * cs];
+        }
+        const cx<T> mx = v[0][j], my = v[1][j], mz = v[2][j];
+        v[0][j] = mk(Ms * (nxx * mx.re + nxy * my.re + nxz * mz.re), Ms * (nxx * mx.im + nxy * my.im + nxz * mz.im));
+        v[1][j] = mk(Ms * (nxy * mx.re + nyy * my.re + nyz * mz.re), Ms * (nxy * mx.im + nyy * my.im + nyz * mz.im));
+        v[2][j] = mk(Ms * (nxz * mx.re + nyz * my.re + nzz * mz.re), Ms * (nxz * mx.im + nyz * my.im + nzz * mz.im));
+    }
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        cx<T> w[F::EPT];
+#pragma unroll
+        for (int j = 0; j < F::EPT; ++j) w[j] = v[comp][out_slot_for_in<P>(j)];
+        p2::fft<P, +1>(w, slab, t, tws);
+        if (ok) {
+            cx<T>* dst = B2 + (((size_t)comp * Py + ky) * Kx + kx0 + xi) * (size_t)nz;
+#pragma unroll
+            for (int j = 0; j < F::EPT; ++j) {
+                const int k = F::slot_out(j);
+                const int zz = t + k * F::TP;
+                if (k < F::EPT / 2 && zz < nz) dst[zz] = w[j];
+            }
+        }
+    }
+}
+
+template <int P>
+constexpr int tpp() { return p2::Fft<P>::TP; }
+
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host launchers: switch on the runtime length to the compile-time instance
+#define DEMAG_P2_SWITCH(P, CALL)                 \
+    switch (P) {                                 \
+    case 2: CALL(2); break;                      \
+    case 4: CALL(4); break;                      \
+    case 8: CALL(8); break;                      \
+    case 16: CALL(16); break;                    \
+    case 32: CALL(32); break;                    \
+    case 64: CALL(64); break;                    \
+    case 128: CALL(128); break;                  \
+    case 256: CALL(256); break;                  \
+    case 512: CALL(512); break;                  \
+    case 1024: CALL(1024); break;                \
+    case 2048: CALL(2048); break;                \
+    case 4096: CALL(4096); break;                \
+    default: return hipErrorInvalidValue;        \
+    }
+
+int kXcds = 8;  // XCDs of the device (workgroup swizzle); set by the plan runtime
+
+bool p2_supported(int P) { return P >= 2 && P <= 4096 && (P & (P - 1)) == 0; }
+int p2_threads_per_pencil(int P) { return P >= 8 ? P / 8 : 1; }
+int p2_slab_elems(int P) { return (P + (P >> 3)) + 1; }
+
+template <typename T>
+hipError_t launch_x_fwd_p2(int lgTy, hipStream_t st, const T* in, cx<T>* out, int nx, int ny, int nz, int C, int P,
+                           const cx<T>* tw, const BatchIO& bio) {
+    const int Bp = 1 << (lgTy - 1);
+    dim3 grid((unsigned)(((ny + (1 << lgTy) - 1) >> lgTy) * nz * C * bio.count));
+    const size_t lds = (size_t)Bp * p2_slab_elems(P) * sizeof(cx<T>);
+#define CALL(PP) \
+    hipLaunchKernelGGL((kx_fwd<T, PP>), grid, dim3(Bp * tpp<PP>()), lds, st, in, out, nx, ny, nz, lgTy, kXcds, tw, \
+                       bio)
+    DEMAG_P2_SWITCH(P, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_x_inv_p2(int lgTy, hipStream_t st, const cx<T>* in, T* out, const T* m, double* partials, int nx,
+                           int ny, int nz, int C, int accumulate, int P, const cx<T>* tw, const BatchIO& bio) {
+    const int Bp = 1 << (lgTy - 1);
+    dim3 grid((unsigned)(((ny + (1 << lgTy) - 1) >> lgTy) * nz * C * bio.count));
+    const size_t lds = (size_t)Bp * p2_slab_elems(P) * sizeof(cx<T>);
+#define CALL(PP)                                                                                            \
+    hipLaunchKernelGGL((kx_inv<T, PP>), grid, dim3(Bp * tpp<PP>()), lds, st, in, out, m, partials, nx, ny, nz, \
+                       lgTy, accumulate, kXcds, tw, bio)
+    DEMAG_P2_SWITCH(P, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_y_fwd_p2(int lgTz, int lgTx, hipStream_t st, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
+                           int C, int P, const cx<T>* tw, const BatchIO& bio) {
+    const int B = 1 << (lgTz + lgTx);
+    dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * ((nz + (1 << lgTz) - 1) >> lgTz) * C * bio.count));
+    const size_t lds = (size_t)B * p2_slab_elems(P) * sizeof(cx<T>);
+#define CALL(PP) \
+    hipLaunchKernelGGL((ky_fwd<T, PP>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, tw, \
+                       bio)
+    DEMAG_P2_SWITCH(P, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_y_inv_p2(int lgTz, int lgTx, hipStream_t st, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
+                           int C, int P, const cx<T>* tw, const BatchIO& bio) {
+    const int B = 1 << (lgTz + lgTx);
+    dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * ((nz + (1 << lgTz) - 1) >> lgTz) * C * bio.count));
+    const size_t lds = (size_t)B * p2_slab_elems(P) * sizeof(cx<T>);
+#define CALL(PP) \
+    hipLaunchKernelGGL((ky_inv<T, PP>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, tw, \
+                       bio)
+    DEMAG_P2_SWITCH(P, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_z_conv_p2(int lgTx, hipStream_t st, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx, int P,
+                            const cx<T>* tw, const BatchIO& bio) {
+    const int G = 2 << lgTx;
+    dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * (Py / 2 + 1) * bio.count));
+    const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>);
+#define CALL(PP) \
+    hipLaunchKernelGGL((kz_conv<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, kXcds, tw, \
+                       bio)
+    DEMAG_P2_SWITCH(P, CALL)
+#undef CALL
+    return hipGetLastError();
+}
+
+#define DEMAG_P2_INSTANTIATE(T)                                                                                    \
+    template hipError_t launch_x_fwd_p2<T>(int, hipStream_t, const T*, cx<T>*, int, int, int, int, int,           \
+                                           const cx<T>*, const BatchIO&);                                          \
+    template hipError_t launch_x_inv_p2<T>(int, hipStream_t, const cx<T>*, T*, const T*, double*, int, int, int,  \
+                                           int, int, int, const cx<T>*, const BatchIO&);                           \
+    template hipError_t launch_y_fwd_p2<T>(int, int, hipStream_t, const cx<T>*, cx<T>*, int, int, int, int, int,  \
+                                           const cx<T>*, const BatchIO&);                                          \
+    template hipError_t launch_y_inv_p2<T>(int, int, hipStream_t, const cx<T>*, cx<T>*, int, int, int, int, int,  \
+                                           const cx<T>*, const BatchIO&);                                          \
+    template hipError_t launch_z_conv_p2<T>(int, hipStream_t, cx<T>*, const T*, T, int, int, int, int,            \
+                                            const cx<T>*, const BatchIO&);
+
+DEMAG_P2_INSTANTIATE(float)
+DEMAG_P2_INSTANTIATE(double)
+
+}  // namespace demag

@@ -167,8 +167,19 @@ struct demag_plan_s {
     long tcount = 0;
 };
 
+// A batch groups its plans by geometry (grid, cell, precision): the members of
+// a group share the tensor spectrum of the first ("lead") plan and run every
+// pass as one launch over the group, driven by per-member pointer lists.
+struct BatchGroup {
+    demag_plan_s* lead = nullptr;
+    int count = 0;
+    void** lists = nullptr;  // device: m[count], H[count], B1[count], B2[count]
+};
+
 struct demag_batch_s {
     std::vector<demag_plan_t> plans;
+    std::vector<BatchGroup> groups;
+    void* dev_lists = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -212,20 +223,101 @@ LaunchCfg cfg_zconv(int P, int Kx, size_t cbytes) {
     return c;
 }
 
+int ilog2i(long v) {
+    int l = 0;
+    while ((1L << (l + 1)) <= v) ++l;
+    return l;
+}
+int pow2_ceil_log(long v) {
+    int l = 0;
+    while ((1L << l) < v) ++l;
+    return l;
+}
+
+// p2 tiles: about `target` threads per workgroup, bounded by the extent the
+// tile covers and by LDS.
+LaunchCfg p2_rows(int P, int rows, size_t cbytes, int target = 512) {
+    LaunchCfg c;
+    c.p2 = 1;
+    const int TP = p2_threads_per_pencil(P);
+    int lgB = ilog2i(std::max(1, target / TP));
+    lgB = std::min(lgB, std::max(0, pow2_ceil_log(rows) - 1));
+    while (lgB > 0 && ((size_t)p2_slab_elems(P) << lgB) * cbytes > kMaxLdsBytes - 256) --lgB;
+    c.t0 = lgB + 1;  // Ty = 2 * pencils
+    c.threads = TP << lgB;
+    return c;
+}
+
+LaunchCfg p2_pencils(int P, int Kx, int nz, size_t cbytes, int target = 512) {
+    LaunchCfg c;
+    c.p2 = 1;
+    const int TP = p2_threads_per_pencil(P);
+    int lgB = ilog2i(std::max(1, target / TP));
+    while (lgB > 0 && ((size_t)p2_slab_elems(P) << lgB) * cbytes > kMaxLdsBytes) --lgB;
+    int lgTz = std::min(lgB, pow2_ceil_log(nz));
+    int lgTx = std::min(lgB - lgTz, pow2_ceil_log(Kx));
+    c.t0 = lgTx;
+    c.t1 = lgTz;
+    c.threads = TP << (lgTx + lgTz);
+    return c;
+}
+
+LaunchCfg p2_zconv(int P, int Kx, size_t cbytes, int target = 512) {
+    LaunchCfg c;
+    c.p2 = 1;
+    const int TP = p2_threads_per_pencil(P);
+    int lgTx = std::max(0, ilog2i(std::max(1, target / (2 * TP))));
+    lgTx = std::min(lgTx, pow2_ceil_log(Kx));
+    while (lgTx > 0 && ((size_t)p2_slab_elems(P) << (lgTx + 1)) * cbytes > kMaxLdsBytes) --lgTx;
+    while (lgTx > 0 && (2 * TP << lgTx) > kP2MaxThreadsZ) --lgTx;
+    c.t0 = lgTx;
+    c.threads = 2 * TP << lgTx;
+    return c;
+}
+
+bool p2_cfg_ok(const LaunchCfg& c, int P, size_t cbytes, int kind /*0 rows, 1 pencils, 2 z*/) {
+    if (!p2_supported(P) || c.t0 < 0 || c.t1 < 0 || c.t0 > 12 || c.t1 > 12) return false;
+    const long TP = p2_threads_per_pencil(P);
+    long pencils = kind == 0 ? (1L << (c.t0 - 1)) : kind == 1 ? (1L << (c.t0 + c.t1)) : (2L << c.t0);
+    if (kind == 0 && c.t0 < 1) return false;
+    long threads = pencils * TP;
+    long maxthr = kind == 2 ? kP2MaxThreadsZ : kP2MaxThreads;
+    return threads == c.threads && threads <= maxthr &&
+           (size_t)pencils * p2_slab_elems(P) * cbytes <= kMaxLdsBytes - 256;  // + static reduction scratch
+}
+
 bool cfg_ok(const LaunchCfg& c, long pencils, int P, size_t cbytes) {
     return c.E > 0 && c.threads > 0 && c.threads <= kMaxThreads && c.threads % 64 == 0 &&
            (long)c.threads * c.E >= pencils * P && (size_t)pencils * P * cbytes <= kMaxLdsBytes;
 }
 
-bool plan_cfgs_ok(const demag_plan_s* p, const PassCfgs& c) {
-    size_t cb = csize(p->dtype);
-    return cfg_ok(c.xf, (c.xf.t0 + 1) / 2, p->P[0], cb) && c.xf.t0 % 2 == 0 &&
-           cfg_ok(c.yf, (long)c.yf.t0 * c.yf.t1, p->P[1], cb) && cfg_ok(c.zc, 6L * c.zc.t0, p->P[2], cb) &&
-           cfg_ok(c.yi, (long)c.yi.t0 * c.yi.t1, p->P[1], cb) && cfg_ok(c.xi, (c.xi.t0 + 1) / 2, p->P[0], cb) &&
-           c.xi.t0 % 2 == 0;
+bool one_cfg_ok(const LaunchCfg& c, int P, size_t cb, int kind) {
+    if (c.p2) return p2_cfg_ok(c, P, cb, kind);
+    if (kind == 0) return cfg_ok(c, (c.t0 + 1) / 2, P, cb) && c.t0 % 2 == 0;
+    if (kind == 1) return cfg_ok(c, (long)c.t0 * c.t1, P, cb);
+    return cfg_ok(c, 6L * c.t0, P, cb);
 }
 
+bool plan_cfgs_ok(const demag_plan_s* p, const PassCfgs& c) {
+    size_t cb = csize(p->dtype);
+    return one_cfg_ok(c.xf, p->P[0], cb, 0) && one_cfg_ok(c.xi, p->P[0], cb, 0) &&
+           one_cfg_ok(c.yf, p->P[1], cb, 1) && one_cfg_ok(c.yi, p->P[1], cb, 1) && one_cfg_ok(c.zc, p->P[2], cb, 2);
+}
+
+// Generic kernels (any 2^a 3^b 5^c length) unless the padded length is a power
+// of two, where the compile-time kernels are used.
 PassCfgs default_cfgs(const demag_plan_s* p) {
+    size_t cb = csize(p->dtype);
+    PassCfgs c;
+    c.xf = p2_supported(p->P[0]) ? p2_rows(p->P[0], p->n[1], cb) : cfg_rows(p->P[0], p->n[1], cb);
+    c.xi = c.xf;
+    c.yf = p2_supported(p->P[1]) ? p2_pencils(p->P[1], p->Kx, p->n[2], cb) : cfg_pencils(p->P[1], p->Kx, p->n[2], cb);
+    c.yi = c.yf;
+    c.zc = p2_supported(p->P[2]) ? p2_zconv(p->P[2], p->Kx, cb) : cfg_zconv(p->P[2], p->Kx, cb);
+    return c;
+}
+
+PassCfgs generic_cfgs(const demag_plan_s* p) {
     size_t cb = csize(p->dtype);
     PassCfgs c;
     c.xf = cfg_rows(p->P[0], p->n[1], cb);
@@ -335,38 +427,68 @@ void free_plan(demag_plan_s* p) {
 
 // ---------------------------------------------------------------------------
 // one evaluation: X-R2C -> Y -> Z (x N) -> Y^-1 -> X-C2R (+ energy)
+// One pass of one evaluation with launch shape lc (which: 0 X-R2C, 1 Y, 2 fused
+// Z, 3 Y-inverse, 4 X-C2R).  m: input of pass 0; H, me, partials, accumulate:
+// outputs of pass 4.
 template <typename T>
-int run_field(demag_plan_s* p, const PassCfgs& c, const T* m, double Ms, T* H, const T* m_energy, double* E_dev,
-              int accumulate, hipStream_t st) {
+hipError_t launch_pass(demag_plan_s* p, int which, const LaunchCfg& lc, hipStream_t st, const T* m, double Ms, T* H,
+                       const T* me, double* partials, int accumulate, const BatchIO& bio = BatchIO()) {
     const int nx = p->n[0], ny = p->n[1], nz = p->n[2], Kx = p->Kx;
+    const int Px = p->P[0], Py = p->P[1], Pz = p->P[2];
     auto* B1 = (cx<T>*)p->B1;
     auto* B2 = (cx<T>*)p->B2;
     const auto* twx = (const cx<T>*)p->tw[0];
     const auto* twy = (const cx<T>*)p->tw[1];
     const auto* twz = (const cx<T>*)p->tw[2];
+    switch (which) {
+    case 0:
+        return lc.p2 ? launch_x_fwd_p2<T>(lc.t0, st, m, B1, nx, ny, nz, 3, Px, twx, bio)
+                     : launch_x_fwd<T>(lc, st, m, B1, nx, ny, nz, Kx, 3, p->fp[0], twx, bio);
+    case 1:
+        return lc.p2 ? launch_y_fwd_p2<T>(lc.t1, lc.t0, st, B1, B2, ny, nz, Kx, 3, Py, twy, bio)
+                     : launch_y_fwd<T>(lc, st, B1, B2, ny, nz, Kx, nz, 3, p->fp[1], twy, bio);
+    case 2:
+        return lc.p2 ? launch_z_conv_p2<T>(lc.t0, st, B2, (const T*)p->nhat, (T)Ms, nz, Py, Kx, Pz, twz, bio)
+                     : launch_z_conv<T>(lc, st, B2, (const T*)p->nhat, (T)Ms, nz, Py, Kx, p->fp[2], twz, bio);
+    case 3:
+        return lc.p2 ? launch_y_inv_p2<T>(lc.t1, lc.t0, st, B2, B1, ny, nz, Kx, 3, Py, twy, bio)
+                     : launch_y_inv<T>(lc, st, B2, B1, ny, nz, Kx, 3, p->fp[1], twy, bio);
+    default:
+        return lc.p2 ? launch_x_inv_p2<T>(lc.t0, st, B1, H, me, partials, nx, ny, nz, 3, accumulate, Px, twx, bio)
+                     : launch_x_inv<T>(lc, st, B1, H, me, partials, nx, ny, nz, Kx, 3, accumulate, p->fp[0], twx,
+                                       bio);
+    }
+}
+
+const LaunchCfg& pass_cfg(const PassCfgs& c, int which) {
+    const LaunchCfg* slot[5] = {&c.xf, &c.yf, &c.zc, &c.yi, &c.xi};
+    return *slot[which];
+}
+
+// one evaluation: X-R2C -> Y -> Z (x N) -> Y^-1 -> X-C2R (+ energy)
+template <typename T>
+int run_field(demag_plan_s* p, const PassCfgs& c, const T* m, double Ms, T* H, const T* m_energy, double* E_dev,
+              int accumulate, hipStream_t st) {
     hipEvent_t* mark = nullptr;
     if (p->tcap > 0 && !p->capturing) mark = &p->tev[(size_t)(p->tcount % p->tcap) * kPassMarks];
-    auto stamp = [&](int k) -> hipError_t { return mark ? hipEventRecord(mark[k], st) : hipSuccess; };
-    HIP_TRY(stamp(0));
-    HIP_TRY(launch_x_fwd<T>(c.xf, st, m, B1, nx, ny, nz, Kx, 3, p->fp[0], twx));
-    HIP_TRY(stamp(1));
-    HIP_TRY(launch_y_fwd<T>(c.yf, st, B1, B2, ny, nz, Kx, nz, 3, p->fp[1], twy));
-    HIP_TRY(stamp(2));
-    HIP_TRY(launch_z_conv<T>(c.zc, st, B2, (const T*)p->nhat, (T)Ms, nz, p->P[1], Kx, p->fp[2], twz));
-    HIP_TRY(stamp(3));
-    HIP_TRY(launch_y_inv<T>(c.yi, st, B2, B1, ny, nz, Kx, 3, p->fp[1], twy));
-    HIP_TRY(stamp(4));
     double* partials = E_dev ? p->partials : nullptr;
-    HIP_TRY(launch_x_inv<T>(c.xi, st, B1, H, E_dev ? m_energy : nullptr, partials, nx, ny, nz, Kx, 3, accumulate,
-                            p->fp[0], twx));
-    HIP_TRY(stamp(5));
+    const T* me = E_dev ? m_energy : nullptr;
+    for (int which = 0; which < 5; ++which) {
+        if (mark) HIP_TRY(hipEventRecord(mark[which], st));
+        HIP_TRY(launch_pass<T>(p, which, pass_cfg(c, which), st, m, Ms, H, me, partials, accumulate));
+    }
+    if (mark) HIP_TRY(hipEventRecord(mark[5], st));
     if (E_dev) {
-        const int nparts = ((ny + c.xi.t0 - 1) / c.xi.t0) * nz * 3;
+        const int Ty = c.xi.p2 ? (1 << c.xi.t0) : c.xi.t0;
+        const int ny = p->n[1], nz = p->n[2];
+        const int nparts = ((ny + Ty - 1) / Ty) * nz * 3;
         const double V = p->d[0] * p->d[1] * p->d[2];
         HIP_TRY(launch_energy_reduce(st, p->partials, nparts, -0.5 * kMu0 * Ms * V, E_dev));
     }
-    HIP_TRY(stamp(6));
-    if (mark) ++p->tcount;
+    if (mark) {
+        HIP_TRY(hipEventRecord(mark[6], st));
+        ++p->tcount;
+    }
     return DEMAG_OK;
 }
 
@@ -447,6 +569,10 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
     p->d[2] = dz;
     p->dtype = dtype;
     p->Kx = Kx;
+    if (const char* xe = getenv("DEMAG_XCDS")) {  // workgroup swizzle width (1 = off)
+        int v = atoi(xe);
+        if (v >= 1 && v <= 64) kXcds = v;
+    }
     hipError_t he = hipGetDevice(&p->device);
     if (he != hipSuccess) {
         delete p;
@@ -499,6 +625,11 @@ int demag_plan_set_option(demag_plan_t p, const char* key, double value) {
         if (!(value >= 0) || value != std::floor(value) || value > 1e9)
             return fail(DEMAG_EINVAL, "fg_cut must be a non-negative integer");
         b.fg_cut = (int)value;
+    } else if (!strcmp(key, "generic_kernels")) {
+        if (value != 0 && value != 1) return fail(DEMAG_EINVAL, "generic_kernels must be 0 or 1");
+        HIP_TRY(hipDeviceSynchronize());
+        p->cfg = value == 1 ? generic_cfgs(p) : default_cfgs(p);
+        return DEMAG_OK;
     } else if (!strcmp(key, "pass_timing")) {
         if (!(value >= 0) || value != std::floor(value) || value > 1e6)
             return fail(DEMAG_EINVAL, "pass_timing must be an integer in [0, 1e6]");
@@ -599,6 +730,24 @@ int demag_plan_tensor(demag_plan_t p, double* out) {
     return DEMAG_OK;
 }
 
+int demag_plan_describe(demag_plan_t p, char* buf, int len) {
+    if (!p || !buf || len < 1) return fail(DEMAG_EINVAL, "NULL argument");
+    const char* names[5] = {"x_r2c", "y_fwd", "z_conv", "y_inv", "x_c2r"};
+    std::string out;
+    for (int w = 0; w < 5; ++w) {
+        const LaunchCfg& c = pass_cfg(p->cfg, w);
+        char b[160];
+        if (c.p2)
+            snprintf(b, sizeof b, "%s:pow2(threads=%d,log2 tiles=%d,%d) ", names[w], c.threads, c.t0, c.t1);
+        else
+            snprintf(b, sizeof b, "%s:generic(threads=%d,E=%d,tiles=%d,%d) ", names[w], c.threads, c.E, c.t0, c.t1);
+        out += b;
+    }
+    if (!out.empty()) out.pop_back();
+    snprintf(buf, (size_t)len, "%s", out.c_str());
+    return (int)out.size() < len ? DEMAG_OK : fail(DEMAG_EINVAL, "buffer too small (%zu bytes needed)", out.size() + 1);
+}
+
 int demag_plan_pass_times(demag_plan_t p, double* ms, int64_t* count) {
     if (!p || !ms || !count) return fail(DEMAG_EINVAL, "NULL argument");
     for (int k = 0; k < kPassMarks - 1; ++k) ms[k] = 0.0;
@@ -671,14 +820,43 @@ std::vector<LaunchCfg> candidates_z(const demag_plan_s* p) {
     return out;
 }
 
+// power-of-two candidates: every tile whose workgroup and LDS fit
+void add_p2_candidates(const demag_plan_s* p, int kind, std::vector<LaunchCfg>& out) {
+    const int P = p->P[kind == 0 ? 0 : kind == 1 ? 1 : 2];
+    if (!p2_supported(P)) return;
+    const size_t cb = csize(p->dtype);
+    const int TP = p2_threads_per_pencil(P);
+    for (int a = 0; a <= 10; ++a)
+        for (int b = 0; b <= (kind == 1 ? 10 : 0); ++b) {
+            LaunchCfg c;
+            c.p2 = 1;
+            if (kind == 0) {
+                if (a < 1 || a > pow2_ceil_log(p->n[1]) + 1) continue;
+                c.t0 = a;
+                c.threads = TP << (a - 1);
+            } else if (kind == 1) {
+                if (a > pow2_ceil_log(p->Kx) || b > pow2_ceil_log(p->n[2])) continue;
+                c.t0 = a;
+                c.t1 = b;
+                c.threads = TP << (a + b);
+            } else {
+                if (a > pow2_ceil_log(p->Kx)) continue;
+                c.t0 = a;
+                c.threads = 2 * TP << a;
+            }
+            if (c.threads < 64 && c.threads < TP * 2) continue;
+            if (p2_cfg_ok(c, P, cb, kind)) out.push_back(c);
+        }
+}
+
 std::string cfg_str(const LaunchCfg& c) {
     char b[64];
-    snprintf(b, sizeof b, "%d,%d,%d,%d", c.threads, c.E, c.t0, c.t1);
+    snprintf(b, sizeof b, "%d,%d,%d,%d,%d", c.threads, c.E, c.t0, c.t1, c.p2);
     return b;
 }
 
 bool cfg_parse(const std::string& s, LaunchCfg& c) {
-    return sscanf(s.c_str(), "%d,%d,%d,%d", &c.threads, &c.E, &c.t0, &c.t1) == 4;
+    return sscanf(s.c_str(), "%d,%d,%d,%d,%d", &c.threads, &c.E, &c.t0, &c.t1, &c.p2) == 5;
 }
 
 std::string cache_key(const demag_plan_s* p) {
@@ -687,7 +865,7 @@ std::string cache_key(const demag_plan_s* p) {
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
     arch = arch.substr(0, arch.find(':'));
     char b[160];
-    snprintf(b, sizeof b, "v1|%s|%s|%d,%d,%d", arch.c_str(), p->dtype == DEMAG_F32 ? "f32" : "f64", p->n[0],
+    snprintf(b, sizeof b, "v2|%s|%s|%d,%d,%d", arch.c_str(), p->dtype == DEMAG_F32 ? "f32" : "f64", p->n[0],
              p->n[1], p->n[2]);
     return b;
 }
@@ -699,7 +877,7 @@ std::map<std::string, std::string> read_cache(const char* path) {
     std::string line;
     while (std::getline(f, line)) {
         auto sp = line.find(' ');
-        if (sp == std::string::npos || line.rfind("v1|", 0) != 0) continue;
+        if (sp == std::string::npos || line.rfind("v2|", 0) != 0) continue;
         m[line.substr(0, sp)] = line.substr(sp + 1);
     }
     return m;
@@ -716,36 +894,27 @@ bool parse_cfgs(const std::string& s, PassCfgs& c) {
 
 template <typename T>
 int time_pass(demag_plan_s* p, int which, const LaunchCfg& lc, hipStream_t st, const T* m, T* H, float* ms_out) {
-    PassCfgs c = p->cfg;
-    LaunchCfg* slot[5] = {&c.xf, &c.yf, &c.zc, &c.yi, &c.xi};
-    *slot[which] = lc;
-    const int nx = p->n[0], ny = p->n[1], nz = p->n[2], Kx = p->Kx;
-    auto* B1 = (cx<T>*)p->B1;
-    auto* B2 = (cx<T>*)p->B2;
-    auto launch = [&]() -> hipError_t {
-        switch (which) {
-        case 0: return launch_x_fwd<T>(c.xf, st, m, B1, nx, ny, nz, Kx, 3, p->fp[0], (const cx<T>*)p->tw[0]);
-        case 1: return launch_y_fwd<T>(c.yf, st, B1, B2, ny, nz, Kx, nz, 3, p->fp[1], (const cx<T>*)p->tw[1]);
-        case 2: return launch_z_conv<T>(c.zc, st, B2, (const T*)p->nhat, T(1), nz, p->P[1], Kx, p->fp[2], (const cx<T>*)p->tw[2]);
-        case 3: return launch_y_inv<T>(c.yi, st, B2, B1, ny, nz, Kx, 3, p->fp[1], (const cx<T>*)p->tw[1]);
-        default: return launch_x_inv<T>(c.xi, st, B1, H, nullptr, nullptr, nx, ny, nz, Kx, 3, 0, p->fp[0], (const cx<T>*)p->tw[0]);
-        }
-    };
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    hipError_t err = launch();
-    const int reps = 5;
-    if (err == hipSuccess) err = hipEventRecord(e0, st);
-    for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
-    if (err == hipSuccess) err = hipEventRecord(e1, st);
-    if (err == hipSuccess) err = hipEventSynchronize(e1);
-    float ms = 0;
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    auto launch = [&]() { return launch_pass<T>(p, which, lc, st, m, 1.0, H, nullptr, nullptr, 0); };
+    hipError_t err = hipSuccess;
+    for (int r = 0; r < 3 && err == hipSuccess; ++r) err = launch();
+    const int reps = 10;
+    float best = 1e30f;
+    for (int trial = 0; trial < 3 && err == hipSuccess; ++trial) {
+        err = hipEventRecord(e0, st);
+        for (int r = 0; r < reps && err == hipSuccess; ++r) err = launch();
+        if (err == hipSuccess) err = hipEventRecord(e1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        best = std::min(best, ms / reps);
+    }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (err != hipSuccess) return hip_fail(err, "autotune timing");
-    *ms_out = ms / reps;
+    *ms_out = best;
     return DEMAG_OK;
 }
 
@@ -759,6 +928,8 @@ int autotune_impl(demag_plan_s* p, hipStream_t st) {
     int rc = DEMAG_OK;
     std::vector<LaunchCfg> cand[5] = {candidates_rows(p), candidates_pencils(p), candidates_z(p),
                                       candidates_pencils(p), candidates_rows(p)};
+    const int kinds[5] = {0, 1, 2, 1, 0};
+    for (int w = 0; w < 5; ++w) add_p2_candidates(p, kinds[w], cand[w]);
     LaunchCfg* slot[5] = {&p->cfg.xf, &p->cfg.yf, &p->cfg.zc, &p->cfg.yi, &p->cfg.xi};
     for (int which = 0; which < 5 && !rc; ++which) {
         float best = 1e30f;
@@ -816,12 +987,42 @@ extern "C" int demag_autotune(demag_plan_t p, void* stream) {
 }
 
 // ---------------------------------------------------------------------------
-// batch: every plan's evaluation recorded once into one HIP graph.  Plans are
-// spread over up to kBranches forked capture streams, so small grids run side
-// by side; one replay of the graph is one evaluation of the whole batch.
+// batch: the plans are grouped by geometry; each group runs each pass as one
+// launch over all its members (pointer lists), and the five launches of every
+// group are recorded once into a HIP graph, groups on forked capture streams
+// so that they overlap.  One replay of the graph evaluates the whole batch.
 namespace {
 constexpr int kBranches = 8;
+
+bool same_geometry(const demag_plan_s* a, const demag_plan_s* b) {
+    return a->dtype == b->dtype && a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] &&
+           a->d[0] == b->d[0] && a->d[1] == b->d[1] && a->d[2] == b->d[2] && a->bands.far_cut == b->bands.far_cut &&
+           a->bands.fg_cut == b->bands.fg_cut;
 }
+
+template <typename T>
+int enqueue_group(const BatchGroup& grp, double Ms, hipStream_t st) {
+    demag_plan_s* p = grp.lead;
+    const int n = grp.count;
+    void** L = grp.lists;  // device array: [0,n) m, [n,2n) H, [2n,3n) B1, [3n,4n) B2
+    BatchIO io[5];
+    io[0].in = (const void* const*)(L);
+    io[0].out = L + 2 * n;
+    io[1].in = (const void* const*)(L + 2 * n);
+    io[1].out = L + 3 * n;
+    io[2].in = (const void* const*)(L + 3 * n);
+    io[2].out = L + 3 * n;
+    io[3].in = (const void* const*)(L + 3 * n);
+    io[3].out = L + 2 * n;
+    io[4].in = (const void* const*)(L + 2 * n);
+    io[4].out = L + n;
+    for (int w = 0; w < 5; ++w) {
+        io[w].count = n;
+        HIP_TRY(launch_pass<T>(p, w, pass_cfg(p->cfg, w), st, nullptr, Ms, nullptr, nullptr, nullptr, 0, io[w]));
+    }
+    return DEMAG_OK;
+}
+}  // namespace
 
 extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans, int count, const void* const* m,
                                   void* const* H, double Ms, void* stream) {
@@ -837,10 +1038,43 @@ extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans,
     HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
     auto* b = new demag_batch_s();
     b->plans.assign(plans, plans + count);
+    // group by geometry, members in batch order
+    std::vector<std::vector<int>> members;
+    for (int i = 0; i < count; ++i) {
+        size_t gi = 0;
+        while (gi < members.size() && !same_geometry(plans[members[gi][0]], plans[i])) ++gi;
+        if (gi == members.size()) members.emplace_back();
+        members[gi].push_back(i);
+    }
+    std::vector<void*> host_lists;
+    for (auto& mem : members) {
+        const int n = (int)mem.size();
+        for (int k = 0; k < n; ++k) host_lists.push_back(const_cast<void*>(m[mem[k]]));
+        for (int k = 0; k < n; ++k) host_lists.push_back(H[mem[k]]);
+        for (int k = 0; k < n; ++k) host_lists.push_back(plans[mem[k]]->B1);
+        for (int k = 0; k < n; ++k) host_lists.push_back(plans[mem[k]]->B2);
+    }
+    int rc = DEMAG_OK;
+    if (hipMalloc(&b->dev_lists, host_lists.size() * sizeof(void*)) != hipSuccess) {
+        (void)hipGetLastError();
+        b->dev_lists = nullptr;
+        rc = fail(DEMAG_ENOMEM, "cannot allocate batch pointer lists");
+    } else if (hipMemcpy(b->dev_lists, host_lists.data(), host_lists.size() * sizeof(void*), hipMemcpyHostToDevice) !=
+               hipSuccess) {
+        rc = fail(DEMAG_EHIP, "cannot upload batch pointer lists");
+    }
+    size_t off = 0;
+    for (auto& mem : members) {
+        BatchGroup g;
+        g.lead = plans[mem[0]];
+        g.count = (int)mem.size();
+        g.lists = (void**)b->dev_lists + off;
+        off += 4 * (size_t)g.count;
+        b->groups.push_back(g);
+    }
+    const int nb = std::min<int>(kBranches, (int)b->groups.size());
     hipStream_t cs[kBranches] = {};
     hipEvent_t ev[kBranches + 1] = {};
-    const int nb = std::min(kBranches, count);
-    int rc = DEMAG_OK;
     for (int k = 0; k < nb && !rc; ++k)
         if (hipStreamCreateWithFlags(&cs[k], hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess)
@@ -857,11 +1091,10 @@ extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans,
     if (!rc) {
         hipEventRecord(ev[kBranches], cs[0]);
         for (int k = 1; k < nb; ++k) hipStreamWaitEvent(cs[k], ev[kBranches], 0);
-        for (int i = 0; i < count && !rc; ++i) {
-            demag_plan_s* p = plans[i];
-            p->capturing = true;
-            rc = dispatch_field(p, m[i], Ms, H[i], nullptr, 0, cs[i % nb]);
-            p->capturing = false;
+        for (size_t gi = 0; gi < b->groups.size() && !rc; ++gi) {
+            const BatchGroup& g = b->groups[gi];
+            rc = g.lead->dtype == DEMAG_F32 ? enqueue_group<float>(g, Ms, cs[gi % nb])
+                                            : enqueue_group<double>(g, Ms, cs[gi % nb]);
         }
         for (int k = 1; k < nb; ++k) {
             hipEventRecord(ev[k], cs[k]);
@@ -884,6 +1117,7 @@ extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans,
     if (rc) {
         if (b->exec) hipGraphExecDestroy(b->exec);
         if (b->graph) hipGraphDestroy(b->graph);
+        hipFree(b->dev_lists);
         delete b;
         return rc;
     }
@@ -911,6 +1145,7 @@ extern "C" int demag_batch_destroy(demag_batch_t b) {
     hipDeviceSynchronize();
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
+    hipFree(b->dev_lists);
     delete b;
     return DEMAG_OK;
 }

@@ -87,6 +87,12 @@ class Plan:
         _lib.call("demag_plan_pass_times", self._h, ms, ctypes.byref(n))
         return {k: ms[i] for i, k in enumerate(self.PASSES)}, int(n.value)
 
+    def describe(self) -> str:
+        """Launch shape of every pass."""
+        buf = ctypes.create_string_buffer(1024)
+        _lib.call("demag_plan_describe", self._h, buf, 1024)
+        return buf.value.decode()
+
     def autotune(self):
         _lib.call("demag_autotune", self._h, _stream_ptr())
 

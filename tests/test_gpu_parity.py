@@ -62,6 +62,11 @@ SHAPES = [
     ((33, 20, 9), (2.5e-9, 2.5e-9, 2.5e-9), 8e5),  # padded 72 (8*9) ragged tiles
     ((48, 12, 6), (2e-9, 2e-9, 2e-9), 8e5),        # 96 = 8*4*3
     ((70, 9, 2), (2e-9, 3e-9, 1e-9), 8e5),         # far band reached along x
+    ((64, 32, 8), (2e-9, 2e-9, 3e-9), 1.4e6),      # power-of-two padded lengths 128, 64, 16
+    ((16, 128, 32), (2.5e-9, 2.5e-9, 2.5e-9), 8e5),  # 32, 256, 64
+    ((4, 4, 64), (1.95e-9, 1.95e-9, 0.75e-9), 8e5),  # 8, 8, 128: thin pencils in x and y
+    ((2, 3, 4), (2e-9, 2e-9, 2e-9), 8e5),          # 4, 6 (generic), 8
+    ((29, 61, 11), (2e-9, 2e-9, 3e-9), 1.4e6),     # 64 (p2, 29 valid), 128 (p2, 61 valid), 24: ragged tiles
 ]
 
 
@@ -76,6 +81,22 @@ def test_field_random_vs_oracle(shape, cell, Ms, dtype):
     err = rel_err(H, ref)
     print(f"shape={shape} dtype={dtype} rel_err={err:.3e}")
     assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+
+
+@pytest.mark.parametrize("shape,cell,Ms", [((64, 32, 8), (2e-9, 2e-9, 3e-9), 1.4e6),
+                                            ((29, 61, 11), (2e-9, 2e-9, 3e-9), 1.4e6)], ids=str)
+def test_generic_and_pow2_kernels_agree(shape, cell, Ms):
+    """Both kernel families on one plan: each within the bar of the oracle."""
+    from paper_1204_4302_amd import Plan
+    o = get_oracle(shape, cell)
+    m = inputs.random_unit(shape, 4)
+    ref = o.field(m, Ms)
+    for generic in (1, 0):
+        plan = Plan(shape, cell, torch.float64)
+        plan.set_option("generic_kernels", generic)
+        H = plan.field(to_gpu(m, torch.float64), Ms).cpu().numpy()
+        assert rel_err(H, ref) <= FP64_TOL
+        plan.close()
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
