@@ -346,7 +346,7 @@ def traffic_summary(fetch_dir, write_dir, out_path, command):
         if f_fetch and f_write:
             scaled = (fv * f_fetch + wv * f_write) * 1024.0
         lines.append(f"{k[:90]}  {fv:.1f}  {wv:.1f}  {scaled}")
-        if "kz_conv" in k and "IfLi128" in k:
+        if "kz_conv" in k and "IfLi" in k:
             zconv = scaled
     if zconv is not None:
         lines.append(f"traffic_bytes_per_launch = {zconv}")

@@ -40,6 +40,12 @@ struct Fft {
     __host__ __device__ static constexpr int radix(int s) { return s < N8 ? 8 : RLAST; }
     __host__ __device__ static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * radix(s - 1); }
     __host__ __device__ static constexpr int pad(int i) { return i + (i >> 3); }
+    // pad(a + c) from pt = pad(a): exact when c is a multiple of 8, or when a
+    // is and 0 <= c < 8 (no carry out of the low three bits); c is a
+    // compile-time constant after unrolling, so the test folds away.
+    __host__ __device__ static constexpr int pad_add(int pt, int a, int c) {
+        return (c & 7) == 0 ? pt + c + (c >> 3) : pad(a + c);
+    }
     static constexpr int PS = pad(P) + 1;  // LDS slab stride of one pencil (elements)
     // slot j = i * R + r of a radix-R stage holds element t + i TP + r (P/R)
     __host__ __device__ static constexpr int slot_k(int j, int R) { return j / R + (j % R) * (EPT / R); }
@@ -121,15 +127,19 @@ __device__ __forceinline__ void stages_from(cx<T>* v, cx<T>* slab, int t, const 
         for (int i = 0; i < NB; ++i) {
             const int b = t + i * F::TP;
             const int k = b & (NS - 1);
+            // base = (b - k) R + k is a multiple of 8 when NS = 1 (R = 8 there),
+            // and r NS is one when NS >= 8: pad(base + r NS) = pad(base) + r NS (9/8)
+            const int pb = F::pad((b - k) * R + k);
 #pragma unroll
-            for (int r = 0; r < R; ++r) slab[F::pad((b - k) * R + k + r * NS)] = v[i * R + r];
+            for (int r = 0; r < R; ++r) slab[pb + r * NS + ((r * NS) >> 3)] = v[i * R + r];
         }
         pencil_sync<F::TP>();
         constexpr int R2 = F::radix(S + 1), NB2 = F::EPT / R2;
+        const int pt = F::pad(t);
 #pragma unroll
         for (int i = 0; i < NB2; ++i)
 #pragma unroll
-            for (int r = 0; r < R2; ++r) v[i * R2 + r] = slab[F::pad(t + i * F::TP + r * (P / R2))];
+            for (int r = 0; r < R2; ++r) v[i * R2 + r] = slab[F::pad_add(pt, t, i * F::TP + r * (P / R2))];
         stages_from<P, S + 1, DIR>(v, slab, t, tws);
     }
 }

@@ -58,9 +58,34 @@ __host__ __device__ constexpr int out_slot_for_in(int j) {
     return -1;
 }
 
+// Global-memory views of pointers (per-grid pointers of a batch are read from
+// memory, where the compiler could not tell their address space).
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(T* p) { return (gptr<T>)p; }
+
+// complex element access through global pointers as one 2-wide vector
+template <typename T>
+struct vec2 {
+    typedef T type __attribute__((ext_vector_type(2)));
+};
+template <typename T>
+__device__ __forceinline__ cx<T> gld(gptr<const cx<T>> p, size_t i) {
+    const typename vec2<T>::type v = ((gptr<const typename vec2<T>::type>)p)[i];
+    return mk(v.x, v.y);
+}
+template <typename T>
+__device__ __forceinline__ void gst(gptr<cx<T>> p, size_t i, cx<T> c) {
+    typename vec2<T>::type v;
+    v.x = c.re;
+    v.y = c.im;
+    ((gptr<typename vec2<T>::type>)p)[i] = v;
+}
+
 // ---------------------------------------------------------------------------
-// X forward (R2C of two rows per complex pencil).  grid (ceil(ny/Ty), nz, C),
-// block (Ty/2) * TP threads.
+// X forward (R2C of two rows per complex pencil).  1-D grid of
+// ceil(ny/Ty) * nz * C (* batch) tiles, block (Ty/2) * TP threads.
 template <typename T, int P>
 __global__ void __launch_bounds__(1024) kx_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, int nx, int ny,
                                                int nz, int lgTy, int nxcd, const cx<T>* __restrict__ tw,
@@ -80,8 +105,9 @@ __global__ void __launch_bounds__(1024) kx_fwd(const T* __restrict__ in, cx<T>* 
     }
     const int y0 = yt << lgTy, z = zc % nz, c = zc / nz;
     const int ty = min(Ty, ny - y0);
-    const T* src = in + (((size_t)c * nz + z) * ny + y0) * (size_t)nx;
+    const gptr<const T> src = gmem(in + (((size_t)c * nz + z) * ny + y0) * (size_t)nx);
     const bool ok0 = 2 * p < ty, ok1 = 2 * p + 1 < ty;
+    const gptr<const T> row0 = src + (size_t)(2 * p) * nx, row1 = row0 + nx;
     cx<T> v[F::EPT];
 #pragma unroll
     for (int j = 0; j < F::EPT; ++j) {
@@ -89,26 +115,54 @@ __global__ void __launch_bounds__(1024) kx_fwd(const T* __restrict__ in, cx<T>* 
         const int x = t + k * F::TP;
         T a = T(0), b = T(0);
         if (k < F::EPT / 2 && x < nx) {  // the padded half is never read
-            if (ok0) a = src[(size_t)(2 * p) * nx + x];
-            if (ok1) b = src[(size_t)(2 * p + 1) * nx + x];
+            if (ok0) a = row0[x];
+            if (ok1) b = row1[x];
         }
         v[j] = mk(a, b);
     }
     cx<T>* slab = lds + p * F::PS;
     p2::fft<P, -1>(v, slab, t, tw);
     __syncthreads();
+    const int pt = F::pad(t);
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) slab[F::pad(t + F::slot_out(j) * F::TP)] = v[j];
+    for (int j = 0; j < F::EPT; ++j) slab[F::pad_add(pt, t, F::slot_out(j) * F::TP)] = v[j];
     __syncthreads();
-    cx<T>* dst = out + ((size_t)c * nz + z) * (size_t)Kx * ny + y0;
-    for (int e = tid; e < (Kx << lgTy); e += nthr) {
-        const int y = e & (Ty - 1), k = e >> lgTy;
+    // spectra of the two rows: X_even = (Z_k + conj Z_{P-k})/2, X_odd = (Z_k - conj Z_{P-k})/(2i),
+    // written y-contiguous
+    const gptr<cx<T>> dst = gmem(out + ((size_t)c * nz + z) * (size_t)Kx * ny + y0);
+    if constexpr (F::TP >= 2) {
+        // nthr = (Ty/2) TP is a multiple of Ty: each thread keeps one row y
+        constexpr int KS = F::TP / 2, KN = (Kx + KS - 1) / KS;
+        const int y = tid & (Ty - 1), k0 = tid >> lgTy;
         if (y < ty) {
             const cx<T>* pen = lds + (y >> 1) * F::PS;
-            const cx<T> a = pen[F::pad(k)], b = pen[F::pad((P - k) & (P - 1))];
-            const cx<T> r = (y & 1) ? mk(T(0.5) * (a.im + b.im), T(0.5) * (b.re - a.re))
-                                    : mk(T(0.5) * (a.re + b.re), T(0.5) * (a.im - b.im));
-            dst[(size_t)k * ny + y] = r;
+            cx<T> r[KN];
+#pragma unroll
+            for (int i = 0; i < KN; ++i) {
+                const int k = k0 + i * KS;
+                if (k < Kx) {
+                    const cx<T> a = pen[F::pad(k)], b = pen[F::pad((P - k) & (P - 1))];
+                    r[i] = (y & 1) ? mk(T(0.5) * (a.im + b.im), T(0.5) * (b.re - a.re))
+                                   : mk(T(0.5) * (a.re + b.re), T(0.5) * (a.im - b.im));
+                }
+            }
+            const gptr<cx<T>> dy = dst + y;
+#pragma unroll
+            for (int i = 0; i < KN; ++i) {
+                const int k = k0 + i * KS;
+                if (k < Kx) gst(dy, k * ny, r[i]);
+            }
+        }
+    } else {
+        for (int e = tid; e < (Kx << lgTy); e += nthr) {
+            const int y = e & (Ty - 1), k = e >> lgTy;
+            if (y < ty) {
+                const cx<T>* pen = lds + (y >> 1) * F::PS;
+                const cx<T> a = pen[F::pad(k)], b = pen[F::pad((P - k) & (P - 1))];
+                gst(dst, (size_t)k * ny + y,
+                    (y & 1) ? mk(T(0.5) * (a.im + b.im), T(0.5) * (b.re - a.re))
+                            : mk(T(0.5) * (a.re + b.re), T(0.5) * (a.im - b.im)));
+            }
         }
     }
 }
@@ -139,28 +193,45 @@ __global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* 
     }
     const int y0 = yt << lgTy, z = zc % nz, c = zc / nz;
     const int ty = min(Ty, ny - y0);
-    const cx<T>* src = in + ((size_t)c * nz + z) * (size_t)Kx * ny + y0;
-    for (int e = tid; e < (Kx << lgB); e += nthr) {
-        const int q = e & (Bp - 1), k = e >> lgB;
-        cx<T> xe = 2 * q < ty ? src[(size_t)k * ny + 2 * q] : czero<T>();
-        cx<T> xo = 2 * q + 1 < ty ? src[(size_t)k * ny + 2 * q + 1] : czero<T>();
-        if (k == 0 || k == Lx) {  // C2R ignores the imaginary parts of DC and Nyquist
-            xe.im = T(0);
-            xo.im = T(0);
+    // pair q = tid mod Bp, frequencies k = tid / Bp + i TP: every load of the
+    // thread is issued before the first LDS write
+    {
+        constexpr int KI = (Kx + F::TP - 1) / F::TP;
+        const int q = tid & (Bp - 1), k0 = tid >> lgB;
+        const bool okq0 = 2 * q < ty, okq1 = 2 * q + 1 < ty;
+        const gptr<const cx<T>> src = gmem(in + ((size_t)c * nz + z) * (size_t)Kx * ny + y0 + 2 * q);
+        cx<T> xe[KI], xo[KI];
+#pragma unroll
+        for (int i = 0; i < KI; ++i) {
+            const int k = k0 + i * F::TP;
+            xe[i] = (k < Kx && okq0) ? gld(src, k * ny) : czero<T>();
+            xo[i] = (k < Kx && okq1) ? gld(src, k * ny + 1) : czero<T>();
         }
-        cx<T>* pen = lds + q * F::PS;
-        pen[F::pad(k)] = mk(xe.re - xo.im, xe.im + xo.re);                           // xe + i xo
-        if (k > 0 && k < Lx) pen[F::pad(P - k)] = mk(xe.re + xo.im, xo.re - xe.im);  // conj(xe) + i conj(xo)
+        cx<T>* pq = lds + q * F::PS;
+#pragma unroll
+        for (int i = 0; i < KI; ++i) {
+            const int k = k0 + i * F::TP;
+            if (k < Kx) {
+                cx<T> a = xe[i], b = xo[i];
+                if (k == 0 || k == Lx) {  // C2R ignores the imaginary parts of DC and Nyquist
+                    a.im = T(0);
+                    b.im = T(0);
+                }
+                pq[F::pad(k)] = mk(a.re - b.im, a.im + b.re);                           // xe + i xo
+                if (k > 0 && k < Lx) pq[F::pad(P - k)] = mk(a.re + b.im, b.re - a.im);  // conj(xe) + i conj(xo)
+            }
+        }
     }
     __syncthreads();
     cx<T>* slab = lds + p * F::PS;
     cx<T> v[F::EPT];
+    const int pt = F::pad(t);
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) v[j] = slab[F::pad(t + F::slot_in(j) * F::TP)];
+    for (int j = 0; j < F::EPT; ++j) v[j] = slab[F::pad_add(pt, t, F::slot_in(j) * F::TP)];
     p2::fft<P, +1>(v, slab, t, tw);
-    const size_t rowbase = (((size_t)c * nz + z) * ny + y0) * (size_t)nx;
-    T* dst = out ? out + rowbase : nullptr;
-    const T* msrc = m ? m + rowbase : nullptr;
+    const size_t rowbase = (((size_t)c * nz + z) * ny + y0 + 2 * p) * (size_t)nx;
+    const gptr<T> dst = out ? gmem(out + rowbase) : nullptr;
+    const gptr<const T> msrc = m ? gmem(m + rowbase) : nullptr;
     const bool ok0 = 2 * p < ty, ok1 = 2 * p + 1 < ty;
     double acc = 0.0;
 #pragma unroll
@@ -168,16 +239,15 @@ __global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* 
         const int k = F::slot_out(j);
         const int x = t + k * F::TP;
         if (k < F::EPT / 2 && x < nx) {  // the discarded half is never written
-            const size_t i0 = (size_t)(2 * p) * nx + x, i1 = i0 + nx;
             if (ok0) {
                 const T h = v[j].re;
-                if (msrc) acc += (double)(msrc[i0] * h);
-                if (dst) dst[i0] = accumulate ? dst[i0] + h : h;
+                if (msrc) acc += (double)(msrc[x] * h);
+                if (dst) dst[x] = accumulate ? dst[x] + h : h;
             }
             if (ok1) {
                 const T h = v[j].im;
-                if (msrc) acc += (double)(msrc[i1] * h);
-                if (dst) dst[i1] = accumulate ? dst[i1] + h : h;
+                if (msrc) acc += (double)(msrc[x + nx] * h);
+                if (dst) dst[x + nx] = accumulate ? dst[x + nx] + h : h;
             }
         }
     }
@@ -186,23 +256,23 @@ __global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* 
         if ((tid & 63) == 0) red[tid >> 6] = acc;
         __syncthreads();
         if (tid == 0) {
-            double s = 0.0;
-            for (int w = 0; w < (nthr + 63) / 64; ++w) s += red[w];
-            partials[L] = s;
+            double sum = 0.0;
+            for (int w = 0; w < (nthr + 63) / 64; ++w) sum += red[w];
+            partials[L] = sum;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Y forward.  Tile Tz x Tx pencils (z, kx); pencil p = zi * Tx + xi.
-// grid (ceil(Kx/Tx), ceil(nz/Tz), C), block Tz * Tx * TP.
+// 1-D grid of ceil(nz/Tz) * ceil(Kx/Tx) * C tiles, block Tz * Tx * TP.
 template <typename T, int P>
 __global__ void __launch_bounds__(1024) ky_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
                                                int nz, int Kx, int lgTz, int lgTx, int nxcd,
                                                const cx<T>* __restrict__ tw, BatchIO bio) {
     using F = p2::Fft<P>;
     cx<T>* lds = lds_base<T>();
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x;
     const int p = tid >> F::LOG_TP, t = tid & (F::TP - 1);
     const int Tx = 1 << lgTx, Tz = 1 << lgTz;
     const int nzt = (nz + Tz - 1) >> lgTz, nxt = (Kx + Tx - 1) >> lgTx;
@@ -216,26 +286,34 @@ __global__ void __launch_bounds__(1024) ky_fwd(const cx<T>* __restrict__ in, cx<
     const int tx = min(Tx, Kx - kx0), tz = min(Tz, nz - z0);
     const int xi = p & (Tx - 1), zi = p >> lgTx;
     const bool ok = xi < tx && zi < tz;
-    const cx<T>* src = in + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny;
+    const gptr<const cx<T>> src = gmem(in + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny);
     cx<T> v[F::EPT];
 #pragma unroll
     for (int j = 0; j < F::EPT; ++j) {
         const int k = F::slot_in(j);
         const int y = t + k * F::TP;
-        v[j] = (k < F::EPT / 2 && ok && y < ny) ? src[y] : czero<T>();
+        v[j] = (k < F::EPT / 2 && ok && y < ny) ? gld(src, y) : czero<T>();
     }
     cx<T>* slab = lds + p * F::PS;
     p2::fft<P, -1>(v, slab, t, tw);
     __syncthreads();
+    const int pt = F::pad(t);
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) slab[F::pad(t + F::slot_out(j) * F::TP)] = v[j];
+    for (int j = 0; j < F::EPT; ++j) slab[F::pad_add(pt, t, F::slot_out(j) * F::TP)] = v[j];
     __syncthreads();
+    // (zj, xj) = tid mod (Tz Tx), ky = tid / (Tz Tx) + i TP; z-contiguous runs
     const int lgB = lgTz + lgTx;
-    for (int e = tid; e < (P << lgB); e += nthr) {
-        const int zj = e & (Tz - 1), xj = (e >> lgTz) & (Tx - 1), ky = e >> lgB;
-        if (zj < tz && xj < tx)
-            out[(((size_t)c * P + ky) * Kx + kx0 + xj) * (size_t)nz + z0 + zj] =
-                lds[((zj << lgTx) + xj) * F::PS + F::pad(ky)];
+    const int zj = tid & (Tz - 1), xj = (tid >> lgTz) & (Tx - 1), ky0 = tid >> lgB;
+    if (zj < tz && xj < tx) {
+        const cx<T>* pj = lds + ((zj << lgTx) + xj) * F::PS;
+        const int pk = F::pad(ky0);
+        cx<T> r[F::EPT];
+#pragma unroll
+        for (int i = 0; i < F::EPT; ++i) r[i] = pj[F::pad_add(pk, ky0, i * F::TP)];
+        const gptr<cx<T>> dst = gmem(out + (((size_t)c * P + ky0) * Kx + kx0 + xj) * (size_t)nz + z0 + zj);
+        const size_t step = (size_t)F::TP * Kx * nz;
+#pragma unroll
+        for (int i = 0; i < F::EPT; ++i) gst(dst, i * step, r[i]);
     }
 }
 
@@ -247,7 +325,7 @@ __global__ void __launch_bounds__(1024) ky_inv(const cx<T>* __restrict__ in, cx<
                                                const cx<T>* __restrict__ tw, BatchIO bio) {
     using F = p2::Fft<P>;
     cx<T>* lds = lds_base<T>();
-    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tid = threadIdx.x;
     const int p = tid >> F::LOG_TP, t = tid & (F::TP - 1);
     const int Tx = 1 << lgTx, Tz = 1 << lgTz;
     const int nzt = (nz + Tz - 1) >> lgTz, nxt = (Kx + Tx - 1) >> lgTx;
@@ -260,25 +338,37 @@ __global__ void __launch_bounds__(1024) ky_inv(const cx<T>* __restrict__ in, cx<
     const int kx0 = (xc % nxt) << lgTx, z0 = zt << lgTz, c = xc / nxt;
     const int tx = min(Tx, Kx - kx0), tz = min(Tz, nz - z0);
     const int lgB = lgTz + lgTx;
-    for (int e = tid; e < (P << lgB); e += nthr) {
-        const int zj = e & (Tz - 1), xj = (e >> lgTz) & (Tx - 1), ky = e >> lgB;
-        lds[((zj << lgTx) + xj) * F::PS + F::pad(ky)] =
-            (zj < tz && xj < tx) ? in[(((size_t)c * P + ky) * Kx + kx0 + xj) * (size_t)nz + z0 + zj] : czero<T>();
+    {
+        // (zj, xj) = tid mod (Tz Tx), ky = tid / (Tz Tx) + i TP: all EPT loads of
+        // the thread are issued before its LDS writes
+        const int zj = tid & (Tz - 1), xj = (tid >> lgTz) & (Tx - 1), ky0 = tid >> lgB;
+        const bool okj = zj < tz && xj < tx;
+        const gptr<const cx<T>> src =
+            gmem(in + (((size_t)c * P + ky0) * Kx + kx0 + xj) * (size_t)nz + z0 + zj);
+        const size_t step = (size_t)F::TP * Kx * nz;
+        cx<T> ld[F::EPT];
+#pragma unroll
+        for (int i = 0; i < F::EPT; ++i) ld[i] = okj ? gld(src, i * step) : czero<T>();
+        cx<T>* pj = lds + ((zj << lgTx) + xj) * F::PS;
+        const int pk = F::pad(ky0);
+#pragma unroll
+        for (int i = 0; i < F::EPT; ++i) pj[F::pad_add(pk, ky0, i * F::TP)] = ld[i];
     }
     __syncthreads();
     cx<T>* slab = lds + p * F::PS;
     cx<T> v[F::EPT];
+    const int pt = F::pad(t);
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) v[j] = slab[F::pad(t + F::slot_in(j) * F::TP)];
+    for (int j = 0; j < F::EPT; ++j) v[j] = slab[F::pad_add(pt, t, F::slot_in(j) * F::TP)];
     p2::fft<P, +1>(v, slab, t, tw);
     const int xi = p & (Tx - 1), zi = p >> lgTx;
     if (xi < tx && zi < tz) {
-        cx<T>* dst = out + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny;
+        const gptr<cx<T>> dst = gmem(out + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny);
 #pragma unroll
         for (int j = 0; j < F::EPT; ++j) {
             const int k = F::slot_out(j);
             const int y = t + k * F::TP;
-            if (k < F::EPT / 2 && y < ny) dst[y] = v[j];
+            if (k < F::EPT / 2 && y < ny) gst(dst, y, v[j]);
         }
     }
 }
@@ -288,7 +378,7 @@ __global__ void __launch_bounds__(1024) ky_inv(const cx<T>* __restrict__ in, cx<
 // at (kx0 + xi, ky_s), ky_0 = ky', ky_1 = Py - ky'; each thread keeps all
 // three components in registers, so the tensor product needs no exchange and
 // the forward output slots are the inverse input slots.
-// grid (ceil(Kx/Tx), Py/2 + 1), block 2 * Tx * TP.
+// 1-D grid of ceil(Kx/Tx) * (Py/2 + 1) tiles, block 2 * Tx * TP.
 template <typename T, int P>
 __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2, const T* __restrict__ nhat, T Ms, int nz,
                                                 int Py, int Kx, int lgTx, int nxcd, const cx<T>* __restrict__ tw,
@@ -309,15 +399,16 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     const int ns = (kyp == 0 || kyp == Ly) ? 1 : 2;
     const bool ok = s < ns && xi < tx;
     const int ky = s ? Py - kyp : kyp;
+    const gptr<cx<T>> base = gmem(B2 + ((size_t)ky * Kx + kx0 + xi) * (size_t)nz);
+    const size_t cstride = (size_t)Py * Kx * nz;  // component stride of B2
     cx<T> v[3][F::EPT];
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
-        const cx<T>* src = B2 + (((size_t)comp * Py + ky) * Kx + kx0 + xi) * (size_t)nz;
 #pragma unroll
         for (int j = 0; j < F::EPT; ++j) {
             const int k = F::slot_in(j);
             const int zz = t + k * F::TP;
-            v[comp][j] = (k < F::EPT / 2 && ok && zz < nz) ? src[zz] : czero<T>();
+            v[comp][j] = (k < F::EPT / 2 && ok && zz < nz) ? gld<T>(base, comp * cstride + zz) : czero<T>();
         }
     }
     cx<T>* slab = lds + g * F::PS;
@@ -327,7 +418,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     for (int comp = 0; comp < 3; ++comp) p2::fft<P, -1>(v[comp], slab, t, tws);
     // H^ = Ms * Nhat(kx, ky, kz) M^ ; octant lookup with parity signs
     const size_t cs = (size_t)Kx * (Lz + 1);
-    const T* nh0 = nhat + ((size_t)kyp * 6 * Kx + kx0 + xi) * (Lz + 1);
+    const gptr<const T> nh0 = gmem(nhat + ((size_t)kyp * 6 * Kx + kx0 + xi) * (Lz + 1));
     const T sy = s ? T(-1) : T(1);
 #pragma unroll
     for (int j = 0; j < F::EPT; ++j) {
@@ -336,18 +427,18 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         const T sz = kz > Lz ? T(-1) : T(1);
         T nxx = T(0), nyy = T(0), nzz = T(0), nxy = T(0), nxz = T(0), nyz = T(0);
         if (ok) {
-            const T* nh = nh0 + kzp;
-            nxx = nh[0];
-            nyy = nh[cs];
-            nzz = nh[2 * cs];
-            nxy = sy * nh[3 * cs];
-            nxz = sz * nh[4 * cs];
-            nyz = sy * sz * nh[5 * cs];
+            const gptr<const T> nh = nh0 + kzp;
+            nxx = Ms * nh[0];
+            nyy = Ms * nh[cs];
+            nzz = Ms * nh[2 * cs];
+            nxy = Ms * sy * nh[3 * cs];
+            nxz = Ms * sz * nh[4 * cs];
+            nyz = Ms * sy * sz * nh[5 * cs];
         }
         const cx<T> mx = v[0][j], my = v[1][j], mz = v[2][j];
-        v[0][j] = mk(Ms * (nxx * mx.re + nxy * my.re + nxz * mz.re), Ms * (nxx * mx.im + nxy * my.im + nxz * mz.im));
-        v[1][j] = mk(Ms * (nxy * mx.re + nyy * my.re + nyz * mz.re), Ms * (nxy * mx.im + nyy * my.im + nyz * mz.im));
-        v[2][j] = mk(Ms * (nxz * mx.re + nyz * my.re + nzz * mz.re), Ms * (nxz * mx.im + nyz * my.im + nzz * mz.im));
+        v[0][j] = mk(nxx * mx.re + nxy * my.re + nxz * mz.re, nxx * mx.im + nxy * my.im + nxz * mz.im);
+        v[1][j] = mk(nxy * mx.re + nyy * my.re + nyz * mz.re, nxy * mx.im + nyy * my.im + nyz * mz.im);
+        v[2][j] = mk(nxz * mx.re + nyz * my.re + nzz * mz.re, nxz * mx.im + nyz * my.im + nzz * mz.im);
     }
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
@@ -356,12 +447,11 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         for (int j = 0; j < F::EPT; ++j) w[j] = v[comp][out_slot_for_in<P>(j)];
         p2::fft<P, +1>(w, slab, t, tws);
         if (ok) {
-            cx<T>* dst = B2 + (((size_t)comp * Py + ky) * Kx + kx0 + xi) * (size_t)nz;
 #pragma unroll
             for (int j = 0; j < F::EPT; ++j) {
                 const int k = F::slot_out(j);
                 const int zz = t + k * F::TP;
-                if (k < F::EPT / 2 && zz < nz) dst[zz] = w[j];
+                if (k < F::EPT / 2 && zz < nz) gst(base, comp * cstride + zz, w[j]);
             }
         }
     }
@@ -369,6 +459,13 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
 
 template <int P>
 constexpr int tpp() { return p2::Fft<P>::TP; }
+
+// Dynamic LDS above 64 KB must be allowed per kernel before its launch.
+template <typename K>
+hipError_t allow_lds(K kernel, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
 
 
 }  // namespace
@@ -405,6 +502,7 @@ hipError_t launch_x_fwd_p2(int lgTy, hipStream_t st, const T* in, cx<T>* out, in
     dim3 grid((unsigned)(((ny + (1 << lgTy) - 1) >> lgTy) * nz * C * bio.count));
     const size_t lds = (size_t)Bp * p2_slab_elems(P) * sizeof(cx<T>);
 #define CALL(PP) \
+    if (hipError_t e_ = allow_lds(&kx_fwd<T, PP>, lds)) return e_; \
     hipLaunchKernelGGL((kx_fwd<T, PP>), grid, dim3(Bp * tpp<PP>()), lds, st, in, out, nx, ny, nz, lgTy, kXcds, tw, \
                        bio)
     DEMAG_P2_SWITCH(P, CALL)
@@ -419,6 +517,7 @@ hipError_t launch_x_inv_p2(int lgTy, hipStream_t st, const cx<T>* in, T* out, co
     dim3 grid((unsigned)(((ny + (1 << lgTy) - 1) >> lgTy) * nz * C * bio.count));
     const size_t lds = (size_t)Bp * p2_slab_elems(P) * sizeof(cx<T>);
 #define CALL(PP)                                                                                            \
+    if (hipError_t e_ = allow_lds(&kx_inv<T, PP>, lds)) return e_; \
     hipLaunchKernelGGL((kx_inv<T, PP>), grid, dim3(Bp * tpp<PP>()), lds, st, in, out, m, partials, nx, ny, nz, \
                        lgTy, accumulate, kXcds, tw, bio)
     DEMAG_P2_SWITCH(P, CALL)
@@ -433,6 +532,7 @@ hipError_t launch_y_fwd_p2(int lgTz, int lgTx, hipStream_t st, const cx<T>* in, 
     dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * ((nz + (1 << lgTz) - 1) >> lgTz) * C * bio.count));
     const size_t lds = (size_t)B * p2_slab_elems(P) * sizeof(cx<T>);
 #define CALL(PP) \
+    if (hipError_t e_ = allow_lds(&ky_fwd<T, PP>, lds)) return e_; \
     hipLaunchKernelGGL((ky_fwd<T, PP>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, tw, \
                        bio)
     DEMAG_P2_SWITCH(P, CALL)
@@ -447,6 +547,7 @@ hipError_t launch_y_inv_p2(int lgTz, int lgTx, hipStream_t st, const cx<T>* in, 
     dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * ((nz + (1 << lgTz) - 1) >> lgTz) * C * bio.count));
     const size_t lds = (size_t)B * p2_slab_elems(P) * sizeof(cx<T>);
 #define CALL(PP) \
+    if (hipError_t e_ = allow_lds(&ky_inv<T, PP>, lds)) return e_; \
     hipLaunchKernelGGL((ky_inv<T, PP>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, tw, \
                        bio)
     DEMAG_P2_SWITCH(P, CALL)
@@ -461,6 +562,7 @@ hipError_t launch_z_conv_p2(int lgTx, hipStream_t st, cx<T>* B2, const T* nhat, 
     dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * (Py / 2 + 1) * bio.count));
     const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>);
 #define CALL(PP) \
+    if (hipError_t e_ = allow_lds(&kz_conv<T, PP>, lds)) return e_; \
     hipLaunchKernelGGL((kz_conv<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, kXcds, tw, \
                        bio)
     DEMAG_P2_SWITCH(P, CALL)

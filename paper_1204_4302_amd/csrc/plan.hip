@@ -53,7 +53,8 @@ int hip_fail(hipError_t e, const char* what) {
 constexpr int kPassMarks = 7;  // before X, Y, Z, Y^-1, X^-1, energy; end
 constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846264338327950288;
 constexpr int kMaxLen = 4096;
-constexpr size_t kMaxLdsBytes = 65536;  // dynamic LDS per workgroup
+constexpr size_t kMaxLdsBytes = 65536;  // dynamic LDS per workgroup, generic kernels
+size_t g_p2_lds = 65536;                 // power-of-two kernels: the device's per-workgroup LDS (set per plan)
 
 // ---------------------------------------------------------------------------
 // lengths, radices, twiddles
@@ -242,18 +243,18 @@ LaunchCfg p2_rows(int P, int rows, size_t cbytes, int target = 512) {
     const int TP = p2_threads_per_pencil(P);
     int lgB = ilog2i(std::max(1, target / TP));
     lgB = std::min(lgB, std::max(0, pow2_ceil_log(rows) - 1));
-    while (lgB > 0 && ((size_t)p2_slab_elems(P) << lgB) * cbytes > kMaxLdsBytes - 256) --lgB;
+    while (lgB > 0 && ((size_t)p2_slab_elems(P) << lgB) * cbytes > g_p2_lds - 256) --lgB;
     c.t0 = lgB + 1;  // Ty = 2 * pencils
     c.threads = TP << lgB;
     return c;
 }
 
-LaunchCfg p2_pencils(int P, int Kx, int nz, size_t cbytes, int target = 512) {
+LaunchCfg p2_pencils(int P, int Kx, int nz, size_t cbytes, int target = 1024) {
     LaunchCfg c;
     c.p2 = 1;
     const int TP = p2_threads_per_pencil(P);
     int lgB = ilog2i(std::max(1, target / TP));
-    while (lgB > 0 && ((size_t)p2_slab_elems(P) << lgB) * cbytes > kMaxLdsBytes) --lgB;
+    while (lgB > 0 && ((size_t)p2_slab_elems(P) << lgB) * cbytes > g_p2_lds - 256) --lgB;
     int lgTz = std::min(lgB, pow2_ceil_log(nz));
     int lgTx = std::min(lgB - lgTz, pow2_ceil_log(Kx));
     c.t0 = lgTx;
@@ -262,13 +263,13 @@ LaunchCfg p2_pencils(int P, int Kx, int nz, size_t cbytes, int target = 512) {
     return c;
 }
 
-LaunchCfg p2_zconv(int P, int Kx, size_t cbytes, int target = 512) {
+LaunchCfg p2_zconv(int P, int Kx, size_t cbytes, int target = 128) {
     LaunchCfg c;
     c.p2 = 1;
     const int TP = p2_threads_per_pencil(P);
     int lgTx = std::max(0, ilog2i(std::max(1, target / (2 * TP))));
     lgTx = std::min(lgTx, pow2_ceil_log(Kx));
-    while (lgTx > 0 && ((size_t)p2_slab_elems(P) << (lgTx + 1)) * cbytes > kMaxLdsBytes) --lgTx;
+    while (lgTx > 0 && ((size_t)p2_slab_elems(P) << (lgTx + 1)) * cbytes > g_p2_lds - 256) --lgTx;
     while (lgTx > 0 && (2 * TP << lgTx) > kP2MaxThreadsZ) --lgTx;
     c.t0 = lgTx;
     c.threads = 2 * TP << lgTx;
@@ -283,7 +284,7 @@ bool p2_cfg_ok(const LaunchCfg& c, int P, size_t cbytes, int kind /*0 rows, 1 pe
     long threads = pencils * TP;
     long maxthr = kind == 2 ? kP2MaxThreadsZ : kP2MaxThreads;
     return threads == c.threads && threads <= maxthr &&
-           (size_t)pencils * p2_slab_elems(P) * cbytes <= kMaxLdsBytes - 256;  // + static reduction scratch
+           (size_t)pencils * p2_slab_elems(P) * cbytes <= g_p2_lds - 256;  // + static reduction scratch
 }
 
 bool cfg_ok(const LaunchCfg& c, long pencils, int P, size_t cbytes) {
@@ -578,6 +579,10 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
         delete p;
         return hip_fail(he, "hipGetDevice");
     }
+    int lds_max = 0;
+    if (hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) == hipSuccess &&
+        lds_max >= 65536)
+        g_p2_lds = std::min<size_t>((size_t)lds_max, 163840);
     hipStream_t st = (hipStream_t)setup_stream;
     const size_t cb = csize(dtype), rb = dtype == DEMAG_F32 ? 4 : 8;
     const size_t nB1 = 3ull * nz * Kx * ny, nB2 = 3ull * P[1] * Kx * nz;
