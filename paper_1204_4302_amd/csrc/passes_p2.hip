@@ -75,6 +75,20 @@ __device__ __forceinline__ cx<T> gld(gptr<const cx<T>> p, size_t i) {
     const typename vec2<T>::type v = ((gptr<const typename vec2<T>::type>)p)[i];
     return mk(v.x, v.y);
 }
+// Load p[i] if `valid`, else zero, without a branch: the load always goes to
+// p[valid ? i : 0] (callers guarantee p[0] is in bounds) and the value is
+// selected afterwards, so no exec-masked block forces an early wait.
+template <typename T>
+__device__ __forceinline__ cx<T> gld_if(gptr<const cx<T>> p, size_t i, bool valid) {
+    const cx<T> v = gld(p, valid ? i : 0);
+    return valid ? v : czero<T>();
+}
+template <typename T>
+__device__ __forceinline__ T gldr_if(gptr<const T> p, size_t i, bool valid) {
+    const T v = p[valid ? i : 0];
+    return valid ? v : T(0);
+}
+
 template <typename T>
 __device__ __forceinline__ void gst(gptr<cx<T>> p, size_t i, cx<T> c) {
     typename vec2<T>::type v;
@@ -105,20 +119,20 @@ __global__ void __launch_bounds__(1024) kx_fwd(const T* __restrict__ in, cx<T>* 
     }
     const int y0 = yt << lgTy, z = zc % nz, c = zc / nz;
     const int ty = min(Ty, ny - y0);
-    const gptr<const T> src = gmem(in + (((size_t)c * nz + z) * ny + y0) * (size_t)nx);
     const bool ok0 = 2 * p < ty, ok1 = 2 * p + 1 < ty;
-    const gptr<const T> row0 = src + (size_t)(2 * p) * nx, row1 = row0 + nx;
+    const T* rb = in + (((size_t)c * nz + z) * ny + y0) * (size_t)nx;
+    const gptr<const T> row0 = gmem(ok0 ? rb + (size_t)(2 * p) * nx : in);
+    const gptr<const T> row1 = gmem(ok1 ? rb + (size_t)(2 * p + 1) * nx : in);
     cx<T> v[F::EPT];
 #pragma unroll
     for (int j = 0; j < F::EPT; ++j) {
         const int k = F::slot_in(j);
         const int x = t + k * F::TP;
-        T a = T(0), b = T(0);
-        if (k < F::EPT / 2 && x < nx) {  // the padded half is never read
-            if (ok0) a = row0[x];
-            if (ok1) b = row1[x];
+        if (k < F::EPT / 2) {  // the padded half is never read
+            v[j] = mk(gldr_if(row0, x, ok0 && x < nx), gldr_if(row1, x, ok1 && x < nx));
+        } else {
+            v[j] = czero<T>();
         }
-        v[j] = mk(a, b);
     }
     cx<T>* slab = lds + p * F::PS;
     p2::fft<P, -1>(v, slab, t, tw);
@@ -199,13 +213,14 @@ __global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* 
         constexpr int KI = (Kx + F::TP - 1) / F::TP;
         const int q = tid & (Bp - 1), k0 = tid >> lgB;
         const bool okq0 = 2 * q < ty, okq1 = 2 * q + 1 < ty;
-        const gptr<const cx<T>> src = gmem(in + ((size_t)c * nz + z) * (size_t)Kx * ny + y0 + 2 * q);
+        const cx<T>* qb = in + ((size_t)c * nz + z) * (size_t)Kx * ny + y0 + 2 * q;
+        const gptr<const cx<T>> s0 = gmem(okq0 ? qb : in), s1 = gmem(okq1 ? qb + 1 : in);
         cx<T> xe[KI], xo[KI];
 #pragma unroll
         for (int i = 0; i < KI; ++i) {
             const int k = k0 + i * F::TP;
-            xe[i] = (k < Kx && okq0) ? gld(src, k * ny) : czero<T>();
-            xo[i] = (k < Kx && okq1) ? gld(src, k * ny + 1) : czero<T>();
+            xe[i] = gld_if(s0, (size_t)k * ny, k < Kx && okq0);
+            xo[i] = gld_if(s1, (size_t)k * ny, k < Kx && okq1);
         }
         cx<T>* pq = lds + q * F::PS;
 #pragma unroll
@@ -286,13 +301,13 @@ __global__ void __launch_bounds__(1024) ky_fwd(const cx<T>* __restrict__ in, cx<
     const int tx = min(Tx, Kx - kx0), tz = min(Tz, nz - z0);
     const int xi = p & (Tx - 1), zi = p >> lgTx;
     const bool ok = xi < tx && zi < tz;
-    const gptr<const cx<T>> src = gmem(in + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny);
+    const gptr<const cx<T>> src = gmem(ok ? in + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny : in);
     cx<T> v[F::EPT];
 #pragma unroll
     for (int j = 0; j < F::EPT; ++j) {
         const int k = F::slot_in(j);
         const int y = t + k * F::TP;
-        v[j] = (k < F::EPT / 2 && ok && y < ny) ? gld(src, y) : czero<T>();
+        v[j] = k < F::EPT / 2 ? gld_if(src, y, ok && y < ny) : czero<T>();
     }
     cx<T>* slab = lds + p * F::PS;
     p2::fft<P, -1>(v, slab, t, tw);
@@ -344,11 +359,11 @@ __global__ void __launch_bounds__(1024) ky_inv(const cx<T>* __restrict__ in, cx<
         const int zj = tid & (Tz - 1), xj = (tid >> lgTz) & (Tx - 1), ky0 = tid >> lgB;
         const bool okj = zj < tz && xj < tx;
         const gptr<const cx<T>> src =
-            gmem(in + (((size_t)c * P + ky0) * Kx + kx0 + xj) * (size_t)nz + z0 + zj);
+            gmem(okj ? in + (((size_t)c * P + ky0) * Kx + kx0 + xj) * (size_t)nz + z0 + zj : in);
         const size_t step = (size_t)F::TP * Kx * nz;
         cx<T> ld[F::EPT];
 #pragma unroll
-        for (int i = 0; i < F::EPT; ++i) ld[i] = okj ? gld(src, i * step) : czero<T>();
+        for (int i = 0; i < F::EPT; ++i) ld[i] = gld_if(src, i * step, okj);
         cx<T>* pj = lds + ((zj << lgTx) + xj) * F::PS;
         const int pk = F::pad(ky0);
 #pragma unroll
@@ -399,7 +414,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     const int ns = (kyp == 0 || kyp == Ly) ? 1 : 2;
     const bool ok = s < ns && xi < tx;
     const int ky = s ? Py - kyp : kyp;
-    const gptr<cx<T>> base = gmem(B2 + ((size_t)ky * Kx + kx0 + xi) * (size_t)nz);
+    const gptr<cx<T>> base = gmem(ok ? B2 + ((size_t)ky * Kx + kx0 + xi) * (size_t)nz : B2);
     const size_t cstride = (size_t)Py * Kx * nz;  // component stride of B2
     cx<T> v[3][F::EPT];
 #pragma unroll
@@ -408,8 +423,20 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         for (int j = 0; j < F::EPT; ++j) {
             const int k = F::slot_in(j);
             const int zz = t + k * F::TP;
-            v[comp][j] = (k < F::EPT / 2 && ok && zz < nz) ? gld<T>(base, comp * cstride + zz) : czero<T>();
+            v[comp][j] = k < F::EPT / 2 ? gld_if<T>(base, comp * cstride + zz, ok && zz < nz) : czero<T>();
         }
+    }
+    // the tensor values of all this thread's frequencies, loaded together with
+    // the data (before the transforms) so that their latency overlaps
+    const size_t cs = (size_t)Kx * (Lz + 1);
+    const gptr<const T> nh0 = gmem(ok ? nhat + ((size_t)kyp * 6 * Kx + kx0 + xi) * (Lz + 1) : nhat);
+    T nt[F::EPT][6];
+#pragma unroll
+    for (int j = 0; j < F::EPT; ++j) {
+        const int kz = t + F::slot_out(j) * F::TP;
+        const int kzp = kz <= Lz ? kz : P - kz;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) nt[j][q] = gldr_if(nh0, q * cs + kzp, ok);
     }
     cx<T>* slab = lds + g * F::PS;
     p2::Twiddles<P, T> tws;  // one load of this thread's twiddles for all six transforms
@@ -417,24 +444,13 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) p2::fft<P, -1>(v[comp], slab, t, tws);
     // H^ = Ms * Nhat(kx, ky, kz) M^ ; octant lookup with parity signs
-    const size_t cs = (size_t)Kx * (Lz + 1);
-    const gptr<const T> nh0 = gmem(nhat + ((size_t)kyp * 6 * Kx + kx0 + xi) * (Lz + 1));
     const T sy = s ? T(-1) : T(1);
 #pragma unroll
     for (int j = 0; j < F::EPT; ++j) {
         const int kz = t + F::slot_out(j) * F::TP;
-        const int kzp = kz <= Lz ? kz : P - kz;
         const T sz = kz > Lz ? T(-1) : T(1);
-        T nxx = T(0), nyy = T(0), nzz = T(0), nxy = T(0), nxz = T(0), nyz = T(0);
-        if (ok) {
-            const gptr<const T> nh = nh0 + kzp;
-            nxx = Ms * nh[0];
-            nyy = Ms * nh[cs];
-            nzz = Ms * nh[2 * cs];
-            nxy = Ms * sy * nh[3 * cs];
-            nxz = Ms * sz * nh[4 * cs];
-            nyz = Ms * sy * sz * nh[5 * cs];
-        }
+        const T nxx = Ms * nt[j][0], nyy = Ms * nt[j][1], nzz = Ms * nt[j][2];
+        const T nxy = Ms * sy * nt[j][3], nxz = Ms * sz * nt[j][4], nyz = Ms * sy * sz * nt[j][5];
         const cx<T> mx = v[0][j], my = v[1][j], mz = v[2][j];
         v[0][j] = mk(nxx * mx.re + nxy * my.re + nxz * mz.re, nxx * mx.im + nxy * my.im + nxz * mz.im);
         v[1][j] = mk(nxy * mx.re + nyy * my.re + nyz * mz.re, nxy * mx.im + nyy * my.im + nyz * mz.im);
