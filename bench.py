@@ -37,7 +37,8 @@ SEED_M, SEED_G, SEED_T = 3, 33, 7
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "traffic_z_conv_256x256x64_f32.txt")
-KERNEL_SOURCES = ["paper_1204_4302_amd/csrc/passes.hip", "paper_1204_4302_amd/csrc/fft_lds.hpp"]
+KERNEL_SOURCES = ["paper_1204_4302_amd/csrc/passes_p2.hip", "paper_1204_4302_amd/csrc/fft_reg.hpp",
+                  "paper_1204_4302_amd/csrc/fft_lds.hpp"]
 
 
 def kernel_source_hash() -> str:
@@ -275,78 +276,72 @@ def bench(args):
 
 
 # ---------------------------------------------------------------------------
-# rocprofv3 output -> short text summaries for profiles/
+# rocprofv3 output (its SQLite results database) -> short text summaries
 def _find(d, pattern):
-    hits = glob.glob(os.path.join(d, "**", pattern), recursive=True)
-    return sorted(hits)
+    return sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+
+
+def _short(name):
+    name = name.replace("demag::(anonymous namespace)::", "").replace("demag::", "")
+    return name.split("(")[0].replace("void ", "")
 
 
 def summarize_profile(d, out_path, command):
-    lines = [f"# command: {command}", f"# kernel_source_hash = {kernel_source_hash()}"]
-    stats = _find(d, "*kernel_stats.csv")
-    if stats:
-        lines.append("# kernel stats (rocprofv3 --kernel-trace --stats)")
-        lines.append(f"{'kernel':60s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}")
-        with open(stats[0]) as f:
-            for row in csv.DictReader(f):
-                name = row.get("Name", "")[:60]
-                lines.append(f"{name:60s} {row.get('Calls', ''):>7s} "
-                             f"{float(row.get('AverageNs', 0)) / 1e3:10.2f} "
-                             f"{float(row.get('TotalDurationNs', 0)) / 1e6:10.3f} "
-                             f"{float(row.get('Percentage', 0)):6.2f}")
-    counters = _find(d, "*counter_collection.csv")
-    if counters:
-        agg = {}
-        with open(counters[0]) as f:
-            for row in csv.DictReader(f):
-                key = (row.get("Kernel_Name", "")[:60], row.get("Counter_Name", ""))
-                agg.setdefault(key, []).append(float(row.get("Counter_Value", 0)))
-        lines.append("# counters per dispatch (mean over dispatches), rocprofv3 --pmc")
-        for (k, c), v in sorted(agg.items()):
-            lines.append(f"{k:60s} {c:12s} n={len(v):5d} mean={sum(v) / len(v):.6g}")
+    """Per-kernel calls / average / total from a --kernel-trace --stats run."""
+    import sqlite3
+    lines = [f"# command: {command}", f"# kernel_source_hash = {kernel_source_hash()}",
+             "# kernel stats (rocprofv3 --kernel-trace --stats)",
+             f"{'kernel':44s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+    for db in _find(d, "*results.db"):
+        con = sqlite3.connect(db)
+        for name, calls, total, avg, pct in con.execute(
+                "select name, total_calls, total_duration, average, percentage from top_kernels"):
+            # this view reports durations in microseconds
+            lines.append(f"{_short(name)[:44]:44s} {calls:6d} {avg:10.2f} {total / 1e3:10.3f} {pct:6.2f}")
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
 
-def _counter_means(d):
-    """{(kernel, counter): (mean per dispatch, dispatches)} from a --pmc run."""
-    files = _find(d, "*counter_collection.csv")
+def _counter_means(d, counter):
+    """{kernel: (mean value per dispatch, dispatches)} of one --pmc counter."""
+    import sqlite3
     agg = {}
-    if files:
-        with open(files[0]) as f:
-            for row in csv.DictReader(f):
-                key = (row.get("Kernel_Name", ""), row.get("Counter_Name", ""))
-                agg.setdefault(key, []).append(float(row.get("Counter_Value", 0)))
+    for db in _find(d, "*results.db"):
+        con = sqlite3.connect(db)
+        for name, val, grid in con.execute(
+                "select kernel_name, value, grid_size from counters_collection where counter_name = ?", (counter,)):
+            agg.setdefault((_short(name), grid), []).append(val)
     return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
 
 
 def traffic_summary(fetch_dir, write_dir, out_path, command):
     """HBM bytes per launch of every pass kernel from FETCH_SIZE / WRITE_SIZE
     (KiB per dispatch), each scaled by what the same counter reads for the
-    plain 256 MiB device copy of --copy-calibration."""
-    fetch, write = _counter_means(fetch_dir), _counter_means(write_dir)
-    copy_bytes = 256 * 1024 * 1024
+    plain 256 MiB device copy of --copy-calibration (runtime copy kernel)."""
+    fetch, write = _counter_means(fetch_dir, "FETCH_SIZE"), _counter_means(write_dir, "WRITE_SIZE")
+    copy_kib = 256 * 1024.0
 
-    def calib(tab, counter):
-        cands = [(v, k) for (k, c), (v, n) in tab.items() if c == counter and "copy" in k.lower()]
-        cands = [x for x in cands if x[0] > 0.5 * copy_bytes / 1024]
-        return (copy_bytes / 1024.0) / max(cands)[0] if cands else None
+    def calib(tab):
+        vals = [v for (k, g), (v, n) in tab.items() if "copyBuffer" in k and v > 0.3 * copy_kib]
+        return vals and max(vals)
 
-    f_fetch, f_write = calib(fetch, "FETCH_SIZE"), calib(write, "WRITE_SIZE")
+    fc, wc = calib(fetch), calib(write)
+    f_fetch = copy_kib / fc if fc else None
+    f_write = copy_kib / wc if wc else None
     lines = [f"# command: {command}", f"kernel_source_hash = {kernel_source_hash()}",
+             f"# calibration: a 256 MiB device copy reads {fc} KiB (FETCH_SIZE) and writes {wc} KiB (WRITE_SIZE)",
              f"copy_calibration_fetch_factor = {f_fetch}", f"copy_calibration_write_factor = {f_write}",
-             "# kernel  FETCH_KiB/dispatch  WRITE_KiB/dispatch  scaled_bytes/dispatch"]
+             f"# {'kernel':40s} {'grid':>9s} {'FETCH_KiB':>11s} {'WRITE_KiB':>11s} {'scaled_MB':>10s}"]
     zconv = None
-    names = sorted({k for (k, c) in fetch} | {k for (k, c) in write})
-    for k in names:
-        fv = fetch.get((k, "FETCH_SIZE"), (0.0, 0))[0]
-        wv = write.get((k, "WRITE_SIZE"), (0.0, 0))[0]
-        scaled = None
-        if f_fetch and f_write:
-            scaled = (fv * f_fetch + wv * f_write) * 1024.0
-        lines.append(f"{k[:90]}  {fv:.1f}  {wv:.1f}  {scaled}")
-        if "kz_conv" in k and "IfLi" in k:
+    for key in sorted(set(fetch) | set(write)):
+        fv, wv = fetch.get(key, (0.0, 0))[0], write.get(key, (0.0, 0))[0]
+        if fv + wv < 1024:
+            continue
+        scaled = (fv * f_fetch + wv * f_write) * 1024.0 if (f_fetch and f_write) else None
+        lines.append(f"  {key[0][:40]:40s} {key[1]:9d} {fv:11.1f} {wv:11.1f} "
+                     f"{(scaled or 0) / 1e6:10.1f}")
+        if key[0].startswith("kz_conv<float"):
             zconv = scaled
     if zconv is not None:
         lines.append(f"traffic_bytes_per_launch = {zconv}")

@@ -263,7 +263,7 @@ LaunchCfg p2_pencils(int P, int Kx, int nz, size_t cbytes, int target = 1024) {
     return c;
 }
 
-LaunchCfg p2_zconv(int P, int Kx, size_t cbytes, int target = 128) {
+LaunchCfg p2_zconv(int P, int Kx, size_t cbytes, int target = 64) {
     LaunchCfg c;
     c.p2 = 1;
     const int TP = p2_threads_per_pencil(P);
