@@ -142,6 +142,12 @@ def bench_batch(args, torch, np):
     shapes = [BATCH_SIZES[i] for i in rng.integers(0, len(BATCH_SIZES), size=96)]
     cell, Ms = (2e-9, 2e-9, 2e-9), 8e5
     plans = [Plan(s, cell, torch.float32) for s in shapes]
+    if not args.no_autotune:  # the first plan of each shape leads its group in the batch
+        seen = set()
+        for s, p in zip(shapes, plans):
+            if s not in seen:
+                seen.add(s)
+                p.autotune()
     ms = [torch.from_numpy(inputs.random_unit(s, 4000 + g)).to("cuda", torch.float32) for g, s in enumerate(shapes)]
     hs = [torch.empty_like(m) for m in ms]
     batch = Batch(plans, ms, hs, Ms)
@@ -188,8 +194,11 @@ def bench(args):
         if steps <= 0:
             continue
         plan = Plan(SHAPE, CELL, dtype)
-        if args.autotune:
+        tune_s = None
+        if not args.no_autotune:
+            t0 = time.perf_counter()
             plan.autotune()
+            tune_s = time.perf_counter() - t0
         m = torch.from_numpy(m_np).to("cuda", dtype)
         gH = torch.from_numpy(g_np).to("cuda", dtype)
         H = torch.empty_like(m)
@@ -208,7 +217,7 @@ def bench(args):
         secs = run_steps(step, steps, torch)
         passes, nrec = plan.pass_times() if timing else ({}, 0)
         print(f"# {dtype} launch: {plan.describe()}", file=sys.stderr, flush=True)
-        results[dtype] = {"plan": plan, "secs": secs, "steps": steps, "H": H.double().cpu().numpy(),
+        results[dtype] = {"plan": plan, "secs": secs, "steps": steps, "H": H.double().cpu().numpy(), "tune_s": tune_s,
                           "E": float(E.cpu()), "passes": passes, "nrec": nrec, "info": plan.info()}
         print(f"# {dtype}: {steps} steps in {secs:.3f} s ({1e3 * secs / steps:.3f} ms/step)", file=sys.stderr,
               flush=True)
@@ -250,7 +259,9 @@ def bench(args):
         "config": {"workload": "256x256x64 cells, 2x2x3 nm, Ms=1.4e6 A/m, seeded random unit m; "
                                "step = forward field+energy and adjoint (2 field evaluations)",
                    "padded": [info["Px"], info["Py"], info["Pz"]], "parallelism": "none (1 GPU)",
-                   "launch": r32["plan"].describe()},
+                   "launch": r32["plan"].describe(),
+                   "launch_shapes": "autotuned" if r32["tune_s"] is not None else "default",
+                   "autotune_s": None if r32["tune_s"] is None else round(r32["tune_s"], 2)},
         "roofline": roofline,
     }
     if torch.float64 in results:
@@ -360,7 +371,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=50, help="replays of the 96-grid batch (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
-    ap.add_argument("--autotune", action="store_true", help="tune launch shapes before timing")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the default launch shapes (default: tune them first; DEMAG_AUTOTUNE_CACHE keeps the result)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of 256 MiB (counter calibration)")
     ap.add_argument("--summarize-profile", metavar="DIR")

@@ -57,13 +57,34 @@ __device__ __forceinline__ void dft4(cx<T>* v) {
     v[3] = sub(t1, t3);
 }
 
+// The same DFTs when the upper half of the inputs is known to be zero (the
+// first stage of a transform of zero-padded data): v[R/2..R-1] are not read.
 template <int DIR, typename T>
+__device__ __forceinline__ void dft2_lo(cx<T>* v) {
+    v[1] = v[0];
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4_lo(cx<T>* v) {
+    const cx<T> a = v[0], b = v[1], rb = rot90<DIR>(b);
+    v[0] = add(a, b);
+    v[2] = sub(a, b);
+    v[1] = add(a, rb);
+    v[3] = sub(a, rb);
+}
+
+template <int DIR, typename T, bool LO = false>
 __device__ __forceinline__ void dft8(cx<T>* v) {
     const T h = T(0.70710678118654752440084436210484903928);
     cx<T> e[4] = {v[0], v[2], v[4], v[6]};
     cx<T> o[4] = {v[1], v[3], v[5], v[7]};
-    dft4<DIR>(e);
-    dft4<DIR>(o);
+    if constexpr (LO) {
+        dft4_lo<DIR>(e);
+        dft4_lo<DIR>(o);
+    } else {
+        dft4<DIR>(e);
+        dft4<DIR>(o);
+    }
     // o[k] *= exp(DIR * 2 pi i k / 8)
     o[1] = DIR < 0 ? mk(h * (o[1].re + o[1].im), h * (o[1].im - o[1].re))
                    : mk(h * (o[1].re - o[1].im), h * (o[1].im + o[1].re));
@@ -114,6 +135,14 @@ __device__ __forceinline__ void dftR(cx<T>* v) {
     else if constexpr (R == 4) dft4<DIR>(v);
     else if constexpr (R == 5) dft5<DIR>(v);
     else dft8<DIR>(v);
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dftR_lo(cx<T>* v) {
+    static_assert(R == 2 || R == 4 || R == 8, "power-of-two radix");
+    if constexpr (R == 2) dft2_lo<DIR>(v);
+    else if constexpr (R == 4) dft4_lo<DIR>(v);
+    else dft8<DIR, T, true>(v);
 }
 
 // Stage schedule of one transform length: radices in execution order.

@@ -10,8 +10,8 @@
 // first stages do not collide on banks; slabs are PS = pad(P) + 1 apart (odd in
 // 8-byte units) so that reads across pencils at one position do not collide
 // either.  All index arithmetic is on compile-time powers of two (shifts and
-// masks).  Twiddles come from the same table as the generic engine,
-// tw[t] = exp(-2 pi i t / P) rounded once from long double.
+// masks).  Twiddles are the generic engine's values, tw[t] = exp(-2 pi i t / P)
+// rounded once from long double, rearranged thread-major (see Twiddles).
 //
 // Register slot j of thread t:
 //   before the first stage it must hold input element  in_pos(t, j),
@@ -69,36 +69,62 @@ __device__ __forceinline__ void pencil_sync() {
     }
 }
 
-// The twiddles one thread applies, per stage S >= 1: entry [S][i (R-1) + r-1]
-// is tw[r k P/(NS R)] for its butterfly i (k = butterfly index mod NS).  They
-// depend on the thread only, so a thread that runs several transforms loads
-// them once; the inverse uses their conjugates.
+// The twiddles one thread applies, per stage S >= 1: entry [S][e], e =
+// i (R-1) + r-1, is tw[r k P/(NS R)] for its butterfly i (k = butterfly index
+// mod NS).  They depend on the thread only, so a thread that runs several
+// transforms loads them once; the inverse uses their conjugates.  They are
+// read from a thread-major table, twt[((S-1) 7 + e) TP + t] (thread_twiddle
+// below), so that the threads of a pencil load consecutive addresses.
 template <int P, typename T>
 struct Twiddles {
     cx<T> w[Fft<P>::NST > 1 ? Fft<P>::NST : 1][7];
 
-    __device__ __forceinline__ void load(int t, const cx<T>* __restrict__ tw) { load_from<1>(t, tw); }
+    __device__ __forceinline__ void load(int t, const cx<T>* __restrict__ twt) { load_from<1>(t, twt); }
 
     template <int S>
-    __device__ __forceinline__ void load_from(int t, const cx<T>* __restrict__ tw) {
+    __device__ __forceinline__ void load_from(int t, const cx<T>* __restrict__ twt) {
         using F = Fft<P>;
         if constexpr (S < F::NST) {
-            constexpr int R = F::radix(S), NS = F::ns(S), NB = F::EPT / R;
+            constexpr int R = F::radix(S), NB = F::EPT / R;
 #pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                const int k = (t + i * F::TP) & (NS - 1);
-#pragma unroll
-                for (int r = 1; r < R; ++r) w[S][i * (R - 1) + r - 1] = tw[r * k * (P / (NS * R))];
-            }
-            load_from<S + 1>(t, tw);
+            for (int e = 0; e < NB * (R - 1); ++e) w[S][e] = twt[((S - 1) * 7 + e) * F::TP + t];
+            load_from<S + 1>(t, twt);
         }
     }
 };
 
-template <int P, int S, int DIR, typename T>
+// Table position of entry [S][e] of thread t, and the index into tw[] it
+// holds; table_size() entries in all.  Host-side builder of the table.
+template <int P>
+struct TwiddleTable {
+    using F = Fft<P>;
+    static constexpr int table_size() { return (F::NST > 1 ? F::NST - 1 : 1) * 7 * F::TP; }
+    template <typename T>
+    static void fill(const cx<T>* tw, cx<T>* twt) {
+        for (int i = 0; i < table_size(); ++i) twt[i] = tw[0];
+        for (int S = 1; S < F::NST; ++S) {
+            const int R = F::radix(S), NS = F::ns(S), NB = F::EPT / R;
+            for (int t = 0; t < F::TP; ++t)
+                for (int i = 0; i < NB; ++i) {
+                    const int k = (t + i * F::TP) & (NS - 1);
+                    for (int r = 1; r < R; ++r)
+                        twt[((S - 1) * 7 + i * (R - 1) + r - 1) * F::TP + t] = tw[r * k * (P / (NS * R))];
+                }
+        }
+    }
+};
+
+// LO: the transform's upper half of inputs (positions >= P/2, i.e. slots
+// j >= EPT/2 of the first stage, whose radix equals EPT) is zero and unread.
+template <int P, int S, int DIR, bool LO, typename T>
 __device__ __forceinline__ void stage_compute(cx<T>* v, const Twiddles<P, T>& tws) {
     using F = Fft<P>;
     constexpr int R = F::radix(S), NS = F::ns(S), NB = F::EPT / R;
+    if constexpr (S == 0 && LO) {
+        static_assert(NB == 1 && NS == 1, "first stage spans the thread's slots");
+        dftR_lo<R, DIR>(v);
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
         if constexpr (NS > 1) {
@@ -114,10 +140,10 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, const Twiddles<P, T>& tw
 }
 
 // Stage S and every later one.  Caller: slots hold stage-S inputs.
-template <int P, int S, int DIR, typename T>
+template <int P, int S, int DIR, bool LO, typename T>
 __device__ __forceinline__ void stages_from(cx<T>* v, cx<T>* slab, int t, const Twiddles<P, T>& tws) {
     using F = Fft<P>;
-    stage_compute<P, S, DIR>(v, tws);
+    stage_compute<P, S, DIR, LO>(v, tws);
     if constexpr (S + 1 < F::NST) {
         constexpr int R = F::radix(S), NS = F::ns(S), NB = F::EPT / R;
         // every thread of the pencil has consumed the slab's previous contents
@@ -140,23 +166,25 @@ __device__ __forceinline__ void stages_from(cx<T>* v, cx<T>* slab, int t, const 
         for (int i = 0; i < NB2; ++i)
 #pragma unroll
             for (int r = 0; r < R2; ++r) v[i * R2 + r] = slab[F::pad_add(pt, t, i * F::TP + r * (P / R2))];
-        stages_from<P, S + 1, DIR>(v, slab, t, tws);
+        stages_from<P, S + 1, DIR, LO>(v, slab, t, tws);
     }
 }
 
 // Full transform.  Every thread of the workgroup must call it (for TP > 64 it
 // contains workgroup barriers).  The slab belongs to this pencil alone; the
 // caller orders any access by other threads (a workgroup barrier) before.
-template <int P, int DIR, typename T>
+// LO = true: input positions >= P/2 are zero (zero-padded data) and the slots
+// holding them are not read.
+template <int P, int DIR, bool LO = false, typename T>
 __device__ __forceinline__ void fft(cx<T>* v, cx<T>* slab, int t, const Twiddles<P, T>& tws) {
-    stages_from<P, 0, DIR>(v, slab, t, tws);
+    stages_from<P, 0, DIR, LO>(v, slab, t, tws);
 }
 
-template <int P, int DIR, typename T>
-__device__ __forceinline__ void fft(cx<T>* v, cx<T>* slab, int t, const cx<T>* __restrict__ tw) {
+template <int P, int DIR, bool LO = false, typename T>
+__device__ __forceinline__ void fft(cx<T>* v, cx<T>* slab, int t, const cx<T>* __restrict__ twt) {
     Twiddles<P, T> tws;
-    tws.load(t, tw);
-    stages_from<P, 0, DIR>(v, slab, t, tws);
+    tws.load(t, twt);
+    stages_from<P, 0, DIR, LO>(v, slab, t, tws);
 }
 
 }  // namespace p2

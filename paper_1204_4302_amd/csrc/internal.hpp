@@ -1,6 +1,7 @@
 // Internal declarations shared by the pass kernels, the tensor setup and the
 // plan runtime (not part of the public C ABI).
 #pragma once
+#include <vector>
 #include <hip/hip_runtime.h>
 
 #include "fft_lds.hpp"
@@ -61,25 +62,40 @@ hipError_t launch_energy_reduce(hipStream_t, const double* partials, int n, doub
 bool p2_supported(int P);
 int p2_threads_per_pencil(int P);
 int p2_slab_elems(int P);
+// The X and Y passes stage twiddle tables of at most this many bytes in LDS
+// per workgroup (larger ones would cost workgroups per CU); the dynamic LDS of
+// such a launch is its slabs plus p2_twiddle_lds_bytes.  The fused Z pass loads
+// its twiddles once per thread for six transforms and reads them from memory.
+constexpr size_t kP2TwLdsMax = 8192;
+size_t p2_twiddle_lds_bytes(int P, size_t cbytes);
 extern int kXcds;                       // XCDs of the device: 8 on MI355X; 1 turns the swizzle off
 constexpr int kP2MaxThreads = 1024;     // X and Y passes
 constexpr int kP2MaxThreadsZ = 512;     // fused Z pass (three pencils per thread)
+// The power-of-two Z pass reaches B2 and the tensor octant through 32-bit
+// buffer offsets: one B2 component and the whole octant must each span fewer
+// bytes than this (larger shapes run the generic Z pass).
+constexpr size_t kP2BufLimit = 0xFFFFF000u;
+// The p2 kernels read their twiddles from a thread-major table: the values of
+// tw (exp(-2 pi i t / P), t < P) rearranged so that the threads of one pencil
+// load consecutive entries.  Empty if P is not a supported power of two.
+template <typename T>
+std::vector<cx<T>> p2_thread_twiddles(int P, const std::vector<cx<T>>& tw);
 template <typename T>
 hipError_t launch_x_fwd_p2(int lgTy, hipStream_t, const T* in, cx<T>* out, int nx, int ny, int nz, int C, int P,
-                           const cx<T>* tw, const BatchIO& bio = BatchIO());
+                           const cx<T>* twt, const BatchIO& bio = BatchIO());
 template <typename T>
 hipError_t launch_x_inv_p2(int lgTy, hipStream_t, const cx<T>* in, T* out, const T* m, double* partials, int nx,
-                           int ny, int nz, int C, int accumulate, int P, const cx<T>* tw,
+                           int ny, int nz, int C, int accumulate, int P, const cx<T>* twt,
                            const BatchIO& bio = BatchIO());
 template <typename T>
 hipError_t launch_y_fwd_p2(int lgTz, int lgTx, hipStream_t, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
-                           int C, int P, const cx<T>* tw, const BatchIO& bio = BatchIO());
+                           int C, int P, const cx<T>* twt, const BatchIO& bio = BatchIO());
 template <typename T>
 hipError_t launch_y_inv_p2(int lgTz, int lgTx, hipStream_t, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
-                           int C, int P, const cx<T>* tw, const BatchIO& bio = BatchIO());
+                           int C, int P, const cx<T>* twt, const BatchIO& bio = BatchIO());
 template <typename T>
 hipError_t launch_z_conv_p2(int lgTx, hipStream_t, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx, int P,
-                            const cx<T>* tw, const BatchIO& bio = BatchIO());
+                            const cx<T>* twt, const BatchIO& bio = BatchIO());
 
 // ---- tensor setup (FP64) ----------------------------------------------------
 struct TensorBands {

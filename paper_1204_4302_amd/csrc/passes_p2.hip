@@ -8,6 +8,7 @@
 // positions of the last); the transposed side goes through the padded LDS
 // slabs.  Tile extents are powers of two, passed as log2.
 #include <algorithm>
+#include <vector>
 
 #include "fft_reg.hpp"
 #include "internal.hpp"
@@ -46,6 +47,28 @@ __device__ __forceinline__ int xcd_tile(int nxcd) {
     const int x = b % nxcd, q = b / nxcd;
     const int per = nb / nxcd, rem = nb % nxcd;
     return x * per + min(x, rem) + q;
+}
+
+// Twiddle source of a p2 kernel.  A table of at most kP2TwLdsMax bytes is
+// copied once per workgroup into LDS after the pencils' slabs, so that each
+// thread's twiddle loads are LDS reads instead of vector-memory instructions
+// (one per thread for the copy instead of one per twiddle); the caller's next
+// workgroup barrier publishes it.  Larger tables are read from global memory.
+template <typename T, int P>
+__host__ __device__ constexpr bool tw_in_lds() {
+    return p2::TwiddleTable<P>::table_size() * sizeof(cx<T>) <= kP2TwLdsMax;
+}
+template <typename T, int P>
+__device__ __forceinline__ const cx<T>* twiddle_source(cx<T>* lds, int npencils, const cx<T>* __restrict__ twt,
+                                                       int tid, int nthr) {
+    if constexpr (tw_in_lds<T, P>()) {
+        constexpr int TS = p2::TwiddleTable<P>::table_size();
+        cx<T>* dst = lds + npencils * p2::Fft<P>::PS;
+        for (int i = tid; i < TS; i += nthr) dst[i] = twt[i];
+        return dst;
+    } else {
+        return twt;
+    }
 }
 
 // register slot of the last stage whose position equals the first-stage input
@@ -97,12 +120,69 @@ __device__ __forceinline__ void gst(gptr<cx<T>> p, size_t i, cx<T> c) {
     ((gptr<typename vec2<T>::type>)p)[i] = v;
 }
 
+// Raw buffer access: a resource (base address and byte range, uniform across
+// the wavefront, so held in scalar registers) plus a 32-bit per-lane byte
+// offset, with compile-time parts folded into the instruction's immediate.
+// The hardware range-checks every access: a load at or beyond the range
+// returns zero and a store there is dropped, so lanes outside the data (zero
+// padding, ragged tiles) take the offset kOob instead of a branch.  Ranges are
+// below kOob (the host keeps such shapes on the generic kernels), and kOob plus
+// any immediate stays below 2^32.
+constexpr unsigned kOob = 0xFFFFF000u;
+constexpr unsigned kBufWord3 = 0x00020000u;  // 32-bit data format, as raw buffers on this family expect
+
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+};
+__device__ __forceinline__ Buf make_buf(const void* base, size_t bytes) {
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)(unsigned)bytes, (int)kBufWord3)};
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> bld(Buf b, unsigned off, unsigned soff = 0) {
+    if constexpr (sizeof(T) == 4) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(b.r, off, soff, 0);
+        const typename vec2<T>::type v = __builtin_bit_cast(typename vec2<T>::type, u);
+        return mk(v.x, v.y);
+    } else {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b128(b.r, off, soff, 0);
+        const typename vec2<T>::type v = __builtin_bit_cast(typename vec2<T>::type, u);
+        return mk(v.x, v.y);
+    }
+}
+template <typename T>
+__device__ __forceinline__ T bldr(Buf b, unsigned off, unsigned soff = 0) {
+    if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(b.r, off, soff, 0));
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(b.r, off, soff, 0));
+    }
+}
+template <typename T>
+__device__ __forceinline__ void bst(Buf b, unsigned off, cx<T> c) {
+    typename vec2<T>::type v;
+    v.x = c.re;
+    v.y = c.im;
+    if constexpr (sizeof(T) == 4) {
+        typedef unsigned u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), b.r, off, 0, 0);
+    } else {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), b.r, off, 0, 0);
+    }
+}
+// byte offset `base + d` of a lane's element, or an out-of-range offset when
+// the element is not valid (d is a compile-time constant after unrolling)
+__device__ __forceinline__ unsigned boff(bool valid, unsigned base, unsigned d) {
+    return (valid ? base : kOob - d) + d;
+}
+
 // ---------------------------------------------------------------------------
 // X forward (R2C of two rows per complex pencil).  1-D grid of
 // ceil(ny/Ty) * nz * C (* batch) tiles, block (Ty/2) * TP threads.
 template <typename T, int P>
 __global__ void __launch_bounds__(1024) kx_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, int nx, int ny,
-                                               int nz, int lgTy, int nxcd, const cx<T>* __restrict__ tw,
+                                               int nz, int lgTy, int nxcd, const cx<T>* __restrict__ twt,
                                                BatchIO bio) {
     using F = p2::Fft<P>;
     constexpr int Kx = P / 2 + 1;
@@ -135,7 +215,9 @@ __global__ void __launch_bounds__(1024) kx_fwd(const T* __restrict__ in, cx<T>* 
         }
     }
     cx<T>* slab = lds + p * F::PS;
-    p2::fft<P, -1>(v, slab, t, tw);
+    const cx<T>* tws = twiddle_source<T, P>(lds, nthr >> F::LOG_TP, twt, tid, nthr);
+    if constexpr (tw_in_lds<T, P>()) __syncthreads();
+    p2::fft<P, -1, true>(v, slab, t, tws);
     __syncthreads();
     const int pt = F::pad(t);
 #pragma unroll
@@ -188,7 +270,7 @@ template <typename T, int P>
 __global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* __restrict__ out,
                                                const T* __restrict__ m, double* __restrict__ partials, int nx,
                                                int ny, int nz, int lgTy, int accumulate, int nxcd,
-                                               const cx<T>* __restrict__ tw, BatchIO bio) {
+                                               const cx<T>* __restrict__ twt, BatchIO bio) {
     using F = p2::Fft<P>;
     constexpr int Kx = P / 2 + 1, Lx = P / 2;
     __shared__ double red[16];
@@ -237,13 +319,14 @@ __global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* 
             }
         }
     }
+    const cx<T>* tws = twiddle_source<T, P>(lds, nthr >> F::LOG_TP, twt, tid, nthr);
     __syncthreads();
     cx<T>* slab = lds + p * F::PS;
     cx<T> v[F::EPT];
     const int pt = F::pad(t);
 #pragma unroll
     for (int j = 0; j < F::EPT; ++j) v[j] = slab[F::pad_add(pt, t, F::slot_in(j) * F::TP)];
-    p2::fft<P, +1>(v, slab, t, tw);
+    p2::fft<P, +1>(v, slab, t, tws);
     const size_t rowbase = (((size_t)c * nz + z) * ny + y0 + 2 * p) * (size_t)nx;
     const gptr<T> dst = out ? gmem(out + rowbase) : nullptr;
     const gptr<const T> msrc = m ? gmem(m + rowbase) : nullptr;
@@ -284,7 +367,7 @@ __global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* 
 template <typename T, int P>
 __global__ void __launch_bounds__(1024) ky_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
                                                int nz, int Kx, int lgTz, int lgTx, int nxcd,
-                                               const cx<T>* __restrict__ tw, BatchIO bio) {
+                                               const cx<T>* __restrict__ twt, BatchIO bio) {
     using F = p2::Fft<P>;
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x;
@@ -310,7 +393,9 @@ __global__ void __launch_bounds__(1024) ky_fwd(const cx<T>* __restrict__ in, cx<
         v[j] = k < F::EPT / 2 ? gld_if(src, y, ok && y < ny) : czero<T>();
     }
     cx<T>* slab = lds + p * F::PS;
-    p2::fft<P, -1>(v, slab, t, tw);
+    const cx<T>* tws = twiddle_source<T, P>(lds, (int)blockDim.x >> F::LOG_TP, twt, tid, blockDim.x);
+    if constexpr (tw_in_lds<T, P>()) __syncthreads();
+    p2::fft<P, -1, true>(v, slab, t, tws);
     __syncthreads();
     const int pt = F::pad(t);
 #pragma unroll
@@ -337,7 +422,7 @@ __global__ void __launch_bounds__(1024) ky_fwd(const cx<T>* __restrict__ in, cx<
 template <typename T, int P>
 __global__ void __launch_bounds__(1024) ky_inv(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
                                                int nz, int Kx, int lgTz, int lgTx, int nxcd,
-                                               const cx<T>* __restrict__ tw, BatchIO bio) {
+                                               const cx<T>* __restrict__ twt, BatchIO bio) {
     using F = p2::Fft<P>;
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x;
@@ -369,13 +454,14 @@ __global__ void __launch_bounds__(1024) ky_inv(const cx<T>* __restrict__ in, cx<
 #pragma unroll
         for (int i = 0; i < F::EPT; ++i) pj[F::pad_add(pk, ky0, i * F::TP)] = ld[i];
     }
+    const cx<T>* tws = twiddle_source<T, P>(lds, (int)blockDim.x >> F::LOG_TP, twt, tid, blockDim.x);
     __syncthreads();
     cx<T>* slab = lds + p * F::PS;
     cx<T> v[F::EPT];
     const int pt = F::pad(t);
 #pragma unroll
     for (int j = 0; j < F::EPT; ++j) v[j] = slab[F::pad_add(pt, t, F::slot_in(j) * F::TP)];
-    p2::fft<P, +1>(v, slab, t, tw);
+    p2::fft<P, +1>(v, slab, t, tws);
     const int xi = p & (Tx - 1), zi = p >> lgTx;
     if (xi < tx && zi < tz) {
         const gptr<cx<T>> dst = gmem(out + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny);
@@ -394,12 +480,16 @@ __global__ void __launch_bounds__(1024) ky_inv(const cx<T>* __restrict__ in, cx<
 // three components in registers, so the tensor product needs no exchange and
 // the forward output slots are the inverse input slots.
 // 1-D grid of ceil(Kx/Tx) * (Py/2 + 1) tiles, block 2 * Tx * TP.
+// Every B2 and tensor access is a raw buffer access (one resource per B2
+// component, one for the tensor octant with the component in the scalar
+// offset); the host guarantees that each range is below kOob.
 template <typename T, int P>
 __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2, const T* __restrict__ nhat, T Ms, int nz,
-                                                int Py, int Kx, int lgTx, int nxcd, const cx<T>* __restrict__ tw,
+                                                int Py, int Kx, int lgTx, int nxcd, const cx<T>* __restrict__ twt,
                                                 BatchIO bio) {
     using F = p2::Fft<P>;
     constexpr int Lz = P / 2;
+    constexpr unsigned CB = sizeof(cx<T>), RB = sizeof(T);
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x;
     const int g = tid >> F::LOG_TP, t = tid & (F::TP - 1);
@@ -414,43 +504,67 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     const int ns = (kyp == 0 || kyp == Ly) ? 1 : 2;
     const bool ok = s < ns && xi < tx;
     const int ky = s ? Py - kyp : kyp;
-    const gptr<cx<T>> base = gmem(ok ? B2 + ((size_t)ky * Kx + kx0 + xi) * (size_t)nz : B2);
-    const size_t cstride = (size_t)Py * Kx * nz;  // component stride of B2
+    const size_t cstride = (size_t)Py * Kx * nz;  // component stride of B2 (elements)
+    const Buf bc[3] = {make_buf(B2, cstride * CB), make_buf(B2 + cstride, cstride * CB),
+                       make_buf(B2 + 2 * cstride, cstride * CB)};
+    // byte offset of this lane's first element; zz = t + k TP adds k TP CB
+    const unsigned row = (unsigned)((((size_t)ky * Kx + kx0 + xi) * nz + t) * CB);
     cx<T> v[3][F::EPT];
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
 #pragma unroll
-        for (int j = 0; j < F::EPT; ++j) {
-            const int k = F::slot_in(j);
-            const int zz = t + k * F::TP;
-            v[comp][j] = k < F::EPT / 2 ? gld_if<T>(base, comp * cstride + zz, ok && zz < nz) : czero<T>();
+        for (int j = 0; j < F::EPT / 2; ++j) {  // first-stage slot j holds position k = j
+            const int zz = t + j * F::TP;
+            v[comp][j] = bld<T>(bc[comp], boff(ok && zz < nz, row, j * F::TP * CB));
         }
     }
-    // the tensor values of all this thread's frequencies, loaded together with
-    // the data (before the transforms) so that their latency overlaps
-    const size_t cs = (size_t)Kx * (Lz + 1);
-    const gptr<const T> nh0 = gmem(ok ? nhat + ((size_t)kyp * 6 * Kx + kx0 + xi) * (Lz + 1) : nhat);
+    // The tensor values of all this thread's frequencies.  Octant index
+    // kz' = kz for kz <= Lz, else P - kz; lanes outside the tile read row 0
+    // (their results are never stored).  In FP32 they are loaded together with
+    // the data, before the transforms, so that their latency overlaps, and the
+    // thread's twiddles are loaded once for all six transforms; in FP64 (twice
+    // the registers) both wait until needed, which keeps the kernel in
+    // registers.
+    constexpr bool kEarly = sizeof(T) == 4;     // tensor loaded before the transforms
+    constexpr bool kKeepTw = sizeof(T) == 4;    // twiddles held in registers across transforms
+    const size_t cs = (size_t)Kx * (Lz + 1);  // component stride of the octant (elements)
+    const Buf bt = make_buf(nhat, (size_t)(Ly + 1) * 6 * cs * RB);
+    const unsigned trow = ok ? (unsigned)((((size_t)kyp * 6 * Kx + kx0 + xi) * (Lz + 1)) * RB) : 0u;
+    const unsigned tpos = trow + t * RB, tneg = trow + (F::TP - 1 - t) * RB;
     T nt[F::EPT][6];
+    auto load_tensor = [&]() {
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) {
-        const int kz = t + F::slot_out(j) * F::TP;
-        const int kzp = kz <= Lz ? kz : P - kz;
+        for (int j = 0; j < F::EPT; ++j) {
+            const int k = F::slot_out(j);
+            // kz = t + k TP; for k >= EPT/2, P - kz = (TP - 1 - t) + P - (k + 1) TP + 1
+            const unsigned off = k < F::EPT / 2 ? tpos + k * F::TP * RB : tneg + (P - (k + 1) * F::TP + 1) * RB;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) nt[j][q] = gldr_if(nh0, q * cs + kzp, ok);
-    }
+            for (int q = 0; q < 6; ++q) nt[j][q] = bldr<T>(bt, off, (unsigned)(q * cs * RB));
+        }
+    };
+    if constexpr (kEarly) load_tensor();
     cx<T>* slab = lds + g * F::PS;
-    p2::Twiddles<P, T> tws;  // one load of this thread's twiddles for all six transforms
-    tws.load(t, tw);
+    const cx<T>* twsrc = twt;
+    p2::Twiddles<P, T> tws;
+    if constexpr (kKeepTw) tws.load(t, twsrc);
 #pragma unroll
-    for (int comp = 0; comp < 3; ++comp) p2::fft<P, -1>(v[comp], slab, t, tws);
-    // H^ = Ms * Nhat(kx, ky, kz) M^ ; octant lookup with parity signs
+    for (int comp = 0; comp < 3; ++comp) {
+        if constexpr (kKeepTw) p2::fft<P, -1, true>(v[comp], slab, t, tws);
+        else p2::fft<P, -1, true>(v[comp], slab, t, twsrc);
+    }
+    if constexpr (!kEarly) load_tensor();
+    // H^ = Nhat(kx, ky, kz) M^ (Ms applied at the store).  Octant lookup with
+    // parity signs: xy, yz odd in ky (negative for ky > Ly, i.e. s = 1); xz, yz
+    // odd in kz, negative for kz > Lz, which is slot k >= EPT/2 except kz = Lz
+    // itself, where the odd components are exactly zero.
     const T sy = s ? T(-1) : T(1);
 #pragma unroll
     for (int j = 0; j < F::EPT; ++j) {
-        const int kz = t + F::slot_out(j) * F::TP;
-        const T sz = kz > Lz ? T(-1) : T(1);
-        const T nxx = Ms * nt[j][0], nyy = Ms * nt[j][1], nzz = Ms * nt[j][2];
-        const T nxy = Ms * sy * nt[j][3], nxz = Ms * sz * nt[j][4], nyz = Ms * sy * sz * nt[j][5];
+        const bool negz = F::slot_out(j) >= F::EPT / 2;
+        const T nxx = nt[j][0], nyy = nt[j][1], nzz = nt[j][2];
+        const T nxy = sy * nt[j][3];
+        const T nxz = negz ? -nt[j][4] : nt[j][4];
+        const T nyz = negz ? -(sy * nt[j][5]) : sy * nt[j][5];
         const cx<T> mx = v[0][j], my = v[1][j], mz = v[2][j];
         v[0][j] = mk(nxx * mx.re + nxy * my.re + nxz * mz.re, nxx * mx.im + nxy * my.im + nxz * mz.im);
         v[1][j] = mk(nxy * mx.re + nyy * my.re + nyz * mz.re, nxy * mx.im + nyy * my.im + nyz * mz.im);
@@ -461,14 +575,14 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         cx<T> w[F::EPT];
 #pragma unroll
         for (int j = 0; j < F::EPT; ++j) w[j] = v[comp][out_slot_for_in<P>(j)];
-        p2::fft<P, +1>(w, slab, t, tws);
-        if (ok) {
+        if constexpr (kKeepTw) p2::fft<P, +1>(w, slab, t, tws);
+        else p2::fft<P, +1>(w, slab, t, twsrc);
 #pragma unroll
-            for (int j = 0; j < F::EPT; ++j) {
-                const int k = F::slot_out(j);
-                const int zz = t + k * F::TP;
-                if (k < F::EPT / 2 && zz < nz) gst(base, comp * cstride + zz, w[j]);
-            }
+        for (int j = 0; j < F::EPT; ++j) {
+            const int k = F::slot_out(j);
+            const int zz = t + k * F::TP;
+            if (k < F::EPT / 2)  // the discarded half is never written
+                bst<T>(bc[comp], boff(ok && zz < nz, row, k * F::TP * CB), mk(Ms * w[j].re, Ms * w[j].im));
         }
     }
 }
@@ -510,16 +624,28 @@ int kXcds = 8;  // XCDs of the device (workgroup swizzle); set by the plan runti
 bool p2_supported(int P) { return P >= 2 && P <= 4096 && (P & (P - 1)) == 0; }
 int p2_threads_per_pencil(int P) { return P >= 8 ? P / 8 : 1; }
 int p2_slab_elems(int P) { return (P + (P >> 3)) + 1; }
+size_t p2_twiddle_lds_bytes(int P, size_t cbytes) {
+    size_t n = 0;
+    switch (P) {
+#define TS(PP) \
+    case PP: n = (size_t)p2::TwiddleTable<PP>::table_size(); break;
+        TS(2) TS(4) TS(8) TS(16) TS(32) TS(64) TS(128) TS(256) TS(512) TS(1024) TS(2048) TS(4096)
+#undef TS
+    default: return 0;
+    }
+    return n * cbytes <= kP2TwLdsMax ? n * cbytes : 0;
+}
 
 template <typename T>
 hipError_t launch_x_fwd_p2(int lgTy, hipStream_t st, const T* in, cx<T>* out, int nx, int ny, int nz, int C, int P,
-                           const cx<T>* tw, const BatchIO& bio) {
+                           const cx<T>* twt, const BatchIO& bio) {
+    if (!twt) return hipErrorInvalidValue;
     const int Bp = 1 << (lgTy - 1);
     dim3 grid((unsigned)(((ny + (1 << lgTy) - 1) >> lgTy) * nz * C * bio.count));
-    const size_t lds = (size_t)Bp * p2_slab_elems(P) * sizeof(cx<T>);
+    const size_t lds = (size_t)Bp * p2_slab_elems(P) * sizeof(cx<T>) + p2_twiddle_lds_bytes(P, sizeof(cx<T>));
 #define CALL(PP) \
     if (hipError_t e_ = allow_lds(&kx_fwd<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((kx_fwd<T, PP>), grid, dim3(Bp * tpp<PP>()), lds, st, in, out, nx, ny, nz, lgTy, kXcds, tw, \
+    hipLaunchKernelGGL((kx_fwd<T, PP>), grid, dim3(Bp * tpp<PP>()), lds, st, in, out, nx, ny, nz, lgTy, kXcds, twt, \
                        bio)
     DEMAG_P2_SWITCH(P, CALL)
 #undef CALL
@@ -528,14 +654,15 @@ hipError_t launch_x_fwd_p2(int lgTy, hipStream_t st, const T* in, cx<T>* out, in
 
 template <typename T>
 hipError_t launch_x_inv_p2(int lgTy, hipStream_t st, const cx<T>* in, T* out, const T* m, double* partials, int nx,
-                           int ny, int nz, int C, int accumulate, int P, const cx<T>* tw, const BatchIO& bio) {
+                           int ny, int nz, int C, int accumulate, int P, const cx<T>* twt, const BatchIO& bio) {
+    if (!twt) return hipErrorInvalidValue;
     const int Bp = 1 << (lgTy - 1);
     dim3 grid((unsigned)(((ny + (1 << lgTy) - 1) >> lgTy) * nz * C * bio.count));
-    const size_t lds = (size_t)Bp * p2_slab_elems(P) * sizeof(cx<T>);
+    const size_t lds = (size_t)Bp * p2_slab_elems(P) * sizeof(cx<T>) + p2_twiddle_lds_bytes(P, sizeof(cx<T>));
 #define CALL(PP)                                                                                            \
     if (hipError_t e_ = allow_lds(&kx_inv<T, PP>, lds)) return e_; \
     hipLaunchKernelGGL((kx_inv<T, PP>), grid, dim3(Bp * tpp<PP>()), lds, st, in, out, m, partials, nx, ny, nz, \
-                       lgTy, accumulate, kXcds, tw, bio)
+                       lgTy, accumulate, kXcds, twt, bio)
     DEMAG_P2_SWITCH(P, CALL)
 #undef CALL
     return hipGetLastError();
@@ -543,13 +670,14 @@ hipError_t launch_x_inv_p2(int lgTy, hipStream_t st, const cx<T>* in, T* out, co
 
 template <typename T>
 hipError_t launch_y_fwd_p2(int lgTz, int lgTx, hipStream_t st, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
-                           int C, int P, const cx<T>* tw, const BatchIO& bio) {
+                           int C, int P, const cx<T>* twt, const BatchIO& bio) {
+    if (!twt) return hipErrorInvalidValue;
     const int B = 1 << (lgTz + lgTx);
     dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * ((nz + (1 << lgTz) - 1) >> lgTz) * C * bio.count));
-    const size_t lds = (size_t)B * p2_slab_elems(P) * sizeof(cx<T>);
+    const size_t lds = (size_t)B * p2_slab_elems(P) * sizeof(cx<T>) + p2_twiddle_lds_bytes(P, sizeof(cx<T>));
 #define CALL(PP) \
     if (hipError_t e_ = allow_lds(&ky_fwd<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((ky_fwd<T, PP>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, tw, \
+    hipLaunchKernelGGL((ky_fwd<T, PP>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, twt, \
                        bio)
     DEMAG_P2_SWITCH(P, CALL)
 #undef CALL
@@ -558,13 +686,14 @@ hipError_t launch_y_fwd_p2(int lgTz, int lgTx, hipStream_t st, const cx<T>* in, 
 
 template <typename T>
 hipError_t launch_y_inv_p2(int lgTz, int lgTx, hipStream_t st, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
-                           int C, int P, const cx<T>* tw, const BatchIO& bio) {
+                           int C, int P, const cx<T>* twt, const BatchIO& bio) {
+    if (!twt) return hipErrorInvalidValue;
     const int B = 1 << (lgTz + lgTx);
     dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * ((nz + (1 << lgTz) - 1) >> lgTz) * C * bio.count));
-    const size_t lds = (size_t)B * p2_slab_elems(P) * sizeof(cx<T>);
+    const size_t lds = (size_t)B * p2_slab_elems(P) * sizeof(cx<T>) + p2_twiddle_lds_bytes(P, sizeof(cx<T>));
 #define CALL(PP) \
     if (hipError_t e_ = allow_lds(&ky_inv<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((ky_inv<T, PP>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, tw, \
+    hipLaunchKernelGGL((ky_inv<T, PP>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, twt, \
                        bio)
     DEMAG_P2_SWITCH(P, CALL)
 #undef CALL
@@ -573,17 +702,35 @@ hipError_t launch_y_inv_p2(int lgTz, int lgTx, hipStream_t st, const cx<T>* in, 
 
 template <typename T>
 hipError_t launch_z_conv_p2(int lgTx, hipStream_t st, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx, int P,
-                            const cx<T>* tw, const BatchIO& bio) {
+                            const cx<T>* twt, const BatchIO& bio) {
+    if (!twt) return hipErrorInvalidValue;
     const int G = 2 << lgTx;
     dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * (Py / 2 + 1) * bio.count));
     const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>);
 #define CALL(PP) \
     if (hipError_t e_ = allow_lds(&kz_conv<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((kz_conv<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, kXcds, tw, \
+    hipLaunchKernelGGL((kz_conv<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, kXcds, twt, \
                        bio)
     DEMAG_P2_SWITCH(P, CALL)
 #undef CALL
     return hipGetLastError();
+}
+
+template <typename T>
+std::vector<cx<T>> p2_thread_twiddles(int P, const std::vector<cx<T>>& tw) {
+    std::vector<cx<T>> out;
+    if ((int)tw.size() != P) return out;
+    switch (P) {
+#define FILL(PP)                                                      \
+    case PP:                                                          \
+        out.resize(p2::TwiddleTable<PP>::table_size());               \
+        p2::TwiddleTable<PP>::fill(tw.data(), out.data());             \
+        break;
+        FILL(2) FILL(4) FILL(8) FILL(16) FILL(32) FILL(64) FILL(128) FILL(256) FILL(512) FILL(1024) FILL(2048) FILL(4096)
+#undef FILL
+    default: break;
+    }
+    return out;
 }
 
 #define DEMAG_P2_INSTANTIATE(T)                                                                                    \
@@ -600,5 +747,7 @@ hipError_t launch_z_conv_p2(int lgTx, hipStream_t st, cx<T>* B2, const T* nhat, 
 
 DEMAG_P2_INSTANTIATE(float)
 DEMAG_P2_INSTANTIATE(double)
+template std::vector<cx<float>> p2_thread_twiddles<float>(int, const std::vector<cx<float>>&);
+template std::vector<cx<double>> p2_thread_twiddles<double>(int, const std::vector<cx<double>>&);
 
 }  // namespace demag

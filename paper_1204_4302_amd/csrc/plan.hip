@@ -147,6 +147,7 @@ struct demag_plan_s {
     int L[3], P[3], Kx;
     FftPlanDev fp[3];
     void* tw[3] = {nullptr, nullptr, nullptr};
+    void* twt[3] = {nullptr, nullptr, nullptr};  // thread-major twiddles of power-of-two axes
     void* nhat = nullptr;
     void* B1 = nullptr;
     void* B2 = nullptr;
@@ -236,14 +237,16 @@ int pow2_ceil_log(long v) {
 }
 
 // p2 tiles: about `target` threads per workgroup, bounded by the extent the
-// tile covers and by LDS.
-LaunchCfg p2_rows(int P, int rows, size_t cbytes, int target = 512) {
+// tile covers and by LDS: the X and Y tiles keep two workgroups per CU (one
+// workgroup's barriers then overlap the other's memory traffic).
+LaunchCfg p2_rows(int P, int rows, size_t cbytes, int target = 1024) {
     LaunchCfg c;
     c.p2 = 1;
     const int TP = p2_threads_per_pencil(P);
     int lgB = ilog2i(std::max(1, target / TP));
     lgB = std::min(lgB, std::max(0, pow2_ceil_log(rows) - 1));
-    while (lgB > 0 && ((size_t)p2_slab_elems(P) << lgB) * cbytes > g_p2_lds - 256) --lgB;
+    while (lgB > 0 && ((size_t)p2_slab_elems(P) << lgB) * cbytes + p2_twiddle_lds_bytes(P, cbytes) > g_p2_lds / 2)
+        --lgB;
     c.t0 = lgB + 1;  // Ty = 2 * pencils
     c.threads = TP << lgB;
     return c;
@@ -254,7 +257,8 @@ LaunchCfg p2_pencils(int P, int Kx, int nz, size_t cbytes, int target = 1024) {
     c.p2 = 1;
     const int TP = p2_threads_per_pencil(P);
     int lgB = ilog2i(std::max(1, target / TP));
-    while (lgB > 0 && ((size_t)p2_slab_elems(P) << lgB) * cbytes > g_p2_lds - 256) --lgB;
+    while (lgB > 0 && ((size_t)p2_slab_elems(P) << lgB) * cbytes + p2_twiddle_lds_bytes(P, cbytes) > g_p2_lds / 2)
+        --lgB;
     int lgTz = std::min(lgB, pow2_ceil_log(nz));
     int lgTx = std::min(lgB - lgTz, pow2_ceil_log(Kx));
     c.t0 = lgTx;
@@ -283,8 +287,17 @@ bool p2_cfg_ok(const LaunchCfg& c, int P, size_t cbytes, int kind /*0 rows, 1 pe
     if (kind == 0 && c.t0 < 1) return false;
     long threads = pencils * TP;
     long maxthr = kind == 2 ? kP2MaxThreadsZ : kP2MaxThreads;
+    const size_t tw = kind == 2 ? 0 : p2_twiddle_lds_bytes(P, cbytes);
     return threads == c.threads && threads <= maxthr &&
-           (size_t)pencils * p2_slab_elems(P) * cbytes <= g_p2_lds - 256;  // + static reduction scratch
+           (size_t)pencils * p2_slab_elems(P) * cbytes + tw <= g_p2_lds - 256;  // + static reduction scratch
+}
+
+// byte spans the power-of-two Z pass addresses with 32-bit buffer offsets
+bool p2_z_ranges_ok(const demag_plan_s* p) {
+    const size_t cb = csize(p->dtype), rb = cb / 2;
+    const size_t b2 = (size_t)p->P[1] * p->Kx * p->n[2] * cb;
+    const size_t oct = (size_t)(p->P[1] / 2 + 1) * 6 * p->Kx * (p->P[2] / 2 + 1) * rb;
+    return b2 < kP2BufLimit && oct < kP2BufLimit;
 }
 
 bool cfg_ok(const LaunchCfg& c, long pencils, int P, size_t cbytes) {
@@ -302,7 +315,8 @@ bool one_cfg_ok(const LaunchCfg& c, int P, size_t cb, int kind) {
 bool plan_cfgs_ok(const demag_plan_s* p, const PassCfgs& c) {
     size_t cb = csize(p->dtype);
     return one_cfg_ok(c.xf, p->P[0], cb, 0) && one_cfg_ok(c.xi, p->P[0], cb, 0) &&
-           one_cfg_ok(c.yf, p->P[1], cb, 1) && one_cfg_ok(c.yi, p->P[1], cb, 1) && one_cfg_ok(c.zc, p->P[2], cb, 2);
+           one_cfg_ok(c.yf, p->P[1], cb, 1) && one_cfg_ok(c.yi, p->P[1], cb, 1) && one_cfg_ok(c.zc, p->P[2], cb, 2) &&
+           (!c.zc.p2 || p2_z_ranges_ok(p));
 }
 
 // Generic kernels (any 2^a 3^b 5^c length) unless the padded length is a power
@@ -314,7 +328,7 @@ PassCfgs default_cfgs(const demag_plan_s* p) {
     c.xi = c.xf;
     c.yf = p2_supported(p->P[1]) ? p2_pencils(p->P[1], p->Kx, p->n[2], cb) : cfg_pencils(p->P[1], p->Kx, p->n[2], cb);
     c.yi = c.yf;
-    c.zc = p2_supported(p->P[2]) ? p2_zconv(p->P[2], p->Kx, cb) : cfg_zconv(p->P[2], p->Kx, cb);
+    c.zc = p2_supported(p->P[2]) && p2_z_ranges_ok(p) ? p2_zconv(p->P[2], p->Kx, cb) : cfg_zconv(p->P[2], p->Kx, cb);
     return c;
 }
 
@@ -416,6 +430,7 @@ int run_setup(demag_plan_s* p, hipStream_t st) {
 
 void free_plan(demag_plan_s* p) {
     for (auto t : p->tw) hipFree(t);
+    for (auto t : p->twt) hipFree(t);
     hipFree(p->nhat);
     hipFree(p->B1);
     hipFree(p->B2);
@@ -441,21 +456,24 @@ hipError_t launch_pass(demag_plan_s* p, int which, const LaunchCfg& lc, hipStrea
     const auto* twx = (const cx<T>*)p->tw[0];
     const auto* twy = (const cx<T>*)p->tw[1];
     const auto* twz = (const cx<T>*)p->tw[2];
+    const auto* ttx = (const cx<T>*)p->twt[0];
+    const auto* tty = (const cx<T>*)p->twt[1];
+    const auto* ttz = (const cx<T>*)p->twt[2];
     switch (which) {
     case 0:
-        return lc.p2 ? launch_x_fwd_p2<T>(lc.t0, st, m, B1, nx, ny, nz, 3, Px, twx, bio)
+        return lc.p2 ? launch_x_fwd_p2<T>(lc.t0, st, m, B1, nx, ny, nz, 3, Px, ttx, bio)
                      : launch_x_fwd<T>(lc, st, m, B1, nx, ny, nz, Kx, 3, p->fp[0], twx, bio);
     case 1:
-        return lc.p2 ? launch_y_fwd_p2<T>(lc.t1, lc.t0, st, B1, B2, ny, nz, Kx, 3, Py, twy, bio)
+        return lc.p2 ? launch_y_fwd_p2<T>(lc.t1, lc.t0, st, B1, B2, ny, nz, Kx, 3, Py, tty, bio)
                      : launch_y_fwd<T>(lc, st, B1, B2, ny, nz, Kx, nz, 3, p->fp[1], twy, bio);
     case 2:
-        return lc.p2 ? launch_z_conv_p2<T>(lc.t0, st, B2, (const T*)p->nhat, (T)Ms, nz, Py, Kx, Pz, twz, bio)
+        return lc.p2 ? launch_z_conv_p2<T>(lc.t0, st, B2, (const T*)p->nhat, (T)Ms, nz, Py, Kx, Pz, ttz, bio)
                      : launch_z_conv<T>(lc, st, B2, (const T*)p->nhat, (T)Ms, nz, Py, Kx, p->fp[2], twz, bio);
     case 3:
-        return lc.p2 ? launch_y_inv_p2<T>(lc.t1, lc.t0, st, B2, B1, ny, nz, Kx, 3, Py, twy, bio)
+        return lc.p2 ? launch_y_inv_p2<T>(lc.t1, lc.t0, st, B2, B1, ny, nz, Kx, 3, Py, tty, bio)
                      : launch_y_inv<T>(lc, st, B2, B1, ny, nz, Kx, 3, p->fp[1], twy, bio);
     default:
-        return lc.p2 ? launch_x_inv_p2<T>(lc.t0, st, B1, H, me, partials, nx, ny, nz, 3, accumulate, Px, twx, bio)
+        return lc.p2 ? launch_x_inv_p2<T>(lc.t0, st, B1, H, me, partials, nx, ny, nz, 3, accumulate, Px, ttx, bio)
                      : launch_x_inv<T>(lc, st, B1, H, me, partials, nx, ny, nz, Kx, 3, accumulate, p->fp[0], twx,
                                        bio);
     }
@@ -606,8 +624,14 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
     p->scratch_bytes = (nB1 + nB2) * cb;
     p->tensor_bytes = nH * rb;
     if (!rc) {
-        for (int k = 0; k < 3 && !rc; ++k)
-            rc = dtype == DEMAG_F32 ? upload(&p->tw[k], twiddles<float>(P[k])) : upload(&p->tw[k], twiddles<double>(P[k]));
+        auto tables = [&](auto proto, int k) {
+            using T = decltype(proto);
+            const std::vector<cx<T>> tw = twiddles<T>(P[k]);
+            int r = upload(&p->tw[k], tw);
+            if (!r && p2_supported(P[k])) r = upload(&p->twt[k], p2_thread_twiddles<T>(P[k], tw));
+            return r;
+        };
+        for (int k = 0; k < 3 && !rc; ++k) rc = dtype == DEMAG_F32 ? tables(float(), k) : tables(double(), k);
     }
     if (!rc && hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess)
         rc = fail(DEMAG_EHIP, "hipEventCreate failed");
@@ -828,7 +852,7 @@ std::vector<LaunchCfg> candidates_z(const demag_plan_s* p) {
 // power-of-two candidates: every tile whose workgroup and LDS fit
 void add_p2_candidates(const demag_plan_s* p, int kind, std::vector<LaunchCfg>& out) {
     const int P = p->P[kind == 0 ? 0 : kind == 1 ? 1 : 2];
-    if (!p2_supported(P)) return;
+    if (!p2_supported(P) || (kind == 2 && !p2_z_ranges_ok(p))) return;
     const size_t cb = csize(p->dtype);
     const int TP = p2_threads_per_pencil(P);
     for (int a = 0; a <= 10; ++a)
@@ -870,7 +894,7 @@ std::string cache_key(const demag_plan_s* p) {
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
     arch = arch.substr(0, arch.find(':'));
     char b[160];
-    snprintf(b, sizeof b, "v2|%s|%s|%d,%d,%d", arch.c_str(), p->dtype == DEMAG_F32 ? "f32" : "f64", p->n[0],
+    snprintf(b, sizeof b, "v3|%s|%s|%d,%d,%d", arch.c_str(), p->dtype == DEMAG_F32 ? "f32" : "f64", p->n[0],
              p->n[1], p->n[2]);
     return b;
 }
@@ -882,7 +906,7 @@ std::map<std::string, std::string> read_cache(const char* path) {
     std::string line;
     while (std::getline(f, line)) {
         auto sp = line.find(' ');
-        if (sp == std::string::npos || line.rfind("v2|", 0) != 0) continue;
+        if (sp == std::string::npos || line.rfind("v3|", 0) != 0) continue;
         m[line.substr(0, sp)] = line.substr(sp + 1);
     }
     return m;

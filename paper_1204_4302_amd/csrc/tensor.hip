@@ -117,6 +117,13 @@ __global__ void __launch_bounds__(256) k_tensor_extract(int comp, int Py, int Pz
     if (t >= total) return;
     int kz = (int)(t % (Lz + 1)), kx = (int)((t / (Lz + 1)) % Kx), ky = (int)(t / ((size_t)(Lz + 1) * Kx));
     double v = B2[((size_t)ky * Kx + kx) * Pz + kz].re * scale;
+    // A component odd in an axis has an exactly zero transform on that axis's
+    // Nyquist plane (its samples at o and P - o cancel, and the sample at P/2
+    // is zero); store the exact zero rather than the transform's rounding.
+    // xy (3) is odd in x and y, xz (4) in x and z, yz (5) in y and z.
+    const int Lx = Kx - 1;
+    const bool oddx = comp == 3 || comp == 4, oddy = comp == 3 || comp == 5, oddz = comp == 4 || comp == 5;
+    if ((oddx && kx == Lx) || (oddy && ky == Ly) || (oddz && kz == Lz)) v = 0.0;
     nhat[(((size_t)ky * 6 + comp) * Kx + kx) * (Lz + 1) + kz] = (T)v;
 }
 
