@@ -141,6 +141,13 @@ int demag_autotune(demag_plan_t plan, void* stream);
  * scratch its evaluation uses).  demag_batch_create synchronises `stream`. */
 int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans, int count, const void* const* m,
                        void* const* H, double Ms, void* stream);
+/* Time the candidate launch shapes of every pass of every group on the
+ * group's own buffers (each candidate launch covering all members), keep the
+ * fastest per group and re-record the graph.  Synchronous; overwrites the
+ * members' H and scratch (the next demag_batch_launch recomputes them); plans'
+ * own launch shapes are unchanged.  Groups then may run other kernels than
+ * single-plan calls, so members agree with demag_field to rounding only. */
+int demag_batch_autotune(demag_batch_t batch, void* stream);
 int demag_batch_launch(demag_batch_t batch, void* stream);
 int demag_batch_destroy(demag_batch_t batch);
 

@@ -37,6 +37,7 @@ SIGNATURES = {
     "demag_autotune": (_I, [_P, _P]),
     "demag_batch_create": (_I, [ctypes.POINTER(_P), ctypes.POINTER(_P), _I, ctypes.POINTER(_P),
                                 ctypes.POINTER(_P), _D, _P]),
+    "demag_batch_autotune": (_I, [_P, _P]),
     "demag_batch_launch": (_I, [_P, _P]),
     "demag_batch_destroy": (_I, [_P]),
     "demag_last_error": (ctypes.c_char_p, []),

@@ -176,12 +176,14 @@ struct BatchGroup {
     demag_plan_s* lead = nullptr;
     int count = 0;
     void** lists = nullptr;  // device: m[count], H[count], B1[count], B2[count]
+    PassCfgs cfg;            // launch shapes of the group's passes (the lead's until tuned)
 };
 
 struct demag_batch_s {
     std::vector<demag_plan_t> plans;
     std::vector<BatchGroup> groups;
     void* dev_lists = nullptr;
+    double Ms = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -1029,12 +1031,10 @@ bool same_geometry(const demag_plan_s* a, const demag_plan_s* b) {
            a->bands.fg_cut == b->bands.fg_cut;
 }
 
-template <typename T>
-int enqueue_group(const BatchGroup& grp, double Ms, hipStream_t st) {
-    demag_plan_s* p = grp.lead;
+// per-pass pointer lists of a group: m -> B1 -> B2 -> B2 -> B1 -> H
+void group_io(const BatchGroup& grp, BatchIO io[5]) {
     const int n = grp.count;
     void** L = grp.lists;  // device array: [0,n) m, [n,2n) H, [2n,3n) B1, [3n,4n) B2
-    BatchIO io[5];
     io[0].in = (const void* const*)(L);
     io[0].out = L + 2 * n;
     io[1].in = (const void* const*)(L + 2 * n);
@@ -1045,10 +1045,114 @@ int enqueue_group(const BatchGroup& grp, double Ms, hipStream_t st) {
     io[3].out = L + 2 * n;
     io[4].in = (const void* const*)(L + 2 * n);
     io[4].out = L + n;
-    for (int w = 0; w < 5; ++w) {
-        io[w].count = n;
-        HIP_TRY(launch_pass<T>(p, w, pass_cfg(p->cfg, w), st, nullptr, Ms, nullptr, nullptr, nullptr, 0, io[w]));
+    for (int w = 0; w < 5; ++w) io[w].count = n;
+}
+
+template <typename T>
+int enqueue_group(const BatchGroup& grp, double Ms, hipStream_t st) {
+    BatchIO io[5];
+    group_io(grp, io);
+    for (int w = 0; w < 5; ++w)
+        HIP_TRY(launch_pass<T>(grp.lead, w, pass_cfg(grp.cfg, w), st, nullptr, Ms, nullptr, nullptr, nullptr, 0, io[w]));
+    return DEMAG_OK;
+}
+
+// Record every group's launches into the batch's graph (replacing an earlier
+// one): groups on up to kBranches forked capture streams, joined at the end.
+int record_graph(demag_batch_s* b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    int rc = DEMAG_OK;
+    const int nb = std::min<int>(kBranches, (int)b->groups.size());
+    hipStream_t cs[kBranches] = {};
+    hipEvent_t ev[kBranches + 1] = {};
+    for (int k = 0; k < nb && !rc; ++k)
+        if (hipStreamCreateWithFlags(&cs[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess)
+            rc = fail(DEMAG_EHIP, "cannot create capture streams");
+    if (!rc && hipEventCreateWithFlags(&ev[kBranches], hipEventDisableTiming) != hipSuccess)
+        rc = fail(DEMAG_EHIP, "cannot create capture event");
+    bool capturing = false;
+    if (!rc) {
+        if (hipStreamBeginCapture(cs[0], hipStreamCaptureModeThreadLocal) != hipSuccess)
+            rc = fail(DEMAG_EHIP, "hipStreamBeginCapture failed");
+        else
+            capturing = true;
     }
+    if (!rc) {
+        hipEventRecord(ev[kBranches], cs[0]);
+        for (int k = 1; k < nb; ++k) hipStreamWaitEvent(cs[k], ev[kBranches], 0);
+        for (size_t gi = 0; gi < b->groups.size() && !rc; ++gi) {
+            const BatchGroup& g = b->groups[gi];
+            rc = g.lead->dtype == DEMAG_F32 ? enqueue_group<float>(g, b->Ms, cs[gi % nb])
+                                            : enqueue_group<double>(g, b->Ms, cs[gi % nb]);
+        }
+        for (int k = 1; k < nb; ++k) {
+            hipEventRecord(ev[k], cs[k]);
+            hipStreamWaitEvent(cs[0], ev[k], 0);
+        }
+    }
+    if (capturing) {
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(cs[0], &g);
+        if (!rc && e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
+        b->graph = g;
+        if (!rc && hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess)
+            rc = fail(DEMAG_EHIP, "hipGraphInstantiate failed");
+    }
+    for (int k = 0; k < nb; ++k) {
+        if (cs[k]) hipStreamDestroy(cs[k]);
+        if (ev[k]) hipEventDestroy(ev[k]);
+    }
+    if (ev[kBranches]) hipEventDestroy(ev[kBranches]);
+    return rc;
+}
+
+// Time candidate launch shapes of each pass of one group on the group's own
+// buffers (one launch covers all members) and keep the fastest.
+template <typename T>
+int tune_group(BatchGroup& g, hipStream_t st) {
+    demag_plan_s* p = g.lead;
+    BatchIO io[5];
+    group_io(g, io);
+    std::vector<LaunchCfg> cand[5] = {candidates_rows(p), candidates_pencils(p), candidates_z(p),
+                                      candidates_pencils(p), candidates_rows(p)};
+    const int kinds[5] = {0, 1, 2, 1, 0};
+    for (int w = 0; w < 5; ++w) add_p2_candidates(p, kinds[w], cand[w]);
+    LaunchCfg* slot[5] = {&g.cfg.xf, &g.cfg.yf, &g.cfg.zc, &g.cfg.yi, &g.cfg.xi};
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    hipError_t err = hipSuccess;
+    for (int w = 0; w < 5 && err == hipSuccess; ++w) {
+        float best = 1e30f;
+        LaunchCfg bestc = *slot[w];
+        for (const auto& lc : cand[w]) {
+            auto launch = [&]() { return launch_pass<T>(p, w, lc, st, nullptr, 1.0, nullptr, nullptr, nullptr, 0, io[w]); };
+            for (int r = 0; r < 2 && err == hipSuccess; ++r) err = launch();
+            float t_best = 1e30f;
+            for (int trial = 0; trial < 3 && err == hipSuccess; ++trial) {
+                err = hipEventRecord(e0, st);
+                for (int r = 0; r < 5 && err == hipSuccess; ++r) err = launch();
+                if (err == hipSuccess) err = hipEventRecord(e1, st);
+                if (err == hipSuccess) err = hipEventSynchronize(e1);
+                float ms = 0;
+                if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+                t_best = std::min(t_best, ms);
+            }
+            if (err != hipSuccess) break;
+            if (t_best < best) {
+                best = t_best;
+                bestc = lc;
+            }
+        }
+        *slot[w] = bestc;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_fail(err, "batch autotune timing");
     return DEMAG_OK;
 }
 }  // namespace
@@ -1098,51 +1202,12 @@ extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans,
         g.lead = plans[mem[0]];
         g.count = (int)mem.size();
         g.lists = (void**)b->dev_lists + off;
+        g.cfg = g.lead->cfg;
         off += 4 * (size_t)g.count;
         b->groups.push_back(g);
     }
-    const int nb = std::min<int>(kBranches, (int)b->groups.size());
-    hipStream_t cs[kBranches] = {};
-    hipEvent_t ev[kBranches + 1] = {};
-    for (int k = 0; k < nb && !rc; ++k)
-        if (hipStreamCreateWithFlags(&cs[k], hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) != hipSuccess)
-            rc = fail(DEMAG_EHIP, "cannot create capture streams");
-    if (!rc && hipEventCreateWithFlags(&ev[kBranches], hipEventDisableTiming) != hipSuccess)
-        rc = fail(DEMAG_EHIP, "cannot create capture event");
-    bool capturing = false;
-    if (!rc) {
-        if (hipStreamBeginCapture(cs[0], hipStreamCaptureModeThreadLocal) != hipSuccess)
-            rc = fail(DEMAG_EHIP, "hipStreamBeginCapture failed");
-        else
-            capturing = true;
-    }
-    if (!rc) {
-        hipEventRecord(ev[kBranches], cs[0]);
-        for (int k = 1; k < nb; ++k) hipStreamWaitEvent(cs[k], ev[kBranches], 0);
-        for (size_t gi = 0; gi < b->groups.size() && !rc; ++gi) {
-            const BatchGroup& g = b->groups[gi];
-            rc = g.lead->dtype == DEMAG_F32 ? enqueue_group<float>(g, Ms, cs[gi % nb])
-                                            : enqueue_group<double>(g, Ms, cs[gi % nb]);
-        }
-        for (int k = 1; k < nb; ++k) {
-            hipEventRecord(ev[k], cs[k]);
-            hipStreamWaitEvent(cs[0], ev[k], 0);
-        }
-    }
-    if (capturing) {
-        hipGraph_t g = nullptr;
-        hipError_t e = hipStreamEndCapture(cs[0], &g);
-        if (!rc && e != hipSuccess) rc = hip_fail(e, "hipStreamEndCapture");
-        b->graph = g;
-        if (!rc && hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess)
-            rc = fail(DEMAG_EHIP, "hipGraphInstantiate failed");
-    }
-    for (int k = 0; k < nb; ++k) {
-        if (cs[k]) hipStreamDestroy(cs[k]);
-        if (ev[k]) hipEventDestroy(ev[k]);
-    }
-    if (ev[kBranches]) hipEventDestroy(ev[kBranches]);
+    b->Ms = Ms;
+    if (!rc) rc = record_graph(b);
     if (rc) {
         if (b->exec) hipGraphExecDestroy(b->exec);
         if (b->graph) hipGraphDestroy(b->graph);
@@ -1152,6 +1217,26 @@ extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans,
     }
     *out = b;
     return DEMAG_OK;
+}
+
+extern "C" int demag_batch_autotune(demag_batch_t b, void* stream) {
+    if (!b || !b->exec) return fail(DEMAG_EINVAL, "NULL batch");
+    hipStream_t st = (hipStream_t)stream;
+    for (auto p : b->plans) {
+        int rc = enter(p, st);
+        if (rc) return rc;
+    }
+    int rc = DEMAG_OK;
+    for (auto& g : b->groups) {
+        rc = g.lead->dtype == DEMAG_F32 ? tune_group<float>(g, st) : tune_group<double>(g, st);
+        if (rc) break;
+    }
+    if (!rc) rc = record_graph(b);
+    for (auto p : b->plans) {
+        int r2 = leave(p, st);
+        if (!rc) rc = r2;
+    }
+    return rc;
 }
 
 extern "C" int demag_batch_launch(demag_batch_t b, void* stream) {

@@ -178,6 +178,11 @@ class Batch:
         _lib.call("demag_batch_create", ctypes.byref(b), arr_p, n, arr_m, arr_h, float(Ms), _stream_ptr())
         self._h = b
 
+    def autotune(self):
+        """Tune each geometry group's launch shapes on the group launch itself
+        (synchronous; the next launch() recomputes every H)."""
+        _lib.call("demag_batch_autotune", self._h, _stream_ptr())
+
     def launch(self):
         _lib.call("demag_batch_launch", self._h, _stream_ptr())
 

@@ -66,6 +66,7 @@ def test_null_handles_rejected():
     assert lib.demag_field_adjoint(None, None, 1.0, None, 0, None) == -1
     assert lib.demag_energy(None, None, 1.0, None, None) == -1
     assert lib.demag_plan_destroy(None) == -1
+    assert lib.demag_batch_autotune(None, None) == -1
     assert lib.demag_batch_launch(None, None) == -1
     assert lib.demag_batch_destroy(None) == -1
     assert lib.demag_plan_set_option(None, b"far_cut", 40.0) == -1
