@@ -97,6 +97,18 @@ __device__ __forceinline__ void dft8(cx<T>* v) {
     }
 }
 
+// radix-3 DFT of (v[0], v[1], 0): v[2] is not read
+template <int DIR, typename T>
+__device__ __forceinline__ void dft3_lo(cx<T>* v) {
+    const T s = T(0.86602540378443864676372317075293618347);  // sin(2 pi / 3)
+    const cx<T> a = v[0], b = v[1];
+    const cx<T> m = mk(a.re - T(0.5) * b.re, a.im - T(0.5) * b.im);
+    const cx<T> r = rot90<DIR>(scale(b, s));
+    v[0] = add(a, b);
+    v[1] = add(m, r);
+    v[2] = sub(m, r);
+}
+
 template <int DIR, typename T>
 __device__ __forceinline__ void dft3(cx<T>* v) {
     const T s = T(0.86602540378443864676372317075293618347);  // sin(2 pi / 3)

@@ -187,5 +187,206 @@ __device__ __forceinline__ void fft(cx<T>* v, cx<T>* slab, int t, const cx<T>* _
     stages_from<P, 0, DIR, LO>(v, slab, t, tws);
 }
 
+// ---------------------------------------------------------------------------
+// Length traits over the lengths the register transforms handle: P = 2^a and
+// P = 3 Q with Q = 2^a (a >= 1).  The pass kernels are written against these:
+//   EPT, TP, LOG_TP, PS, pad()     registers per thread, threads per pencil,
+//                                  LDS slab stride of one pencil of length P
+//   fin_k(j)   forward input slot j holds position  t + fin_k(j) TP
+//   iout_k(j)  inverse output slot j holds position t + iout_k(j) TP
+//   fout(t,j)  frequency held by forward output slot j
+//   iin(t,j)   frequency the inverse input slot j must hold
+//   fout_slab / iin_slab   their padded LDS positions
+//   fwd_slot_of_iin(j)     forward output slot with the frequency of inverse
+//                          input slot j (register hand-over in the Z pass)
+//   Tw<T>      one thread's twiddles (load from the thread-major table)
+//   fft<DIR, LO>(v, slab, t, tw)
+// In both cases positions >= P/2 are exactly the slots with fin_k or iout_k
+// >= EPT/2 (zero-skip of the forward input, pruning of the inverse output).
+constexpr bool is_pow2(int v) { return v >= 1 && (v & (v - 1)) == 0; }
+constexpr bool reg_length(int P) { return P >= 2 && (is_pow2(P) || (P % 3 == 0 && P >= 6 && is_pow2(P / 3))); }
+
+template <int P, bool POW2 = is_pow2(P)>
+struct Len;
+
+template <int P>
+struct Len<P, true> {
+    using F = Fft<P>;
+    static constexpr int EPT = F::EPT, TP = F::TP, LOG_TP = F::LOG_TP, PS = F::PS;
+    __host__ __device__ static constexpr int pad(int i) { return F::pad(i); }
+    __host__ __device__ static constexpr int pad_add(int pt, int a, int c) { return F::pad_add(pt, a, c); }
+    __host__ __device__ static constexpr int fin_k(int j) { return F::slot_in(j); }
+    __host__ __device__ static constexpr int iout_k(int j) { return F::slot_out(j); }
+    __device__ static int fout(int t, int j) { return t + F::slot_out(j) * TP; }
+    __device__ static int iin(int t, int j) { return t + F::slot_in(j) * TP; }
+    __device__ static int fout_slab(int pt, int t, int j) { return F::pad_add(pt, t, F::slot_out(j) * TP); }
+    __device__ static int iin_slab(int pt, int t, int j) { return F::pad_add(pt, t, F::slot_in(j) * TP); }
+    __host__ __device__ static constexpr int fwd_slot_of_iin(int j) {
+        for (int jj = 0; jj < EPT; ++jj)
+            if (F::slot_out(jj) == F::slot_in(j)) return jj;
+        return -1;
+    }
+    template <typename T>
+    using Tw = Twiddles<P, T>;
+    template <int DIR, bool LO, typename T>
+    __device__ static void fft(cx<T>* v, cx<T>* slab, int t, const Tw<T>& tw) {
+        p2::fft<P, DIR, LO>(v, slab, t, tw);
+    }
+    // the same with the twiddles read from the table `src` when needed
+    template <int DIR, bool LO, typename T>
+    __device__ static void fft_src(cx<T>* v, cx<T>* slab, int t, const cx<T>* __restrict__ src) {
+        Tw<T> tw;
+        tw.load(t, src);
+        p2::fft<P, DIR, LO>(v, slab, t, tw);
+    }
+    static constexpr int table_size() { return TwiddleTable<P>::table_size(); }
+    template <typename T>
+    static void fill(const cx<T>* tw, cx<T>* twt) {
+        TwiddleTable<P>::fill(tw, twt);
+    }
+};
+
+// P = 3 Q.  Position n = n1 + Q n2 (n1 < Q, n2 < 3), frequency k = 3 k1 + k2.
+// Forward: a radix-3 DFT over n2 for every n1, the twiddle W_P^(n1 k2), then
+// one Q-point transform per k2 (its output k1 is frequency 3 k1 + k2).
+// Inverse: the Q-point transforms first, the conjugate twiddle, then the
+// radix-3 DFT, whose output n2 is position n1 + Q n2.  Thread t keeps the
+// three Q-transforms' slots side by side: slot j = g EPTQ + jj, g = n2 (input
+// side) or k2 (frequency side).  The Q-transforms use the pencil's slab in
+// turn.  Twiddle table: the Q-transform's, then W_P^(m (t + k TPQ)) for m = 1,
+// 2 and k < EPTQ, thread-major.
+template <int P>
+struct Len<P, false> {
+    static_assert(P % 3 == 0 && is_pow2(P / 3) && P >= 6, "length 3 * 2^a");
+    static constexpr int Q = P / 3;
+    using FQ = Fft<Q>;
+    static constexpr int EQ = FQ::EPT;
+    static constexpr int EPT = 3 * EQ, TP = FQ::TP, LOG_TP = FQ::LOG_TP;
+    __host__ __device__ static constexpr int pad(int i) { return i + (i >> 3); }
+    __host__ __device__ static constexpr int pad_add(int pt, int a, int c) { return FQ::pad_add(pt, a, c); }
+    static constexpr int PS = pad(P) + 1;
+    __host__ __device__ static constexpr int fin_k(int j) { return FQ::slot_in(j % EQ) + (j / EQ) * EQ; }
+    __host__ __device__ static constexpr int iout_k(int j) { return FQ::slot_out(j % EQ) + (j / EQ) * EQ; }
+    __device__ static int fout(int t, int j) { return 3 * (t + FQ::slot_out(j % EQ) * TP) + j / EQ; }
+    __device__ static int iin(int t, int j) { return 3 * (t + FQ::slot_in(j % EQ) * TP) + j / EQ; }
+    __device__ static int fout_slab(int, int t, int j) { return pad(fout(t, j)); }
+    __device__ static int iin_slab(int, int t, int j) { return pad(iin(t, j)); }
+    __host__ __device__ static constexpr int fwd_slot_of_iin(int j) {
+        for (int jj = 0; jj < EQ; ++jj)
+            if (FQ::slot_out(jj) == FQ::slot_in(j % EQ)) return (j / EQ) * EQ + jj;
+        return -1;
+    }
+    template <typename T>
+    struct Tw {
+        Twiddles<Q, T> q;
+        cx<T> w3[2][EQ];  // W_P^(m (t + k TP)), m = 1, 2
+        __device__ __forceinline__ void load(int t, const cx<T>* __restrict__ twt) {
+            q.load(t, twt);
+            constexpr int TSQ = TwiddleTable<Q>::table_size();
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int k = 0; k < EQ; ++k) w3[m][k] = twt[TSQ + (m * EQ + k) * TP + t];
+        }
+    };
+    template <int DIR, bool LO, typename T>
+    __device__ static void fft(cx<T>* v, cx<T>* slab, int t, const Tw<T>& tw) {
+        if constexpr (DIR < 0) {
+#pragma unroll
+            for (int jj = 0; jj < EQ; ++jj) {
+                const int k = FQ::slot_in(jj);  // n1 = t + k TP
+                cx<T> y[3] = {v[jj], v[EQ + jj], v[2 * EQ + jj]};
+                // LO: positions >= P/2 are zero, i.e. n2 = 2 always and n2 = 1 for n1 >= Q/2
+                if constexpr (LO) {
+                    if (k >= EQ / 2) {  // a compile-time constant after unrolling
+                        y[1] = y[0];
+                        y[2] = y[0];
+                    } else {
+                        dft3_lo<DIR>(y);
+                    }
+                } else {
+                    dft3<DIR>(y);
+                }
+                v[jj] = y[0];
+                v[EQ + jj] = mul(y[1], tw.w3[0][k]);
+                v[2 * EQ + jj] = mul(y[2], tw.w3[1][k]);
+            }
+#pragma unroll
+            for (int g = 0; g < 3; ++g) p2::fft<Q, DIR, false>(v + g * EQ, slab, t, tw.q);
+        } else {
+#pragma unroll
+            for (int g = 0; g < 3; ++g) p2::fft<Q, DIR, false>(v + g * EQ, slab, t, tw.q);
+#pragma unroll
+            for (int jj = 0; jj < EQ; ++jj) {
+                const int k = FQ::slot_out(jj);  // n1 = t + k TP
+                cx<T> y[3] = {v[jj], mul(v[EQ + jj], conj_(tw.w3[0][k])), mul(v[2 * EQ + jj], conj_(tw.w3[1][k]))};
+                dft3<DIR>(y);
+                v[jj] = y[0];
+                v[EQ + jj] = y[1];
+                v[2 * EQ + jj] = y[2];
+            }
+        }
+    }
+    // The same with the twiddles read from the table `src` when needed: the
+    // radix-3 twiddles of one slot right before its radix-3 DFT, the
+    // Q-transforms' right before them (fewer live registers).
+    template <int DIR, bool LO, typename T>
+    __device__ static void fft_src(cx<T>* v, cx<T>* slab, int t, const cx<T>* __restrict__ src) {
+        constexpr int TSQ = TwiddleTable<Q>::table_size();
+        if constexpr (DIR < 0) {
+#pragma unroll
+            for (int jj = 0; jj < EQ; ++jj) {
+                const int k = FQ::slot_in(jj);
+                cx<T> y[3] = {v[jj], v[EQ + jj], v[2 * EQ + jj]};
+                if constexpr (LO) {
+                    if (k >= EQ / 2) {  // a compile-time constant after unrolling
+                        y[1] = y[0];
+                        y[2] = y[0];
+                    } else {
+                        dft3_lo<DIR>(y);
+                    }
+                } else {
+                    dft3<DIR>(y);
+                }
+                v[jj] = y[0];
+                v[EQ + jj] = mul(y[1], src[TSQ + k * TP + t]);
+                v[2 * EQ + jj] = mul(y[2], src[TSQ + (EQ + k) * TP + t]);
+            }
+            Twiddles<Q, T> q;
+            q.load(t, src);
+#pragma unroll
+            for (int g = 0; g < 3; ++g) p2::fft<Q, DIR, false>(v + g * EQ, slab, t, q);
+        } else {
+            {
+                Twiddles<Q, T> q;
+                q.load(t, src);
+#pragma unroll
+                for (int g = 0; g < 3; ++g) p2::fft<Q, DIR, false>(v + g * EQ, slab, t, q);
+            }
+#pragma unroll
+            for (int jj = 0; jj < EQ; ++jj) {
+                const int k = FQ::slot_out(jj);
+                cx<T> y[3] = {v[jj], mul(v[EQ + jj], conj_(src[TSQ + k * TP + t])),
+                              mul(v[2 * EQ + jj], conj_(src[TSQ + (EQ + k) * TP + t]))};
+                dft3<DIR>(y);
+                v[jj] = y[0];
+                v[EQ + jj] = y[1];
+                v[2 * EQ + jj] = y[2];
+            }
+        }
+    }
+    static constexpr int table_size() { return TwiddleTable<Q>::table_size() + 2 * Q; }
+    template <typename T>
+    static void fill(const cx<T>* tw, cx<T>* twt) {
+        cx<T> twq[Q];  // exp(-2 pi i t / Q) = tw[3 t]
+        for (int i = 0; i < Q; ++i) twq[i] = tw[3 * i];
+        TwiddleTable<Q>::fill(twq, twt);
+        constexpr int TSQ = TwiddleTable<Q>::table_size();
+        for (int m = 0; m < 2; ++m)
+            for (int k = 0; k < EQ; ++k)
+                for (int t = 0; t < TP; ++t) twt[TSQ + (m * EQ + k) * TP + t] = tw[((m + 1) * (t + k * TP)) % P];
+    }
+};
+
 }  // namespace p2
 }  // namespace demag

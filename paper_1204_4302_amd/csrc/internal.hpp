@@ -17,7 +17,8 @@ constexpr int kMaxThreads = 256;  // workgroup size bound of every pass kernel
 //   Y fwd / Y inv : t0 = kx per workgroup (Tx), t1 = z per workgroup (Tz)
 //   Z conv / fwd  : t0 = kx per workgroup (Tx)
 //
-// p2 = 1 selects the compile-time power-of-two kernels (passes_p2.hip); then
+// p2 = 1 selects the compile-time register kernels (passes_p2.hip; lengths
+// 2^a and 3 * 2^a); then
 // t0, t1 are log2 of the tile extents (X: Ty; Y: Tx, Tz; Z: Tx) and the
 // workgroup size follows from them (pencils x threads per pencil).
 struct LaunchCfg {
@@ -58,8 +59,11 @@ hipError_t launch_x_inv(const LaunchCfg&, hipStream_t, const cx<T>* in, T* out, 
                         const BatchIO& bio = BatchIO());
 hipError_t launch_energy_reduce(hipStream_t, const double* partials, int n, double scale, double* out);
 
-// power-of-two lengths (2 <= P <= 4096): compile-time instances
+// lengths 2^a and 3 * 2^a (2 <= P <= 4096): compile-time instances
+// compile-time register kernels ("p2" family): lengths 2^a and 3 * 2^a up to
+// 4096; the fused Z pass in FP64 only for 2^a
 bool p2_supported(int P);
+bool p2_z_supported(int P, size_t cbytes);
 int p2_threads_per_pencil(int P);
 int p2_slab_elems(int P);
 // The X and Y passes stage twiddle tables of at most this many bytes in LDS
@@ -68,10 +72,11 @@ int p2_slab_elems(int P);
 // its twiddles once per thread for six transforms and reads them from memory.
 constexpr size_t kP2TwLdsMax = 8192;
 size_t p2_twiddle_lds_bytes(int P, size_t cbytes);
+size_t p2_z_twiddle_lds_bytes(int P, size_t cbytes);  // extra LDS of a fused Z launch
 extern int kXcds;                       // XCDs of the device: 8 on MI355X; 1 turns the swizzle off
-constexpr int kP2MaxThreads = 1024;     // X and Y passes
+int p2_max_threads(int P);              // X and Y passes: 1024 (2^a) or 512 (3 * 2^a)
 constexpr int kP2MaxThreadsZ = 512;     // fused Z pass (three pencils per thread)
-// The power-of-two Z pass reaches B2 and the tensor octant through 32-bit
+// The register-kernel Z pass reaches B2 and the tensor octant through 32-bit
 // buffer offsets: one B2 component and the whole octant must each span fewer
 // bytes than this (larger shapes run the generic Z pass).
 constexpr size_t kP2BufLimit = 0xFFFFF000u;

@@ -56,14 +56,14 @@ __device__ __forceinline__ int xcd_tile(int nxcd) {
 // workgroup barrier publishes it.  Larger tables are read from global memory.
 template <typename T, int P>
 __host__ __device__ constexpr bool tw_in_lds() {
-    return p2::TwiddleTable<P>::table_size() * sizeof(cx<T>) <= kP2TwLdsMax;
+    return p2::Len<P>::table_size() * sizeof(cx<T>) <= kP2TwLdsMax;
 }
 template <typename T, int P>
 __device__ __forceinline__ const cx<T>* twiddle_source(cx<T>* lds, int npencils, const cx<T>* __restrict__ twt,
                                                        int tid, int nthr) {
     if constexpr (tw_in_lds<T, P>()) {
-        constexpr int TS = p2::TwiddleTable<P>::table_size();
-        cx<T>* dst = lds + npencils * p2::Fft<P>::PS;
+        constexpr int TS = p2::Len<P>::table_size();
+        cx<T>* dst = lds + npencils * p2::Len<P>::PS;
         for (int i = tid; i < TS; i += nthr) dst[i] = twt[i];
         return dst;
     } else {
@@ -71,15 +71,18 @@ __device__ __forceinline__ const cx<T>* twiddle_source(cx<T>* lds, int npencils,
     }
 }
 
-// register slot of the last stage whose position equals the first-stage input
-// position of slot j (forward output -> inverse input hand-over in registers)
-template <int P>
-__host__ __device__ constexpr int out_slot_for_in(int j) {
-    using F = p2::Fft<P>;
-    for (int jj = 0; jj < F::EPT; ++jj)
-        if (F::slot_out(jj) == F::slot_in(j)) return jj;
-    return -1;
+// One transform of a pencil with this thread's twiddles loaded from `src`
+// (thread-major table, in LDS or global memory).
+template <typename T, int P, int DIR, bool LO = false>
+__device__ __forceinline__ void run_fft(cx<T>* v, cx<T>* slab, int t, const cx<T>* __restrict__ src) {
+    p2::Len<P>::template fft_src<DIR, LO>(v, slab, t, src);
 }
+
+// Workgroup size bound of the X and Y kernels: 1024 threads for power-of-two
+// lengths; 512 for 3 * 2^a, whose threads hold three times the slots (up to
+// 256 registers then).
+template <int P>
+constexpr int xy_max_threads() { return p2::is_pow2(P) ? 1024 : 512; }
 
 // Global-memory views of pointers (per-grid pointers of a batch are read from
 // memory, where the compiler could not tell their address space).
@@ -181,14 +184,14 @@ __device__ __forceinline__ unsigned boff(bool valid, unsigned base, unsigned d) 
 // X forward (R2C of two rows per complex pencil).  1-D grid of
 // ceil(ny/Ty) * nz * C (* batch) tiles, block (Ty/2) * TP threads.
 template <typename T, int P>
-__global__ void __launch_bounds__(1024) kx_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, int nx, int ny,
+__global__ void __launch_bounds__(xy_max_threads<P>()) kx_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, int nx, int ny,
                                                int nz, int lgTy, int nxcd, const cx<T>* __restrict__ twt,
                                                BatchIO bio) {
-    using F = p2::Fft<P>;
+    using LT = p2::Len<P>;
     constexpr int Kx = P / 2 + 1;
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int p = tid >> F::LOG_TP, t = tid & (F::TP - 1);
+    const int p = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
     const int Ty = 1 << lgTy;
     const int nyt = (ny + Ty - 1) >> lgTy;
     int g;
@@ -203,41 +206,41 @@ __global__ void __launch_bounds__(1024) kx_fwd(const T* __restrict__ in, cx<T>* 
     const T* rb = in + (((size_t)c * nz + z) * ny + y0) * (size_t)nx;
     const gptr<const T> row0 = gmem(ok0 ? rb + (size_t)(2 * p) * nx : in);
     const gptr<const T> row1 = gmem(ok1 ? rb + (size_t)(2 * p + 1) * nx : in);
-    cx<T> v[F::EPT];
+    cx<T> v[LT::EPT];
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) {
-        const int k = F::slot_in(j);
-        const int x = t + k * F::TP;
-        if (k < F::EPT / 2) {  // the padded half is never read
+    for (int j = 0; j < LT::EPT; ++j) {
+        const int k = LT::fin_k(j);
+        const int x = t + k * LT::TP;
+        if (k < LT::EPT / 2) {  // the padded half is never read
             v[j] = mk(gldr_if(row0, x, ok0 && x < nx), gldr_if(row1, x, ok1 && x < nx));
         } else {
             v[j] = czero<T>();
         }
     }
-    cx<T>* slab = lds + p * F::PS;
-    const cx<T>* tws = twiddle_source<T, P>(lds, nthr >> F::LOG_TP, twt, tid, nthr);
+    cx<T>* slab = lds + p * LT::PS;
+    const cx<T>* tws = twiddle_source<T, P>(lds, nthr >> LT::LOG_TP, twt, tid, nthr);
     if constexpr (tw_in_lds<T, P>()) __syncthreads();
-    p2::fft<P, -1, true>(v, slab, t, tws);
+    run_fft<T, P, -1, true>(v, slab, t, tws);
     __syncthreads();
-    const int pt = F::pad(t);
+    const int pt = LT::pad(t);
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) slab[F::pad_add(pt, t, F::slot_out(j) * F::TP)] = v[j];
+    for (int j = 0; j < LT::EPT; ++j) slab[LT::fout_slab(pt, t, j)] = v[j];
     __syncthreads();
     // spectra of the two rows: X_even = (Z_k + conj Z_{P-k})/2, X_odd = (Z_k - conj Z_{P-k})/(2i),
     // written y-contiguous
     const gptr<cx<T>> dst = gmem(out + ((size_t)c * nz + z) * (size_t)Kx * ny + y0);
-    if constexpr (F::TP >= 2) {
+    if constexpr (LT::TP >= 2) {
         // nthr = (Ty/2) TP is a multiple of Ty: each thread keeps one row y
-        constexpr int KS = F::TP / 2, KN = (Kx + KS - 1) / KS;
+        constexpr int KS = LT::TP / 2, KN = (Kx + KS - 1) / KS;
         const int y = tid & (Ty - 1), k0 = tid >> lgTy;
         if (y < ty) {
-            const cx<T>* pen = lds + (y >> 1) * F::PS;
+            const cx<T>* pen = lds + (y >> 1) * LT::PS;
             cx<T> r[KN];
 #pragma unroll
             for (int i = 0; i < KN; ++i) {
                 const int k = k0 + i * KS;
                 if (k < Kx) {
-                    const cx<T> a = pen[F::pad(k)], b = pen[F::pad((P - k) & (P - 1))];
+                    const cx<T> a = pen[LT::pad(k)], b = pen[LT::pad(k == 0 ? 0 : P - k)];
                     r[i] = (y & 1) ? mk(T(0.5) * (a.im + b.im), T(0.5) * (b.re - a.re))
                                    : mk(T(0.5) * (a.re + b.re), T(0.5) * (a.im - b.im));
                 }
@@ -253,8 +256,8 @@ __global__ void __launch_bounds__(1024) kx_fwd(const T* __restrict__ in, cx<T>* 
         for (int e = tid; e < (Kx << lgTy); e += nthr) {
             const int y = e & (Ty - 1), k = e >> lgTy;
             if (y < ty) {
-                const cx<T>* pen = lds + (y >> 1) * F::PS;
-                const cx<T> a = pen[F::pad(k)], b = pen[F::pad((P - k) & (P - 1))];
+                const cx<T>* pen = lds + (y >> 1) * LT::PS;
+                const cx<T> a = pen[LT::pad(k)], b = pen[LT::pad(k == 0 ? 0 : P - k)];
                 gst(dst, (size_t)k * ny + y,
                     (y & 1) ? mk(T(0.5) * (a.im + b.im), T(0.5) * (b.re - a.re))
                             : mk(T(0.5) * (a.re + b.re), T(0.5) * (a.im - b.im)));
@@ -267,16 +270,16 @@ __global__ void __launch_bounds__(1024) kx_fwd(const T* __restrict__ in, cx<T>* 
 // X inverse (C2R of two rows per pencil), first nx outputs, optional
 // accumulate and energy partial (one FP64 value per workgroup).
 template <typename T, int P>
-__global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* __restrict__ out,
+__global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __restrict__ in, T* __restrict__ out,
                                                const T* __restrict__ m, double* __restrict__ partials, int nx,
                                                int ny, int nz, int lgTy, int accumulate, int nxcd,
                                                const cx<T>* __restrict__ twt, BatchIO bio) {
-    using F = p2::Fft<P>;
+    using LT = p2::Len<P>;
     constexpr int Kx = P / 2 + 1, Lx = P / 2;
     __shared__ double red[16];
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int p = tid >> F::LOG_TP, t = tid & (F::TP - 1);
+    const int p = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
     const int Ty = 1 << lgTy, lgB = lgTy - 1, Bp = Ty >> 1;
     const int nyt = (ny + Ty - 1) >> lgTy;
     int g;
@@ -292,7 +295,7 @@ __global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* 
     // pair q = tid mod Bp, frequencies k = tid / Bp + i TP: every load of the
     // thread is issued before the first LDS write
     {
-        constexpr int KI = (Kx + F::TP - 1) / F::TP;
+        constexpr int KI = (Kx + LT::TP - 1) / LT::TP;
         const int q = tid & (Bp - 1), k0 = tid >> lgB;
         const bool okq0 = 2 * q < ty, okq1 = 2 * q + 1 < ty;
         const cx<T>* qb = in + ((size_t)c * nz + z) * (size_t)Kx * ny + y0 + 2 * q;
@@ -300,43 +303,43 @@ __global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* 
         cx<T> xe[KI], xo[KI];
 #pragma unroll
         for (int i = 0; i < KI; ++i) {
-            const int k = k0 + i * F::TP;
+            const int k = k0 + i * LT::TP;
             xe[i] = gld_if(s0, (size_t)k * ny, k < Kx && okq0);
             xo[i] = gld_if(s1, (size_t)k * ny, k < Kx && okq1);
         }
-        cx<T>* pq = lds + q * F::PS;
+        cx<T>* pq = lds + q * LT::PS;
 #pragma unroll
         for (int i = 0; i < KI; ++i) {
-            const int k = k0 + i * F::TP;
+            const int k = k0 + i * LT::TP;
             if (k < Kx) {
                 cx<T> a = xe[i], b = xo[i];
                 if (k == 0 || k == Lx) {  // C2R ignores the imaginary parts of DC and Nyquist
                     a.im = T(0);
                     b.im = T(0);
                 }
-                pq[F::pad(k)] = mk(a.re - b.im, a.im + b.re);                           // xe + i xo
-                if (k > 0 && k < Lx) pq[F::pad(P - k)] = mk(a.re + b.im, b.re - a.im);  // conj(xe) + i conj(xo)
+                pq[LT::pad(k)] = mk(a.re - b.im, a.im + b.re);                           // xe + i xo
+                if (k > 0 && k < Lx) pq[LT::pad(P - k)] = mk(a.re + b.im, b.re - a.im);  // conj(xe) + i conj(xo)
             }
         }
     }
-    const cx<T>* tws = twiddle_source<T, P>(lds, nthr >> F::LOG_TP, twt, tid, nthr);
+    const cx<T>* tws = twiddle_source<T, P>(lds, nthr >> LT::LOG_TP, twt, tid, nthr);
     __syncthreads();
-    cx<T>* slab = lds + p * F::PS;
-    cx<T> v[F::EPT];
-    const int pt = F::pad(t);
+    cx<T>* slab = lds + p * LT::PS;
+    cx<T> v[LT::EPT];
+    const int pt = LT::pad(t);
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) v[j] = slab[F::pad_add(pt, t, F::slot_in(j) * F::TP)];
-    p2::fft<P, +1>(v, slab, t, tws);
+    for (int j = 0; j < LT::EPT; ++j) v[j] = slab[LT::iin_slab(pt, t, j)];
+    run_fft<T, P, +1>(v, slab, t, tws);
     const size_t rowbase = (((size_t)c * nz + z) * ny + y0 + 2 * p) * (size_t)nx;
     const gptr<T> dst = out ? gmem(out + rowbase) : nullptr;
     const gptr<const T> msrc = m ? gmem(m + rowbase) : nullptr;
     const bool ok0 = 2 * p < ty, ok1 = 2 * p + 1 < ty;
     double acc = 0.0;
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) {
-        const int k = F::slot_out(j);
-        const int x = t + k * F::TP;
-        if (k < F::EPT / 2 && x < nx) {  // the discarded half is never written
+    for (int j = 0; j < LT::EPT; ++j) {
+        const int k = LT::iout_k(j);
+        const int x = t + k * LT::TP;
+        if (k < LT::EPT / 2 && x < nx) {  // the discarded half is never written
             if (ok0) {
                 const T h = v[j].re;
                 if (msrc) acc += (double)(msrc[x] * h);
@@ -365,13 +368,13 @@ __global__ void __launch_bounds__(1024) kx_inv(const cx<T>* __restrict__ in, T* 
 // Y forward.  Tile Tz x Tx pencils (z, kx); pencil p = zi * Tx + xi.
 // 1-D grid of ceil(nz/Tz) * ceil(Kx/Tx) * C tiles, block Tz * Tx * TP.
 template <typename T, int P>
-__global__ void __launch_bounds__(1024) ky_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
+__global__ void __launch_bounds__(xy_max_threads<P>()) ky_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
                                                int nz, int Kx, int lgTz, int lgTx, int nxcd,
                                                const cx<T>* __restrict__ twt, BatchIO bio) {
-    using F = p2::Fft<P>;
+    using LT = p2::Len<P>;
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x;
-    const int p = tid >> F::LOG_TP, t = tid & (F::TP - 1);
+    const int p = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
     const int Tx = 1 << lgTx, Tz = 1 << lgTz;
     const int nzt = (nz + Tz - 1) >> lgTz, nxt = (Kx + Tx - 1) >> lgTx;
     int g;
@@ -385,48 +388,48 @@ __global__ void __launch_bounds__(1024) ky_fwd(const cx<T>* __restrict__ in, cx<
     const int xi = p & (Tx - 1), zi = p >> lgTx;
     const bool ok = xi < tx && zi < tz;
     const gptr<const cx<T>> src = gmem(ok ? in + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny : in);
-    cx<T> v[F::EPT];
+    cx<T> v[LT::EPT];
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) {
-        const int k = F::slot_in(j);
-        const int y = t + k * F::TP;
-        v[j] = k < F::EPT / 2 ? gld_if(src, y, ok && y < ny) : czero<T>();
+    for (int j = 0; j < LT::EPT; ++j) {
+        const int k = LT::fin_k(j);
+        const int y = t + k * LT::TP;
+        v[j] = k < LT::EPT / 2 ? gld_if(src, y, ok && y < ny) : czero<T>();
     }
-    cx<T>* slab = lds + p * F::PS;
-    const cx<T>* tws = twiddle_source<T, P>(lds, (int)blockDim.x >> F::LOG_TP, twt, tid, blockDim.x);
+    cx<T>* slab = lds + p * LT::PS;
+    const cx<T>* tws = twiddle_source<T, P>(lds, (int)blockDim.x >> LT::LOG_TP, twt, tid, blockDim.x);
     if constexpr (tw_in_lds<T, P>()) __syncthreads();
-    p2::fft<P, -1, true>(v, slab, t, tws);
+    run_fft<T, P, -1, true>(v, slab, t, tws);
     __syncthreads();
-    const int pt = F::pad(t);
+    const int pt = LT::pad(t);
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) slab[F::pad_add(pt, t, F::slot_out(j) * F::TP)] = v[j];
+    for (int j = 0; j < LT::EPT; ++j) slab[LT::fout_slab(pt, t, j)] = v[j];
     __syncthreads();
     // (zj, xj) = tid mod (Tz Tx), ky = tid / (Tz Tx) + i TP; z-contiguous runs
     const int lgB = lgTz + lgTx;
     const int zj = tid & (Tz - 1), xj = (tid >> lgTz) & (Tx - 1), ky0 = tid >> lgB;
     if (zj < tz && xj < tx) {
-        const cx<T>* pj = lds + ((zj << lgTx) + xj) * F::PS;
-        const int pk = F::pad(ky0);
-        cx<T> r[F::EPT];
+        const cx<T>* pj = lds + ((zj << lgTx) + xj) * LT::PS;
+        const int pk = LT::pad(ky0);
+        cx<T> r[LT::EPT];
 #pragma unroll
-        for (int i = 0; i < F::EPT; ++i) r[i] = pj[F::pad_add(pk, ky0, i * F::TP)];
+        for (int i = 0; i < LT::EPT; ++i) r[i] = pj[LT::pad_add(pk, ky0, i * LT::TP)];
         const gptr<cx<T>> dst = gmem(out + (((size_t)c * P + ky0) * Kx + kx0 + xj) * (size_t)nz + z0 + zj);
-        const size_t step = (size_t)F::TP * Kx * nz;
+        const size_t step = (size_t)LT::TP * Kx * nz;
 #pragma unroll
-        for (int i = 0; i < F::EPT; ++i) gst(dst, i * step, r[i]);
+        for (int i = 0; i < LT::EPT; ++i) gst(dst, i * step, r[i]);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Y inverse: first ny outputs, written y-contiguous.
 template <typename T, int P>
-__global__ void __launch_bounds__(1024) ky_inv(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
+__global__ void __launch_bounds__(xy_max_threads<P>()) ky_inv(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
                                                int nz, int Kx, int lgTz, int lgTx, int nxcd,
                                                const cx<T>* __restrict__ twt, BatchIO bio) {
-    using F = p2::Fft<P>;
+    using LT = p2::Len<P>;
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x;
-    const int p = tid >> F::LOG_TP, t = tid & (F::TP - 1);
+    const int p = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
     const int Tx = 1 << lgTx, Tz = 1 << lgTz;
     const int nzt = (nz + Tz - 1) >> lgTz, nxt = (Kx + Tx - 1) >> lgTx;
     int g;
@@ -445,31 +448,31 @@ __global__ void __launch_bounds__(1024) ky_inv(const cx<T>* __restrict__ in, cx<
         const bool okj = zj < tz && xj < tx;
         const gptr<const cx<T>> src =
             gmem(okj ? in + (((size_t)c * P + ky0) * Kx + kx0 + xj) * (size_t)nz + z0 + zj : in);
-        const size_t step = (size_t)F::TP * Kx * nz;
-        cx<T> ld[F::EPT];
+        const size_t step = (size_t)LT::TP * Kx * nz;
+        cx<T> ld[LT::EPT];
 #pragma unroll
-        for (int i = 0; i < F::EPT; ++i) ld[i] = gld_if(src, i * step, okj);
-        cx<T>* pj = lds + ((zj << lgTx) + xj) * F::PS;
-        const int pk = F::pad(ky0);
+        for (int i = 0; i < LT::EPT; ++i) ld[i] = gld_if(src, i * step, okj);
+        cx<T>* pj = lds + ((zj << lgTx) + xj) * LT::PS;
+        const int pk = LT::pad(ky0);
 #pragma unroll
-        for (int i = 0; i < F::EPT; ++i) pj[F::pad_add(pk, ky0, i * F::TP)] = ld[i];
+        for (int i = 0; i < LT::EPT; ++i) pj[LT::pad_add(pk, ky0, i * LT::TP)] = ld[i];
     }
-    const cx<T>* tws = twiddle_source<T, P>(lds, (int)blockDim.x >> F::LOG_TP, twt, tid, blockDim.x);
+    const cx<T>* tws = twiddle_source<T, P>(lds, (int)blockDim.x >> LT::LOG_TP, twt, tid, blockDim.x);
     __syncthreads();
-    cx<T>* slab = lds + p * F::PS;
-    cx<T> v[F::EPT];
-    const int pt = F::pad(t);
+    cx<T>* slab = lds + p * LT::PS;
+    cx<T> v[LT::EPT];
+    const int pt = LT::pad(t);
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) v[j] = slab[F::pad_add(pt, t, F::slot_in(j) * F::TP)];
-    p2::fft<P, +1>(v, slab, t, tws);
+    for (int j = 0; j < LT::EPT; ++j) v[j] = slab[LT::iin_slab(pt, t, j)];
+    run_fft<T, P, +1>(v, slab, t, tws);
     const int xi = p & (Tx - 1), zi = p >> lgTx;
     if (xi < tx && zi < tz) {
         const gptr<cx<T>> dst = gmem(out + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny);
 #pragma unroll
-        for (int j = 0; j < F::EPT; ++j) {
-            const int k = F::slot_out(j);
-            const int y = t + k * F::TP;
-            if (k < F::EPT / 2 && y < ny) gst(dst, y, v[j]);
+        for (int j = 0; j < LT::EPT; ++j) {
+            const int k = LT::iout_k(j);
+            const int y = t + k * LT::TP;
+            if (k < LT::EPT / 2 && y < ny) gst(dst, y, v[j]);
         }
     }
 }
@@ -478,28 +481,43 @@ __global__ void __launch_bounds__(1024) ky_inv(const cx<T>* __restrict__ in, cx<
 // Fused Z pass.  Group g = s * Tx + xi handles the three component pencils
 // at (kx0 + xi, ky_s), ky_0 = ky', ky_1 = Py - ky'; each thread keeps all
 // three components in registers, so the tensor product needs no exchange and
-// the forward output slots are the inverse input slots.
+// the forward output slots hand over to the inverse input slots in registers.
 // 1-D grid of ceil(Kx/Tx) * (Py/2 + 1) tiles, block 2 * Tx * TP.
 // Every B2 and tensor access is a raw buffer access (one resource per B2
 // component, one for the tensor octant with the component in the scalar
 // offset); the host guarantees that each range is below kOob.
+//
+// Register budget.  FP32 power-of-two lengths load the tensor values of all
+// the thread's frequencies together with the data, before the transforms, so
+// that their latency overlaps, and keep the thread's twiddles in registers for
+// all six transforms.  FP64 (twice the registers) and lengths 3 * 2^a (three
+// times the slots) load the tensor after the forward transforms and read the
+// twiddles per transform from the workgroup's LDS copy of the table (from
+// memory if it is larger than kP2TwLdsMax), which keeps them in registers.
+template <typename T, int P>
+__host__ __device__ constexpr bool z_keep_twiddles() {
+    return sizeof(T) == 4 && p2::is_pow2(P);
+}
+
 template <typename T, int P>
 __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2, const T* __restrict__ nhat, T Ms, int nz,
                                                 int Py, int Kx, int lgTx, int nxcd, const cx<T>* __restrict__ twt,
                                                 BatchIO bio) {
-    using F = p2::Fft<P>;
+    using LT = p2::Len<P>;
+    constexpr bool kPow2 = p2::is_pow2(P);
+    constexpr bool kKeep = z_keep_twiddles<T, P>();
     constexpr int Lz = P / 2;
     constexpr unsigned CB = sizeof(cx<T>), RB = sizeof(T);
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x;
-    const int g = tid >> F::LOG_TP, t = tid & (F::TP - 1);
+    const int g = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
     const int Tx = 1 << lgTx, Ly = Py >> 1;
     const int xi = g & (Tx - 1), s = g >> lgTx;
     const int nxt = (Kx + Tx - 1) >> lgTx;
     int gb;
-    const int L = batch_tile(xcd_tile(nxcd), bio, &gb);
+    const int tile = batch_tile(xcd_tile(nxcd), bio, &gb);
     if (bio.in) B2 = (cx<T>*)bio.out[gb];
-    const int kx0 = (L % nxt) << lgTx, kyp = L / nxt;
+    const int kx0 = (tile % nxt) << lgTx, kyp = tile / nxt;
     const int tx = min(Tx, Kx - kx0);
     const int ns = (kyp == 0 || kyp == Ly) ? 1 : 2;
     const bool ok = s < ns && xi < tx;
@@ -509,58 +527,65 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
                        make_buf(B2 + 2 * cstride, cstride * CB)};
     // byte offset of this lane's first element; zz = t + k TP adds k TP CB
     const unsigned row = (unsigned)((((size_t)ky * Kx + kx0 + xi) * nz + t) * CB);
-    cx<T> v[3][F::EPT];
+    cx<T> v[3][LT::EPT];
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
 #pragma unroll
-        for (int j = 0; j < F::EPT / 2; ++j) {  // first-stage slot j holds position k = j
-            const int zz = t + j * F::TP;
-            v[comp][j] = bld<T>(bc[comp], boff(ok && zz < nz, row, j * F::TP * CB));
+        for (int j = 0; j < LT::EPT; ++j) {
+            const int k = LT::fin_k(j);
+            const int zz = t + k * LT::TP;
+            v[comp][j] = k < LT::EPT / 2 ? bld<T>(bc[comp], boff(ok && zz < nz, row, k * LT::TP * CB)) : czero<T>();
         }
     }
-    // The tensor values of all this thread's frequencies.  Octant index
-    // kz' = kz for kz <= Lz, else P - kz; lanes outside the tile read row 0
-    // (their results are never stored).  In FP32 they are loaded together with
-    // the data, before the transforms, so that their latency overlaps, and the
-    // thread's twiddles are loaded once for all six transforms; in FP64 (twice
-    // the registers) both wait until needed, which keeps the kernel in
-    // registers.
-    constexpr bool kEarly = sizeof(T) == 4;     // tensor loaded before the transforms
-    constexpr bool kKeepTw = sizeof(T) == 4;    // twiddles held in registers across transforms
+    // Tensor values of this thread's frequencies kz (forward output slots);
+    // octant index kz' = kz for kz <= Lz, else P - kz; lanes outside the tile
+    // read row 0 (their results are never stored).
     const size_t cs = (size_t)Kx * (Lz + 1);  // component stride of the octant (elements)
     const Buf bt = make_buf(nhat, (size_t)(Ly + 1) * 6 * cs * RB);
     const unsigned trow = ok ? (unsigned)((((size_t)kyp * 6 * Kx + kx0 + xi) * (Lz + 1)) * RB) : 0u;
-    const unsigned tpos = trow + t * RB, tneg = trow + (F::TP - 1 - t) * RB;
-    T nt[F::EPT][6];
+    T nt[LT::EPT][6];
     auto load_tensor = [&]() {
 #pragma unroll
-        for (int j = 0; j < F::EPT; ++j) {
-            const int k = F::slot_out(j);
-            // kz = t + k TP; for k >= EPT/2, P - kz = (TP - 1 - t) + P - (k + 1) TP + 1
-            const unsigned off = k < F::EPT / 2 ? tpos + k * F::TP * RB : tneg + (P - (k + 1) * F::TP + 1) * RB;
+        for (int j = 0; j < LT::EPT; ++j) {
+            unsigned off;
+            if constexpr (kPow2) {
+                // kz = t + k TP; for k >= EPT/2, P - kz = (TP - 1 - t) + P - (k + 1) TP + 1
+                const int k = LT::F::slot_out(j);
+                off = k < LT::EPT / 2 ? trow + (t + k * LT::TP) * RB : trow + ((LT::TP - 1 - t) + P - (k + 1) * LT::TP + 1) * RB;
+            } else {
+                const int kz = LT::fout(t, j);
+                off = trow + (kz <= Lz ? kz : P - kz) * RB;
+            }
 #pragma unroll
             for (int q = 0; q < 6; ++q) nt[j][q] = bldr<T>(bt, off, (unsigned)(q * cs * RB));
         }
     };
-    if constexpr (kEarly) load_tensor();
-    cx<T>* slab = lds + g * F::PS;
+    if constexpr (kKeep) load_tensor();
+    cx<T>* slab = lds + g * LT::PS;
     const cx<T>* twsrc = twt;
-    p2::Twiddles<P, T> tws;
-    if constexpr (kKeepTw) tws.load(t, twsrc);
+    if constexpr (!kKeep) {
+        twsrc = twiddle_source<T, P>(lds, (int)blockDim.x >> LT::LOG_TP, twt, tid, blockDim.x);
+        if constexpr (tw_in_lds<T, P>()) __syncthreads();
+    }
+    typename LT::template Tw<T> tws;
+    if constexpr (kKeep) tws.load(t, twsrc);
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
-        if constexpr (kKeepTw) p2::fft<P, -1, true>(v[comp], slab, t, tws);
-        else p2::fft<P, -1, true>(v[comp], slab, t, twsrc);
+        if constexpr (kKeep) LT::template fft<-1, true>(v[comp], slab, t, tws);
+        else run_fft<T, P, -1, true>(v[comp], slab, t, twsrc);
     }
-    if constexpr (!kEarly) load_tensor();
+    if constexpr (!kKeep) load_tensor();
     // H^ = Nhat(kx, ky, kz) M^ (Ms applied at the store).  Octant lookup with
     // parity signs: xy, yz odd in ky (negative for ky > Ly, i.e. s = 1); xz, yz
-    // odd in kz, negative for kz > Lz, which is slot k >= EPT/2 except kz = Lz
-    // itself, where the odd components are exactly zero.
+    // odd in kz, negative for kz > Lz.  For power-of-two lengths that is slot
+    // k >= EPT/2 (a compile-time property) except kz = Lz itself, where the odd
+    // components are exactly zero.
     const T sy = s ? T(-1) : T(1);
 #pragma unroll
-    for (int j = 0; j < F::EPT; ++j) {
-        const bool negz = F::slot_out(j) >= F::EPT / 2;
+    for (int j = 0; j < LT::EPT; ++j) {
+        bool negz;
+        if constexpr (kPow2) negz = LT::F::slot_out(j) >= LT::EPT / 2;
+        else negz = LT::fout(t, j) > Lz;
         const T nxx = nt[j][0], nyy = nt[j][1], nzz = nt[j][2];
         const T nxy = sy * nt[j][3];
         const T nxz = negz ? -nt[j][4] : nt[j][4];
@@ -572,23 +597,23 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     }
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
-        cx<T> w[F::EPT];
+        cx<T> w[LT::EPT];
 #pragma unroll
-        for (int j = 0; j < F::EPT; ++j) w[j] = v[comp][out_slot_for_in<P>(j)];
-        if constexpr (kKeepTw) p2::fft<P, +1>(w, slab, t, tws);
-        else p2::fft<P, +1>(w, slab, t, twsrc);
+        for (int j = 0; j < LT::EPT; ++j) w[j] = v[comp][LT::fwd_slot_of_iin(j)];
+        if constexpr (kKeep) LT::template fft<+1, false>(w, slab, t, tws);
+        else run_fft<T, P, +1>(w, slab, t, twsrc);
 #pragma unroll
-        for (int j = 0; j < F::EPT; ++j) {
-            const int k = F::slot_out(j);
-            const int zz = t + k * F::TP;
-            if (k < F::EPT / 2)  // the discarded half is never written
-                bst<T>(bc[comp], boff(ok && zz < nz, row, k * F::TP * CB), mk(Ms * w[j].re, Ms * w[j].im));
+        for (int j = 0; j < LT::EPT; ++j) {
+            const int k = LT::iout_k(j);
+            const int zz = t + k * LT::TP;
+            if (k < LT::EPT / 2)  // the discarded half is never written
+                bst<T>(bc[comp], boff(ok && zz < nz, row, k * LT::TP * CB), mk(Ms * w[j].re, Ms * w[j].im));
         }
     }
 }
 
 template <int P>
-constexpr int tpp() { return p2::Fft<P>::TP; }
+constexpr int tpp() { return p2::Len<P>::TP; }
 
 // Dynamic LDS above 64 KB must be allowed per kernel before its launch.
 template <typename K>
@@ -602,38 +627,66 @@ hipError_t allow_lds(K kernel, size_t lds) {
 
 // ---------------------------------------------------------------------------
 // host launchers: switch on the runtime length to the compile-time instance
-#define DEMAG_P2_SWITCH(P, CALL)                 \
-    switch (P) {                                 \
-    case 2: CALL(2); break;                      \
-    case 4: CALL(4); break;                      \
-    case 8: CALL(8); break;                      \
-    case 16: CALL(16); break;                    \
-    case 32: CALL(32); break;                    \
-    case 64: CALL(64); break;                    \
-    case 128: CALL(128); break;                  \
-    case 256: CALL(256); break;                  \
-    case 512: CALL(512); break;                  \
-    case 1024: CALL(1024); break;                \
-    case 2048: CALL(2048); break;                \
-    case 4096: CALL(4096); break;                \
-    default: return hipErrorInvalidValue;        \
+#define DEMAG_P2_CASES_POW2(CALL)                                                                  \
+    case 2: CALL(2); break;                                                                        \
+    case 4: CALL(4); break;                                                                        \
+    case 8: CALL(8); break;                                                                        \
+    case 16: CALL(16); break;                                                                      \
+    case 32: CALL(32); break;                                                                      \
+    case 64: CALL(64); break;                                                                      \
+    case 128: CALL(128); break;                                                                    \
+    case 256: CALL(256); break;                                                                    \
+    case 512: CALL(512); break;                                                                    \
+    case 1024: CALL(1024); break;                                                                  \
+    case 2048: CALL(2048); break;                                                                  \
+    case 4096: CALL(4096); break;
+#define DEMAG_P2_CASES_3POW2(CALL)                                                                 \
+    case 6: CALL(6); break;                                                                        \
+    case 12: CALL(12); break;                                                                      \
+    case 24: CALL(24); break;                                                                      \
+    case 48: CALL(48); break;                                                                      \
+    case 96: CALL(96); break;                                                                      \
+    case 192: CALL(192); break;                                                                    \
+    case 384: CALL(384); break;                                                                    \
+    case 768: CALL(768); break;                                                                    \
+    case 1536: CALL(1536); break;                                                                  \
+    case 3072: CALL(3072); break;
+#define DEMAG_P2_SWITCH(P, CALL)                                                                   \
+    switch (P) {                                                                                   \
+        DEMAG_P2_CASES_POW2(CALL)                                                                  \
+        DEMAG_P2_CASES_3POW2(CALL)                                                                 \
+    default: return hipErrorInvalidValue;                                                          \
     }
 
 int kXcds = 8;  // XCDs of the device (workgroup swizzle); set by the plan runtime
 
-bool p2_supported(int P) { return P >= 2 && P <= 4096 && (P & (P - 1)) == 0; }
-int p2_threads_per_pencil(int P) { return P >= 8 ? P / 8 : 1; }
+bool p2_supported(int P) { return P <= 4096 && p2::reg_length(P); }
+bool p2_z_supported(int P, size_t cbytes) {
+    return p2_supported(P) && (p2::is_pow2(P) || cbytes == sizeof(cx<float>));
+}
+int p2_threads_per_pencil(int P) {
+    const int q = p2::is_pow2(P) ? P : P / 3;  // the power-of-two transforms' length
+    return q >= 8 ? q / 8 : 1;
+}
 int p2_slab_elems(int P) { return (P + (P >> 3)) + 1; }
-size_t p2_twiddle_lds_bytes(int P, size_t cbytes) {
-    size_t n = 0;
+int p2_max_threads(int P) { return p2::is_pow2(P) ? 1024 : 512; }  // xy_max_threads
+static size_t table_entries(int P) {
     switch (P) {
 #define TS(PP) \
-    case PP: n = (size_t)p2::TwiddleTable<PP>::table_size(); break;
+    case PP: return (size_t)p2::Len<PP>::table_size();
         TS(2) TS(4) TS(8) TS(16) TS(32) TS(64) TS(128) TS(256) TS(512) TS(1024) TS(2048) TS(4096)
+        TS(6) TS(12) TS(24) TS(48) TS(96) TS(192) TS(384) TS(768) TS(1536) TS(3072)
 #undef TS
     default: return 0;
     }
+}
+size_t p2_twiddle_lds_bytes(int P, size_t cbytes) {
+    const size_t n = table_entries(P);
     return n * cbytes <= kP2TwLdsMax ? n * cbytes : 0;
+}
+size_t p2_z_twiddle_lds_bytes(int P, size_t cbytes) {
+    const bool keep = cbytes == sizeof(cx<float>) && p2::is_pow2(P);  // z_keep_twiddles
+    return keep ? 0 : p2_twiddle_lds_bytes(P, cbytes);
 }
 
 template <typename T>
@@ -704,14 +757,22 @@ template <typename T>
 hipError_t launch_z_conv_p2(int lgTx, hipStream_t st, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx, int P,
                             const cx<T>* twt, const BatchIO& bio) {
     if (!twt) return hipErrorInvalidValue;
+    if (!p2_z_supported(P, sizeof(cx<T>))) return hipErrorInvalidValue;
     const int G = 2 << lgTx;
     dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * (Py / 2 + 1) * bio.count));
-    const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>);
+    const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
 #define CALL(PP) \
     if (hipError_t e_ = allow_lds(&kz_conv<T, PP>, lds)) return e_; \
     hipLaunchKernelGGL((kz_conv<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, kXcds, twt, \
                        bio)
-    DEMAG_P2_SWITCH(P, CALL)
+    if constexpr (sizeof(T) == 4) {
+        DEMAG_P2_SWITCH(P, CALL)
+    } else {  // FP64 lengths 3 * 2^a would not fit the registers: generic kernels
+        switch (P) {
+            DEMAG_P2_CASES_POW2(CALL)
+        default: return hipErrorInvalidValue;
+        }
+    }
 #undef CALL
     return hipGetLastError();
 }
@@ -723,10 +784,11 @@ std::vector<cx<T>> p2_thread_twiddles(int P, const std::vector<cx<T>>& tw) {
     switch (P) {
 #define FILL(PP)                                                      \
     case PP:                                                          \
-        out.resize(p2::TwiddleTable<PP>::table_size());               \
-        p2::TwiddleTable<PP>::fill(tw.data(), out.data());             \
+        out.resize(p2::Len<PP>::table_size());                        \
+        p2::Len<PP>::fill(tw.data(), out.data());                     \
         break;
         FILL(2) FILL(4) FILL(8) FILL(16) FILL(32) FILL(64) FILL(128) FILL(256) FILL(512) FILL(1024) FILL(2048) FILL(4096)
+        FILL(6) FILL(12) FILL(24) FILL(48) FILL(96) FILL(192) FILL(384) FILL(768) FILL(1536) FILL(3072)
 #undef FILL
     default: break;
     }

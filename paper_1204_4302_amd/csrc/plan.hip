@@ -244,6 +244,7 @@ int pow2_ceil_log(long v) {
 LaunchCfg p2_rows(int P, int rows, size_t cbytes, int target = 1024) {
     LaunchCfg c;
     c.p2 = 1;
+    target = std::min(target, p2_max_threads(P));
     const int TP = p2_threads_per_pencil(P);
     int lgB = ilog2i(std::max(1, target / TP));
     lgB = std::min(lgB, std::max(0, pow2_ceil_log(rows) - 1));
@@ -257,6 +258,7 @@ LaunchCfg p2_rows(int P, int rows, size_t cbytes, int target = 1024) {
 LaunchCfg p2_pencils(int P, int Kx, int nz, size_t cbytes, int target = 1024) {
     LaunchCfg c;
     c.p2 = 1;
+    target = std::min(target, p2_max_threads(P));
     const int TP = p2_threads_per_pencil(P);
     int lgB = ilog2i(std::max(1, target / TP));
     while (lgB > 0 && ((size_t)p2_slab_elems(P) << lgB) * cbytes + p2_twiddle_lds_bytes(P, cbytes) > g_p2_lds / 2)
@@ -275,7 +277,9 @@ LaunchCfg p2_zconv(int P, int Kx, size_t cbytes, int target = 64) {
     const int TP = p2_threads_per_pencil(P);
     int lgTx = std::max(0, ilog2i(std::max(1, target / (2 * TP))));
     lgTx = std::min(lgTx, pow2_ceil_log(Kx));
-    while (lgTx > 0 && ((size_t)p2_slab_elems(P) << (lgTx + 1)) * cbytes > g_p2_lds - 256) --lgTx;
+    while (lgTx > 0 &&
+           ((size_t)p2_slab_elems(P) << (lgTx + 1)) * cbytes + p2_z_twiddle_lds_bytes(P, cbytes) > g_p2_lds - 256)
+        --lgTx;
     while (lgTx > 0 && (2 * TP << lgTx) > kP2MaxThreadsZ) --lgTx;
     c.t0 = lgTx;
     c.threads = 2 * TP << lgTx;
@@ -288,8 +292,9 @@ bool p2_cfg_ok(const LaunchCfg& c, int P, size_t cbytes, int kind /*0 rows, 1 pe
     long pencils = kind == 0 ? (1L << (c.t0 - 1)) : kind == 1 ? (1L << (c.t0 + c.t1)) : (2L << c.t0);
     if (kind == 0 && c.t0 < 1) return false;
     long threads = pencils * TP;
-    long maxthr = kind == 2 ? kP2MaxThreadsZ : kP2MaxThreads;
-    const size_t tw = kind == 2 ? 0 : p2_twiddle_lds_bytes(P, cbytes);
+    long maxthr = kind == 2 ? kP2MaxThreadsZ : p2_max_threads(P);
+    if (kind == 2 && !p2_z_supported(P, cbytes)) return false;
+    const size_t tw = kind == 2 ? p2_z_twiddle_lds_bytes(P, cbytes) : p2_twiddle_lds_bytes(P, cbytes);
     return threads == c.threads && threads <= maxthr &&
            (size_t)pencils * p2_slab_elems(P) * cbytes + tw <= g_p2_lds - 256;  // + static reduction scratch
 }
@@ -321,8 +326,8 @@ bool plan_cfgs_ok(const demag_plan_s* p, const PassCfgs& c) {
            (!c.zc.p2 || p2_z_ranges_ok(p));
 }
 
-// Generic kernels (any 2^a 3^b 5^c length) unless the padded length is a power
-// of two, where the compile-time kernels are used.
+// Generic kernels (any 2^a 3^b 5^c length) unless the padded length is 2^a or
+// 3 * 2^a, where the compile-time register kernels are used.
 PassCfgs default_cfgs(const demag_plan_s* p) {
     size_t cb = csize(p->dtype);
     PassCfgs c;
@@ -330,7 +335,8 @@ PassCfgs default_cfgs(const demag_plan_s* p) {
     c.xi = c.xf;
     c.yf = p2_supported(p->P[1]) ? p2_pencils(p->P[1], p->Kx, p->n[2], cb) : cfg_pencils(p->P[1], p->Kx, p->n[2], cb);
     c.yi = c.yf;
-    c.zc = p2_supported(p->P[2]) && p2_z_ranges_ok(p) ? p2_zconv(p->P[2], p->Kx, cb) : cfg_zconv(p->P[2], p->Kx, cb);
+    c.zc = p2_z_supported(p->P[2], cb) && p2_z_ranges_ok(p) ? p2_zconv(p->P[2], p->Kx, cb)
+                                                             : cfg_zconv(p->P[2], p->Kx, cb);
     return c;
 }
 
@@ -854,7 +860,7 @@ std::vector<LaunchCfg> candidates_z(const demag_plan_s* p) {
 // power-of-two candidates: every tile whose workgroup and LDS fit
 void add_p2_candidates(const demag_plan_s* p, int kind, std::vector<LaunchCfg>& out) {
     const int P = p->P[kind == 0 ? 0 : kind == 1 ? 1 : 2];
-    if (!p2_supported(P) || (kind == 2 && !p2_z_ranges_ok(p))) return;
+    if (!p2_supported(P) || (kind == 2 && (!p2_z_supported(P, csize(p->dtype)) || !p2_z_ranges_ok(p)))) return;
     const size_t cb = csize(p->dtype);
     const int TP = p2_threads_per_pencil(P);
     for (int a = 0; a <= 10; ++a)

@@ -67,6 +67,7 @@ SHAPES = [
     ((4, 4, 64), (1.95e-9, 1.95e-9, 0.75e-9), 8e5),  # 8, 8, 128: thin pencils in x and y
     ((2, 3, 4), (2e-9, 2e-9, 2e-9), 8e5),          # 4, 6 (generic), 8
     ((29, 61, 11), (2e-9, 2e-9, 3e-9), 1.4e6),     # 64 (p2, 29 valid), 128 (p2, 61 valid), 24: ragged tiles
+    ((47, 11, 23), (2e-9, 2e-9, 3e-9), 1.4e6),     # 96, 24, 48 = 3 * 2^a, all ragged (47, 11, 23 valid)
 ]
 
 
@@ -84,7 +85,8 @@ def test_field_random_vs_oracle(shape, cell, Ms, dtype):
 
 
 @pytest.mark.parametrize("shape,cell,Ms", [((64, 32, 8), (2e-9, 2e-9, 3e-9), 1.4e6),
-                                            ((29, 61, 11), (2e-9, 2e-9, 3e-9), 1.4e6)], ids=str)
+                                            ((29, 61, 11), (2e-9, 2e-9, 3e-9), 1.4e6),
+                                            ((47, 11, 23), (2e-9, 2e-9, 3e-9), 1.4e6)], ids=str)
 def test_generic_and_pow2_kernels_agree(shape, cell, Ms):
     """Both kernel families on one plan: each within the bar of the oracle."""
     from paper_1204_4302_amd import Plan
