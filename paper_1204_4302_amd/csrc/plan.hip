@@ -160,6 +160,7 @@ struct demag_plan_s {
     double setup_us = 0;
     int device = 0;
     hipEvent_t done = nullptr;
+    hipEvent_t busy = nullptr;  // marks the plan's last enqueued work: `done`, or its batch's event
     hipStream_t last_stream = nullptr;
     bool used = false;
     bool capturing = false;
@@ -183,6 +184,7 @@ struct demag_batch_s {
     std::vector<demag_plan_t> plans;
     std::vector<BatchGroup> groups;
     void* dev_lists = nullptr;
+    hipEvent_t done = nullptr;  // recorded after every replay; the members' busy marker
     double Ms = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -533,8 +535,8 @@ int enter(demag_plan_s* p, hipStream_t st) {
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
     if (cur != p->device) return fail(DEMAG_ESTATE, "plan was created on device %d, current device is %d", p->device, cur);
-    if (p->used && st != p->last_stream) {
-        hipError_t q = hipEventQuery(p->done);
+    if (p->used && st != p->last_stream && p->busy) {
+        hipError_t q = hipEventQuery(p->busy);
         if (q == hipErrorNotReady)
             return fail(DEMAG_ESTATE, "plan is still busy on another stream");
         if (q != hipSuccess) return hip_fail(q, "hipEventQuery");
@@ -545,6 +547,7 @@ int enter(demag_plan_s* p, hipStream_t st) {
 int leave(demag_plan_s* p, hipStream_t st) {
     if (p->capturing) return DEMAG_OK;
     HIP_TRY(hipEventRecord(p->done, st));
+    p->busy = p->done;
     p->last_stream = st;
     p->used = true;
     return DEMAG_OK;
@@ -1213,10 +1216,15 @@ extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans,
         b->groups.push_back(g);
     }
     b->Ms = Ms;
+    if (!rc && hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+        b->done = nullptr;
+        rc = fail(DEMAG_EHIP, "hipEventCreate failed");
+    }
     if (!rc) rc = record_graph(b);
     if (rc) {
         if (b->exec) hipGraphExecDestroy(b->exec);
         if (b->graph) hipGraphDestroy(b->graph);
+        if (b->done) hipEventDestroy(b->done);
         hipFree(b->dev_lists);
         delete b;
         return rc;
@@ -1245,6 +1253,8 @@ extern "C" int demag_batch_autotune(demag_batch_t b, void* stream) {
     return rc;
 }
 
+// One event for the whole replay (not one per member: the host cost of the
+// per-member bookkeeping would exceed the replay itself for small grids).
 extern "C" int demag_batch_launch(demag_batch_t b, void* stream) {
     if (!b || !b->exec) return fail(DEMAG_EINVAL, "NULL batch");
     hipStream_t st = (hipStream_t)stream;
@@ -1253,9 +1263,11 @@ extern "C" int demag_batch_launch(demag_batch_t b, void* stream) {
         if (rc) return rc;
     }
     HIP_TRY(hipGraphLaunch(b->exec, st));
+    HIP_TRY(hipEventRecord(b->done, st));
     for (auto p : b->plans) {
-        int rc = leave(p, st);
-        if (rc) return rc;
+        p->busy = b->done;
+        p->last_stream = st;
+        p->used = true;
     }
     return DEMAG_OK;
 }
@@ -1263,8 +1275,11 @@ extern "C" int demag_batch_launch(demag_batch_t b, void* stream) {
 extern "C" int demag_batch_destroy(demag_batch_t b) {
     if (!b) return fail(DEMAG_EINVAL, "NULL batch");
     hipDeviceSynchronize();
+    for (auto p : b->plans)  // the replays are complete: drop the reference to the batch's event
+        if (p->busy == b->done) p->busy = nullptr;
     if (b->exec) hipGraphExecDestroy(b->exec);
     if (b->graph) hipGraphDestroy(b->graph);
+    if (b->done) hipEventDestroy(b->done);
     hipFree(b->dev_lists);
     delete b;
     return DEMAG_OK;
