@@ -19,6 +19,11 @@ Functions and the passages they follow (Abert et al., arXiv:1204.4302):
                      selected cells: ``field_T_targets``).
 * ``energy``      -- E = -(mu0/2) Ms V sum m.H, Sec. 2 (stray-field energy).
 * ``matrix``      -- the explicit 3N x 3N operator for tiny grids.
+
+The scalar-potential method (SP, Sec. 3.1 eqs. (scpot), (convolution),
+(field)) is in ``sp_oracle.c``, class ``SPOracle``: the kernel S of
+homogeneously magnetized cells (two charged faces per cell), the potential as
+a plain sum, and the field as its finite-difference gradient.
 """
 from __future__ import annotations
 
@@ -30,6 +35,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "demag_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "sp_oracle.c")]
 _LIB = os.path.join(_HERE, "_demag_oracle.so")
 _lib = None
 
@@ -40,10 +46,10 @@ def build(force: bool = False, extra_flags: list[str] | None = None,
           out: str | None = None) -> str:
     """Compile the oracle with gcc (-O2, OpenMP, libquadmath)."""
     out = out or _LIB
-    if not force and os.path.exists(out) and os.path.getmtime(out) >= os.path.getmtime(_SRC):
+    if not force and os.path.exists(out) and all(os.path.getmtime(out) >= os.path.getmtime(f) for f in _SRCS):
         return out
     cmd = ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-std=gnu11",
-           _SRC, "-o", out + ".tmp", "-lquadmath", "-lm"]
+           *_SRCS, "-o", out + ".tmp", "-lquadmath", "-lm"]
     if extra_flags:
         cmd[1:1] = list(extra_flags)
     subprocess.run(cmd, check=True)
@@ -82,6 +88,20 @@ def load(path: str | None = None):
     lib.oracle_mu0.restype = d
     lib.oracle_threads.argtypes = []
     lib.oracle_threads.restype = i
+    lib.sp_face_potential.argtypes = [d, d, d, d, d]
+    lib.sp_face_potential.restype = d
+    lib.oracle_sp_kernel_at.argtypes = [i, l, l, l, d, d, d]
+    lib.oracle_sp_kernel_at.restype = d
+    lib.oracle_sp_kernel.argtypes = [i, i, i, d, d, d, p]
+    lib.oracle_sp_kernel.restype = i
+    lib.oracle_sp_potential.argtypes = [i, i, i, p, p, d, p]
+    lib.oracle_sp_potential.restype = i
+    lib.oracle_sp_gradient.argtypes = [i, i, i, d, d, d, p, p]
+    lib.oracle_sp_gradient.restype = i
+    lib.oracle_sp_field.argtypes = [i, i, i, d, d, d, p, p, d, p]
+    lib.oracle_sp_field.restype = i
+    lib.oracle_sp_field_targets.argtypes = [i, i, i, d, d, d, p, p, d, p, l, p]
+    lib.oracle_sp_field_targets.restype = i
     if path is None:
         _lib = lib
     return lib
@@ -177,6 +197,74 @@ class Oracle:
         if self.lib.oracle_matrix(*self.shape, _ptr(self.Noct), float(Ms), _ptr(A)) != 0:
             raise ValueError("grid too large for an explicit matrix")
         return A
+
+
+class SPOracle:
+    """The SP method on one grid: kernel octant S (FP64, from binary128 face
+    potentials), potential phi = Ms S * m as a plain sum, H = -grad phi by
+    finite differences (central inside, second-order one-sided on the faces)."""
+
+    def __init__(self, shape, cell, lib=None):
+        self.lib = lib or load()
+        self.shape = tuple(int(v) for v in shape)
+        self.cell = tuple(float(v) for v in cell)
+        nx, ny, nz = self.shape
+        self.Soct = np.empty((3, nz, ny, nx), dtype=np.float64)
+        if self.lib.oracle_sp_kernel(nx, ny, nz, *self.cell, _ptr(self.Soct)) != 0:
+            raise ValueError("oracle_sp_kernel failed")
+
+    @property
+    def volume(self) -> float:
+        dx, dy, dz = self.cell
+        return dx * dy * dz
+
+    def potential(self, m, Ms):
+        m = _vec(m, self.shape)
+        nx, ny, nz = self.shape
+        phi = np.empty((nz, ny, nx), dtype=np.float64)
+        self.lib.oracle_sp_potential(*self.shape, _ptr(self.Soct), _ptr(m), float(Ms), _ptr(phi))
+        return phi
+
+    def gradient(self, phi):
+        nx, ny, nz = self.shape
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(nz, ny, nx)
+        H = np.empty((3, nz, ny, nx), dtype=np.float64)
+        self.lib.oracle_sp_gradient(*self.shape, *self.cell, _ptr(phi), _ptr(H))
+        return H
+
+    def field(self, m, Ms):
+        m = _vec(m, self.shape)
+        H = np.empty_like(m)
+        if self.lib.oracle_sp_field(*self.shape, *self.cell, _ptr(self.Soct), _ptr(m), float(Ms), _ptr(H)) != 0:
+            raise MemoryError("oracle_sp_field")
+        return H
+
+    def field_targets(self, m, Ms, targets):
+        m = _vec(m, self.shape)
+        t = np.ascontiguousarray(targets, dtype=np.int64)
+        out = np.empty((3, t.size), dtype=np.float64)
+        rc = self.lib.oracle_sp_field_targets(*self.shape, *self.cell, _ptr(self.Soct), _ptr(m), float(Ms),
+                                              _ptr(t), t.size, _ptr(out))
+        if rc != 0:
+            raise ValueError("target index out of range")
+        return out
+
+    def energy(self, m, H, Ms) -> float:
+        m = _vec(m, self.shape)
+        H = _vec(H, self.shape)
+        return load().oracle_energy(*self.shape, *self.cell, _ptr(m), _ptr(H), float(Ms))
+
+
+def sp_kernel_at(a: int, offset, cell) -> float:
+    """S_a at one signed integer offset, straight from the two faces (binary128)."""
+    ox, oy, oz = (int(v) for v in offset)
+    return load().oracle_sp_kernel_at(int(a), ox, oy, oz, *(float(c) for c in cell))
+
+
+def face_potential(X, Y, W, A, B) -> float:
+    """Newton potential at (X, Y, W) of the unit-density rectangle A x B
+    centred at the origin in the plane W = 0."""
+    return load().sp_face_potential(float(X), float(Y), float(W), float(A), float(B))
 
 
 def threads() -> int:

@@ -1,0 +1,186 @@
+"""Pins of the SP oracle (scalar potential + finite-difference gradient,
+Sec. 3.1 eqs. (scpot), (convolution), (field)) against what the mathematics
+fixes independently of the oracle's own formulas:
+
+* the charged-rectangle potential against brute-force 2-D Gauss-Legendre
+  quadrature of its defining integral;
+* parity of the kernel S_a (odd in axis a, even in the others) and its
+  point-dipole limit V R_a / (4 pi |R|^3);
+* superposition: for a uniform magnetization the cells' potentials sum to the
+  potential of the whole block, i.e. of its two charged faces;
+* the difference stencils are exact on quadratic potentials;
+* convergence of the uniform-cube energy to the exact mu0 Ms^2 V / 6 (Sec. 5.1);
+* the paper's SP tables (Sec. 5): the SP energies and field errors w.r.t. DM
+  printed there bound ours in order of magnitude (the paper does not give its
+  difference stencil, so they cannot agree to the digit).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1204_4302_amd import inputs
+
+
+def gl_rect_potential(X, Y, W, A, B, n=400):
+    """Brute-force quadrature of int int dx dy / |(X,Y,W) - (x,y,0)| over the
+    rectangle [-A/2, A/2] x [-B/2, B/2] (panels split at X, Y when inside)."""
+    t, w = np.polynomial.legendre.leggauss(n)
+
+    def nodes(lo, hi, cut):
+        parts = [(lo, hi)] if not (lo < cut < hi) else [(lo, cut), (cut, hi)]
+        xs, ws = [], []
+        for a, b in parts:
+            xs.append(0.5 * (b - a) * t + 0.5 * (a + b))
+            ws.append(0.5 * (b - a) * w)
+        return np.concatenate(xs), np.concatenate(ws)
+
+    xs, wx = nodes(-A / 2, A / 2, X)
+    ys, wy = nodes(-B / 2, B / 2, Y)
+    R = np.sqrt((X - xs[:, None]) ** 2 + (Y - ys[None, :]) ** 2 + W * W)
+    return float((wx[:, None] * wy[None, :] / R).sum())
+
+
+@pytest.mark.parametrize("pt", [(0.3, 0.2, 0.7), (-1.4, 0.9, 0.05), (2.5, -3.0, 1.5), (1.7, 0.1, 0.0),
+                                (0.0, 0.0, 0.4), (-0.6, -1.2, 0.0)])
+def test_face_potential_vs_quadrature(pt):
+    X, Y, W = pt
+    A, B = 1.0, 2.0
+    ref = gl_rect_potential(X, Y, W, A, B)
+    got = oracle.face_potential(X, Y, W, A, B)
+    assert abs(got / ref - 1) < 1e-9, (got, ref)
+
+
+def test_kernel_parity_and_zero_plane():
+    cell = (2e-9, 2e-9, 3e-9)
+    rng = np.random.default_rng(7)
+    for _ in range(20):
+        o = rng.integers(-6, 7, size=3)
+        for a in range(3):
+            v = oracle.sp_kernel_at(a, o, cell)
+            for axis in range(3):
+                f = o.copy()
+                f[axis] = -f[axis]
+                s = -1.0 if axis == a else 1.0
+                assert oracle.sp_kernel_at(a, f, cell) == pytest.approx(s * v, rel=1e-14, abs=1e-40)
+            z = o.copy()
+            z[a] = 0
+            assert abs(oracle.sp_kernel_at(a, z, cell)) <= 1e-15 * abs(oracle.sp_kernel_at(a, (1, 0, 0) if a == 0 else
+                                                                                        (0, 1, 0) if a == 1 else (0, 0, 1),
+                                                                                        cell))
+
+
+@pytest.mark.parametrize("cell", [(1.0, 1.0, 1.0), (2.0, 2.0, 3.0), (1.95, 1.95, 0.75)])
+def test_kernel_dipole_limit(cell):
+    """S_a(R) -> V R_a / (4 pi |R|^3), the correction falling like |R|^-2."""
+    V = cell[0] * cell[1] * cell[2]
+    direction = np.array([3, 2, 1])
+    errs = []
+    for k in (8, 16, 32):
+        o = direction * k
+        R = o * np.array(cell)
+        r = np.linalg.norm(R)
+        for a in range(3):
+            dip = V * R[a] / (4 * np.pi * r ** 3)
+            errs.append((k, abs(oracle.sp_kernel_at(a, o, cell) / dip - 1)))
+    by_k = {}
+    for k, e in errs:
+        by_k[k] = max(by_k.get(k, 0.0), e)
+    assert by_k[32] < 1e-3
+    assert by_k[32] < by_k[16] / 3 < by_k[8] / 9
+
+
+def test_octant_matches_direct_faces():
+    """The octant (reduced units) equals the kernel evaluated in physical units."""
+    shape, cell = (7, 5, 4), (2e-9, 2e-9, 3e-9)
+    so = oracle.SPOracle(shape, cell)
+    for a in range(3):
+        for o in [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (6, 4, 3), (3, 2, 1), (5, 0, 2)]:
+            ref = oracle.sp_kernel_at(a, o, cell)
+            got = so.Soct[a, o[2], o[1], o[0]]
+            assert got == pytest.approx(ref, rel=1e-13, abs=1e-30)
+
+
+@pytest.mark.parametrize("a", [0, 1, 2])
+def test_superposition_uniform_block(a):
+    """Uniform m along a: the potential at every cell centre is that of the
+    whole block, whose charges sit on its two faces normal to a."""
+    shape, cell = (9, 6, 5), (2.0, 1.5, 3.0)
+    Ms = 1.7
+    so = oracle.SPOracle(shape, cell)
+    d = np.zeros(3)
+    d[a] = 1.0
+    m = inputs.uniform(shape, d)
+    phi = so.potential(m, Ms)
+    size = np.array(shape) * np.array(cell)
+    b, c = (a + 1) % 3, (a + 2) % 3
+    nx, ny, nz = shape
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                r = (np.array([x, y, z]) + 0.5) * np.array(cell) - size / 2  # relative to the block centre
+                top = oracle.face_potential(r[b], r[c], r[a] - size[a] / 2, size[b], size[c])
+                bot = oracle.face_potential(r[b], r[c], r[a] + size[a] / 2, size[b], size[c])
+                ref = Ms * (top - bot) / (4 * np.pi)
+                assert phi[z, y, x] == pytest.approx(ref, rel=1e-11, abs=1e-12 * abs(Ms * size.max()))
+
+
+def test_gradient_exact_on_quadratics():
+    """Central and second-order one-sided differences reproduce the gradient
+    of any quadratic exactly (first order with two cells: linear only)."""
+    shape, cell = (6, 5, 3), (0.7, 1.3, 2.1)
+    so = oracle.SPOracle(shape, cell)
+    X, Y, Z = inputs.cell_centres(shape, cell)
+    phi = 1.5 + 0.3 * X - 2.0 * Y + 0.7 * Z + 0.4 * X * X - 0.2 * Y * Y + 0.9 * Z * Z + 0.25 * X * Y - 0.6 * Y * Z + 1.1 * X * Z
+    H = so.gradient(phi)
+    ref = -np.stack([0.3 + 0.8 * X + 0.25 * Y + 1.1 * Z,
+                     -2.0 - 0.4 * Y + 0.25 * X - 0.6 * Z,
+                     0.7 + 1.8 * Z - 0.6 * Y + 1.1 * X])
+    assert np.abs(H - ref).max() < 1e-12 * np.abs(ref).max()
+    thin = oracle.SPOracle((4, 3, 2), cell)
+    X, Y, Z = inputs.cell_centres((4, 3, 2), cell)
+    H = thin.gradient(0.5 * X - 1.5 * Y + 2.5 * Z)
+    assert np.allclose(H[0], -0.5) and np.allclose(H[1], 1.5) and np.allclose(H[2], -2.5)
+    flat = oracle.SPOracle((4, 3, 1), cell)
+    X, Y, Z = inputs.cell_centres((4, 3, 1), cell)
+    assert np.all(flat.gradient(X + Y)[2] == 0)
+
+
+def test_uniform_cube_energy_converges():
+    """Sec. 5.1: the exact energy of the uniform cube is mu0 Ms^2 V / 6."""
+    errs = {}
+    for n in (4, 8, 16):
+        so = oracle.SPOracle((n, n, n), (1.0 / n,) * 3)
+        m = inputs.uniform((n, n, n), (0, 0, 1))
+        e = so.energy(m, so.field(m, 1.0), 1.0) / (oracle.MU0 / 6)
+        errs[n] = abs(e - 1)
+    assert errs[8] < 1e-2 and errs[16] < 1e-3
+    assert errs[16] < errs[8] < errs[4]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,shape,body,state,e_sp_paper,relerr_paper", [
+    ("cube_homo", (40, 40, 40), (1, 1, 1), "uniform_z", 1.0 / 6 * (1 - 1.1e-3), 1.1e-3),
+    ("cube_flower", (40, 40, 40), (1, 1, 1), "flower", 1.526e-01, 1.8e-3),
+    ("cube_vortex", (40, 40, 40), (1, 1, 1), "vortex", 2.163e-02, 2.4e-3),
+])
+def test_paper_sp_tables_order_of_magnitude(name, shape, body, state, e_sp_paper, relerr_paper):
+    """Sec. 5 Tables cube_homo / cube_flower / cube_vortex, SP rows: energy and
+    field error w.r.t. DM (eq. (relerr)).  Ours must be at least as close to
+    DM in energy as the paper's SP, and its field error of the same order."""
+    cell = tuple(body[k] / shape[k] for k in range(3))
+    if state == "uniform_z":
+        m = inputs.uniform(shape, (0, 0, 1))
+        e_dm = 1.0 / 6
+    elif state == "flower":
+        m = inputs.paper_flower(shape, cell, a=1.0, b=2.0, c=1.0)
+        e_dm = 1.528e-01
+    else:
+        m = inputs.paper_vortex(shape, cell, rc=0.14)
+        e_dm = 2.189e-02
+    so = oracle.SPOracle(shape, cell)
+    Hsp = so.field(m, 1.0)
+    e_sp = so.energy(m, Hsp, 1.0) / oracle.MU0
+    assert abs(e_sp / e_dm - 1) <= abs(e_sp_paper / e_dm - 1) + 1e-3
+    Hdm = oracle.Oracle(shape, cell).field(m, 1.0)
+    relerr = np.sqrt(((Hsp - Hdm) ** 2).sum() / np.prod(shape))
+    assert relerr_paper / 5 < relerr < 5 * relerr_paper
