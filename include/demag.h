@@ -114,6 +114,29 @@ int demag_plan_spectrum(demag_plan_t plan, void* out);
  * memory `out` [6][nz][ny][nx] (components xx yy zz xy xz yz).  Synchronous. */
 int demag_plan_tensor(demag_plan_t plan, double* out);
 
+/* ---- Scalar-potential method (SP), Sec. 3.1 eqs. (scpot), (convolution),
+ * (field) -------------------------------------------------------------------
+ * phi = Ms S * m on the cell centres, S_a(R) the potential at R of a cell
+ * magnetized along axis a with unit magnetization (two charged faces), then
+ * H = -grad phi by finite differences: central inside, second-order one-sided
+ * on the grid's faces (first order with two cells along an axis, zero with
+ * one).  Same plan, buffers, layouts and units as the DM calls.
+ *
+ * demag_sp_prepare builds the kernel spectrum (FP64 setup; distance bands as
+ * for the tensor; Im of the transform of the odd kernel on the octant with
+ * h/(Px Py Pz) folded in) once; synchronous.  DEMAG_EUNSUPPORTED unless the
+ * padded z length is 2^a or 3 * 2^a (FP64: 2^a); idempotent. */
+int demag_sp_prepare(demag_plan_t plan, void* stream);
+/* H (device, [3][nz][ny][nx]) for m; asynchronous on `stream`.  DEMAG_ESTATE
+ * before demag_sp_prepare.  m and H must not alias. */
+int demag_sp_field(demag_plan_t plan, const void* m, double Ms, void* H, void* stream);
+/* The same and the energy -(mu0/2) Ms V sum m.H into the device double
+ * *E_dev; H may be NULL (energy only). */
+int demag_sp_field_energy(demag_plan_t plan, const void* m, double Ms, void* H, double* E_dev, void* stream);
+/* Recompute the FP64 kernel octant S_a(o), o in [0,n), in metres (potential
+ * per unit magnetization), to HOST memory `out` [3][nz][ny][nx].  Synchronous. */
+int demag_sp_kernel(demag_plan_t plan, double* out);
+
 /* Text description of the launch shape of every pass (kernel family, threads,
  * tiles) into `buf` (len bytes, NUL-terminated); DEMAG_EINVAL if too small. */
 int demag_plan_describe(demag_plan_t plan, char* buf, int len);

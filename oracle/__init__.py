@@ -204,14 +204,31 @@ class SPOracle:
     potentials), potential phi = Ms S * m as a plain sum, H = -grad phi by
     finite differences (central inside, second-order one-sided on the faces)."""
 
-    def __init__(self, shape, cell, lib=None):
+    def __init__(self, shape, cell, lib=None, cache_dir: str | None = None):
+        """cache_dir: optional folder keeping the kernel octant (.npy, keyed by
+        shape and cell) for later instances."""
         self.lib = lib or load()
         self.shape = tuple(int(v) for v in shape)
         self.cell = tuple(float(v) for v in cell)
         nx, ny, nz = self.shape
+        path = None
+        if cache_dir:
+            key = "soct_%dx%dx%d_%s_%s_%s.npy" % (nx, ny, nz, *(v.hex() for v in self.cell))
+            path = os.path.join(cache_dir, key)
+            if os.path.exists(path):
+                self.Soct = np.load(path)
+                self.kernel_seconds = 0.0
+                return
+        import time
+        t0 = time.perf_counter()
         self.Soct = np.empty((3, nz, ny, nx), dtype=np.float64)
         if self.lib.oracle_sp_kernel(nx, ny, nz, *self.cell, _ptr(self.Soct)) != 0:
             raise ValueError("oracle_sp_kernel failed")
+        self.kernel_seconds = time.perf_counter() - t0
+        if path:
+            os.makedirs(cache_dir, exist_ok=True)
+            np.save(path + ".tmp.npy", self.Soct)
+            os.replace(path + ".tmp.npy", path)
 
     @property
     def volume(self) -> float:

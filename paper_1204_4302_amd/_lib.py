@@ -37,6 +37,10 @@ SIGNATURES = {
     "demag_autotune": (_I, [_P, _P]),
     "demag_batch_create": (_I, [ctypes.POINTER(_P), ctypes.POINTER(_P), _I, ctypes.POINTER(_P),
                                 ctypes.POINTER(_P), _D, _P]),
+    "demag_sp_prepare": (_I, [_P, _P]),
+    "demag_sp_field": (_I, [_P, _P, _D, _P, _P]),
+    "demag_sp_field_energy": (_I, [_P, _P, _D, _P, _P, _P]),
+    "demag_sp_kernel": (_I, [_P, _P]),
     "demag_batch_autotune": (_I, [_P, _P]),
     "demag_batch_launch": (_I, [_P, _P]),
     "demag_batch_destroy": (_I, [_P]),

@@ -102,6 +102,12 @@ template <typename T>
 hipError_t launch_z_conv_p2(int lgTx, hipStream_t, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx, int P,
                             const cx<T>* twt, const BatchIO& bio = BatchIO());
 
+// scalar-potential method: fused Z pass (3 components in, Ms phi out in
+// component 0 of B2), register-kernel lengths only
+template <typename T>
+hipError_t launch_z_sp_p2(int lgTx, hipStream_t, cx<T>* B2, const T* shat, T Ms, int nz, int Py, int Kx, int P,
+                          const cx<T>* twt);
+
 // ---- tensor setup (FP64) ----------------------------------------------------
 struct TensorBands {
     double far_cut = 40.0;  // rho = |o (.) d| / max d >= far_cut -> moment series
@@ -123,5 +129,22 @@ hipError_t launch_tensor_embed(hipStream_t, int comp, int nx, int ny, int nz, in
 template <typename T>
 hipError_t launch_tensor_extract(hipStream_t, int comp, int Px, int Py, int Pz, int Kx, double scale,
                                  const cx<double>* B2, T* nhat);
+
+// ---- scalar-potential method (sp.hip) ----------------------------------------
+// Kernel octant S_a(o), o in [0,n) per axis, [3][nz][ny][nx] (FP64, device),
+// with the same distance bands as the tensor.
+hipError_t launch_sp_kernel_octant(hipStream_t, int nx, int ny, int nz, const double dt[3], const TensorBands&,
+                                   const double* gl_x_dev, const double* gl_w_dev, double* Soct);
+// Component a mirrored into A [Pz][Py][Px] (odd in axis a, zero in the gap).
+hipError_t launch_sp_embed(hipStream_t, int a, int nx, int ny, int nz, int Px, int Py, int Pz, const double* Soct,
+                           double* A);
+// Im of the FFT'd component on the octant, scaled, into shat [Ly+1][3][Kx][Lz+1].
+template <typename T>
+hipError_t launch_sp_extract(hipStream_t, int a, int Py, int Pz, int Kx, double scale, const cx<double>* B2,
+                             T* shat);
+// H = -grad phi (d = cell edges), optional energy partials m.H, one per (y, z) row.
+template <typename T>
+hipError_t launch_sp_gradient(hipStream_t, int nx, int ny, int nz, const double d[3], const T* phi, T* H,
+                              const T* m, double* partials);
 
 }  // namespace demag

@@ -612,6 +612,108 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused Z pass of the scalar-potential method (Sec. 3.1, eq. (convolution)):
+// per (kx, ky) the three component pencils are transformed along z, combined
+// with the kernel spectrum S^_a = i s_a (s_a real: Im of the transform of the
+// odd kernel, octant [Py/2+1][3][Kx][Pz/2+1], +1/(Px Py Pz) folded in) into
+// phi^ = i sum_a s_a M^_a, transformed back, and Ms phi (first nz outputs) is
+// written in place to component 0 of B2.  Parity signs: s_y odd in ky (s = 1
+// groups), s_z odd in kz; s_x needs none (kx <= Px/2).  Tiles, groups, buffer
+// access and register budget as in kz_conv.
+template <typename T, int P>
+__global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, const T* __restrict__ shat, T Ms,
+                                                        int nz, int Py, int Kx, int lgTx, int nxcd,
+                                                        const cx<T>* __restrict__ twt) {
+    using LT = p2::Len<P>;
+    constexpr bool kPow2 = p2::is_pow2(P);
+    constexpr bool kKeep = z_keep_twiddles<T, P>();
+    constexpr int Lz = P / 2;
+    constexpr unsigned CB = sizeof(cx<T>), RB = sizeof(T);
+    cx<T>* lds = lds_base<T>();
+    const int tid = threadIdx.x;
+    const int g = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
+    const int Tx = 1 << lgTx, Ly = Py >> 1;
+    const int xi = g & (Tx - 1), s = g >> lgTx;
+    const int nxt = (Kx + Tx - 1) >> lgTx;
+    const int tile = xcd_tile(nxcd);
+    const int kx0 = (tile % nxt) << lgTx, kyp = tile / nxt;
+    const int tx = min(Tx, Kx - kx0);
+    const int ns = (kyp == 0 || kyp == Ly) ? 1 : 2;
+    const bool ok = s < ns && xi < tx;
+    const int ky = s ? Py - kyp : kyp;
+    const size_t cstride = (size_t)Py * Kx * nz;
+    const Buf bc[3] = {make_buf(B2, cstride * CB), make_buf(B2 + cstride, cstride * CB),
+                       make_buf(B2 + 2 * cstride, cstride * CB)};
+    const unsigned row = (unsigned)((((size_t)ky * Kx + kx0 + xi) * nz + t) * CB);
+    cx<T> v[3][LT::EPT];
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+#pragma unroll
+        for (int j = 0; j < LT::EPT; ++j) {
+            const int k = LT::fin_k(j);
+            const int zz = t + k * LT::TP;
+            v[comp][j] = k < LT::EPT / 2 ? bld<T>(bc[comp], boff(ok && zz < nz, row, k * LT::TP * CB)) : czero<T>();
+        }
+    }
+    const size_t cs = (size_t)Kx * (Lz + 1);  // component stride of the spectrum octant
+    const Buf bt = make_buf(shat, (size_t)(Ly + 1) * 3 * cs * RB);
+    const unsigned trow = ok ? (unsigned)((((size_t)kyp * 3 * Kx + kx0 + xi) * (Lz + 1)) * RB) : 0u;
+    T sk[LT::EPT][3];
+    auto load_kernel = [&]() {
+#pragma unroll
+        for (int j = 0; j < LT::EPT; ++j) {
+            unsigned off;
+            if constexpr (kPow2) {
+                const int k = LT::F::slot_out(j);
+                off = k < LT::EPT / 2 ? trow + (t + k * LT::TP) * RB : trow + ((LT::TP - 1 - t) + P - (k + 1) * LT::TP + 1) * RB;
+            } else {
+                const int kz = LT::fout(t, j);
+                off = trow + (kz <= Lz ? kz : P - kz) * RB;
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) sk[j][a] = bldr<T>(bt, off, (unsigned)(a * cs * RB));
+        }
+    };
+    if constexpr (kKeep) load_kernel();
+    cx<T>* slab = lds + g * LT::PS;
+    const cx<T>* twsrc = twt;
+    if constexpr (!kKeep) {
+        twsrc = twiddle_source<T, P>(lds, (int)blockDim.x >> LT::LOG_TP, twt, tid, blockDim.x);
+        if constexpr (tw_in_lds<T, P>()) __syncthreads();
+    }
+    typename LT::template Tw<T> tws;
+    if constexpr (kKeep) tws.load(t, twsrc);
+#pragma unroll
+    for (int comp = 0; comp < 3; ++comp) {
+        if constexpr (kKeep) LT::template fft<-1, true>(v[comp], slab, t, tws);
+        else run_fft<T, P, -1, true>(v[comp], slab, t, twsrc);
+    }
+    if constexpr (!kKeep) load_kernel();
+    const T sy = s ? T(-1) : T(1);
+    cx<T> w[LT::EPT];
+#pragma unroll
+    for (int j = 0; j < LT::EPT; ++j) {
+        bool negz;
+        if constexpr (kPow2) negz = LT::F::slot_out(j) >= LT::EPT / 2;
+        else negz = LT::fout(t, j) > Lz;
+        const T ax = sk[j][0], ay = sy * sk[j][1], az = negz ? -sk[j][2] : sk[j][2];
+        const cx<T> c = mk(ax * v[0][j].re + ay * v[1][j].re + az * v[2][j].re,
+                           ax * v[0][j].im + ay * v[1][j].im + az * v[2][j].im);
+        v[0][j] = mk(-c.im, c.re);  // times i
+    }
+#pragma unroll
+    for (int j = 0; j < LT::EPT; ++j) w[j] = v[0][LT::fwd_slot_of_iin(j)];
+    if constexpr (kKeep) LT::template fft<+1, false>(w, slab, t, tws);
+    else run_fft<T, P, +1>(w, slab, t, twsrc);
+#pragma unroll
+    for (int j = 0; j < LT::EPT; ++j) {
+        const int k = LT::iout_k(j);
+        const int zz = t + k * LT::TP;
+        if (k < LT::EPT / 2) bst<T>(bc[0], boff(ok && zz < nz, row, k * LT::TP * CB), mk(Ms * w[j].re, Ms * w[j].im));
+    }
+}
+
 template <int P>
 constexpr int tpp() { return p2::Len<P>::TP; }
 
@@ -778,6 +880,29 @@ hipError_t launch_z_conv_p2(int lgTx, hipStream_t st, cx<T>* B2, const T* nhat, 
 }
 
 template <typename T>
+hipError_t launch_z_sp_p2(int lgTx, hipStream_t st, cx<T>* B2, const T* shat, T Ms, int nz, int Py, int Kx, int P,
+                          const cx<T>* twt) {
+    if (!twt) return hipErrorInvalidValue;
+    if (!p2_z_supported(P, sizeof(cx<T>))) return hipErrorInvalidValue;
+    const int G = 2 << lgTx;
+    dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * (Py / 2 + 1)));
+    const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
+#define CALL(PP) \
+    if (hipError_t e_ = allow_lds(&kz_sp<T, PP>, lds)) return e_; \
+    hipLaunchKernelGGL((kz_sp<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, shat, Ms, nz, Py, Kx, lgTx, kXcds, twt)
+    if constexpr (sizeof(T) == 4) {
+        DEMAG_P2_SWITCH(P, CALL)
+    } else {
+        switch (P) {
+            DEMAG_P2_CASES_POW2(CALL)
+        default: return hipErrorInvalidValue;
+        }
+    }
+#undef CALL
+    return hipGetLastError();
+}
+
+template <typename T>
 std::vector<cx<T>> p2_thread_twiddles(int P, const std::vector<cx<T>>& tw) {
     std::vector<cx<T>> out;
     if ((int)tw.size() != P) return out;
@@ -805,7 +930,8 @@ std::vector<cx<T>> p2_thread_twiddles(int P, const std::vector<cx<T>>& tw) {
     template hipError_t launch_y_inv_p2<T>(int, int, hipStream_t, const cx<T>*, cx<T>*, int, int, int, int, int,  \
                                            const cx<T>*, const BatchIO&);                                          \
     template hipError_t launch_z_conv_p2<T>(int, hipStream_t, cx<T>*, const T*, T, int, int, int, int,            \
-                                            const cx<T>*, const BatchIO&);
+                                            const cx<T>*, const BatchIO&);                                         \
+    template hipError_t launch_z_sp_p2<T>(int, hipStream_t, cx<T>*, const T*, T, int, int, int, int, const cx<T>*);
 
 DEMAG_P2_INSTANTIATE(float)
 DEMAG_P2_INSTANTIATE(double)

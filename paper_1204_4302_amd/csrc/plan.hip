@@ -149,6 +149,8 @@ struct demag_plan_s {
     void* tw[3] = {nullptr, nullptr, nullptr};
     void* twt[3] = {nullptr, nullptr, nullptr};  // thread-major twiddles of power-of-two axes
     void* nhat = nullptr;
+    void* shat = nullptr;  // scalar-potential kernel spectrum (after demag_sp_prepare)
+    LaunchCfg zs;          // launch shape of the scalar-potential Z pass
     void* B1 = nullptr;
     void* B2 = nullptr;
     double* partials = nullptr;
@@ -431,6 +433,55 @@ int setup_spectrum(demag_plan_s* p, hipStream_t st) {
     return DEMAG_OK;
 }
 
+// Scalar-potential kernel: octant S_a (FP64, reduced units), odd mirror, FP64
+// FFT passes, Im on the octant with h / (Px Py Pz) folded in (S scales as
+// length: S_physical = h S_reduced, h the largest cell edge).
+int compute_sp_octant(demag_plan_s* p, hipStream_t st, SetupBufs& sb) {
+    const size_t ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
+    HIP_TRY(hipMalloc(&sb.Noct, 3 * ncell * sizeof(double)));
+    std::vector<double> gx, gw;
+    gauss_legendre(p->bands.gl_q, gx, gw);
+    int rc = upload((void**)&sb.glx, gx);
+    if (rc) return rc;
+    rc = upload((void**)&sb.glw, gw);
+    if (rc) return rc;
+    double dt[3];
+    reduced_cell(p->d, dt);
+    HIP_TRY(launch_sp_kernel_octant(st, p->n[0], p->n[1], p->n[2], dt, p->bands, sb.glx, sb.glw, sb.Noct));
+    return DEMAG_OK;
+}
+
+template <typename T>
+int setup_sp_spectrum(demag_plan_s* p, hipStream_t st) {
+    SetupBufs sb;
+    int rc = compute_sp_octant(p, st, sb);
+    if (rc) return rc;
+    const int Px = p->P[0], Py = p->P[1], Pz = p->P[2], Kx = p->Kx;
+    const size_t nA = (size_t)Px * Py * Pz, nS = (size_t)Pz * Kx * Py;
+    HIP_TRY(hipMalloc(&sb.A, nA * sizeof(double)));
+    HIP_TRY(hipMalloc(&sb.B1, nS * sizeof(cx<double>)));
+    HIP_TRY(hipMalloc(&sb.B2, nS * sizeof(cx<double>)));
+    for (int k = 0; k < 3; ++k) {
+        rc = upload(&sb.tw[k], twiddles<double>(p->P[k]));
+        if (rc) return rc;
+    }
+    const size_t cb = sizeof(cx<double>);
+    LaunchCfg xf = cfg_rows(Px, Py, cb), yf = cfg_pencils(Py, Kx, Pz, cb), zf;
+    zf.t0 = (int)std::max<long>(1, std::min<long>(Kx, 2048 / Pz));
+    zf.E = pick_E((long)zf.t0 * Pz, zf.threads);
+    const double h = std::max(p->d[0], std::max(p->d[1], p->d[2]));
+    const double scale = h / ((double)Px * Py * Pz);
+    for (int a = 0; a < 3; ++a) {
+        HIP_TRY(launch_sp_embed(st, a, p->n[0], p->n[1], p->n[2], Px, Py, Pz, sb.Noct, sb.A));
+        HIP_TRY(launch_x_fwd<double>(xf, st, sb.A, sb.B1, Px, Py, Pz, Kx, 1, p->fp[0], (const cx<double>*)sb.tw[0]));
+        HIP_TRY(launch_y_fwd<double>(yf, st, sb.B1, sb.B2, Py, Pz, Kx, Pz, 1, p->fp[1], (const cx<double>*)sb.tw[1]));
+        HIP_TRY(launch_z_fwd<double>(zf, st, sb.B2, Py, Kx, p->fp[2], (const cx<double>*)sb.tw[2]));
+        HIP_TRY(launch_sp_extract<T>(st, a, Py, Pz, Kx, scale, sb.B2, (T*)p->shat));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return DEMAG_OK;
+}
+
 int run_setup(demag_plan_s* p, hipStream_t st) {
     auto t0 = std::chrono::steady_clock::now();
     int rc = p->dtype == DEMAG_F32 ? setup_spectrum<float>(p, st) : setup_spectrum<double>(p, st);
@@ -442,6 +493,7 @@ void free_plan(demag_plan_s* p) {
     for (auto t : p->tw) hipFree(t);
     for (auto t : p->twt) hipFree(t);
     hipFree(p->nhat);
+    hipFree(p->shat);
     hipFree(p->B1);
     hipFree(p->B2);
     hipFree(p->partials);
@@ -520,6 +572,38 @@ int run_field(demag_plan_s* p, const PassCfgs& c, const T* m, double Ms, T* H, c
     }
     return DEMAG_OK;
 }
+
+// One scalar-potential evaluation: the DM forward X and Y passes on m, the
+// fused SP Z pass (phi^ into component 0 of B2), one-component Y-inverse and
+// X-C2R (phi into B2's memory), the gradient (H; energy partials when E_dev).
+template <typename T>
+int run_sp_field(demag_plan_s* p, const T* m, double Ms, T* H, double* E_dev, hipStream_t st) {
+    const int nx = p->n[0], ny = p->n[1], nz = p->n[2], Kx = p->Kx;
+    const int Px = p->P[0], Py = p->P[1], Pz = p->P[2];
+    auto* B1 = (cx<T>*)p->B1;
+    auto* B2 = (cx<T>*)p->B2;
+    T* phi = (T*)p->B2;                 // free once the Y-inverse has read B2
+    T* Hout = H ? H : (T*)p->B1;        // energy only: the field goes to scratch
+    const PassCfgs& c = p->cfg;
+    HIP_TRY(launch_pass<T>(p, 0, c.xf, st, m, Ms, nullptr, nullptr, nullptr, 0));
+    HIP_TRY(launch_pass<T>(p, 1, c.yf, st, nullptr, Ms, nullptr, nullptr, nullptr, 0));
+    HIP_TRY(launch_z_sp_p2<T>(p->zs.t0, st, B2, (const T*)p->shat, (T)Ms, nz, Py, Kx, Pz, (const cx<T>*)p->twt[2]));
+    const LaunchCfg& yi = c.yi;
+    HIP_TRY(yi.p2 ? launch_y_inv_p2<T>(yi.t1, yi.t0, st, B2, B1, ny, nz, Kx, 1, Py, (const cx<T>*)p->twt[1])
+                  : launch_y_inv<T>(yi, st, B2, B1, ny, nz, Kx, 1, p->fp[1], (const cx<T>*)p->tw[1]));
+    const LaunchCfg& xi = c.xi;
+    HIP_TRY(xi.p2 ? launch_x_inv_p2<T>(xi.t0, st, B1, phi, nullptr, nullptr, nx, ny, nz, 1, 0, Px,
+                                       (const cx<T>*)p->twt[0])
+                  : launch_x_inv<T>(xi, st, B1, phi, nullptr, nullptr, nx, ny, nz, Kx, 1, 0, p->fp[0],
+                                    (const cx<T>*)p->tw[0]));
+    HIP_TRY(launch_sp_gradient<T>(st, nx, ny, nz, p->d, phi, Hout, E_dev ? m : nullptr, E_dev ? p->partials : nullptr));
+    if (E_dev) {
+        const double V = p->d[0] * p->d[1] * p->d[2];
+        HIP_TRY(launch_energy_reduce(st, p->partials, ny * nz, -0.5 * kMu0 * Ms * V, E_dev));
+    }
+    return DEMAG_OK;
+}
+
 
 int dispatch_field(demag_plan_s* p, const void* m, double Ms, void* H, double* E_dev, int accumulate,
                    hipStream_t st) {
@@ -767,6 +851,64 @@ int demag_plan_tensor(demag_plan_t p, double* out) {
     if (rc) return rc;
     const size_t ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
     HIP_TRY(hipMemcpy(out, sb.Noct, 6 * ncell * sizeof(double), hipMemcpyDeviceToHost));
+    return DEMAG_OK;
+}
+
+int demag_sp_prepare(demag_plan_t p, void* stream) {
+    if (!p) return fail(DEMAG_EINVAL, "NULL plan");
+    if (p->shat) return DEMAG_OK;
+    const size_t cb = csize(p->dtype), rb = cb / 2;
+    if (!p2_z_supported(p->P[2], cb) || !p2_z_ranges_ok(p))
+        return fail(DEMAG_EUNSUPPORTED, "scalar-potential method: padded z length %d not supported in %s", p->P[2],
+                    p->dtype == DEMAG_F32 ? "FP32" : "FP64");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    const size_t bytes = (size_t)(p->P[1] / 2 + 1) * 3 * p->Kx * (p->P[2] / 2 + 1) * rb;
+    if (hipMalloc(&p->shat, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p->shat = nullptr;
+        return fail(DEMAG_ENOMEM, "cannot allocate %zu bytes for the scalar-potential spectrum", bytes);
+    }
+    rc = p->dtype == DEMAG_F32 ? setup_sp_spectrum<float>(p, st) : setup_sp_spectrum<double>(p, st);
+    if (rc) {
+        hipFree(p->shat);
+        p->shat = nullptr;
+        return rc;
+    }
+    p->zs = p->cfg.zc.p2 ? p->cfg.zc : p2_zconv(p->P[2], p->Kx, cb);
+    return leave(p, st);
+}
+
+int demag_sp_field_energy(demag_plan_t p, const void* m, double Ms, void* H, double* E_dev, void* stream) {
+    if (!p || !m || (!H && !E_dev)) return fail(DEMAG_EINVAL, "NULL plan or m, or neither H nor E_dev");
+    if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
+    if (!p->shat) return fail(DEMAG_ESTATE, "scalar-potential method not prepared (call demag_sp_prepare)");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    rc = p->dtype == DEMAG_F32 ? run_sp_field<float>(p, (const float*)m, Ms, (float*)H, E_dev, st)
+                               : run_sp_field<double>(p, (const double*)m, Ms, (double*)H, E_dev, st);
+    if (rc) return rc;
+    return leave(p, st);
+}
+
+int demag_sp_field(demag_plan_t p, const void* m, double Ms, void* H, void* stream) {
+    if (!H) return fail(DEMAG_EINVAL, "H is NULL");
+    return demag_sp_field_energy(p, m, Ms, H, nullptr, stream);
+}
+
+int demag_sp_kernel(demag_plan_t p, double* out) {
+    if (!p || !out) return fail(DEMAG_EINVAL, "NULL argument");
+    HIP_TRY(hipDeviceSynchronize());
+    SetupBufs sb;
+    int rc = compute_sp_octant(p, nullptr, sb);
+    if (rc) return rc;
+    const size_t ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
+    const double h = std::max(p->d[0], std::max(p->d[1], p->d[2]));
+    std::vector<double> tmp(3 * ncell);
+    HIP_TRY(hipMemcpy(tmp.data(), sb.Noct, 3 * ncell * sizeof(double), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < tmp.size(); ++i) out[i] = tmp[i] * h;
     return DEMAG_OK;
 }
 

@@ -1,0 +1,300 @@
+// Scalar-potential (SP) method: FP64 setup of the kernel spectrum and the
+// finite-difference gradient (Sec. 3.1, eqs. (scpot), (convolution), (field)).
+//
+// phi = Ms S * m with S_a(R) the potential at R of a cell centred at the
+// origin and magnetized along axis a with unit magnetization; H = -grad phi.
+// Integrating eq. (scpot) along a turns the cell into two charged faces,
+//     S_a(R) = (1/4pi) [ G_a(R - (d_a/2) e_a) - G_a(R + (d_a/2) e_a) ],
+// G_a the potential of the unit-density d_b x d_c rectangle (closed form: the
+// corner sum of u asinh(v/sqrt(u^2+w^2)) + v asinh(u/sqrt(v^2+w^2))
+// - w atan(uv/(w r))).  As for the DM tensor, three routes by distance:
+//   near (Chebyshev distance <= fg_cut): that closed form;
+//   mid:  Gauss-Legendre of the defining volume integral
+//         S_a(R) = (1/4pi) int_cell (R_a - u_a) / |R - u|^3 du (the pole is
+//         outside the cell; panels no longer than its distance to the cell);
+//   far  (rho >= far_cut): S_a = -(V/4pi) sum_beta c_beta d^(beta + e_a)(1/r)
+//         over even multi-indices |beta| <= 6, c_beta the moments of the
+//         uniform cell (d^2/12, d^4/80, d^6/448) over beta!.
+// S_a is odd in axis a and even in the others; its transform is imaginary.
+// The spectrum stored is Im(S^) on the octant with +1/(Px Py Pz) folded in,
+// layout [Py/2+1][3][Kx][Pz/2+1].
+#include "internal.hpp"
+#include "newell.hpp"
+
+namespace demag {
+
+namespace {
+
+constexpr double kPi = newell::kPi;
+
+// ---- near: charged faces ---------------------------------------------------
+__device__ double face_F(double u, double v, double w) {
+    const double r = sqrt(u * u + v * v + w * w);
+    double t = newell::asinh_term(u, v, u * u + w * w) + newell::asinh_term(v, u, v * v + w * w);
+    if (w != 0.0 && u != 0.0 && v != 0.0) t -= w * atan(u * v / (w * r));
+    return t;
+}
+
+// potential at (X, Y, W) of the unit-density rectangle A x B centred at 0 in the plane W = 0
+__device__ double face_G(double X, double Y, double W, double A, double B) {
+    const double u1 = -0.5 * A - X, u2 = 0.5 * A - X, v1 = -0.5 * B - Y, v2 = 0.5 * B - Y;
+    return face_F(u2, v2, W) - face_F(u1, v2, W) - face_F(u2, v1, W) + face_F(u1, v1, W);
+}
+
+__device__ void sp_near(const double R[3], const double dt[3], double out[3]) {
+    for (int a = 0; a < 3; ++a) {
+        const int b = (a + 1) % 3, c = (a + 2) % 3;
+        const double top = face_G(R[b], R[c], R[a] - 0.5 * dt[a], dt[b], dt[c]);
+        const double bot = face_G(R[b], R[c], R[a] + 0.5 * dt[a], dt[b], dt[c]);
+        out[a] = (top - bot) / (4.0 * kPi);
+    }
+}
+
+// ---- far: moment series ----------------------------------------------------
+// average of s^p over [-d/2, d/2], p even
+__device__ double uniform_moment(int p, double d) {
+    return p == 0 ? 1.0 : pow(0.5 * d, (double)p) / (p + 1.0);
+}
+
+__device__ void sp_far(const double R[3], const double dt[3], double out[3]) {
+    double a[newell::kTaylorLen];
+    newell::inv_r_taylor(R[0], R[1], R[2], a);
+    out[0] = out[1] = out[2] = 0.0;
+    for (int bx = 0; bx <= 6; bx += 2)
+        for (int by = 0; by <= 6 - bx; by += 2)
+            for (int bz = 0; bz <= 6 - bx - by; bz += 2) {
+                const double cb = uniform_moment(bx, dt[0]) / newell::fact(bx) * uniform_moment(by, dt[1]) /
+                                  newell::fact(by) * uniform_moment(bz, dt[2]) / newell::fact(bz);
+                for (int c = 0; c < 3; ++c) {
+                    int g[3] = {bx, by, bz};
+                    g[c] += 1;
+                    out[c] += cb * newell::fact(g[0]) * newell::fact(g[1]) * newell::fact(g[2]) *
+                              a[newell::tidx(g[0], g[1], g[2])];
+                }
+            }
+    const double V = dt[0] * dt[1] * dt[2];
+    for (int c = 0; c < 3; ++c) out[c] *= -V / (4.0 * kPi);
+}
+
+__device__ __forceinline__ bool sp_in_far(const double R[3], double far_cut) {
+    return R[0] * R[0] + R[1] * R[1] + R[2] * R[2] >= far_cut * far_cut;
+}
+
+// distance from the point R to the cell [-d/2, d/2]^3
+__device__ double point_gap(const double R[3], const double dt[3]) {
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        const double g = fabs(R[k]) - 0.5 * dt[k];
+        if (g > 0) s += g * g;
+    }
+    return sqrt(s);
+}
+
+// Near and far bands: one thread per octant offset.
+__global__ void __launch_bounds__(256) k_sp_pointwise(int nx, int ny, int nz, double dt0, double dt1, double dt2,
+                                                      double far_cut, int fg_cut, double* __restrict__ Soct) {
+    const size_t ncell = (size_t)nx * ny * nz;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ncell) return;
+    const int ox = (int)(t % nx), oy = (int)((t / nx) % ny), oz = (int)(t / ((size_t)nx * ny));
+    const double dt[3] = {dt0, dt1, dt2};
+    const double R[3] = {ox * dt0, oy * dt1, oz * dt2};
+    double v[3];
+    if (max(ox, max(oy, oz)) <= fg_cut) {
+        sp_near(R, dt, v);
+    } else if (sp_in_far(R, far_cut)) {
+        sp_far(R, dt, v);
+    } else {
+        return;  // mid band: k_sp_mid
+    }
+    for (int c = 0; c < 3; ++c) Soct[c * ncell + t] = v[c];
+}
+
+// Mid band: one 64-lane workgroup per offset of the bounding box
+// [0,bx) x [0,by) x [0,bz); offsets outside the band return at once.
+__global__ void __launch_bounds__(64) k_sp_mid(int nx, int ny, int nz, int bx, int by, double dt0, double dt1,
+                                               double dt2, double far_cut, int fg_cut, int q, int max_panels,
+                                               const double* __restrict__ gl_x, const double* __restrict__ gl_w,
+                                               double* __restrict__ Soct) {
+    const int b = blockIdx.x;
+    const int ox = b % bx, oy = (b / bx) % by, oz = b / (bx * by);
+    if (ox >= nx || oy >= ny || oz >= nz) return;
+    const double dt[3] = {dt0, dt1, dt2};
+    const double R[3] = {ox * dt0, oy * dt1, oz * dt2};
+    if (max(ox, max(oy, oz)) <= fg_cut || sp_in_far(R, far_cut)) return;
+    const double gap = point_gap(R, dt);
+    int m[3], Q[3];
+    for (int k = 0; k < 3; ++k) {
+        m[k] = newell::mid_panels(dt[k], gap, max_panels);
+        Q[k] = m[k] * q;
+    }
+    double acc[3] = {0, 0, 0};
+    const int total = Q[0] * Q[1] * Q[2];
+    for (int n = threadIdx.x; n < total; n += 64) {
+        const int idx[3] = {n % Q[0], (n / Q[0]) % Q[1], n / (Q[0] * Q[1])};
+        double u[3], w = 1.0;
+        for (int k = 0; k < 3; ++k) {  // panel p, node j of axis k on [-d/2, d/2]
+            const int p = idx[k] / q, j = idx[k] - p * q;
+            const double h = dt[k] / m[k];
+            u[k] = -0.5 * dt[k] + p * h + 0.5 * h * (gl_x[j] + 1.0);
+            w *= 0.5 * h * gl_w[j];
+        }
+        const double X = R[0] - u[0], Y = R[1] - u[1], Z = R[2] - u[2];
+        const double r2 = X * X + Y * Y + Z * Z;
+        const double ir = 1.0 / sqrt(r2);
+        const double f = w * ir * ir * ir / (4.0 * kPi);
+        acc[0] += X * f;
+        acc[1] += Y * f;
+        acc[2] += Z * f;
+    }
+    const size_t ncell = (size_t)nx * ny * nz;
+    const size_t t = ((size_t)oz * ny + oy) * nx + ox;
+    for (int c = 0; c < 3; ++c) {
+        double s = acc[c];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (threadIdx.x == 0) Soct[c * ncell + t] = s;
+    }
+}
+
+// Signed offset of padded index i (period P, n valid offsets each side), or
+// a flag for the zero gap.
+__device__ __forceinline__ bool unpad_sp(int i, int n, int P, int* o) {
+    if (i < n) { *o = i; return true; }
+    if (i > P - n) { *o = i - P; return true; }
+    return false;
+}
+
+// component a of the octant mirrored into the P-periodic array (odd in axis a)
+__global__ void __launch_bounds__(256) k_sp_embed(int a, int nx, int ny, int nz, int Px, int Py, int Pz,
+                                                  const double* __restrict__ Soct, double* __restrict__ A) {
+    const size_t total = (size_t)Px * Py * Pz;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int x = (int)(t % Px), y = (int)((t / Px) % Py), z = (int)(t / ((size_t)Px * Py));
+    int o[3];
+    double v = 0.0;
+    if (unpad_sp(x, nx, Px, &o[0]) && unpad_sp(y, ny, Py, &o[1]) && unpad_sp(z, nz, Pz, &o[2])) {
+        const size_t ncell = (size_t)nx * ny * nz;
+        v = Soct[a * ncell + ((size_t)abs(o[2]) * ny + abs(o[1])) * nx + abs(o[0])];
+        if (o[a] < 0) v = -v;
+    }
+    A[t] = v;
+}
+
+// Im of the transform on the octant, scaled; the transform of a function odd
+// in axis a vanishes on that axis's Nyquist plane: stored as an exact zero.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sp_extract(int a, int Py, int Pz, int Kx, double scale,
+                                                    const cx<double>* __restrict__ B2, T* __restrict__ shat) {
+    const int Ly = Py / 2, Lz = Pz / 2;
+    const size_t total = (size_t)(Ly + 1) * Kx * (Lz + 1);
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const int kz = (int)(t % (Lz + 1)), kx = (int)((t / (Lz + 1)) % Kx), ky = (int)(t / ((size_t)(Lz + 1) * Kx));
+    double v = B2[((size_t)ky * Kx + kx) * Pz + kz].im * scale;
+    if ((a == 0 && kx == Kx - 1) || (a == 1 && ky == Ly) || (a == 2 && kz == Lz)) v = 0.0;
+    shat[(((size_t)ky * 3 + a) * Kx + kx) * (Lz + 1) + kz] = (T)v;
+}
+
+// ---- field: H = -grad phi (eq. (field)) ---------------------------------------
+// -d phi / d axis at index i of n along an axis (stride s, spacing h): central
+// inside, second-order one-sided on the faces, first order for n = 2, 0 for n = 1.
+template <typename T>
+__device__ __forceinline__ T minus_d(const T* __restrict__ p, int i, int n, long s, T h) {
+    if (n == 1) return T(0);
+    if (n == 2) return i == 0 ? -(p[s] - p[0]) / h : -(p[0] - p[-s]) / h;
+    if (i == 0) return -(T(-3) * p[0] + T(4) * p[s] - p[2 * s]) / (T(2) * h);
+    if (i == n - 1) return -(T(3) * p[0] - T(4) * p[-s] + p[-2 * s]) / (T(2) * h);
+    return -(p[s] - p[-s]) / (T(2) * h);
+}
+
+// One workgroup per (y, z) row; optional energy partial sum m.H per row (FP64).
+template <typename T>
+__global__ void __launch_bounds__(256) k_sp_gradient(int nx, int ny, int nz, T dx, T dy, T dz,
+                                                     const T* __restrict__ phi, T* __restrict__ H,
+                                                     const T* __restrict__ m, double* __restrict__ partials) {
+    __shared__ double red[4];
+    const int row = blockIdx.x, y = row % ny, z = row / ny;
+    const size_t N = (size_t)nx * ny * nz;
+    const size_t base = ((size_t)z * ny + y) * nx;
+    double acc = 0.0;
+    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
+        const size_t i = base + x;
+        const T hx = minus_d(phi + i, x, nx, 1, dx);
+        const T hy = minus_d(phi + i, y, ny, (long)nx, dy);
+        const T hz = minus_d(phi + i, z, nz, (long)nx * ny, dz);
+        H[i] = hx;
+        H[N + i] = hy;
+        H[2 * N + i] = hz;
+        if (m) acc += (double)(m[i] * hx) + (double)(m[N + i] * hy) + (double)(m[2 * N + i] * hz);
+    }
+    if (partials) {
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double s = 0.0;
+            for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) s += red[w];
+            partials[row] = s;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_sp_kernel_octant(hipStream_t st, int nx, int ny, int nz, const double dt[3], const TensorBands& tb,
+                                   const double* gl_x_dev, const double* gl_w_dev, double* Soct) {
+    const size_t ncell = (size_t)nx * ny * nz;
+    hipLaunchKernelGGL(k_sp_pointwise, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, nx, ny, nz, dt[0],
+                       dt[1], dt[2], tb.far_cut, tb.fg_cut, Soct);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    int bx = nx, by = ny, bz = nz;
+    const int lim[3] = {(int)ceil(tb.far_cut / dt[0]) + 1, (int)ceil(tb.far_cut / dt[1]) + 1,
+                        (int)ceil(tb.far_cut / dt[2]) + 1};
+    bx = bx < lim[0] ? bx : lim[0];
+    by = by < lim[1] ? by : lim[1];
+    bz = bz < lim[2] ? bz : lim[2];
+    const long nb = (long)bx * by * bz;
+    if (nb > 0 && tb.far_cut > 0) {
+        hipLaunchKernelGGL(k_sp_mid, dim3((unsigned)nb), dim3(64), 0, st, nx, ny, nz, bx, by, dt[0], dt[1], dt[2],
+                           tb.far_cut, tb.fg_cut, tb.gl_q, tb.max_panels, gl_x_dev, gl_w_dev, Soct);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t launch_sp_embed(hipStream_t st, int a, int nx, int ny, int nz, int Px, int Py, int Pz, const double* Soct,
+                           double* A) {
+    const size_t total = (size_t)Px * Py * Pz;
+    hipLaunchKernelGGL(k_sp_embed, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, nx, ny, nz, Px, Py, Pz,
+                       Soct, A);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sp_extract(hipStream_t st, int a, int Py, int Pz, int Kx, double scale, const cx<double>* B2,
+                             T* shat) {
+    const size_t total = (size_t)(Py / 2 + 1) * Kx * (Pz / 2 + 1);
+    hipLaunchKernelGGL((k_sp_extract<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, Py, Pz, Kx,
+                       scale, B2, shat);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sp_gradient(hipStream_t st, int nx, int ny, int nz, const double d[3], const T* phi, T* H,
+                              const T* m, double* partials) {
+    const int threads = nx >= 256 ? 256 : nx >= 128 ? 128 : 64;
+    hipLaunchKernelGGL((k_sp_gradient<T>), dim3((unsigned)ny * nz), dim3(threads), 0, st, nx, ny, nz, (T)d[0],
+                       (T)d[1], (T)d[2], phi, H, m, partials);
+    return hipGetLastError();
+}
+
+template hipError_t launch_sp_extract<float>(hipStream_t, int, int, int, int, double, const cx<double>*, float*);
+template hipError_t launch_sp_extract<double>(hipStream_t, int, int, int, int, double, const cx<double>*, double*);
+template hipError_t launch_sp_gradient<float>(hipStream_t, int, int, int, const double[3], const float*, float*,
+                                              const float*, double*);
+template hipError_t launch_sp_gradient<double>(hipStream_t, int, int, int, const double[3], const double*, double*,
+                                               const double*, double*);
+
+}  // namespace demag

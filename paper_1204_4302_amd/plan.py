@@ -155,6 +155,40 @@ class Plan:
                   self._ptr(H) if H is not None else None, ctypes.c_void_p(E.data_ptr()), _stream_ptr())
         return H, E
 
+    # -- scalar-potential method (SP) ---------------------------------------
+    def sp_prepare(self):
+        """Build the SP kernel spectrum (synchronous, once)."""
+        _lib.call("demag_sp_prepare", self._h, _stream_ptr())
+
+    def sp_field(self, m: torch.Tensor, Ms: float, out: torch.Tensor | None = None) -> torch.Tensor:
+        """H = -grad (Ms S * m) by finite differences (SP method)."""
+        self._check(m, "m")
+        H = torch.empty_like(m) if out is None else out
+        self._check(H, "out")
+        _lib.call("demag_sp_field", self._h, self._ptr(m), float(Ms), self._ptr(H), _stream_ptr())
+        return H
+
+    def sp_field_energy(self, m: torch.Tensor, Ms: float, with_field: bool = True,
+                        out: torch.Tensor | None = None, E_out: torch.Tensor | None = None):
+        """(H or None, E) of the SP method, E a 0-dim float64 CUDA tensor."""
+        self._check(m, "m")
+        H = (torch.empty_like(m) if out is None else out) if with_field else None
+        if H is not None:
+            self._check(H, "out")
+        E = torch.empty((), dtype=torch.float64, device=m.device) if E_out is None else E_out
+        if E.dtype != torch.float64 or E.device.type != "cuda" or E.numel() != 1:
+            raise TypeError("E_out must be a one-element float64 CUDA tensor")
+        _lib.call("demag_sp_field_energy", self._h, self._ptr(m), float(Ms),
+                  self._ptr(H) if H is not None else None, ctypes.c_void_p(E.data_ptr()), _stream_ptr())
+        return H, E
+
+    def sp_kernel(self) -> np.ndarray:
+        """FP64 SP kernel octant S_a(o) in metres, [3][nz][ny][nx]."""
+        nx, ny, nz = self.shape
+        a = np.empty((3, nz, ny, nx), dtype=np.float64)
+        _lib.call("demag_sp_kernel", self._h, a.ctypes.data_as(ctypes.c_void_p))
+        return a
+
     def energy(self, m: torch.Tensor, Ms: float) -> float:
         self._check(m, "m")
         e = ctypes.c_double()

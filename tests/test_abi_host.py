@@ -67,6 +67,10 @@ def test_null_handles_rejected():
     assert lib.demag_energy(None, None, 1.0, None, None) == -1
     assert lib.demag_plan_destroy(None) == -1
     assert lib.demag_batch_autotune(None, None) == -1
+    assert lib.demag_sp_prepare(None, None) == -1
+    assert lib.demag_sp_field(None, None, 1.0, None, None) == -1
+    assert lib.demag_sp_field_energy(None, None, 1.0, None, None, None) == -1
+    assert lib.demag_sp_kernel(None, None) == -1
     assert lib.demag_batch_launch(None, None) == -1
     assert lib.demag_batch_destroy(None) == -1
     assert lib.demag_plan_set_option(None, b"far_cut", 40.0) == -1

@@ -1,0 +1,150 @@
+"""Scalar-potential method (SP, Sec. 3.1 eqs. (scpot), (convolution),
+(field)) on the GPU against the SP oracle: the kernel octant per distance
+band, the field element by element on small grids (power-of-two, 3 * 2^a and
+ragged padded lengths, degenerate axes), the energy, and the full
+256 x 256 x 64 grid at sampled cells in the launch shapes bench.py times.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1204_4302_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL, FP32_TOL = 1e-12, 1e-5
+CACHE = os.environ.get("DEMAG_ORACLE_CACHE", "/tmp/demag_oracle_cache")
+
+
+def rel_err(a, b):
+    """Relative max-norm error; the absolute one where the reference is zero
+    (one cell: no neighbour to difference, so H = 0 exactly)."""
+    scale = np.abs(b).max()
+    return float(np.abs(a - b).max() / scale) if scale > 0 else float(np.abs(a).max())
+
+
+def _gpu(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def _quantised(m, dtype):
+    return m.astype(np.float32).astype(np.float64) if dtype == torch.float32 else m
+
+
+@pytest.mark.parametrize("shape,cell", [((8, 8, 8), (2e-9,) * 3), ((70, 9, 2), (2e-9, 3e-9, 1e-9)),
+                                        ((5, 23, 11), (1.95e-9, 1.95e-9, 0.75e-9)), ((1, 1, 1), (2e-9, 2e-9, 3e-9))])
+def test_sp_kernel_octant_vs_oracle(shape, cell):
+    """Near (closed form), middle (Gauss-Legendre) and far (moment series)
+    bands of S against the binary128 two-face kernel."""
+    from paper_1204_4302_amd import Plan
+    plan = Plan(shape, cell, torch.float64)
+    got = plan.sp_kernel()
+    ref = oracle.SPOracle(shape, cell).Soct
+    scale = np.abs(ref).max()
+    if scale == 0:  # a single cell: S(0) = 0 by parity
+        assert np.abs(got).max() == 0
+        return
+    err = np.abs(got - ref).max() / scale
+    big = np.abs(ref) > 1e-6 * scale
+    rel = (np.abs(got - ref)[big] / np.abs(ref)[big]).max() if big.any() else 0.0
+    print(f"{shape}: max err {err:.2e} of max, worst relative {rel:.2e}")
+    assert err <= 1e-13 and rel <= 1e-11
+
+
+SHAPES = [
+    ((8, 8, 8), (2e-9, 2e-9, 2e-9), 8e5),
+    ((1, 1, 1), (2e-9, 2e-9, 3e-9), 1.4e6),
+    ((5, 1, 1), (2e-9, 2e-9, 2e-9), 8e5),          # x generic (10), single-cell y and z
+    ((2, 3, 4), (2e-9, 2e-9, 2e-9), 8e5),          # two cells along x: first-order stencil
+    ((64, 32, 8), (2e-9, 2e-9, 3e-9), 1.4e6),
+    ((4, 4, 64), (1.95e-9, 1.95e-9, 0.75e-9), 8e5),
+    ((24, 17, 3), (1.95e-9, 1.95e-9, 0.75e-9), 8e5),  # 48, 36 (generic), 6 = 3 * 2
+    ((47, 11, 23), (2e-9, 2e-9, 3e-9), 1.4e6),     # 96, 24, 48: 3 * 2^a, ragged
+    ((29, 61, 11), (2e-9, 2e-9, 3e-9), 1.4e6),     # 60 (generic), 128, 24
+]
+
+
+def _supported(plan, dtype):
+    """FP64 runs the SP Z pass for power-of-two padded z lengths only."""
+    Pz = plan.info()["Pz"]
+    return dtype == torch.float32 or (Pz & (Pz - 1)) == 0
+
+
+@pytest.mark.parametrize("shape,cell,Ms", SHAPES, ids=lambda v: str(v))
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_sp_field_vs_oracle(shape, cell, Ms, dtype):
+    from paper_1204_4302_amd import Plan
+    from paper_1204_4302_amd._lib import DemagError
+    plan = Plan(shape, cell, dtype)
+    if not _supported(plan, dtype):
+        with pytest.raises(DemagError):
+            plan.sp_prepare()
+        return
+    plan.sp_prepare()
+    m = inputs.random_unit(shape, 1)
+    H = plan.sp_field(_gpu(m, dtype), Ms).double().cpu().numpy()
+    ref = oracle.SPOracle(shape, cell).field(_quantised(m, dtype), Ms)
+    err = rel_err(H, ref)
+    print(f"shape={shape} dtype={dtype} rel_err={err:.3e}")
+    assert err <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_sp_energy_vs_oracle(dtype):
+    from paper_1204_4302_amd import Plan
+    shape, cell, Ms = (32, 16, 8), (2e-9, 2e-9, 3e-9), 1.4e6
+    plan = Plan(shape, cell, dtype)
+    plan.sp_prepare()
+    m = inputs.gaussian_vortex(shape, cell, 10e-9)
+    H, E = plan.sp_field_energy(_gpu(m, dtype), Ms)
+    _, E_only = plan.sp_field_energy(_gpu(m, dtype), Ms, with_field=False)
+    so = oracle.SPOracle(shape, cell)
+    mq = _quantised(m, dtype)
+    ref = so.energy(mq, so.field(mq, Ms), Ms)
+    tol = 1e-12 if dtype == torch.float64 else 1e-6
+    assert abs(float(E) / ref - 1) <= tol
+    assert float(E_only) == float(E)
+
+
+def test_sp_unprepared_and_repeat():
+    from paper_1204_4302_amd import Plan
+    from paper_1204_4302_amd._lib import DemagError
+    shape, cell = (16, 8, 4), (2e-9,) * 3
+    plan = Plan(shape, cell, torch.float32)
+    m = _gpu(inputs.random_unit(shape, 2), torch.float32)
+    with pytest.raises(DemagError):
+        plan.sp_field(m, 8e5)
+    plan.sp_prepare()
+    plan.sp_prepare()  # idempotent
+    a = plan.sp_field(m, 8e5)
+    b = plan.sp_field(m, 8e5)
+    assert torch.equal(a, b)
+    # the DM path of the same plan is unaffected by SP scratch use
+    h1 = plan.field(m, 8e5)
+    plan.sp_field(m, 8e5)
+    h2 = plan.field(m, 8e5)
+    assert torch.equal(h1, h2)
+
+
+@pytest.mark.slow
+def test_sp_full_size_sampled():
+    """256 x 256 x 64, 2 x 2 x 3 nm, Ms = 1.4e6: sampled cells vs the oracle,
+    plans tuned as bench.py tunes them."""
+    from paper_1204_4302_amd import Plan
+    shape, cell, Ms = (256, 256, 64), (2e-9, 2e-9, 3e-9), 1.4e6
+    so = oracle.SPOracle(shape, cell, cache_dir=CACHE)
+    m = inputs.random_unit(shape, 3)
+    t = inputs.sample_targets(shape, 96, 17)
+    for dtype, tol in [(torch.float64, FP64_TOL), (torch.float32, FP32_TOL)]:
+        plan = Plan(shape, cell, dtype)
+        plan.autotune()
+        plan.sp_prepare()
+        H = plan.sp_field(_gpu(m, dtype), Ms).double().cpu().numpy().reshape(3, -1)[:, t]
+        ref = so.field_targets(_quantised(m, dtype), Ms, t)
+        err = rel_err(H, ref)
+        print(f"{dtype}: {t.size} cells, rel err {err:.3e}")
+        assert err <= tol
+        plan.close()
