@@ -68,6 +68,65 @@ def pass_bytes(shape, Px, Py, Pz, Kx, real_bytes):
     }
 
 
+def sp_pass_bytes(shape, Px, Py, Pz, Kx, real_bytes):
+    """Algorithmic bytes per launch of each kernel of one scalar-potential
+    evaluation with energy (X and Y forward as for DM; the SP Z pass reads
+    three components and the kernel spectrum, writes one; one-component
+    inverse passes; the gradient reads phi and m, writes H)."""
+    nx, ny, nz = shape
+    N = nx * ny * nz
+    c = 2 * real_bytes
+    vec = 3 * N * real_bytes
+    B1c = nz * Kx * ny * c
+    B2c = Py * Kx * nz * c
+    shat = (Py // 2 + 1) * 3 * Kx * (Pz // 2 + 1) * real_bytes
+    return {
+        "x_r2c": vec + 3 * B1c,
+        "y_fwd": 3 * B1c + 3 * B2c,
+        "z_sp": 3 * B2c + shat + B2c,
+        "y_inv_1": B2c + B1c,
+        "x_c2r_1": B1c + N * real_bytes,
+        "gradient": N * real_bytes + 2 * vec,
+    }
+
+
+def bench_sp(args, torch, np, m_np, dm_value):
+    """Scalar-potential method on the same workload, FP32: field + energy.
+    Its energy is compared with DM's on a smooth state (the Gaussian vortex):
+    on i.i.d. random directions the finite-difference gradient cannot resolve
+    the cell-scale structure, and the two methods differ at O(1) there."""
+    from paper_1204_4302_amd import Plan, inputs
+    plan = Plan(SHAPE, CELL, torch.float32)
+    if not args.no_autotune:
+        plan.autotune()
+    plan.sp_prepare()
+    m = torch.from_numpy(m_np).to("cuda", torch.float32)
+    H = torch.empty_like(m)
+    E = torch.empty((), dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.sp_field_energy(m, MS, out=H, E_out=E)
+
+    for _ in range(args.warmup):
+        step()
+    k = args.sp_steps
+    secs = run_steps(step, k, torch)
+    i = plan.info()
+    pb = sp_pass_bytes(SHAPE, i["Px"], i["Py"], i["Pz"], i["Kx"], 4)
+    nbytes = sum(pb.values())
+    mv = torch.from_numpy(inputs.gaussian_vortex(SHAPE, CELL, 10e-9)).to("cuda", torch.float32)
+    _, e_sp = plan.sp_field_energy(mv, MS, with_field=False)
+    e_dm = plan.energy(mv, MS)
+    e_sp = float(e_sp.cpu())
+    out = {"value": round(k / secs, 2), "unit": "evals/s", "ms_per_eval": round(1e3 * secs / k, 4),
+           "modelled_bytes_per_eval": nbytes, "achieved_GBs": round(nbytes * k / secs / 1e9, 1),
+           "bytes_per_kernel": pb, "speedup_over_dm": round(k / secs / dm_value, 3),
+           "vortex_energy_rel_diff_vs_dm": abs(e_sp - e_dm) / abs(e_dm),
+           "step": "one SP field evaluation with energy (potential by FFT convolution, finite-difference gradient)"}
+    plan.close()
+    return out
+
+
 def read_traffic():
     """HBM bytes per z_conv launch from the committed --pmc summary, or None if
     the kernels changed since the counters were taken."""
@@ -273,6 +332,9 @@ def bench(args):
         H64 = r64["H"]
         out["accuracy"] = {"f32_vs_f64_gpu_field": float(np.max(np.abs(r32["H"] - H64)) / np.max(np.abs(H64))),
                            "f32_vs_f64_gpu_energy": abs(r32["E"] - r64["E"]) / abs(r64["E"])}
+    if args.sp_steps > 0:
+        out["sp"] = bench_sp(args, torch, np, m_np, value)
+        print(f"# sp: {out['sp']}", file=sys.stderr, flush=True)
     if args.batch_steps > 0:
         out["batch"] = bench_batch(args, torch, np)
         print(f"# batch: {out['batch']}", file=sys.stderr, flush=True)
@@ -301,14 +363,17 @@ def summarize_profile(d, out_path, command):
     """Per-kernel calls / average / total from a --kernel-trace --stats run."""
     import sqlite3
     lines = [f"# command: {command}", f"# kernel_source_hash = {kernel_source_hash()}",
-             "# kernel stats (rocprofv3 --kernel-trace --stats)",
-             f"{'kernel':44s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+             "# per kernel and grid size (work-items), from the trace's dispatch records",
+             f"{'kernel':44s} {'grid':>9s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
     for db in _find(d, "*results.db"):
         con = sqlite3.connect(db)
-        for name, calls, total, avg, pct in con.execute(
-                "select name, total_calls, total_duration, average, percentage from top_kernels"):
-            # this view reports durations in microseconds
-            lines.append(f"{_short(name)[:44]:44s} {calls:6d} {avg:10.2f} {total / 1e3:10.3f} {pct:6.2f}")
+        rows = con.execute("select name, grid_x * grid_y * grid_z, count(*), sum(end - start), avg(end - start) "
+                           "from kernels group by name, grid_x, grid_y, grid_z").fetchall()
+        total_ns = sum(r[3] for r in rows) or 1
+        for name, grid, calls, tot, avg in sorted(rows, key=lambda r: -r[3]):
+            # dispatch timestamps are in nanoseconds
+            lines.append(f"{_short(name)[:44]:44s} {grid:9d} {calls:6d} {avg / 1e3:10.2f} {tot / 1e6:10.3f} "
+                         f"{100.0 * tot / total_ns:6.2f}")
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -369,6 +434,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample budget")
     ap.add_argument("--batch-steps", type=int, default=50, help="replays of the 96-grid batch (0: skip)")
+    ap.add_argument("--sp-steps", type=int, default=200, help="scalar-potential evaluations (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
