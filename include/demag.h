@@ -137,6 +137,33 @@ int demag_sp_field_energy(demag_plan_t plan, const void* m, double Ms, void* H, 
  * per unit magnetization), to HOST memory `out` [3][nz][ny][nx].  Synchronous. */
 int demag_sp_kernel(demag_plan_t plan, double* out);
 
+/* ---- Tensor-grid method (TG, dense), Sec. 3.2 eqs. (transform), (gausspot),
+ * (sumpot), (Dmat), (gs) -----------------------------------------------------
+ * The same potential phi as the SP calls (exact for cell-wise constant m up
+ * to the quadrature), computed as the block-CP sum of eq. (sumpot): Sinc
+ * quadrature of the Gaussian representation of 1/r^3 in t = log(tau) (step
+ * 0.25 in FP32, 0.15 in FP64; relative kernel error about 2e-7 and 6e-13 on
+ * distances from the smallest cell edge to the body diagonal), closed-form
+ * Gaussian matrices per axis and node, mode products as GEMMs (rocBLAS);
+ * H = -grad phi with the SP difference stencils.
+ *
+ * demag_tg_prepare builds nodes and matrices and allocates the GEMM scratch
+ * (2 R N values; R nodes, about 75 in FP32 and 125 in FP64 at 256 x 256 x 64);
+ * synchronous; idempotent; DEMAG_ENOMEM if the scratch does not fit. */
+int demag_tg_prepare(demag_plan_t plan, void* stream);
+/* H (device, [3][nz][ny][nx]) for m; asynchronous.  DEMAG_ESTATE before
+ * demag_tg_prepare. */
+int demag_tg_field(demag_plan_t plan, const void* m, double Ms, void* H, void* stream);
+/* The same and the energy into the device double *E_dev; H may be NULL. */
+int demag_tg_field_energy(demag_plan_t plan, const void* m, double Ms, void* H, double* E_dev, void* stream);
+/* out[0] = R (nodes), out[1] = scratch bytes, out[2] = flops per evaluation. */
+int demag_tg_info(demag_plan_t plan, int64_t* out);
+/* Host only: the Sinc nodes tau_l and weights w_l (w_l = step tau_l^3 /
+ * pi^(3/2), so that 1/r^3 ~ 4 pi sum_l w_l exp(-tau_l^2 r^2)) for
+ * distances in [rmin, rmax]; returns R (the count) and fills tau, w when both
+ * are non-NULL and cap >= R; negative status on bad arguments. */
+int demag_tg_sinc_nodes(double rmin, double rmax, double step, double* tau, double* w, int cap);
+
 /* Text description of the launch shape of every pass (kernel family, threads,
  * tiles) into `buf` (len bytes, NUL-terminated); DEMAG_EINVAL if too small. */
 int demag_plan_describe(demag_plan_t plan, char* buf, int len);

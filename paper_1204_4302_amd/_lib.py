@@ -41,6 +41,11 @@ SIGNATURES = {
     "demag_sp_field": (_I, [_P, _P, _D, _P, _P]),
     "demag_sp_field_energy": (_I, [_P, _P, _D, _P, _P, _P]),
     "demag_sp_kernel": (_I, [_P, _P]),
+    "demag_tg_prepare": (_I, [_P, _P]),
+    "demag_tg_field": (_I, [_P, _P, _D, _P, _P]),
+    "demag_tg_field_energy": (_I, [_P, _P, _D, _P, _P, _P]),
+    "demag_tg_info": (_I, [_P, _P]),
+    "demag_tg_sinc_nodes": (_I, [_D, _D, _D, _P, _P, _I]),
     "demag_batch_autotune": (_I, [_P, _P]),
     "demag_batch_launch": (_I, [_P, _P]),
     "demag_batch_destroy": (_I, [_P]),

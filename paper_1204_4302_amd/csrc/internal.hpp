@@ -142,6 +142,19 @@ hipError_t launch_sp_embed(hipStream_t, int a, int nx, int ny, int nz, int Px, i
 template <typename T>
 hipError_t launch_sp_extract(hipStream_t, int a, int Py, int Pz, int Kx, double scale, const cx<double>* B2,
                              T* shat);
+// ---- tensor-grid method (tg.hip) ----------------------------------------------
+// Sinc nodes tau_l and weights h tau_l^3 / pi^(3/2) for 1/r^3 on [rmin, rmax]
+// (reduced units), step h; returns R (or -1 for bad arguments).
+int tg_sinc_nodes(double rmin, double rmax, double h, std::vector<double>& tau, std::vector<double>& w);
+template <typename T>
+hipError_t launch_tg_axis(hipStream_t, int n, double d, int R, const double* tau, T* E, T* O);
+template <typename T>
+hipError_t launch_tg_stack3(hipStream_t, int n3, int R, const double* c, const T* D3, T* B3);
+template <typename T>
+int tg_potential(void* handle, hipStream_t st, int n1, int n2, int n3, int R, const T* m, const T* D1E,
+                 const T* D1O, const T* const* D2p[3], const T* const* Y1k, T* const* Y2k, const T* const B3[3], T* Y1,
+                 T* Y2, T* phi, double alpha);
+
 // H = -grad phi (d = cell edges), optional energy partials m.H, one per (y, z) row.
 template <typename T>
 hipError_t launch_sp_gradient(hipStream_t, int nx, int ny, int nz, const double d[3], const T* phi, T* H,

@@ -6,6 +6,7 @@
 // allocates the two spectrum scratch buffers; each field evaluation then
 // enqueues five pass kernels and, for the energy, one reduction.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -140,6 +141,21 @@ struct PassCfgs {
     LaunchCfg xf, yf, zc, yi, xi;
 };
 
+// Tensor-grid (TG) state of a plan (after demag_tg_prepare): Sinc nodes,
+// Gaussian matrices, stacked mode-3 factors, GEMM scratch and the device
+// pointer arrays of the mode-2 batch.
+struct TGState {
+    void* handle = nullptr;  // rocblas_handle
+    int R = 0;
+    double step = 0;
+    double* tau = nullptr;
+    double* c = nullptr;
+    void *D1E = nullptr, *D1O = nullptr, *D2E = nullptr, *D2O = nullptr, *B3E = nullptr, *B3O = nullptr;
+    void *Y1 = nullptr, *Y2 = nullptr;
+    void **Y1k = nullptr, **Y2k = nullptr, **D2kE = nullptr, **D2kO = nullptr;
+    size_t bytes = 0;
+};
+
 struct demag_plan_s {
     int n[3];
     double d[3];
@@ -150,6 +166,7 @@ struct demag_plan_s {
     void* twt[3] = {nullptr, nullptr, nullptr};  // thread-major twiddles of power-of-two axes
     void* nhat = nullptr;
     void* shat = nullptr;  // scalar-potential kernel spectrum (after demag_sp_prepare)
+    TGState* tg = nullptr; // tensor-grid state (after demag_tg_prepare)
     LaunchCfg zs;          // launch shape of the scalar-potential Z pass
     void* B1 = nullptr;
     void* B2 = nullptr;
@@ -482,6 +499,114 @@ int setup_sp_spectrum(demag_plan_s* p, hipStream_t st) {
     return DEMAG_OK;
 }
 
+// One tensor-grid evaluation: Phi by the GEMM chain into B2's memory, then
+// the finite-difference gradient (and energy) as for SP.
+template <typename T>
+int run_tg_field(demag_plan_s* p, const T* m, double Ms, T* H, double* E_dev, hipStream_t st) {
+    const int nx = p->n[0], ny = p->n[1], nz = p->n[2];
+    TGState* g = p->tg;
+    T* phi = (T*)p->B2;
+    T* Hout = H ? H : (T*)p->B1;
+    const T* const* D2p[3] = {(const T* const*)g->D2kE, (const T* const*)g->D2kO, (const T* const*)g->D2kE};
+    const T* B3[3] = {(const T*)g->B3E, (const T*)g->B3E, (const T*)g->B3O};
+    const double hmax = std::max(p->d[0], std::max(p->d[1], p->d[2]));
+    const int rc = tg_potential<T>(g->handle, st, nx, ny, nz, g->R, m, (const T*)g->D1E, (const T*)g->D1O, D2p,
+                                   (const T* const*)g->Y1k, (T* const*)g->Y2k, B3, (T*)g->Y1, (T*)g->Y2, phi,
+                                   Ms * hmax);
+    if (rc) return fail(DEMAG_EHIP, "tensor-grid GEMM failed (%d)", rc);
+    HIP_TRY(launch_sp_gradient<T>(st, nx, ny, nz, p->d, phi, Hout, E_dev ? m : nullptr, E_dev ? p->partials : nullptr));
+    if (E_dev) {
+        const double V = p->d[0] * p->d[1] * p->d[2];
+        HIP_TRY(launch_energy_reduce(st, p->partials, ny * nz, -0.5 * kMu0 * Ms * V, E_dev));
+    }
+    return DEMAG_OK;
+}
+
+template <typename T>
+int setup_tg(demag_plan_s* p, hipStream_t st, double step) {
+    auto* g = new TGState();
+    p->tg = g;
+    const int n1 = p->n[0], n2 = p->n[1], n3 = p->n[2];
+    const size_t N = (size_t)n1 * n2 * n3;
+    double dt[3];
+    reduced_cell(p->d, dt);
+    const double rmin = std::min(dt[0], std::min(dt[1], dt[2]));
+    const double rmax = std::sqrt((n1 * dt[0]) * (n1 * dt[0]) + (n2 * dt[1]) * (n2 * dt[1]) + (n3 * dt[2]) * (n3 * dt[2]));
+    std::vector<double> tau, w;
+    const int R = tg_sinc_nodes(rmin, std::max(rmax, rmin), step, tau, w);
+    if (R <= 0) return fail(DEMAG_EINVAL, "tensor-grid quadrature");
+    g->R = R;
+    g->step = step;
+    const size_t sz = sizeof(T);
+    const size_t need = sz * ((size_t)R * 2 * ((size_t)n1 * n1 + (size_t)n2 * n2) + 2 * (size_t)R * n3 * n3 + 2 * (size_t)R * N) +
+                        4 * sizeof(void*) * (size_t)R * n3;
+    g->bytes = need;
+    int rc = DEMAG_OK;
+    auto alloc = [&](void** ptr, size_t bytes, const char* what) {
+        if (rc) return;
+        if (hipMalloc(ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *ptr = nullptr;
+            rc = fail(DEMAG_ENOMEM, "cannot allocate %zu bytes for the tensor-grid %s", bytes, what);
+        }
+    };
+    void *D3E = nullptr, *D3O = nullptr;
+    alloc((void**)&g->tau, R * sizeof(double), "nodes");
+    alloc((void**)&g->c, R * sizeof(double), "weights");
+    alloc(&g->D1E, (size_t)R * n1 * n1 * sz, "matrices");
+    alloc(&g->D1O, (size_t)R * n1 * n1 * sz, "matrices");
+    alloc(&g->D2E, (size_t)R * n2 * n2 * sz, "matrices");
+    alloc(&g->D2O, (size_t)R * n2 * n2 * sz, "matrices");
+    alloc(&D3E, (size_t)R * n3 * n3 * sz, "matrices");
+    alloc(&D3O, (size_t)R * n3 * n3 * sz, "matrices");
+    alloc(&g->B3E, (size_t)R * n3 * n3 * sz, "mode-3 factors");
+    alloc(&g->B3O, (size_t)R * n3 * n3 * sz, "mode-3 factors");
+    alloc(&g->Y1, (size_t)R * N * sz, "scratch");
+    alloc(&g->Y2, (size_t)R * N * sz, "scratch");
+    const size_t nb = (size_t)R * n3;
+    alloc((void**)&g->Y1k, nb * sizeof(void*), "pointer arrays");
+    alloc((void**)&g->Y2k, nb * sizeof(void*), "pointer arrays");
+    alloc((void**)&g->D2kE, nb * sizeof(void*), "pointer arrays");
+    alloc((void**)&g->D2kO, nb * sizeof(void*), "pointer arrays");
+    if (!rc && hipMemcpy(g->tau, tau.data(), R * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        rc = fail(DEMAG_EHIP, "upload");
+    if (!rc && hipMemcpy(g->c, w.data(), R * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+        rc = fail(DEMAG_EHIP, "upload");
+    if (!rc) {
+        std::vector<void*> y1(nb), y2(nb), de(nb), dO(nb);
+        for (int l = 0; l < R; ++l)
+            for (int k = 0; k < n3; ++k) {
+                const size_t b = (size_t)l * n3 + k, off = (size_t)l * N + (size_t)k * n1 * n2;
+                y1[b] = (T*)g->Y1 + off;
+                y2[b] = (T*)g->Y2 + off;
+                de[b] = (T*)g->D2E + (size_t)l * n2 * n2;
+                dO[b] = (T*)g->D2O + (size_t)l * n2 * n2;
+            }
+        if (hipMemcpy(g->Y1k, y1.data(), nb * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(g->Y2k, y2.data(), nb * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(g->D2kE, de.data(), nb * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(g->D2kO, dO.data(), nb * sizeof(void*), hipMemcpyHostToDevice) != hipSuccess)
+            rc = fail(DEMAG_EHIP, "upload");
+    }
+    if (!rc) {
+        hipError_t e = launch_tg_axis<T>(st, n1, dt[0], R, g->tau, (T*)g->D1E, (T*)g->D1O);
+        if (e == hipSuccess) e = launch_tg_axis<T>(st, n2, dt[1], R, g->tau, (T*)g->D2E, (T*)g->D2O);
+        if (e == hipSuccess) e = launch_tg_axis<T>(st, n3, dt[2], R, g->tau, (T*)D3E, (T*)D3O);
+        if (e == hipSuccess) e = launch_tg_stack3<T>(st, n3, R, g->c, (const T*)D3E, (T*)g->B3E);
+        if (e == hipSuccess) e = launch_tg_stack3<T>(st, n3, R, g->c, (const T*)D3O, (T*)g->B3O);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(e, "tensor-grid setup");
+    }
+    hipFree(D3E);
+    hipFree(D3O);
+    if (!rc) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) rc = fail(DEMAG_EHIP, "rocblas_create_handle failed");
+        g->handle = h;
+    }
+    return rc;
+}
+
 int run_setup(demag_plan_s* p, hipStream_t st) {
     auto t0 = std::chrono::steady_clock::now();
     int rc = p->dtype == DEMAG_F32 ? setup_spectrum<float>(p, st) : setup_spectrum<double>(p, st);
@@ -489,11 +614,21 @@ int run_setup(demag_plan_s* p, hipStream_t st) {
     return rc;
 }
 
+void free_tg(TGState* g) {
+    if (!g) return;
+    if (g->handle) rocblas_destroy_handle((rocblas_handle)g->handle);
+    for (void* q : {(void*)g->tau, (void*)g->c, g->D1E, g->D1O, g->D2E, g->D2O, g->B3E, g->B3O, g->Y1, g->Y2,
+                    (void*)g->Y1k, (void*)g->Y2k, (void*)g->D2kE, (void*)g->D2kO})
+        hipFree(q);
+    delete g;
+}
+
 void free_plan(demag_plan_s* p) {
     for (auto t : p->tw) hipFree(t);
     for (auto t : p->twt) hipFree(t);
     hipFree(p->nhat);
     hipFree(p->shat);
+    free_tg(p->tg);
     hipFree(p->B1);
     hipFree(p->B2);
     hipFree(p->partials);
@@ -910,6 +1045,64 @@ int demag_sp_kernel(demag_plan_t p, double* out) {
     HIP_TRY(hipMemcpy(tmp.data(), sb.Noct, 3 * ncell * sizeof(double), hipMemcpyDeviceToHost));
     for (size_t i = 0; i < tmp.size(); ++i) out[i] = tmp[i] * h;
     return DEMAG_OK;
+}
+
+int demag_tg_prepare(demag_plan_t p, void* stream) {
+    if (!p) return fail(DEMAG_EINVAL, "NULL plan");
+    if (p->tg) return DEMAG_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    const double step = p->dtype == DEMAG_F32 ? 0.25 : 0.15;
+    rc = p->dtype == DEMAG_F32 ? setup_tg<float>(p, st, step) : setup_tg<double>(p, st, step);
+    if (rc) {
+        free_tg(p->tg);
+        p->tg = nullptr;
+        return rc;
+    }
+    return leave(p, st);
+}
+
+int demag_tg_field_energy(demag_plan_t p, const void* m, double Ms, void* H, double* E_dev, void* stream) {
+    if (!p || !m || (!H && !E_dev)) return fail(DEMAG_EINVAL, "NULL plan or m, or neither H nor E_dev");
+    if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
+    if (!p->tg) return fail(DEMAG_ESTATE, "tensor-grid method not prepared (call demag_tg_prepare)");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    rc = p->dtype == DEMAG_F32 ? run_tg_field<float>(p, (const float*)m, Ms, (float*)H, E_dev, st)
+                               : run_tg_field<double>(p, (const double*)m, Ms, (double*)H, E_dev, st);
+    if (rc) return rc;
+    return leave(p, st);
+}
+
+int demag_tg_field(demag_plan_t p, const void* m, double Ms, void* H, void* stream) {
+    if (!H) return fail(DEMAG_EINVAL, "H is NULL");
+    return demag_tg_field_energy(p, m, Ms, H, nullptr, stream);
+}
+
+int demag_tg_info(demag_plan_t p, int64_t* out) {
+    if (!p || !out) return fail(DEMAG_EINVAL, "NULL argument");
+    if (!p->tg) return fail(DEMAG_ESTATE, "tensor-grid method not prepared");
+    out[0] = p->tg->R;
+    out[1] = (int64_t)p->tg->bytes;
+    const double n1 = p->n[0], n2 = p->n[1], n3 = p->n[2];
+    out[2] = (int64_t)(3.0 * 2.0 * p->tg->R * n1 * n2 * n3 * (n1 + n2 + n3));  // flops per evaluation
+    return DEMAG_OK;
+}
+
+int demag_tg_sinc_nodes(double rmin, double rmax, double step, double* tau, double* w, int cap) {
+    std::vector<double> t, ww;
+    const int R = tg_sinc_nodes(rmin, rmax, step, t, ww);
+    if (R < 0) return fail(DEMAG_EINVAL, "need 0 < rmin <= rmax and step > 0");
+    if (tau && w) {
+        if (cap < R) return fail(DEMAG_EINVAL, "capacity %d below the %d nodes", cap, R);
+        for (int l = 0; l < R; ++l) {
+            tau[l] = t[l];
+            w[l] = ww[l];
+        }
+    }
+    return R;
 }
 
 int demag_plan_describe(demag_plan_t p, char* buf, int len) {

@@ -189,11 +189,59 @@ class Plan:
         _lib.call("demag_sp_kernel", self._h, a.ctypes.data_as(ctypes.c_void_p))
         return a
 
+    # -- tensor-grid method (TG, dense) --------------------------------------
+    def tg_prepare(self):
+        """Sinc nodes, Gaussian matrices and GEMM scratch (synchronous, once)."""
+        _lib.call("demag_tg_prepare", self._h, _stream_ptr())
+
+    def tg_info(self) -> dict:
+        out = (ctypes.c_int64 * 3)()
+        _lib.call("demag_tg_info", self._h, out)
+        return {"nodes": out[0], "scratch_bytes": out[1], "flops_per_eval": out[2]}
+
+    def tg_field(self, m: torch.Tensor, Ms: float, out: torch.Tensor | None = None) -> torch.Tensor:
+        """H = -grad phi, phi by the block-CP sum of Gaussian mode products."""
+        self._check(m, "m")
+        H = torch.empty_like(m) if out is None else out
+        self._check(H, "out")
+        _lib.call("demag_tg_field", self._h, self._ptr(m), float(Ms), self._ptr(H), _stream_ptr())
+        return H
+
+    def tg_field_energy(self, m: torch.Tensor, Ms: float, with_field: bool = True,
+                        out: torch.Tensor | None = None, E_out: torch.Tensor | None = None):
+        """(H or None, E) of the TG method, E a 0-dim float64 CUDA tensor."""
+        self._check(m, "m")
+        H = (torch.empty_like(m) if out is None else out) if with_field else None
+        if H is not None:
+            self._check(H, "out")
+        E = torch.empty((), dtype=torch.float64, device=m.device) if E_out is None else E_out
+        if E.dtype != torch.float64 or E.device.type != "cuda" or E.numel() != 1:
+            raise TypeError("E_out must be a one-element float64 CUDA tensor")
+        _lib.call("demag_tg_field_energy", self._h, self._ptr(m), float(Ms),
+                  self._ptr(H) if H is not None else None, ctypes.c_void_p(E.data_ptr()), _stream_ptr())
+        return H, E
+
     def energy(self, m: torch.Tensor, Ms: float) -> float:
         self._check(m, "m")
         e = ctypes.c_double()
         _lib.call("demag_energy", self._h, self._ptr(m), float(Ms), ctypes.byref(e), _stream_ptr())
         return e.value
+
+
+def tg_sinc_nodes(rmin: float, rmax: float, step: float):
+    """Host-side Sinc nodes and weights of the TG kernel quadrature:
+    1/r^3 ~ 4 pi sum_l w_l exp(-tau_l^2 r^2) for r in [rmin, rmax]."""
+    lib = _lib.load()
+    R = lib.demag_tg_sinc_nodes(float(rmin), float(rmax), float(step), None, None, 0)
+    if R < 0:
+        _lib.check("demag_tg_sinc_nodes", R)
+    tau = np.empty(R)
+    w = np.empty(R)
+    rc = lib.demag_tg_sinc_nodes(float(rmin), float(rmax), float(step), tau.ctypes.data_as(ctypes.c_void_p),
+                                 w.ctypes.data_as(ctypes.c_void_p), R)
+    if rc != R:
+        _lib.check("demag_tg_sinc_nodes", rc)
+    return tau, w
 
 
 class Batch:
