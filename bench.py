@@ -127,6 +127,41 @@ def bench_sp(args, torch, np, m_np, dm_value):
     return out
 
 
+MFMA_FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
+
+
+def bench_tg(args, torch, np, m_np, dm_value):
+    """Tensor-grid method (dense block-CP sum of Gaussian mode products) on the
+    same workload, FP32: potential by GEMMs (MFMA), field by differences."""
+    from paper_1204_4302_amd import Plan
+    plan = Plan(SHAPE, CELL, torch.float32)
+    plan.tg_prepare()
+    info = plan.tg_info()
+    m = torch.from_numpy(m_np).to("cuda", torch.float32)
+    H = torch.empty_like(m)
+    E = torch.empty((), dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.tg_field_energy(m, MS, out=H, E_out=E)
+
+    for _ in range(2):
+        step()
+    k = args.tg_steps
+    secs = run_steps(step, k, torch)
+    tflops = info["flops_per_eval"] * k / secs / 1e12
+    out = {"value": round(k / secs, 2), "unit": "evals/s", "ms_per_eval": round(1e3 * secs / k, 3),
+           "sinc_nodes": info["nodes"], "flops_per_eval": info["flops_per_eval"],
+           "scratch_bytes": info["scratch_bytes"],
+           "roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": MFMA_FP32_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(tflops / MFMA_FP32_PEAK_TFLOPS, 4),
+                        "note": "mode-product GEMM flops over the whole evaluation (gradient included in the time)"},
+           "speedup_over_dm": round(k / secs / dm_value, 4),
+           "step": "one TG field evaluation with energy (Sinc quadrature, Gaussian mode products as GEMMs, "
+                   "finite-difference gradient)"}
+    plan.close()
+    return out
+
+
 def read_traffic():
     """HBM bytes per z_conv launch from the committed --pmc summary, or None if
     the kernels changed since the counters were taken."""
@@ -335,6 +370,9 @@ def bench(args):
     if args.sp_steps > 0:
         out["sp"] = bench_sp(args, torch, np, m_np, value)
         print(f"# sp: {out['sp']}", file=sys.stderr, flush=True)
+    if args.tg_steps > 0:
+        out["tg"] = bench_tg(args, torch, np, m_np, value)
+        print(f"# tg: {out['tg']}", file=sys.stderr, flush=True)
     if args.batch_steps > 0:
         out["batch"] = bench_batch(args, torch, np)
         print(f"# batch: {out['batch']}", file=sys.stderr, flush=True)
@@ -435,6 +473,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample budget")
     ap.add_argument("--batch-steps", type=int, default=50, help="replays of the 96-grid batch (0: skip)")
     ap.add_argument("--sp-steps", type=int, default=200, help="scalar-potential evaluations (0: skip)")
+    ap.add_argument("--tg-steps", type=int, default=10, help="tensor-grid evaluations (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
