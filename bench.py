@@ -127,6 +127,37 @@ def bench_sp(args, torch, np, m_np, dm_value):
     return out
 
 
+def bench_llg(args, torch, np, dm_value):
+    """LLG driver on the same grid, FP32: explicit Heun steps with the DM field
+    (two field evaluations and two elementwise kernels per step)."""
+    from paper_1204_4302_amd import Plan, inputs
+    plan = Plan(SHAPE, CELL, torch.float32)
+    if not args.no_autotune:
+        plan.autotune()
+    m = torch.from_numpy(inputs.gaussian_vortex(SHAPE, CELL, 10e-9)).to("cuda", torch.float32)
+    work = torch.empty((9,) + tuple(m.shape[1:]), dtype=torch.float32, device="cuda")
+    dt = 1e-13
+
+    def step():
+        plan.llg_heun(m, MS, 0.5, dt, 1, H_ext=(0.0, 0.0, 5e4), work=work)
+
+    for _ in range(3):
+        step()
+    k = args.llg_steps
+    secs = run_steps(step, k, torch)
+    i = plan.info()
+    field = sum(pass_bytes(SHAPE, i["Px"], i["Py"], i["Pz"], i["Kx"], 4).values())
+    vec = 3 * SHAPE[0] * SHAPE[1] * SHAPE[2] * 4
+    nbytes = 2 * field + 4 * vec + 5 * vec  # two fields, predictor (m, H -> k1, m*), corrector (m, H, k1, m* -> m)
+    out = {"value": round(k / secs, 2), "unit": "Heun steps/s", "ms_per_step": round(1e3 * secs / k, 4),
+           "modelled_bytes_per_step": nbytes, "achieved_GBs": round(nbytes * k / secs / 1e9, 1),
+           "field_evals_per_s": round(2 * k / secs, 1),
+           "step": "one explicit Heun step of the LLG equation (alpha 0.5, dt 1e-13 s, H_ext 5e4 A/m along z, "
+                   "Gaussian vortex start), demag field by DM"}
+    plan.close()
+    return out
+
+
 MFMA_FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix peak
 
 
@@ -370,6 +401,9 @@ def bench(args):
     if args.sp_steps > 0:
         out["sp"] = bench_sp(args, torch, np, m_np, value)
         print(f"# sp: {out['sp']}", file=sys.stderr, flush=True)
+    if args.llg_steps > 0:
+        out["llg"] = bench_llg(args, torch, np, value)
+        print(f"# llg: {out['llg']}", file=sys.stderr, flush=True)
     if args.tg_steps > 0:
         out["tg"] = bench_tg(args, torch, np, m_np, value)
         print(f"# tg: {out['tg']}", file=sys.stderr, flush=True)
@@ -474,6 +508,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=50, help="replays of the 96-grid batch (0: skip)")
     ap.add_argument("--sp-steps", type=int, default=200, help="scalar-potential evaluations (0: skip)")
     ap.add_argument("--tg-steps", type=int, default=10, help="tensor-grid evaluations (0: skip)")
+    ap.add_argument("--llg-steps", type=int, default=100, help="LLG Heun steps (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",

@@ -137,6 +137,18 @@ int demag_sp_field_energy(demag_plan_t plan, const void* m, double Ms, void* H, 
  * per unit magnetization), to HOST memory `out` [3][nz][ny][nx].  Synchronous. */
 int demag_sp_kernel(demag_plan_t plan, double* out);
 
+/* ---- LLG driver, Sec. 2 (the LLG equation) ------------------------------------
+ * nsteps explicit Heun steps of
+ *     m_t = -g (m x H) - alpha g (m x (m x H)),  g = gamma / (1 + alpha^2),
+ * H = H_demag(m) (this plan, Ms) + (hx, hy, hz) (uniform, A/m), gamma > 0 in
+ * m/(A s) (2.2128e5 for the free electron), dt in s; each step renormalises
+ * the predictor and the result to unit length.  m (device, [3][nz][ny][nx],
+ * plan dtype) is updated in place; `work` is caller-owned device scratch of
+ * 9 nx ny nz values of the plan dtype (H, k1, predictor); nothing is
+ * allocated.  Asynchronous on `stream`. */
+int demag_llg_heun(demag_plan_t plan, void* m, double Ms, double alpha, double gamma, double hx, double hy, double hz,
+                   double dt, int nsteps, void* work, void* stream);
+
 /* ---- Tensor-grid method (TG, dense), Sec. 3.2 eqs. (transform), (gausspot),
  * (sumpot), (Dmat), (gs) -----------------------------------------------------
  * The same potential phi as the SP calls (exact for cell-wise constant m up

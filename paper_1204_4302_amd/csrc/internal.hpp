@@ -155,6 +155,16 @@ int tg_potential(void* handle, hipStream_t st, int n1, int n2, int n3, int R, co
                  const T* D1O, const T* const* D2p[3], const T* const* Y1k, T* const* Y2k, const T* const B3[3], T* Y1,
                  T* Y2, T* phi, double alpha);
 
+// ---- LLG driver (llg.hip) ------------------------------------------------------
+// Heun predictor: k1 = f(m, H + hext), ms = unit(m + dt k1); corrector:
+// m = unit(m + dt/2 (k1 + f(ms, H2 + hext))); f = -g m x h - alpha g m x (m x h).
+template <typename T>
+hipError_t launch_llg_predict(hipStream_t, size_t N, const T* m, const T* H, const double hext[3], double g,
+                              double alpha, double dt, T* k1, T* ms);
+template <typename T>
+hipError_t launch_llg_correct(hipStream_t, size_t N, T* m, const T* H2, const T* k1, const T* ms,
+                              const double hext[3], double g, double alpha, double dt);
+
 // H = -grad phi (d = cell edges), optional energy partials m.H, one per (y, z) row.
 template <typename T>
 hipError_t launch_sp_gradient(hipStream_t, int nx, int ny, int nz, const double d[3], const T* phi, T* H,

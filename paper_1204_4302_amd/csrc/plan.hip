@@ -1047,6 +1047,39 @@ int demag_sp_kernel(demag_plan_t p, double* out) {
     return DEMAG_OK;
 }
 
+int demag_llg_heun(demag_plan_t p, void* m, double Ms, double alpha, double gamma, double hx, double hy, double hz,
+                   double dt, int nsteps, void* work, void* stream) {
+    if (!p || !m || !work) return fail(DEMAG_EINVAL, "NULL plan, m or work");
+    if (!std::isfinite(Ms) || !(alpha >= 0) || !std::isfinite(alpha) || !(gamma > 0) || !std::isfinite(gamma) ||
+        !std::isfinite(hx) || !std::isfinite(hy) || !std::isfinite(hz) || !(dt > 0) || !std::isfinite(dt) || nsteps < 0)
+        return fail(DEMAG_EINVAL, "need finite Ms, alpha >= 0, gamma > 0, finite H_ext, dt > 0, nsteps >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    const size_t N = (size_t)p->n[0] * p->n[1] * p->n[2];
+    const double hext[3] = {hx, hy, hz};
+    const double g = gamma / (1.0 + alpha * alpha);
+    auto steps = [&](auto proto) -> int {
+        using T = decltype(proto);
+        T* mm = (T*)m;
+        T* H = (T*)work;
+        T* k1 = H + 3 * N;
+        T* ms = k1 + 3 * N;
+        for (int s = 0; s < nsteps; ++s) {
+            int r = run_field<T>(p, p->cfg, mm, Ms, H, nullptr, nullptr, 0, st);
+            if (r) return r;
+            HIP_TRY(launch_llg_predict<T>(st, N, mm, H, hext, g, alpha, dt, k1, ms));
+            r = run_field<T>(p, p->cfg, ms, Ms, H, nullptr, nullptr, 0, st);
+            if (r) return r;
+            HIP_TRY(launch_llg_correct<T>(st, N, mm, H, k1, ms, hext, g, alpha, dt));
+        }
+        return DEMAG_OK;
+    };
+    rc = p->dtype == DEMAG_F32 ? steps(float()) : steps(double());
+    if (rc) return rc;
+    return leave(p, st);
+}
+
 int demag_tg_prepare(demag_plan_t p, void* stream) {
     if (!p) return fail(DEMAG_EINVAL, "NULL plan");
     if (p->tg) return DEMAG_OK;

@@ -189,6 +189,23 @@ class Plan:
         _lib.call("demag_sp_kernel", self._h, a.ctypes.data_as(ctypes.c_void_p))
         return a
 
+    # -- LLG driver (Sec. 2) ------------------------------------------------
+    GAMMA = 2.2128e5  # m/(A s): free-electron gyromagnetic ratio times mu0
+
+    def llg_heun(self, m: torch.Tensor, Ms: float, alpha: float, dt: float, steps: int,
+                 H_ext=(0.0, 0.0, 0.0), gamma: float = GAMMA, work: torch.Tensor | None = None) -> torch.Tensor:
+        """Advance the unit magnetization m in place by `steps` Heun steps of
+        the LLG equation with H = H_demag(m) + H_ext; returns m."""
+        self._check(m, "m")
+        if work is None:
+            work = torch.empty((9,) + tuple(m.shape[1:]), dtype=m.dtype, device=m.device)
+        if work.dtype != m.dtype or work.numel() < 3 * m.numel() or not work.is_contiguous():
+            raise ValueError("work must be a contiguous tensor of 3 m.numel() values of m's dtype")
+        hx, hy, hz = (float(v) for v in H_ext)
+        _lib.call("demag_llg_heun", self._h, self._ptr(m), float(Ms), float(alpha), float(gamma), hx, hy, hz,
+                  float(dt), int(steps), ctypes.c_void_p(work.data_ptr()), _stream_ptr())
+        return m
+
     # -- tensor-grid method (TG, dense) --------------------------------------
     def tg_prepare(self):
         """Sinc nodes, Gaussian matrices and GEMM scratch (synchronous, once)."""

@@ -68,6 +68,7 @@ def test_null_handles_rejected():
     assert lib.demag_plan_destroy(None) == -1
     assert lib.demag_batch_autotune(None, None) == -1
     assert lib.demag_sp_prepare(None, None) == -1
+    assert lib.demag_llg_heun(None, None, 1.0, 0.1, 2.2e5, 0.0, 0.0, 0.0, 1e-13, 1, None, None) == -1
     assert lib.demag_sp_field(None, None, 1.0, None, None) == -1
     assert lib.demag_sp_field_energy(None, None, 1.0, None, None, None) == -1
     assert lib.demag_sp_kernel(None, None) == -1
