@@ -78,7 +78,9 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
  *             shapes to their defaults.
  *  "pass_timing": K > 0 records HIP events around every pass of the next
  *             evaluations on their own stream (a ring of K evaluations; 0 turns
- *             it off); read the averages with demag_plan_pass_times. */
+ *             it off); read the averages with demag_plan_pass_times.
+ *  "lowrank_scratch": byte cap of the low-rank dense-expansion scratch
+ *             (default 256 MB; at least one z slice is always held). */
 int demag_plan_set_option(demag_plan_t plan, const char* key, double value);
 int demag_plan_destroy(demag_plan_t plan);
 
@@ -175,6 +177,58 @@ int demag_tg_info(demag_plan_t plan, int64_t* out);
  * distances in [rmin, rmax]; returns R (the count) and fills tau, w when both
  * are non-NULL and cap >= R; negative status on bad arguments. */
 int demag_tg_sinc_nodes(double rmin, double rmax, double step, double* tau, double* w, int cap);
+
+/* ---- Tensor-grid method on low-rank magnetization, Sec. 3.2 (Low-Rank
+ * Magnetization), Tables 1 and 2 (TG Tucker / TG CP rows), Appendix eqs. (CP)
+ * and (tucker) ------------------------------------------------------------------
+ * Each component M_p (p = x, y, z) is given compressed, with one rank r for
+ * every mode:
+ *   DEMAG_TUCKER: M_p = C_p x_1 U_1^p x_2 U_2^p x_3 U_3^p, core C_p r x r x r;
+ *   DEMAG_CP:     M_p(i1,i2,i3) = sum_s lambda_p(s) U_1^p(i1,s) U_2^p(i2,s) U_3^p(i3,s).
+ * Tensor index (i1, i2, i3) = cell (x, y, z).  The potential and the field
+ * are block-CP tensors on the same grid as the dense TG calls (same Sinc
+ * nodes, same difference stencils), computed on the factors only:
+ *   Phi   = sum_{p,l} alpha c_l  C_p x_1 F_1^{pl} x_2 F_2^{pl} x_3 F_3^{pl},
+ *   H_a   = the same with F_a replaced by G_a^{pl} (a = x, y, z),
+ *   F_q^{pl} = D_q^{l,p} U_q^p  (the Gaussian matrix of node l, odd kind when
+ *   q = p), G_q^{pl} = -delta_q F_q^{pl} (difference along axis q, 1/m),
+ *   alpha = Ms h_max (h_max the largest cell edge, m), c_l = w_l of
+ *   demag_tg_sinc_nodes for this plan's nodes;
+ * the energy -(mu0/2) Ms V sum_a <M_a, H_a> from inner products of the
+ * compressed tensors (no dense tensor is formed); the dense field on the grid
+ * only when H is given.
+ *
+ * demag_tg_lowrank_prepare builds the nodes and the stacked Gaussian matrices
+ * of the three axes (4 R (n1^2 + n2^2 + n3^2) values); synchronous;
+ * idempotent. */
+#define DEMAG_TUCKER 0
+#define DEMAG_CP 1
+#define DEMAG_TUCKER_MAX_RANK 16
+#define DEMAG_CP_MAX_RANK 64
+int demag_tg_lowrank_prepare(demag_plan_t plan, void* stream);
+/* One evaluation; asynchronous on `stream`.  All pointers are device memory
+ * of the plan dtype (E_dev: double), caller-owned:
+ *   core  Tucker: [3][r][r][r] (s1 fastest), C_p(s1,s2,s3) at
+ *         p r^3 + s1 + r s2 + r^2 s3;  CP: lambda [3][r];
+ *   U     the three axis blocks one after another; block q (n_q x 3r,
+ *         column-major) holds U_q^x, U_q^y, U_q^z side by side: U_q^p(i, s) at
+ *         offset(q) + i + n_q (p r + s), offset(q) = 3 r (n_1 + .. + n_{q-1});
+ *   FG    output, the compressed potential and field: block q
+ *         (2 n_q x 3 R r, column-major) at 6 R r (n_1 + .. + n_{q-1}); column
+ *         (p R + l) r + s holds F_q^{pl}(:, s) in rows [0, n_q) and
+ *         G_q^{pl}(:, s) in rows [n_q, 2 n_q);
+ *   H     optional dense field [3][nz][ny][nx] (NULL: not formed);
+ *   E_dev optional energy (one double, J).
+ * rank in [1, DEMAG_TUCKER_MAX_RANK] (Tucker) or [1, DEMAG_CP_MAX_RANK] (CP),
+ * else DEMAG_EINVAL; DEMAG_ESTATE before demag_tg_lowrank_prepare.  The dense
+ * expansion uses plan-owned scratch (within the "lowrank_scratch" cap, at
+ * least one z slice; allocated on first use and grown when a later call needs
+ * more), taking as many z slices per GEMM as fit. */
+int demag_tg_lowrank_field(demag_plan_t plan, int format, int rank, const void* core, const void* U, double Ms,
+                           void* FG, void* H, double* E_dev, void* stream);
+/* out[0] = R (nodes), out[1] = bytes of the stacked Gaussian matrices and
+ * scratch held, out[2] = alpha / Ms = h_max in metres. */
+int demag_tg_lowrank_info(demag_plan_t plan, int64_t* out);
 
 /* Text description of the launch shape of every pass (kernel family, threads,
  * tiles) into `buf` (len bytes, NUL-terminated); DEMAG_EINVAL if too small. */

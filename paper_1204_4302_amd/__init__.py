@@ -5,7 +5,7 @@ Sec. 3.1), evaluated by hand-written gfx950 HIP kernels behind a C ABI
 (include/demag.h).  Import the GPU classes from here; the submodule `inputs`
 (seeded synthetic states) needs neither torch nor the library.
 """
-__all__ = ["Plan", "Batch", "DemagField", "DemagEnergy", "demag_field", "demag_energy", "MU0"]
+__all__ = ["Plan", "Batch", "DemagField", "DemagEnergy", "demag_field", "demag_energy", "MU0", "TUCKER", "CP"]
 
 
 def __getattr__(name):

@@ -155,6 +155,19 @@ int tg_potential(void* handle, hipStream_t st, int n1, int n2, int n3, int R, co
                  const T* D1O, const T* const* D2p[3], const T* const* Y1k, T* const* Y2k, const T* const B3[3], T* Y1,
                  T* Y2, T* phi, double alpha);
 
+// ---- low-rank tensor grid (lowrank.hip) ---------------------------------------
+// Stacked Gaussian matrices of one axis for every node: [R][2n x n] column-major,
+// rows [0, n) D, rows [n, 2n) -delta D (spacing h).
+template <typename T>
+hipError_t launch_lr_axis(hipStream_t, int n, double d, double h, int R, const double* tau, T* E, T* O);
+size_t lr_energy_lds_bytes(int r, bool tucker);
+// Factors FG, then (partials != null) 9 R energy partials, then (H != null) the
+// dense field using W (w_elems values of scratch).  Returns 0 or a negative code.
+template <typename T>
+int lr_evaluate(void* handle, hipStream_t st, const int n[3], int R, int r, bool tucker, const T* core, const T* U,
+                const T* const DE[3], const T* const DO[3], const double* c, double alpha, T* FG, double* partials,
+                T* H, T* W, size_t w_elems);
+
 // ---- LLG driver (llg.hip) ------------------------------------------------------
 // Heun predictor: k1 = f(m, H + hext), ms = unit(m + dt k1); corrector:
 // m = unit(m + dt/2 (k1 + f(ms, H2 + hext))); f = -g m x h - alpha g m x (m x h).

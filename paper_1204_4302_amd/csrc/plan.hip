@@ -156,6 +156,22 @@ struct TGState {
     size_t bytes = 0;
 };
 
+// Low-rank tensor-grid state (after demag_tg_lowrank_prepare): nodes,
+// weights, stacked Gaussian matrices per axis, energy partials, expansion
+// scratch (grown on demand).
+struct LRState {
+    void* handle = nullptr;  // rocblas_handle
+    int R = 0;
+    double* tau = nullptr;
+    double* c = nullptr;
+    void* DE[3] = {nullptr, nullptr, nullptr};
+    void* DO[3] = {nullptr, nullptr, nullptr};
+    double* partials = nullptr;
+    void* W = nullptr;
+    size_t w_bytes = 0;
+    size_t bytes = 0;
+};
+
 struct demag_plan_s {
     int n[3];
     double d[3];
@@ -167,6 +183,8 @@ struct demag_plan_s {
     void* nhat = nullptr;
     void* shat = nullptr;  // scalar-potential kernel spectrum (after demag_sp_prepare)
     TGState* tg = nullptr; // tensor-grid state (after demag_tg_prepare)
+    LRState* lr = nullptr; // low-rank tensor-grid state (after demag_tg_lowrank_prepare)
+    size_t lr_cap = (size_t)256 << 20;  // byte cap of the low-rank expansion scratch
     LaunchCfg zs;          // launch shape of the scalar-potential Z pass
     void* B1 = nullptr;
     void* B2 = nullptr;
@@ -623,12 +641,73 @@ void free_tg(TGState* g) {
     delete g;
 }
 
+void free_lr(LRState* g) {
+    if (!g) return;
+    if (g->handle) rocblas_destroy_handle((rocblas_handle)g->handle);
+    for (void* q : {(void*)g->tau, (void*)g->c, g->DE[0], g->DE[1], g->DE[2], g->DO[0], g->DO[1], g->DO[2],
+                    (void*)g->partials, g->W})
+        hipFree(q);
+    delete g;
+}
+
+// Nodes (the dense TG quadrature: same range and step) and the stacked
+// Gaussian matrices of the three axes.
+template <typename T>
+int setup_lr(demag_plan_s* p, hipStream_t st, double step) {
+    auto* g = new LRState();
+    p->lr = g;
+    double dt[3];
+    reduced_cell(p->d, dt);
+    const int* n = p->n;
+    const double rmin = std::min(dt[0], std::min(dt[1], dt[2]));
+    const double rmax = std::sqrt((n[0] * dt[0]) * (n[0] * dt[0]) + (n[1] * dt[1]) * (n[1] * dt[1]) +
+                                  (n[2] * dt[2]) * (n[2] * dt[2]));
+    std::vector<double> tau, w;
+    const int R = tg_sinc_nodes(rmin, std::max(rmax, rmin), step, tau, w);
+    if (R <= 0) return fail(DEMAG_EINVAL, "tensor-grid quadrature");
+    g->R = R;
+    int rc = DEMAG_OK;
+    auto alloc = [&](void** ptr, size_t bytes, const char* what) {
+        if (rc) return;
+        if (hipMalloc(ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *ptr = nullptr;
+            rc = fail(DEMAG_ENOMEM, "cannot allocate %zu bytes for the low-rank %s", bytes, what);
+        }
+        g->bytes += bytes;
+    };
+    alloc((void**)&g->tau, R * sizeof(double), "nodes");
+    alloc((void**)&g->c, R * sizeof(double), "weights");
+    alloc((void**)&g->partials, 9 * (size_t)R * sizeof(double), "energy partials");
+    for (int q = 0; q < 3; ++q) {
+        alloc(&g->DE[q], (size_t)R * 2 * n[q] * n[q] * sizeof(T), "Gaussian matrices");
+        alloc(&g->DO[q], (size_t)R * 2 * n[q] * n[q] * sizeof(T), "Gaussian matrices");
+    }
+    if (!rc && (hipMemcpy(g->tau, tau.data(), R * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(g->c, w.data(), R * sizeof(double), hipMemcpyHostToDevice) != hipSuccess))
+        rc = fail(DEMAG_EHIP, "upload");
+    if (!rc) {
+        hipError_t e = hipSuccess;
+        for (int q = 0; q < 3 && e == hipSuccess; ++q)
+            e = launch_lr_axis<T>(st, n[q], dt[q], p->d[q], R, g->tau, (T*)g->DE[q], (T*)g->DO[q]);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(e, "low-rank tensor-grid setup");
+    }
+    if (!rc) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) rc = fail(DEMAG_EHIP, "rocblas_create_handle failed");
+        g->handle = h;
+    }
+    return rc;
+}
+
 void free_plan(demag_plan_s* p) {
     for (auto t : p->tw) hipFree(t);
     for (auto t : p->twt) hipFree(t);
     hipFree(p->nhat);
     hipFree(p->shat);
     free_tg(p->tg);
+    free_lr(p->lr);
     hipFree(p->B1);
     hipFree(p->B2);
     hipFree(p->partials);
@@ -899,6 +978,10 @@ int demag_plan_set_option(demag_plan_t p, const char* key, double value) {
         p->tcap = (int)value;
         p->tcount = 0;
         return DEMAG_OK;
+    } else if (!strcmp(key, "lowrank_scratch")) {
+        if (!(value >= 0) || value > 1e15) return fail(DEMAG_EINVAL, "lowrank_scratch must be in [0, 1e15] bytes");
+        p->lr_cap = (size_t)value;
+        return DEMAG_OK;
     } else {
         return fail(DEMAG_EINVAL, "unknown option '%s'", key);
     }
@@ -1121,6 +1204,87 @@ int demag_tg_info(demag_plan_t p, int64_t* out) {
     out[1] = (int64_t)p->tg->bytes;
     const double n1 = p->n[0], n2 = p->n[1], n3 = p->n[2];
     out[2] = (int64_t)(3.0 * 2.0 * p->tg->R * n1 * n2 * n3 * (n1 + n2 + n3));  // flops per evaluation
+    return DEMAG_OK;
+}
+
+int demag_tg_lowrank_prepare(demag_plan_t p, void* stream) {
+    if (!p) return fail(DEMAG_EINVAL, "NULL plan");
+    if (p->lr) return DEMAG_OK;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    const double step = p->dtype == DEMAG_F32 ? 0.25 : 0.15;
+    rc = p->dtype == DEMAG_F32 ? setup_lr<float>(p, st, step) : setup_lr<double>(p, st, step);
+    if (rc) {
+        free_lr(p->lr);
+        p->lr = nullptr;
+        return rc;
+    }
+    return leave(p, st);
+}
+
+int demag_tg_lowrank_field(demag_plan_t p, int format, int rank, const void* core, const void* U, double Ms, void* FG,
+                           void* H, double* E_dev, void* stream) {
+    if (!p || !core || !U || !FG) return fail(DEMAG_EINVAL, "NULL plan, core, U or FG");
+    if (format != DEMAG_TUCKER && format != DEMAG_CP) return fail(DEMAG_EINVAL, "format must be DEMAG_TUCKER or DEMAG_CP");
+    const int rmax = format == DEMAG_TUCKER ? DEMAG_TUCKER_MAX_RANK : DEMAG_CP_MAX_RANK;
+    if (rank < 1 || rank > rmax) return fail(DEMAG_EINVAL, "rank %d outside [1, %d]", rank, rmax);
+    if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
+    if (!p->lr) return fail(DEMAG_ESTATE, "low-rank tensor grid not prepared (call demag_tg_lowrank_prepare)");
+    LRState* g = p->lr;
+    const size_t tsz = p->dtype == DEMAG_F32 ? 4 : 8;
+    size_t w_elems = 0;
+    if (H) {  // expansion scratch: the z slices of one GEMM, within the cap
+        const size_t per_slice = (size_t)3 * g->R * rank * p->n[1] * tsz;
+        const size_t want = std::min<size_t>((size_t)p->n[2] * per_slice, std::max(p->lr_cap, per_slice));
+        if (want != g->w_bytes && (want > g->w_bytes || g->w_bytes > std::max(p->lr_cap, per_slice))) {
+            HIP_TRY(hipDeviceSynchronize());  // the old scratch may still be in use
+            hipFree(g->W);
+            g->bytes -= g->w_bytes;
+            g->W = nullptr;
+            g->w_bytes = 0;
+            if (hipMalloc(&g->W, want) != hipSuccess) {
+                (void)hipGetLastError();
+                g->W = nullptr;
+                return fail(DEMAG_ENOMEM, "cannot allocate %zu bytes of low-rank expansion scratch", want);
+            }
+            g->w_bytes = want;
+            g->bytes += want;
+        }
+        w_elems = g->w_bytes / tsz;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    const double hmax = std::max(p->d[0], std::max(p->d[1], p->d[2]));
+    const bool tucker = format == DEMAG_TUCKER;
+    double* parts = E_dev ? g->partials : nullptr;
+    if (p->dtype == DEMAG_F32) {
+        const float* DE[3] = {(const float*)g->DE[0], (const float*)g->DE[1], (const float*)g->DE[2]};
+        const float* DO[3] = {(const float*)g->DO[0], (const float*)g->DO[1], (const float*)g->DO[2]};
+        rc = lr_evaluate<float>(g->handle, st, p->n, g->R, rank, tucker, (const float*)core, (const float*)U, DE, DO,
+                                g->c, Ms * hmax, (float*)FG, parts, (float*)H, (float*)g->W, w_elems);
+    } else {
+        const double* DE[3] = {(const double*)g->DE[0], (const double*)g->DE[1], (const double*)g->DE[2]};
+        const double* DO[3] = {(const double*)g->DO[0], (const double*)g->DO[1], (const double*)g->DO[2]};
+        rc = lr_evaluate<double>(g->handle, st, p->n, g->R, rank, tucker, (const double*)core, (const double*)U, DE,
+                                 DO, g->c, Ms * hmax, (double*)FG, parts, (double*)H, (double*)g->W, w_elems);
+    }
+    if (rc) return fail(DEMAG_EHIP, "low-rank tensor-grid evaluation failed (%d)", rc);
+    if (E_dev) {
+        const double V = p->d[0] * p->d[1] * p->d[2];
+        HIP_TRY(launch_energy_reduce(st, g->partials, 9 * g->R, -0.5 * kMu0 * Ms * V, E_dev));
+    }
+    return leave(p, st);
+}
+
+int demag_tg_lowrank_info(demag_plan_t p, int64_t* out) {
+    if (!p || !out) return fail(DEMAG_EINVAL, "NULL argument");
+    if (!p->lr) return fail(DEMAG_ESTATE, "low-rank tensor grid not prepared");
+    out[0] = p->lr->R;
+    out[1] = (int64_t)p->lr->bytes;
+    double hm = std::max(p->d[0], std::max(p->d[1], p->d[2]));
+    std::memcpy(&out[2], &hm, sizeof(double));
     return DEMAG_OK;
 }
 

@@ -25,28 +25,13 @@
 #include <cmath>
 #include <vector>
 
+#include "blas.hpp"
 #include "internal.hpp"
+#include "tg_gauss.hpp"
 
 namespace demag {
 
 namespace {
-
-// int_{c - d/2}^{c + d/2} exp(-s^2 (a - x)^2) dx, with the erf difference taken
-// through erfc where both arguments have one sign (no cancellation)
-__device__ double gauss_even(double a, double c, double d, double s) {
-    const double A = s * (a - c + 0.5 * d), B = s * (a - c - 0.5 * d);  // A > B
-    double diff;
-    if (B >= 0) diff = erfc(B) - erfc(A);
-    else if (A <= 0) diff = erfc(-A) - erfc(-B);
-    else diff = erf(A) - erf(B);
-    return 0.5 * 1.7724538509055160273 / s * diff;
-}
-
-// int_{c - d/2}^{c + d/2} (a - x) exp(-s^2 (a - x)^2) dx
-__device__ double gauss_odd(double a, double c, double d, double s) {
-    const double ua = a - c + 0.5 * d, ub = a - c - 0.5 * d;  // a - x at x = c - d/2 and c + d/2
-    return (exp(-s * s * ub * ub) - exp(-s * s * ua * ua)) / (2.0 * s * s);
-}
 
 // Gaussian matrices of one axis (n cells of edge d, reduced units) for every
 // node: E[l][i][i'] and O[l][i][i'] column-major (entry (i', i) at i' + i n).
@@ -116,38 +101,6 @@ template hipError_t launch_tg_stack3<float>(hipStream_t, int, int, const double*
 template hipError_t launch_tg_stack3<double>(hipStream_t, int, int, const double*, const double*, double*);
 
 // ---- the GEMM chain ----------------------------------------------------------
-namespace {
-rocblas_status gemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-                       const float* al, const float* A, int lda, rocblas_stride sa, const float* B, int ldb,
-                       rocblas_stride sb, const float* be, float* C, int ldc, rocblas_stride sc, int batch) {
-    return rocblas_sgemm_strided_batched(h, ta, tb, m, n, k, al, A, lda, sa, B, ldb, sb, be, C, ldc, sc, batch);
-}
-rocblas_status gemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-                       const double* al, const double* A, int lda, rocblas_stride sa, const double* B, int ldb,
-                       rocblas_stride sb, const double* be, double* C, int ldc, rocblas_stride sc, int batch) {
-    return rocblas_dgemm_strided_batched(h, ta, tb, m, n, k, al, A, lda, sa, B, ldb, sb, be, C, ldc, sc, batch);
-}
-rocblas_status gemm_b(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-                      const float* al, const float* const* A, int lda, const float* const* B, int ldb,
-                      const float* be, float* const* C, int ldc, int batch) {
-    return rocblas_sgemm_batched(h, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc, batch);
-}
-rocblas_status gemm_b(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-                      const double* al, const double* const* A, int lda, const double* const* B, int ldb,
-                      const double* be, double* const* C, int ldc, int batch) {
-    return rocblas_dgemm_batched(h, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc, batch);
-}
-rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-                    const float* al, const float* A, int lda, const float* B, int ldb, const float* be, float* C,
-                    int ldc) {
-    return rocblas_sgemm(h, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc);
-}
-rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n, int k,
-                    const double* al, const double* A, int lda, const double* B, int ldb, const double* be,
-                    double* C, int ldc) {
-    return rocblas_dgemm(h, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc);
-}
-}  // namespace
 
 // Phi (column-major n1 x n2 x n3, i.e. [n3][n2][n1]) for the three components
 // of m.  D1E/D1O [R][n1][n1], D2E/D2O [R][n2][n2] column-major, B3[p]

@@ -104,3 +104,31 @@ def sample_targets(shape, count, seed):
     for z in range(nz):
         t.add((z * ny + cy) * nx + cx)
     return np.array(sorted(t), dtype=np.int64)
+
+
+def lowrank(shape, fmt, rank, seed, smooth=False):
+    """Seeded compressed magnetization for the low-rank tensor-grid calls.
+
+    Returns (core, factors): core [3][r][r][r] (Tucker, fmt 0; indexed
+    [p][s3][s2][s1]) or [3][r] (CP, fmt 1); factors a list of three arrays
+    (3, r, n_q), factor s of component p along axis q at [p][s].  smooth=True
+    takes the first r cosine modes cos(pi s (i + 1/2) / n_q) as factors (a
+    smooth state of rank r); otherwise the factors are standard normal.  The
+    core / weights are standard normal, scaled by r^(-3/2) (Tucker) or r^(-1/2)
+    (CP) so that the expanded components stay of order one."""
+    rng = np.random.default_rng(seed)
+    r = int(rank)
+    factors = []
+    for n in shape:
+        if smooth:
+            i = np.arange(n) + 0.5
+            base = np.stack([np.cos(np.pi * s * i / n) for s in range(r)])
+            f = np.broadcast_to(base, (3, r, n)).copy()
+        else:
+            f = rng.standard_normal((3, r, n))
+        factors.append(f)
+    if fmt == 0:
+        core = rng.standard_normal((3, r, r, r)) * r ** -1.5
+    else:
+        core = rng.standard_normal((3, r)) * r ** -0.5
+    return core, factors

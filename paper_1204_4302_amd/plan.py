@@ -238,11 +238,74 @@ class Plan:
                   self._ptr(H) if H is not None else None, ctypes.c_void_p(E.data_ptr()), _stream_ptr())
         return H, E
 
+    # -- tensor grid on low-rank magnetization --------------------------------
+    def tg_lowrank_prepare(self):
+        """Sinc nodes and the stacked Gaussian matrices of the three axes
+        (synchronous, once)."""
+        _lib.call("demag_tg_lowrank_prepare", self._h, _stream_ptr())
+
+    def tg_lowrank_info(self) -> dict:
+        out = (ctypes.c_int64 * 3)()
+        _lib.call("demag_tg_lowrank_info", self._h, out)
+        h_max = np.frombuffer(bytes(ctypes.c_int64(out[2])), dtype=np.float64)[0]
+        return {"nodes": out[0], "bytes": out[1], "h_max": float(h_max)}
+
+    def tg_lowrank_field(self, fmt: int, core: torch.Tensor, factors, Ms: float, dense: bool = True,
+                         energy: bool = True, FG: torch.Tensor | None = None):
+        """Field of a low-rank magnetization (fmt TUCKER: core [3][r][r][r]
+        indexed [p][s3][s2][s1]; CP: lambda [3][r]; factors: three tensors
+        (3, r, n_q), factor s of component p along axis q at [p][s]).
+        Returns (FG, H or None, E or None): FG the compressed potential and
+        field, one (3, R, r, 2 n_q) view per axis (rows [:n_q] potential
+        factors F, [n_q:] field factors G), H the dense field, E a 0-dim float64
+        CUDA tensor."""
+        r = int(core.shape[1])
+        want = (3, r, r, r) if fmt == TUCKER else (3, r)
+        if fmt not in (TUCKER, CP):
+            raise ValueError("fmt must be TUCKER or CP")
+        if tuple(core.shape) != want:
+            raise ValueError(f"core has shape {tuple(core.shape)}, expected {want}")
+        if len(factors) != 3:
+            raise ValueError("three factor tensors (one per axis) expected")
+        for q, f in enumerate(factors):
+            if tuple(f.shape) != (3, r, self.shape[q]):
+                raise ValueError(f"factor {q} has shape {tuple(f.shape)}, expected {(3, r, self.shape[q])}")
+        for t, name in [(core, "core")] + [(f, f"factor {q}") for q, f in enumerate(factors)]:
+            if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != self.dtype:
+                raise TypeError(f"{name} must be a CUDA tensor of {self.dtype}")
+        core = core.contiguous()
+        U = torch.cat([f.contiguous().reshape(-1) for f in factors])
+        R = self.tg_lowrank_info()["nodes"]
+        nfg = 6 * R * r * sum(self.shape)
+        if FG is None:
+            FG = torch.empty(nfg, dtype=self.dtype, device=core.device)
+        elif FG.dtype != self.dtype or FG.device.type != "cuda" or FG.numel() != nfg or not FG.is_contiguous():
+            raise ValueError(f"FG must be a contiguous CUDA tensor of {nfg} {self.dtype} values")
+        H = torch.empty(self.vec_shape, dtype=self.dtype, device=core.device) if dense else None
+        E = torch.empty((), dtype=torch.float64, device=core.device) if energy else None
+        _lib.call("demag_tg_lowrank_field", self._h, int(fmt), r, self._ptr(core), self._ptr(U), float(Ms),
+                  self._ptr(FG), self._ptr(H) if H is not None else None,
+                  ctypes.c_void_p(E.data_ptr()) if E is not None else None, _stream_ptr())
+        return FG, H, E
+
+    def lowrank_fg_views(self, FG: torch.Tensor, rank: int):
+        """The per-axis (3, R, r, 2 n_q) views of a compressed field buffer."""
+        R = self.tg_lowrank_info()["nodes"]
+        out, off = [], 0
+        for n in self.shape:
+            size = 6 * R * rank * n
+            out.append(FG[off:off + size].view(3, R, rank, 2 * n))
+            off += size
+        return out
+
     def energy(self, m: torch.Tensor, Ms: float) -> float:
         self._check(m, "m")
         e = ctypes.c_double()
         _lib.call("demag_energy", self._h, self._ptr(m), float(Ms), ctypes.byref(e), _stream_ptr())
         return e.value
+
+
+TUCKER, CP = 0, 1  # low-rank formats of the magnetization
 
 
 def tg_sinc_nodes(rmin: float, rmax: float, step: float):

@@ -72,6 +72,11 @@ def test_null_handles_rejected():
     assert lib.demag_sp_field(None, None, 1.0, None, None) == -1
     assert lib.demag_sp_field_energy(None, None, 1.0, None, None, None) == -1
     assert lib.demag_sp_kernel(None, None) == -1
+    assert lib.demag_tg_prepare(None, None) == -1
+    assert lib.demag_tg_info(None, None) == -1
+    assert lib.demag_tg_lowrank_prepare(None, None) == -1
+    assert lib.demag_tg_lowrank_field(None, 0, 1, None, None, 1.0, None, None, None, None) == -1
+    assert lib.demag_tg_lowrank_info(None, None) == -1
     assert lib.demag_batch_launch(None, None) == -1
     assert lib.demag_batch_destroy(None) == -1
     assert lib.demag_plan_set_option(None, b"far_cut", 40.0) == -1

@@ -1,0 +1,215 @@
+"""Tensor grid on low-rank magnetization (Sec. 3.2 "Low-Rank Magnetization";
+Appendix eqs. (CP), (tucker)) on the GPU, against the oracle: the compressed
+magnetization expanded by the plain format definitions, then the SP oracle
+(the exact cell-centre potential and the difference stencils, which the Sinc
+quadrature approximates).  Tolerances as for dense TG, whose quadrature this
+is: FP64 1e-10, FP32 1e-5 (relative max-norm; the energy relative).  FP32
+inputs are the FP32-rounded core and factors, expanded in FP64."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import lowrank as olr
+from paper_1204_4302_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-10, torch.float32: 1e-5}
+CACHE = os.environ.get("DEMAG_ORACLE_CACHE", "/tmp/demag_oracle_cache")
+
+
+def rel_err(a, b):
+    scale = np.abs(b).max()
+    return float(np.abs(a - b).max() / scale) if scale > 0 else float(np.abs(a).max())
+
+
+def _q(a, dtype):
+    return np.asarray(a, dtype=np.float32).astype(np.float64) if dtype == torch.float32 else np.asarray(a)
+
+
+def _gpu(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype)
+
+
+def _setup(shape, cell, fmt, rank, dtype, seed=1, smooth=False):
+    from paper_1204_4302_amd import Plan
+    plan = Plan(shape, cell, dtype)
+    plan.tg_lowrank_prepare()
+    core, factors = inputs.lowrank(shape, fmt, rank, seed, smooth=smooth)
+    core_q, factors_q = _q(core, dtype), [_q(f, dtype) for f in factors]
+    m = olr.magnetization(fmt, core_q, factors_q)
+    return plan, _gpu(core, dtype), [_gpu(f, dtype) for f in factors], m
+
+
+CASES = [
+    ((12, 10, 6), (2e-9, 2e-9, 3e-9), 0, 3),
+    ((12, 10, 6), (2e-9, 2e-9, 3e-9), 1, 4),
+    ((16, 9, 5), (1.95e-9, 1.95e-9, 0.75e-9), 0, 1),
+    ((16, 9, 5), (1.95e-9, 1.95e-9, 0.75e-9), 1, 1),
+    ((7, 5, 1), (2e-9, 2e-9, 2e-9), 0, 2),          # one cell along z
+    ((2, 9, 7), (2e-9, 2e-9, 3e-9), 1, 3),          # two cells along x
+    ((33, 17, 9), (2e-9, 2e-9, 3e-9), 0, 5),
+    ((20, 20, 20), (1e-9, 1e-9, 1e-9), 1, 12),
+]
+
+
+@pytest.mark.parametrize("shape,cell,fmt,rank", CASES, ids=lambda v: str(v))
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_lowrank_field_and_energy_vs_oracle(shape, cell, fmt, rank, dtype):
+    Ms = 1.4e6
+    plan, core, factors, m = _setup(shape, cell, fmt, rank, dtype)
+    FG, H, E = plan.tg_lowrank_field(fmt, core, factors, Ms)
+    so = oracle.SPOracle(shape, cell)
+    Href = so.field(m, Ms)
+    err = rel_err(H.double().cpu().numpy(), Href)
+    Eref = so.energy(m, Href, Ms)
+    eerr = abs(float(E) / Eref - 1)
+    print(f"shape={shape} fmt={fmt} r={rank} {dtype}: field {err:.3e} energy {eerr:.3e} nodes={plan.tg_lowrank_info()['nodes']}")
+    assert err <= TOL[dtype]
+    assert eerr <= TOL[dtype]
+
+
+@pytest.mark.parametrize("fmt", [0, 1], ids=["tucker", "cp"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_compressed_potential_and_field_factors(fmt, dtype):
+    """The FG output is the compressed potential and field: expanded on the
+    host with the documented layout they give the oracle's potential and
+    field."""
+    shape, cell, Ms, rank = (11, 8, 6), (2e-9, 2e-9, 3e-9), 8e5, 3
+    plan, core, factors, m = _setup(shape, cell, fmt, rank, dtype, seed=2)
+    FG, H, _ = plan.tg_lowrank_field(fmt, core, factors, Ms, dense=False, energy=False)
+    assert H is None
+    views = [v.double().cpu().numpy() for v in plan.lowrank_fg_views(FG, rank)]
+    info = plan.tg_lowrank_info()
+    R, alpha = info["nodes"], Ms * info["h_max"]
+    rmin = min(cell) / max(cell)
+    rmax = np.sqrt(sum((n * d / max(cell)) ** 2 for n, d in zip(shape, cell)))
+    from paper_1204_4302_amd.plan import tg_sinc_nodes
+    _, w = tg_sinc_nodes(rmin, max(rmax, rmin), 0.25 if dtype == torch.float32 else 0.15)
+    assert len(w) == R
+    core_h = _q(core.double().cpu().numpy(), dtype)
+
+    def expand(rows_for_axis):
+        out = np.zeros((shape[2], shape[1], shape[0]))
+        for p in range(3):
+            for l in range(R):
+                fac = []
+                for q in range(3):
+                    n = shape[q]
+                    blk = views[q][p, l]  # (r, 2n)
+                    fac.append([blk[:, :n], blk[:, n:]][rows_for_axis[q]])
+                fac3 = [np.broadcast_to(f, (3,) + f.shape) for f in fac]  # the same factors for index p
+                out += alpha * w[l] * olr.component(fmt, core_h, fac3, p).transpose(2, 1, 0)
+        return out
+
+    so = oracle.SPOracle(shape, cell)
+    phi = expand((0, 0, 0))
+    phi_ref = so.potential(m, Ms)
+    assert rel_err(phi, phi_ref) <= TOL[dtype]
+    Href = so.field(m, Ms)
+    H = np.stack([expand(tuple(1 if q == a else 0 for q in range(3))) for a in range(3)])
+    assert rel_err(H, Href) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_lowrank_matches_dense_tg(dtype):
+    """The compressed path and the dense TG path on the expanded m agree to
+    rounding (same nodes, same stencils)."""
+    shape, cell, Ms = (24, 16, 8), (2e-9, 2e-9, 3e-9), 1.4e6
+    plan, core, factors, m = _setup(shape, cell, 0, 4, dtype, seed=3, smooth=True)
+    _, H, E = plan.tg_lowrank_field(0, core, factors, Ms)
+    plan.tg_prepare()
+    Hd, Ed = plan.tg_field_energy(_gpu(m, dtype), Ms)
+    tol = 1e-12 if dtype == torch.float64 else 2e-6
+    assert rel_err(H.double().cpu().numpy(), Hd.double().cpu().numpy()) <= tol
+    assert abs(float(E) / float(Ed) - 1) <= tol
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_energy_from_factors_matches_dense_product(dtype):
+    """E from the compressed inner products equals -(mu0/2) Ms V sum m.H of
+    the expanded field (the energy never forms a dense tensor)."""
+    from paper_1204_4302_amd import MU0
+    shape, cell, Ms = (20, 12, 7), (2e-9, 2e-9, 3e-9), 8e5
+    for fmt, rank in ((0, 6), (1, 9)):
+        plan, core, factors, m = _setup(shape, cell, fmt, rank, dtype, seed=4)
+        _, H, E = plan.tg_lowrank_field(fmt, core, factors, Ms)
+        V = np.prod(cell)
+        Edense = -0.5 * MU0 * Ms * V * float((m * H.double().cpu().numpy()).sum())
+        assert abs(float(E) / Edense - 1) <= (1e-12 if dtype == torch.float64 else 1e-5)
+
+
+def test_chunked_expansion_and_scratch_reuse():
+    """A scratch cap of one z slice forces one GEMM per slice; ranks that grow
+    and shrink between calls reuse or regrow the scratch; results stay equal."""
+    shape, cell, Ms = (14, 10, 9), (2e-9, 2e-9, 3e-9), 1.4e6
+    dtype = torch.float64
+    plan, core, factors, m = _setup(shape, cell, 0, 5, dtype, seed=5)
+    _, H_full, _ = plan.tg_lowrank_field(0, core, factors, Ms, energy=False)
+    plan.set_option("lowrank_scratch", 0)
+    _, H_chunk, _ = plan.tg_lowrank_field(0, core, factors, Ms, energy=False)
+    assert torch.equal(H_full, H_chunk) or rel_err(H_chunk.cpu().numpy(), H_full.cpu().numpy()) <= 1e-14
+    plan.set_option("lowrank_scratch", 256 << 20)
+    for rank, seed in ((2, 6), (7, 7), (2, 6)):
+        core_h, fac_h = inputs.lowrank(shape, 1, rank, seed)
+        _, H, E = plan.tg_lowrank_field(1, _gpu(core_h, dtype), [_gpu(f, dtype) for f in fac_h], Ms)
+        so = oracle.SPOracle(shape, cell)
+        mm = olr.magnetization(1, core_h, fac_h)
+        assert rel_err(H.cpu().numpy(), so.field(mm, Ms)) <= TOL[dtype]
+
+
+def test_lowrank_errors():
+    from paper_1204_4302_amd import Plan
+    from paper_1204_4302_amd._lib import DemagError
+    shape, cell = (6, 5, 4), (2e-9, 2e-9, 2e-9)
+    plan = Plan(shape, cell, torch.float64)
+    core, factors = inputs.lowrank(shape, 0, 2, 0)
+    cg, fg = _gpu(core, torch.float64), [_gpu(f, torch.float64) for f in factors]
+    with pytest.raises(DemagError, match="ESTATE"):
+        plan.tg_lowrank_info()
+    plan.tg_lowrank_prepare()
+    plan.tg_lowrank_prepare()  # idempotent
+    big, bigf = inputs.lowrank(shape, 0, 17, 0)
+    with pytest.raises(DemagError, match="EINVAL"):
+        plan.tg_lowrank_field(0, _gpu(big, torch.float64), [_gpu(f, torch.float64) for f in bigf], 1.0)
+    cpb, cpf = inputs.lowrank(shape, 1, 65, 0)
+    with pytest.raises(DemagError, match="EINVAL"):
+        plan.tg_lowrank_field(1, _gpu(cpb, torch.float64), [_gpu(f, torch.float64) for f in cpf], 1.0)
+    with pytest.raises(ValueError):
+        plan.tg_lowrank_field(2, cg, fg, 1.0)
+    with pytest.raises(DemagError, match="EINVAL"):
+        plan.tg_lowrank_field(0, cg, fg, float("nan"))
+    # rank 16 Tucker and rank 64 CP (the limits) run
+    for fmt, r in ((0, 16), (1, 64)):
+        c, f = inputs.lowrank(shape, fmt, r, 1)
+        _, H, E = plan.tg_lowrank_field(fmt, _gpu(c, torch.float64), [_gpu(x, torch.float64) for x in f], 8e5)
+        mm = olr.magnetization(fmt, c, f)
+        so = oracle.SPOracle(shape, cell)
+        Href = so.field(mm, 8e5)
+        assert rel_err(H.cpu().numpy(), Href) <= 1e-10
+        assert abs(float(E) / so.energy(mm, Href, 8e5) - 1) <= 1e-10
+
+
+@pytest.mark.slow
+def test_fullsize_tucker_rank8_f32_sampled():
+    """256 x 256 x 64 (2 x 2 x 3 nm), smooth Tucker rank 8, FP32: the dense
+    field at seeded sampled cells against the oracle's direct field there, and
+    the compressed energy against the expanded field's."""
+    from paper_1204_4302_amd import MU0
+    shape, cell, Ms = (256, 256, 64), (2e-9, 2e-9, 3e-9), 1.4e6
+    dtype = torch.float32
+    plan, core, factors, m = _setup(shape, cell, 0, 8, dtype, seed=8, smooth=True)
+    _, H, E = plan.tg_lowrank_field(0, core, factors, Ms)
+    Hn = H.double().cpu().numpy()
+    targets = inputs.sample_targets(shape, 48, 8)
+    so = oracle.SPOracle(shape, cell, cache_dir=CACHE)
+    ref = so.field_targets(m, Ms, targets)
+    got = Hn.reshape(3, -1)[:, targets]
+    err = float(np.abs(got - ref).max() / np.abs(ref).max())
+    Edense = -0.5 * MU0 * Ms * np.prod(cell) * float((m * Hn).sum())
+    print(f"full size: sampled rel err {err:.3e}, energy vs expanded {abs(float(E) / Edense - 1):.3e}")
+    assert err <= TOL[dtype]
+    assert abs(float(E) / Edense - 1) <= 1e-5
