@@ -193,6 +193,63 @@ def bench_tg(args, torch, np, m_np, dm_value):
     return out
 
 
+def bench_lowrank(args, torch, np, dm_value):
+    """Tensor grid on low-rank magnetization, FP32, same grid: compressed
+    potential + field + energy from Tucker (rank 8) and CP (rank 16) factors
+    of a smooth state (cosine modes); the dense expansion timed on its own."""
+    import ctypes
+    from paper_1204_4302_amd import CP, Plan, TUCKER, inputs, _lib
+    plan = Plan(SHAPE, CELL, torch.float32)
+    plan.tg_lowrank_prepare()
+    info = plan.tg_lowrank_info()
+    R = info["nodes"]
+    out = {"sinc_nodes": R, "gaussian_matrix_bytes": info["bytes"]}
+    E = torch.empty((), dtype=torch.float64, device="cuda")
+    H = torch.empty((3, SHAPE[2], SHAPE[1], SHAPE[0]), dtype=torch.float32, device="cuda")
+    n1, n2, n3 = SHAPE
+    for name, fmt, rank in (("tucker_r8", TUCKER, 8), ("cp_r16", CP, 16)):
+        core_np, fac_np = inputs.lowrank(SHAPE, fmt, rank, seed=8, smooth=True)
+        core = torch.from_numpy(core_np).to("cuda", torch.float32).contiguous()
+        U = torch.cat([torch.from_numpy(f).to("cuda", torch.float32).reshape(-1) for f in fac_np])
+        FG = torch.empty(6 * R * rank * sum(SHAPE), dtype=torch.float32, device="cuda")
+        fn = _lib.load().demag_tg_lowrank_field
+        args_c = [plan._h, fmt, rank, ctypes.c_void_p(core.data_ptr()), ctypes.c_void_p(U.data_ptr()), MS,
+                  ctypes.c_void_p(FG.data_ptr())]
+        e_ptr, h_ptr = ctypes.c_void_p(E.data_ptr()), ctypes.c_void_p(H.data_ptr())
+
+        def compressed():
+            _lib.check("demag_tg_lowrank_field", fn(*args_c, None, e_ptr, None))
+
+        def dense():
+            _lib.check("demag_tg_lowrank_field", fn(*args_c, h_ptr, e_ptr, None))
+
+        for _ in range(3):
+            compressed()
+            dense()
+        k = args.lowrank_steps
+        sc = run_steps(compressed, k, torch)
+        kd = max(1, k // 10)
+        sd = run_steps(dense, kd, torch)
+        # algorithmic bytes of the compressed evaluation: per axis q the even
+        # stack for the two components p != q and the odd one for p = q
+        # (R x 2 n_q x n_q each), the factors in, the factor buffer out
+        gbytes = sum(3 * R * 2 * n * n * 4 for n in SHAPE)
+        fbytes = 4 * (3 * rank * sum(SHAPE) + FG.numel())
+        nbytes = gbytes + fbytes
+        stored = (core.numel() + U.numel())
+        out[name] = {
+            "value": round(k / sc, 1), "unit": "evals/s", "ms_per_eval": round(1e3 * sc / k, 4),
+            "speedup_over_dm": round(k / sc / dm_value, 2),
+            "modelled_bytes_per_eval": nbytes, "achieved_GBs": round(nbytes * k / sc / 1e9, 1),
+            "magnetization_values": stored, "dense_values": 3 * n1 * n2 * n3,
+            "with_dense_field": {"value": round(kd / sd, 2), "unit": "evals/s", "ms_per_eval": round(1e3 * sd / kd, 3),
+                                 "expansion_gemm_flops": 2 * 3 * n1 * n2 * n3 * 3 * R * rank},
+            "step": f"compressed potential, field and energy from a rank-{rank} "
+                    f"{'Tucker' if fmt == TUCKER else 'CP'} magnetization (no dense tensor formed)"}
+    plan.close()
+    return out
+
+
 def read_traffic():
     """HBM bytes per z_conv launch from the committed --pmc summary, or None if
     the kernels changed since the counters were taken."""
@@ -401,6 +458,9 @@ def bench(args):
     if args.sp_steps > 0:
         out["sp"] = bench_sp(args, torch, np, m_np, value)
         print(f"# sp: {out['sp']}", file=sys.stderr, flush=True)
+    if args.lowrank_steps > 0:
+        out["tg_lowrank"] = bench_lowrank(args, torch, np, value)
+        print(f"# tg_lowrank: {out['tg_lowrank']}", file=sys.stderr, flush=True)
     if args.llg_steps > 0:
         out["llg"] = bench_llg(args, torch, np, value)
         print(f"# llg: {out['llg']}", file=sys.stderr, flush=True)
@@ -509,6 +569,7 @@ def main():
     ap.add_argument("--sp-steps", type=int, default=200, help="scalar-potential evaluations (0: skip)")
     ap.add_argument("--tg-steps", type=int, default=10, help="tensor-grid evaluations (0: skip)")
     ap.add_argument("--llg-steps", type=int, default=100, help="LLG Heun steps (0: skip)")
+    ap.add_argument("--lowrank-steps", type=int, default=200, help="low-rank TG evaluations (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",

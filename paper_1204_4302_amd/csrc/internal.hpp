@@ -160,13 +160,13 @@ int tg_potential(void* handle, hipStream_t st, int n1, int n2, int n3, int R, co
 // rows [0, n) D, rows [n, 2n) -delta D (spacing h).
 template <typename T>
 hipError_t launch_lr_axis(hipStream_t, int n, double d, double h, int R, const double* tau, T* E, T* O);
-size_t lr_energy_lds_bytes(int r, bool tucker);
-// Factors FG, then (partials != null) 9 R energy partials, then (H != null) the
-// dense field using W (w_elems values of scratch).  Returns 0 or a negative code.
+// Factors FG, then (partials != null) 9 R energy partials via 27 R r^2 Gram
+// values in gram, then (H != null) the dense field using W (w_elems values of
+// scratch).  Returns 0 or a negative code.
 template <typename T>
 int lr_evaluate(void* handle, hipStream_t st, const int n[3], int R, int r, bool tucker, const T* core, const T* U,
                 const T* const DE[3], const T* const DO[3], const double* c, double alpha, T* FG, double* partials,
-                T* H, T* W, size_t w_elems);
+                double* gram, T* H, T* W, size_t w_elems);
 
 // ---- LLG driver (llg.hip) ------------------------------------------------------
 // Heun predictor: k1 = f(m, H + hext), ms = unit(m + dt k1); corrector:

@@ -24,7 +24,8 @@
 // Tucker (CP) tensors, taken on the factors: with the r x r Gram matrices
 // Gamma_q = (U_q^a)^T X_q (X_q = G_q or F_q),
 //     <C x_q U_q, C' x_q X_q> = sum_{s,s'} C(s) C'(s') prod_q Gamma_q(s_q, s'_q)
-// (Tucker: r^4 per term; CP: r^2), so the energy is sub-linear in N too.
+// (Tucker: r^4 per term; CP: r^2), so the energy is sub-linear in N too; the
+// Gram matrices (27 R of them) and the contractions (9 R) are two launches.
 //
 // The dense field on the grid, when asked for, is one GEMM per component
 // with K = 3 R r:  H_a(i1, (i2, i3)) = sum_{p,l,s1} A_1(i1, s1) W(s1, i2, i3),
@@ -41,6 +42,13 @@
 namespace demag {
 
 namespace {
+
+// The stacked Gaussian matrices of the three axes (kernel argument).
+template <typename T>
+struct LrStacks {
+    const T* E[3];
+    const T* O[3];
+};
 
 // -d/dx of the values v(j) = f(j) along an axis of n cells at row j (spacing h):
 // central inside, second-order one-sided on the two faces, first order for
@@ -79,39 +87,165 @@ __global__ void __launch_bounds__(256) k_lr_axis(int n, double d, double h, int 
     }
 }
 
-// Energy terms: one workgroup per (a, p, l), blockIdx.x = (a * 3 + p) * R + l.
-// partials[b] = alpha c_l <M_a, term (p, l) of H_a>, evaluated on the factors.
-// LDS (doubles): three r x r Gram matrices, then two r^3 buffers (Tucker).
+// Potential and field factors of all three components in one launch:
+//     FG_q(:, (p R + l) r + s) = S_q^{l,p} U_q^p(:, s),
+// S_q^{l,p} the stacked (2 n_q x n_q) even matrix for p != q, the odd one for
+// p = q.  Each matrix element is read once and used for every column (p, s)
+// of the thread's column group.  Grid: x = row tiles of the three axes one
+// after another, y = node l, z = column group (COLS of the 3 r columns);
+// one thread per stacked row; the factors staged in LDS by row chunks.
+constexpr int kLrRows = 128;   // stacked rows (threads) per workgroup
+constexpr int kLrChunk = 64;   // factor rows per staged chunk
+// matrix columns loaded ahead of their products (64 resp. 32 loads in flight per thread)
+template <typename T>
+constexpr int lr_batch() { return sizeof(T) == 4 ? 32 : 16; }
+
+template <typename T, int COLS>
+__global__ void __launch_bounds__(kLrRows) k_lr_factors(int n1, int n2, int n3, int R, int r, LrStacks<T> S,
+                                                        const T* __restrict__ U, T* __restrict__ FG) {
+    __shared__ T Us[kLrChunk][COLS];
+    const int t1 = (2 * n1 + kLrRows - 1) / kLrRows, t2 = (2 * n2 + kLrRows - 1) / kLrRows;
+    const int bx = blockIdx.x, l = blockIdx.y, c0 = blockIdx.z * COLS;
+    const int q = bx < t1 ? 0 : bx < t1 + t2 ? 1 : 2;
+    const int tile = q == 0 ? bx : q == 1 ? bx - t1 : bx - t1 - t2;
+    const int nq = q == 0 ? n1 : q == 1 ? n2 : n3;
+    const size_t uoff = q == 0 ? 0 : q == 1 ? (size_t)3 * r * n1 : (size_t)3 * r * (n1 + n2);
+    const size_t foff = q == 0 ? 0 : q == 1 ? (size_t)6 * R * r * n1 : (size_t)6 * R * r * (n1 + n2);
+    const size_t ld = (size_t)2 * nq;
+    const T* __restrict__ E = S.E[q] + (size_t)l * ld * nq;
+    const T* __restrict__ O = S.O[q] + (size_t)l * ld * nq;
+    const int row = tile * kLrRows + (int)threadIdx.x;
+    const bool live = row < 2 * nq;
+    const int ncol = 3 * r;
+    bool odd[COLS];
+#pragma unroll
+    for (int k = 0; k < COLS; ++k) odd[k] = (c0 + k) / r == q;
+    T acc[COLS];
+#pragma unroll
+    for (int k = 0; k < COLS; ++k) acc[k] = T(0);
+    for (int j0 = 0; j0 < nq; j0 += kLrChunk) {
+        const int rows = nq - j0 < kLrChunk ? nq - j0 : kLrChunk;
+        __syncthreads();
+        for (int v = threadIdx.x; v < kLrChunk * COLS; v += kLrRows) {
+            const int jj = v % kLrChunk, k = v / kLrChunk, c = c0 + k;
+            Us[jj][k] = (jj < rows && c < ncol) ? U[uoff + (size_t)(j0 + jj) + (size_t)c * nq] : T(0);
+        }
+        __syncthreads();
+        if (live) {
+            const T* e_col = E + row + (size_t)j0 * ld;
+            const T* o_col = O + row + (size_t)j0 * ld;
+            // JB columns of both matrices in flight before the products
+            // (the staged factor rows past `rows` are zero)
+            constexpr int JB = lr_batch<T>();
+            for (int jb = 0; jb < rows; jb += JB) {
+                T e[JB], o[JB];
+#pragma unroll
+                for (int u = 0; u < JB; ++u) {
+                    const bool ok = jb + u < rows;
+                    e[u] = ok ? e_col[(size_t)(jb + u) * ld] : T(0);
+                    o[u] = ok ? o_col[(size_t)(jb + u) * ld] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < JB; ++u)
+#pragma unroll
+                    for (int k = 0; k < COLS; ++k) acc[k] += (odd[k] ? o[u] : e[u]) * Us[jb + u][k];
+            }
+        }
+    }
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < COLS; ++k) {
+            const int c = c0 + k;
+            if (c < ncol) {
+                const int pp = c / r, ss = c - pp * r;
+                FG[foff + ((size_t)(pp * R + l) * r + ss) * ld + row] = acc[k];
+            }
+        }
+    }
+}
+
+// Energy, step 1: the Gram matrices Gamma_q = (U_q^a)^T X_q (r x r, X_q the
+// field factor G_q^{pl} when q = a, else the potential factor F_q^{pl}), one
+// workgroup per (a, p, l, q), blockIdx.x = ((a * 3 + p) * R + l) * 3 + q.
+// Rows are summed over chunks staged in LDS; when the r^2 entries are fewer
+// than 256 the rows of a chunk are split over 256 / r^2 thread groups.
+// gram[blockIdx.x][s + r s'] (FP64).
+constexpr int kLrStage = 2048;  // staged values per operand (rows x r)
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_lr_gram(int n1, int n2, int n3, int R, int r, const T* __restrict__ U,
+                                                 const T* __restrict__ FG, double* __restrict__ gram) {
+    extern __shared__ double lds[];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int q = b % 3, l = (b / 3) % R, p = (b / (3 * R)) % 3, a = b / (9 * R);
+    const int rr = r * r;
+    const int nq = q == 0 ? n1 : q == 1 ? n2 : n3;
+    const size_t uoff = q == 0 ? 0 : q == 1 ? (size_t)3 * r * n1 : (size_t)3 * r * (n1 + n2);
+    const size_t foff = q == 0 ? 0 : q == 1 ? (size_t)6 * R * r * n1 : (size_t)6 * R * r * (n1 + n2);
+    const T* Ua = U + uoff + (size_t)a * r * nq;                                   // n_q x r, ld n_q
+    const T* X = FG + foff + (size_t)(p * R + l) * r * 2 * nq + (q == a ? nq : 0);  // n_q x r, ld 2 n_q
+    const int CH = kLrStage / r;  // rows per chunk
+    const int ldc = CH + 1;       // padded stride of a staged column
+    double* Us = lds;
+    double* Xs = lds + (size_t)ldc * r;
+    double* out = gram + (size_t)b * rr;
+    const int G = rr >= 256 ? 1 : 256 / rr;  // row groups when the entries are few
+    const int e1 = tid % rr, g1 = tid / rr;
+    double acc = 0.0;
+    for (int e = tid; e < rr; e += blockDim.x) out[e] = 0.0;
+    for (int i0 = 0; i0 < nq; i0 += CH) {
+        const int rows = nq - i0 < CH ? nq - i0 : CH;
+        __syncthreads();
+        for (int j = tid; j < rows * r; j += blockDim.x) {
+            const int i = j % rows, s = j / rows;
+            Us[i + ldc * s] = (double)Ua[i0 + i + (size_t)s * nq];
+            Xs[i + ldc * s] = (double)X[i0 + i + (size_t)s * 2 * nq];
+        }
+        __syncthreads();
+        if (G > 1) {
+            if (g1 < G) {
+                const double* u = Us + ldc * (e1 % r);
+                const double* x = Xs + ldc * (e1 / r);
+                for (int i = g1; i < rows; i += G) acc += u[i] * x[i];
+            }
+        } else {
+            for (int e = tid; e < rr; e += blockDim.x) {
+                const double* u = Us + ldc * (e % r);
+                const double* x = Xs + ldc * (e / r);
+                double v = 0.0;
+                for (int i = 0; i < rows; ++i) v += u[i] * x[i];
+                out[e] += v;  // each entry owned by one thread
+            }
+        }
+    }
+    if (G > 1) {
+        __syncthreads();
+        if (g1 < G) lds[tid] = acc;  // staging is free: reuse it for the group sums
+        __syncthreads();
+        if (tid < rr) {
+            double v = 0.0;
+            for (int g = 0; g < G; ++g) v += lds[g * rr + tid];
+            out[tid] = v;
+        }
+    }
+}
+
+// Energy, step 2: one workgroup per (a, p, l), blockIdx.x = (a * 3 + p) * R + l:
+// partials[b] = alpha c_l sum_{s,s'} C_a(s) C_p(s') prod_q Gamma_q(s_q, s'_q)
+// (Tucker: one mode at a time, r^4 per mode; CP: lambda_a(s) lambda_p(s')
+// prod_q Gamma_q(s, s'), r^2).  LDS (doubles): Gram [3 r^2], Tucker buffers
+// [2 r^3].
 template <typename T, bool TUCKER>
-__global__ void __launch_bounds__(256) k_lr_energy(int n1, int n2, int n3, int R, int r, const T* __restrict__ core,
-                                                   const T* __restrict__ U, const T* __restrict__ FG,
-                                                   const double* __restrict__ c, double alpha,
-                                                   double* __restrict__ partials) {
+__global__ void __launch_bounds__(256) k_lr_contract(int R, int r, const T* __restrict__ core,
+                                                     const double* __restrict__ gram, const double* __restrict__ c,
+                                                     double alpha, double* __restrict__ partials) {
     extern __shared__ double lds[];
     __shared__ double red[4];
-    const int b = blockIdx.x;
+    const int b = blockIdx.x, tid = threadIdx.x;
     const int l = b % R, p = (b / R) % 3, a = b / (3 * R);
     const int rr = r * r;
     double* gam = lds;  // [q][s][s'] at q r^2 + s + r s'
-    const int n[3] = {n1, n2, n3};
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    // Gram matrices: one wave per dot product, lanes over the rows
-    size_t uoff = 0, foff = 0;
-    for (int q = 0; q < 3; ++q) {
-        const int nq = n[q];
-        const T* Ua = U + uoff + (size_t)a * r * nq;                                   // n_q x r, ld n_q
-        const T* X = FG + foff + (size_t)(p * R + l) * r * 2 * nq + (q == a ? nq : 0);  // n_q x r, ld 2 n_q
-        for (int e = wave; e < rr; e += nw) {
-            const int s = e % r, sp = e / r;
-            double acc = 0.0;
-            for (int i = lane; i < nq; i += 64) acc += (double)Ua[i + (size_t)s * nq] * (double)X[i + (size_t)sp * 2 * nq];
-            for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-            if (lane == 0) gam[q * rr + e] = acc;
-        }
-        uoff += (size_t)3 * r * nq;
-        foff += (size_t)2 * nq * 3 * R * r;
-    }
-    __syncthreads();
+    for (int e = tid; e < 3 * rr; e += blockDim.x) gam[e] = gram[(size_t)b * 3 * rr + e];
     double acc = 0.0;
     if constexpr (TUCKER) {
         const int r3 = rr * r;
@@ -119,10 +253,10 @@ __global__ void __launch_bounds__(256) k_lr_energy(int n1, int n2, int n3, int R
         double* B = A + r3;
         const T* Ca = core + (size_t)a * r3;
         const T* Cp = core + (size_t)p * r3;
-        for (int e = threadIdx.x; e < r3; e += blockDim.x) A[e] = (double)Ca[e];
+        for (int e = tid; e < r3; e += blockDim.x) A[e] = (double)Ca[e];
         __syncthreads();
         // B(s1', s2, s3) = sum_s1 Gamma_1(s1, s1') A(s1, s2, s3)
-        for (int e = threadIdx.x; e < r3; e += blockDim.x) {
+        for (int e = tid; e < r3; e += blockDim.x) {
             const int x = e % r, yz = e / r;
             double v = 0.0;
             for (int k = 0; k < r; ++k) v += gam[k + r * x] * A[k + r * yz];
@@ -130,7 +264,7 @@ __global__ void __launch_bounds__(256) k_lr_energy(int n1, int n2, int n3, int R
         }
         __syncthreads();
         // A(s1', s2', s3) = sum_s2 Gamma_2(s2, s2') B(s1', s2, s3)
-        for (int e = threadIdx.x; e < r3; e += blockDim.x) {
+        for (int e = tid; e < r3; e += blockDim.x) {
             const int x = e % r, y = (e / r) % r, z = e / rr;
             double v = 0.0;
             for (int k = 0; k < r; ++k) v += gam[rr + k + r * y] * B[x + r * k + rr * z];
@@ -138,27 +272,29 @@ __global__ void __launch_bounds__(256) k_lr_energy(int n1, int n2, int n3, int R
         }
         __syncthreads();
         // sum_{s'} C_p(s') sum_s3 Gamma_3(s3, s3') A(s1', s2', s3)
-        for (int e = threadIdx.x; e < r3; e += blockDim.x) {
+        for (int e = tid; e < r3; e += blockDim.x) {
             const int xy = e % rr, z = e / rr;
             double v = 0.0;
             for (int k = 0; k < r; ++k) v += gam[2 * rr + k + r * z] * A[xy + rr * k];
             acc += v * (double)Cp[e];
         }
     } else {
+        __syncthreads();
         const T* la = core + (size_t)a * r;
         const T* lp = core + (size_t)p * r;
-        for (int e = threadIdx.x; e < rr; e += blockDim.x) {
+        for (int e = tid; e < rr; e += blockDim.x) {
             const int s = e % r, sp = e / r;
             acc += (double)la[s] * (double)lp[sp] * gam[e] * gam[rr + e] * gam[2 * rr + e];
         }
     }
+    const int lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
     if (lane == 0) red[wave] = acc;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += red[w];
-        partials[b] = alpha * c[l] * s;
+    if (tid == 0) {
+        double sum = 0.0;
+        for (int w = 0; w < nw; ++w) sum += red[w];
+        partials[b] = alpha * c[l] * sum;
     }
 }
 
@@ -219,7 +355,11 @@ hipError_t launch_lr_axis(hipStream_t st, int n, double d, double h, int R, cons
     return hipGetLastError();
 }
 
-size_t lr_energy_lds_bytes(int r, bool tucker) {
+size_t lr_gram_lds_bytes(int r) {
+    return sizeof(double) * std::max<size_t>(2 * (size_t)(kLrStage / r + 1) * r, 256);
+}
+
+size_t lr_contract_lds_bytes(int r, bool tucker) {
     const size_t rr = (size_t)r * r;
     return sizeof(double) * (3 * rr + (tucker ? 2 * rr * r : 0));
 }
@@ -230,38 +370,42 @@ size_t lr_energy_lds_bytes(int r, bool tucker) {
 template <typename T>
 int lr_evaluate(void* handle, hipStream_t st, const int n[3], int R, int r, bool tucker, const T* core, const T* U,
                 const T* const DE[3], const T* const DO[3], const double* c, double alpha, T* FG, double* partials,
-                T* H, T* W, size_t w_elems) {
+                double* gram, T* H, T* W, size_t w_elems) {
     rocblas_handle hd = (rocblas_handle)handle;
     if (rocblas_set_stream(hd, st) != rocblas_status_success) return -1;
     const T one = 1, zero = 0;
-    size_t uoff = 0, foff = 0;
-    for (int q = 0; q < 3; ++q) {
-        const int nq = n[q];
-        for (int p = 0; p < 3; ++p) {
-            // [F; G] (2 n_q x r) for every node l = stacked D (2 n_q x n_q) U_q^p (n_q x r)
-            const T* S = p == q ? DO[q] : DE[q];
-            if (gemm_sb(hd, rocblas_operation_none, rocblas_operation_none, 2 * nq, r, nq, &one, S, 2 * nq,
-                        (rocblas_stride)2 * nq * nq, U + uoff + (size_t)p * r * nq, nq, 0, &zero,
-                        FG + foff + (size_t)p * R * r * 2 * nq, 2 * nq, (rocblas_stride)r * 2 * nq,
-                        R) != rocblas_status_success)
-                return -2;
+    {
+        LrStacks<T> S;
+        for (int q = 0; q < 3; ++q) {
+            S.E[q] = DE[q];
+            S.O[q] = DO[q];
         }
-        uoff += (size_t)3 * r * nq;
-        foff += (size_t)2 * nq * 3 * R * r;
+        const int tiles = (2 * n[0] + kLrRows - 1) / kLrRows + (2 * n[1] + kLrRows - 1) / kLrRows +
+                          (2 * n[2] + kLrRows - 1) / kLrRows;
+        if (3 * r <= 24)
+            hipLaunchKernelGGL((k_lr_factors<T, 24>), dim3(tiles, R, 1), dim3(kLrRows), 0, st, n[0], n[1], n[2], R, r,
+                               S, U, FG);
+        else
+            hipLaunchKernelGGL((k_lr_factors<T, 48>), dim3(tiles, R, (3 * r + 47) / 48), dim3(kLrRows), 0, st, n[0],
+                               n[1], n[2], R, r, S, U, FG);
+        if (hipGetLastError() != hipSuccess) return -2;
     }
     if (partials) {
-        const size_t lds = lr_energy_lds_bytes(r, tucker);
-        if (lds > 65536) {  // dynamic LDS above 64 KB must be allowed per kernel
-            const void* kern = tucker ? (const void*)k_lr_energy<T, true> : (const void*)k_lr_energy<T, false>;
-            if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        // partials doubles as [9 R] energy terms; the Gram matrices go to gram
+        const size_t lg = lr_gram_lds_bytes(r), lc = lr_contract_lds_bytes(r, tucker);
+        hipLaunchKernelGGL((k_lr_gram<T>), dim3(27 * R), dim3(256), lg, st, n[0], n[1], n[2], R, r, U, FG, gram);
+        if (hipGetLastError() != hipSuccess) return -3;
+        if (lc > 65536) {  // dynamic LDS above 64 KB must be allowed per kernel
+            const void* kern = tucker ? (const void*)k_lr_contract<T, true> : (const void*)k_lr_contract<T, false>;
+            if (hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lc) != hipSuccess)
                 return -6;
         }
         if (tucker)
-            hipLaunchKernelGGL((k_lr_energy<T, true>), dim3(9 * R), dim3(256), lds, st, n[0], n[1], n[2], R, r, core,
-                               U, FG, c, alpha, partials);
+            hipLaunchKernelGGL((k_lr_contract<T, true>), dim3(9 * R), dim3(256), lc, st, R, r, core, gram, c, alpha,
+                               partials);
         else
-            hipLaunchKernelGGL((k_lr_energy<T, false>), dim3(9 * R), dim3(256), lds, st, n[0], n[1], n[2], R, r, core,
-                               U, FG, c, alpha, partials);
+            hipLaunchKernelGGL((k_lr_contract<T, false>), dim3(9 * R), dim3(256), lc, st, R, r, core, gram, c, alpha,
+                               partials);
         if (hipGetLastError() != hipSuccess) return -3;
     }
     if (H) {
@@ -296,9 +440,9 @@ template hipError_t launch_lr_axis<float>(hipStream_t, int, double, double, int,
 template hipError_t launch_lr_axis<double>(hipStream_t, int, double, double, int, const double*, double*, double*);
 template int lr_evaluate<float>(void*, hipStream_t, const int[3], int, int, bool, const float*, const float*,
                                 const float* const[3], const float* const[3], const double*, double, float*, double*,
-                                float*, float*, size_t);
+                                double*, float*, float*, size_t);
 template int lr_evaluate<double>(void*, hipStream_t, const int[3], int, int, bool, const double*, const double*,
                                  const double* const[3], const double* const[3], const double*, double, double*,
-                                 double*, double*, double*, size_t);
+                                 double*, double*, double*, double*, size_t);
 
 }  // namespace demag

@@ -167,6 +167,8 @@ struct LRState {
     void* DE[3] = {nullptr, nullptr, nullptr};
     void* DO[3] = {nullptr, nullptr, nullptr};
     double* partials = nullptr;
+    double* gram = nullptr;  // 27 R r^2 Gram values (grown on demand)
+    size_t gram_bytes = 0;
     void* W = nullptr;
     size_t w_bytes = 0;
     size_t bytes = 0;
@@ -645,7 +647,7 @@ void free_lr(LRState* g) {
     if (!g) return;
     if (g->handle) rocblas_destroy_handle((rocblas_handle)g->handle);
     for (void* q : {(void*)g->tau, (void*)g->c, g->DE[0], g->DE[1], g->DE[2], g->DO[0], g->DO[1], g->DO[2],
-                    (void*)g->partials, g->W})
+                    (void*)g->partials, (void*)g->gram, g->W})
         hipFree(q);
     delete g;
 }
@@ -1253,6 +1255,23 @@ int demag_tg_lowrank_field(demag_plan_t p, int format, int rank, const void* cor
         }
         w_elems = g->w_bytes / tsz;
     }
+    if (E_dev) {  // Gram matrices of the energy: 27 R r^2 values
+        const size_t want = (size_t)27 * g->R * rank * rank * sizeof(double);
+        if (want > g->gram_bytes) {
+            HIP_TRY(hipDeviceSynchronize());  // the old buffer may still be in use
+            hipFree(g->gram);
+            g->bytes -= g->gram_bytes;
+            g->gram = nullptr;
+            g->gram_bytes = 0;
+            if (hipMalloc((void**)&g->gram, want) != hipSuccess) {
+                (void)hipGetLastError();
+                g->gram = nullptr;
+                return fail(DEMAG_ENOMEM, "cannot allocate %zu bytes for the low-rank Gram matrices", want);
+            }
+            g->gram_bytes = want;
+            g->bytes += want;
+        }
+    }
     hipStream_t st = (hipStream_t)stream;
     int rc = enter(p, st);
     if (rc) return rc;
@@ -1263,12 +1282,13 @@ int demag_tg_lowrank_field(demag_plan_t p, int format, int rank, const void* cor
         const float* DE[3] = {(const float*)g->DE[0], (const float*)g->DE[1], (const float*)g->DE[2]};
         const float* DO[3] = {(const float*)g->DO[0], (const float*)g->DO[1], (const float*)g->DO[2]};
         rc = lr_evaluate<float>(g->handle, st, p->n, g->R, rank, tucker, (const float*)core, (const float*)U, DE, DO,
-                                g->c, Ms * hmax, (float*)FG, parts, (float*)H, (float*)g->W, w_elems);
+                                g->c, Ms * hmax, (float*)FG, parts, g->gram, (float*)H, (float*)g->W, w_elems);
     } else {
         const double* DE[3] = {(const double*)g->DE[0], (const double*)g->DE[1], (const double*)g->DE[2]};
         const double* DO[3] = {(const double*)g->DO[0], (const double*)g->DO[1], (const double*)g->DO[2]};
         rc = lr_evaluate<double>(g->handle, st, p->n, g->R, rank, tucker, (const double*)core, (const double*)U, DE,
-                                 DO, g->c, Ms * hmax, (double*)FG, parts, (double*)H, (double*)g->W, w_elems);
+                                 DO, g->c, Ms * hmax, (double*)FG, parts, g->gram, (double*)H, (double*)g->W,
+                                 w_elems);
     }
     if (rc) return fail(DEMAG_EHIP, "low-rank tensor-grid evaluation failed (%d)", rc);
     if (E_dev) {
