@@ -229,6 +229,29 @@ int demag_tg_lowrank_field(demag_plan_t plan, int format, int rank, const void* 
 /* out[0] = R (nodes), out[1] = bytes of the stacked Gaussian matrices and
  * scratch held, out[2] = alpha / Ms = h_max in metres. */
 int demag_tg_lowrank_info(demag_plan_t plan, int64_t* out);
+/* Alternating least squares compression of a dense magnetization m (device,
+ * [3][nz][ny][nx], plan dtype) into the format above, each component on its
+ * own, from the caller's initial factors (Sec. 3.2: ALS from random initial
+ * guesses), `sweeps` >= 1 sweeps over the three modes:
+ *   DEMAG_TUCKER: higher-order orthogonal iteration; per mode the leading
+ *     rank-r left singular subspace of Y_(n) = (X x_{m != n} U_m^T)_(n) by one
+ *     step of orthogonal iteration from the current factor (Cholesky QR,
+ *     twice); the factors are orthonormalised first; afterwards
+ *     core = X x_1 U1^T x_2 U2^T x_3 U3^T.  rank <= min(nx, ny, nz).
+ *   DEMAG_CP: CP-ALS; per mode U_n = X_(n) (U_c (.) U_b) V^-1 with
+ *     V = (U_b^T U_b) * (U_c^T U_c), then columns normalised to unit 2-norm,
+ *     core = the weights lambda.  The initial factor of axis x is not read.
+ * U (in: initial factors, out: result) and core use the layouts of
+ * demag_tg_lowrank_field.  *relerr (host, may be NULL) receives eq. (relr)
+ * of the result, from the factor identities in FP64 (Tucker:
+ * ||X||^2 - ||C||^2; CP: ||X||^2 - 2 <X, X^> + ||X^||^2), so values below
+ * about 1e-7 (FP64) or 1e-3 (FP32) are rounding-limited.  Allocates its
+ * scratch for the call and synchronises `stream`.  DEMAG_EINVAL for a rank
+ * outside the format's range, sweeps < 1, or a Gram matrix that is not
+ * positive definite (a rank above the numerical rank of the data or of the
+ * initial guess). */
+int demag_lowrank_compress(demag_plan_t plan, int format, int rank, int sweeps, const void* m, void* core, void* U,
+                           double* relerr, void* stream);
 
 /* Text description of the launch shape of every pass (kernel family, threads,
  * tiles) into `buf` (len bytes, NUL-terminated); DEMAG_EINVAL if too small. */

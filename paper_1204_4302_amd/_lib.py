@@ -50,6 +50,7 @@ SIGNATURES = {
     "demag_tg_lowrank_prepare": (_I, [_P, _P]),
     "demag_tg_lowrank_field": (_I, [_P, _I, _I, _P, _P, _D, _P, _P, _P, _P]),
     "demag_tg_lowrank_info": (_I, [_P, ctypes.POINTER(ctypes.c_int64)]),
+    "demag_lowrank_compress": (_I, [_P, _I, _I, _I, _P, _P, _P, ctypes.POINTER(_D), _P]),
     "demag_batch_autotune": (_I, [_P, _P]),
     "demag_batch_launch": (_I, [_P, _P]),
     "demag_batch_destroy": (_I, [_P]),

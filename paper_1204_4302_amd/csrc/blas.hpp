@@ -34,5 +34,15 @@ inline rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_opera
                     double* C, int ldc) {
     return rocblas_dgemm(h, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc);
 }
+inline rocblas_status gemv_sb(rocblas_handle h, rocblas_operation ta, int m, int n, const float* al, const float* A,
+                              int lda, rocblas_stride sa, const float* x, int incx, rocblas_stride sx, const float* be,
+                              float* y, int incy, rocblas_stride sy, int batch) {
+    return rocblas_sgemv_strided_batched(h, ta, m, n, al, A, lda, sa, x, incx, sx, be, y, incy, sy, batch);
+}
+inline rocblas_status gemv_sb(rocblas_handle h, rocblas_operation ta, int m, int n, const double* al, const double* A,
+                              int lda, rocblas_stride sa, const double* x, int incx, rocblas_stride sx, const double* be,
+                              double* y, int incy, rocblas_stride sy, int batch) {
+    return rocblas_dgemv_strided_batched(h, ta, m, n, al, A, lda, sa, x, incx, sx, be, y, incy, sy, batch);
+}
 
 }  // namespace demag

@@ -168,6 +168,26 @@ int lr_evaluate(void* handle, hipStream_t st, const int n[3], int R, int r, bool
                 const T* const DE[3], const T* const DO[3], const double* c, double alpha, T* FG, double* partials,
                 double* gram, T* H, T* W, size_t w_elems);
 
+// ---- ALS compression (als.hip) ------------------------------------------------
+// Device scratch of one compression (sizes for rank r, n_max = max n_q):
+// Tm max(n1 n2, n2 n3) r; Y n_max r^2; W r^3; P n_max r; Q max(n_max r, r^3);
+// Rinv r^2; G[4] r^2 doubles; partials 1024 doubles; scal 1 double; flag 1 int
+// (set when a Gram matrix is not positive definite).
+template <typename T>
+struct AlsScratch {
+    T *Tm, *Y, *W, *P, *Q, *Rinv;
+    double* G[4];
+    double* partials;
+    double* scal;
+    int* flag;
+};
+// Compress the three components of m in place of the initial factors U
+// (layout of the low-rank calls), writing core (Tucker core / CP weights) and
+// err2[3][2] = (residual^2, ||X||^2) per component.  Returns 0 or a negative code.
+template <typename T>
+int als_compress(void* handle, hipStream_t st, const int n[3], int r, bool tucker, int sweeps, const T* m, T* core,
+                 T* U, double* err2, const AlsScratch<T>& w);
+
 // ---- LLG driver (llg.hip) ------------------------------------------------------
 // Heun predictor: k1 = f(m, H + hext), ms = unit(m + dt k1); corrector:
 // m = unit(m + dt/2 (k1 + f(ms, H2 + hext))); f = -g m x h - alpha g m x (m x h).

@@ -187,6 +187,7 @@ struct demag_plan_s {
     TGState* tg = nullptr; // tensor-grid state (after demag_tg_prepare)
     LRState* lr = nullptr; // low-rank tensor-grid state (after demag_tg_lowrank_prepare)
     size_t lr_cap = (size_t)256 << 20;  // byte cap of the low-rank expansion scratch
+    void* als_handle = nullptr;          // rocblas_handle of the ALS compression (created on first use)
     LaunchCfg zs;          // launch shape of the scalar-potential Z pass
     void* B1 = nullptr;
     void* B2 = nullptr;
@@ -710,6 +711,7 @@ void free_plan(demag_plan_s* p) {
     hipFree(p->shat);
     free_tg(p->tg);
     free_lr(p->lr);
+    if (p->als_handle) rocblas_destroy_handle((rocblas_handle)p->als_handle);
     hipFree(p->B1);
     hipFree(p->B2);
     hipFree(p->partials);
@@ -859,6 +861,70 @@ bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 
 // ===========================================================================
 // C ABI
+template <typename T>
+int run_compress(demag_plan_s* p, hipStream_t st, int format, int r, int sweeps, const T* m, T* core, T* U,
+                 double* relerr) {
+    const int* n = p->n;
+    const int nmax = std::max(n[0], std::max(n[1], n[2]));
+    const size_t rr = (size_t)r * r, r3 = rr * r;
+    const size_t nT = std::max((size_t)n[0] * n[1], (size_t)n[1] * n[2]) * r;
+    const size_t nY = (size_t)nmax * rr, nW = r3, nP = (size_t)nmax * r, nQ = std::max((size_t)nmax * r, r3);
+    const size_t elems = nT + nY + nW + nP + nQ + rr;
+    const size_t dbl = 4 * rr + 1024 + 1 + 6;
+    void* buf = nullptr;
+    const size_t bytes = elems * sizeof(T) + dbl * sizeof(double) + 64;
+    if (hipMalloc(&buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DEMAG_ENOMEM, "cannot allocate %zu bytes of ALS scratch", bytes);
+    }
+    double* d = (double*)buf;
+    AlsScratch<T> w;
+    for (int i = 0; i < 4; ++i) w.G[i] = d + i * rr;
+    w.partials = d + 4 * rr;
+    w.scal = w.partials + 1024;
+    double* err2 = w.scal + 1;
+    w.flag = (int*)(err2 + 6);
+    T* t = (T*)((char*)buf + dbl * sizeof(double) + 64);
+    w.Tm = t;
+    w.Y = w.Tm + nT;
+    w.W = w.Y + nY;
+    w.P = w.W + nW;
+    w.Q = w.P + nP;
+    w.Rinv = w.Q + nQ;
+    int rc = DEMAG_OK;
+    if (!p->als_handle) {
+        rocblas_handle h = nullptr;
+        if (rocblas_create_handle(&h) != rocblas_status_success) rc = fail(DEMAG_EHIP, "rocblas_create_handle failed");
+        p->als_handle = h;
+    }
+    double e2[6] = {0, 0, 0, 0, 0, 0};
+    int flag = 0;
+    if (!rc) {
+        hipError_t e = hipMemsetAsync(w.flag, 0, sizeof(int), st);
+        if (e != hipSuccess) rc = hip_fail(e, "hipMemsetAsync");
+    }
+    if (!rc) {
+        const int k = als_compress<T>(p->als_handle, st, n, r, format == DEMAG_TUCKER, sweeps, m, core, U, err2, w);
+        if (k) rc = fail(DEMAG_EHIP, "ALS compression failed (%d)", k);
+    }
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(e2, err2, sizeof(e2), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(&flag, w.flag, sizeof(int), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) rc = hip_fail(e, "ALS compression");
+    }
+    hipFree(buf);
+    if (rc) return rc;
+    if (flag)
+        return fail(DEMAG_EINVAL, "a Gram matrix of the factors is not positive definite (rank %d above the "
+                                  "numerical rank of the data or of the initial guess)", r);
+    if (relerr) {
+        const double res = e2[0] + e2[2] + e2[4], xx = e2[1] + e2[3] + e2[5];
+        *relerr = xx > 0 ? std::sqrt(std::max(0.0, res) / xx) : 0.0;
+    }
+    return DEMAG_OK;
+}
+
 extern "C" {
 
 const char* demag_last_error(void) { return g_last_error.c_str(); }
@@ -1295,6 +1361,25 @@ int demag_tg_lowrank_field(demag_plan_t p, int format, int rank, const void* cor
         const double V = p->d[0] * p->d[1] * p->d[2];
         HIP_TRY(launch_energy_reduce(st, g->partials, 9 * g->R, -0.5 * kMu0 * Ms * V, E_dev));
     }
+    return leave(p, st);
+}
+
+int demag_lowrank_compress(demag_plan_t p, int format, int rank, int sweeps, const void* m, void* core, void* U,
+                           double* relerr, void* stream) {
+    if (!p || !m || !core || !U) return fail(DEMAG_EINVAL, "NULL plan, m, core or U");
+    if (format != DEMAG_TUCKER && format != DEMAG_CP) return fail(DEMAG_EINVAL, "format must be DEMAG_TUCKER or DEMAG_CP");
+    const int rmax = format == DEMAG_TUCKER ? std::min(DEMAG_TUCKER_MAX_RANK, std::min(p->n[0], std::min(p->n[1], p->n[2])))
+                                            : DEMAG_CP_MAX_RANK;
+    if (rank < 1 || rank > rmax) return fail(DEMAG_EINVAL, "rank %d outside [1, %d]", rank, rmax);
+    if (sweeps < 1 || sweeps > 100000) return fail(DEMAG_EINVAL, "sweeps must be in [1, 100000]");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    rc = p->dtype == DEMAG_F32 ? run_compress<float>(p, st, format, rank, sweeps, (const float*)m, (float*)core,
+                                                     (float*)U, relerr)
+                               : run_compress<double>(p, st, format, rank, sweeps, (const double*)m, (double*)core,
+                                                      (double*)U, relerr);
+    if (rc) return rc;
     return leave(p, st);
 }
 

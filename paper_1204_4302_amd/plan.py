@@ -288,6 +288,33 @@ class Plan:
                   ctypes.c_void_p(E.data_ptr()) if E is not None else None, _stream_ptr())
         return FG, H, E
 
+    def lowrank_compress(self, m: torch.Tensor, fmt: int, rank: int, sweeps: int, factors):
+        """ALS compression of the dense m ([3][nz][ny][nx]) into `fmt` with
+        `rank`, from the initial factors (three tensors (3, r, n_q), not
+        modified).  Returns (core, factors, relerr) in the layouts of
+        tg_lowrank_field; relerr is eq. (relr) of the result."""
+        self._check(m, "m")
+        r = int(rank)
+        if fmt not in (TUCKER, CP):
+            raise ValueError("fmt must be TUCKER or CP")
+        if len(factors) != 3:
+            raise ValueError("three factor tensors (one per axis) expected")
+        for q, f in enumerate(factors):
+            if tuple(f.shape) != (3, r, self.shape[q]):
+                raise ValueError(f"factor {q} has shape {tuple(f.shape)}, expected {(3, r, self.shape[q])}")
+            if not isinstance(f, torch.Tensor) or f.device.type != "cuda" or f.dtype != self.dtype:
+                raise TypeError(f"factor {q} must be a CUDA tensor of {self.dtype}")
+        U = torch.cat([f.contiguous().reshape(-1) for f in factors])
+        core = torch.empty((3, r, r, r) if fmt == TUCKER else (3, r), dtype=self.dtype, device=m.device)
+        err = ctypes.c_double()
+        _lib.call("demag_lowrank_compress", self._h, int(fmt), r, int(sweeps), self._ptr(m), self._ptr(core),
+                  self._ptr(U), ctypes.byref(err), _stream_ptr())
+        out, off = [], 0
+        for n in self.shape:
+            out.append(U[off:off + 3 * r * n].view(3, r, n))
+            off += 3 * r * n
+        return core, out, err.value
+
     def lowrank_fg_views(self, FG: torch.Tensor, rank: int):
         """The per-axis (3, R, r, 2 n_q) views of a compressed field buffer."""
         R = self.tg_lowrank_info()["nodes"]
