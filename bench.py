@@ -491,8 +491,10 @@ def _short(name):
     return name.split("(")[0].replace("void ", "")
 
 
-def summarize_profile(d, out_path, command):
-    """Per-kernel calls / average / total from a --kernel-trace --stats run."""
+def summarize_profile(d, out_path, command, match=None):
+    """Per-kernel calls / average / total from a --kernel-trace --stats run
+    (only kernels whose name contains one of the comma-separated `match`
+    strings, when given)."""
     import sqlite3
     lines = [f"# command: {command}", f"# kernel_source_hash = {kernel_source_hash()}",
              "# per kernel and grid size (work-items), from the trace's dispatch records",
@@ -502,6 +504,10 @@ def summarize_profile(d, out_path, command):
         rows = con.execute("select name, grid_x * grid_y * grid_z, count(*), sum(end - start), avg(end - start) "
                            "from kernels group by name, grid_x, grid_y, grid_z").fetchall()
         total_ns = sum(r[3] for r in rows) or 1
+        if match:
+            keys = [k for k in match.split(",") if k]
+            rows = [r for r in rows if any(k in r[0] for k in keys)]
+            lines.insert(3, f"# kernels matching: {match}")
         for name, grid, calls, tot, avg in sorted(rows, key=lambda r: -r[3]):
             # dispatch timestamps are in nanoseconds
             lines.append(f"{_short(name)[:44]:44s} {grid:9d} {calls:6d} {avg / 1e3:10.2f} {tot / 1e6:10.3f} "
@@ -580,12 +586,14 @@ def main():
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--out", metavar="FILE")
     ap.add_argument("--command", default="", help="command line recorded in the summary")
+    ap.add_argument("--match", default=None, help="--summarize-profile: keep kernels whose name contains one of "
+                                                  "these comma-separated strings")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary, args.out or "/dev/stdout", args.command)
         return 0
     if args.summarize_profile:
-        summarize_profile(args.summarize_profile, args.out or "/dev/stdout", args.command)
+        summarize_profile(args.summarize_profile, args.out or "/dev/stdout", args.command, args.match)
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
