@@ -163,10 +163,15 @@ hipError_t launch_lr_axis(hipStream_t, int n, double d, double h, int R, const d
 // Factors FG, then (partials != null) 9 R energy partials via 27 R r^2 Gram
 // values in gram, then (H != null) the dense field using W (w_elems values of
 // scratch).  Returns 0 or a negative code.
+// FP32 plans keep the Gaussian matrices swizzled for the MFMA factor product
+// (R lr_swizzled_elems(n) values per kind and axis, no difference rows); FP64
+// plans keep the stacked [D; -delta D] matrices.
+hipError_t launch_lr_axis_sw(hipStream_t, int n, double d, int R, const double* tau, float* E, float* O);
+size_t lr_swizzled_elems(int n);
 template <typename T>
-int lr_evaluate(void* handle, hipStream_t st, const int n[3], int R, int r, bool tucker, const T* core, const T* U,
-                const T* const DE[3], const T* const DO[3], const double* c, double alpha, T* FG, double* partials,
-                double* gram, T* H, T* W, size_t w_elems);
+int lr_evaluate(void* handle, hipStream_t st, const int n[3], const double h[3], int R, int r, bool tucker,
+                const T* core, const T* U, const T* const DE[3], const T* const DO[3], const double* c, double alpha,
+                T* FG, double* partials, double* gram, T* H, T* W, size_t w_elems);
 
 // ---- ALS compression (als.hip) ------------------------------------------------
 // Device scratch of one compression (sizes for rank r, n_max = max n_q):

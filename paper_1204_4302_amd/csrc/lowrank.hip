@@ -164,6 +164,181 @@ __global__ void __launch_bounds__(kLrRows) k_lr_factors(int n1, int n2, int n3, 
     }
 }
 
+// ---- FP32: the factor product on MFMA ------------------------------------------
+constexpr int kMfChunk = 128;  // factor rows staged per chunk (8 tiles of 16)
+constexpr int kMfGroups = kMfChunk / 16;
+
+// Tiles of 16 columns per row block in the swizzled layout: ceil(n / 16)
+// rounded up to whole chunks (the padding is zero).
+__host__ __device__ inline int lr_sw_cols(int n) {
+    const int nb = (n + 15) / 16;
+    return (nb + kMfGroups - 1) / kMfGroups * kMfGroups;
+}
+
+// Swizzled Gaussian matrices (FP32): per node l, for the 16 x 16 tile (row
+// block rb, column group kg) of D, the 256 values in the operand order of
+// v_mfma_f32_16x16x4f32 over four k-steps: entry ((rb nc + kg) 64 + lane) 4 + v
+// = D(16 rb + lane % 16, 16 kg + 4 v + lane / 16), zero outside n x n
+// (nb = ceil(n / 16) row blocks, nc = lr_sw_cols(n) column groups).  A wave
+// then loads each 16 x 16 tile as one 1 KB run.
+__global__ void __launch_bounds__(256) k_lr_axis_sw(int n, double d, int R, const double* __restrict__ tau,
+                                                    float* __restrict__ E, float* __restrict__ O) {
+    const int nb = (n + 15) / 16, nc = lr_sw_cols(n);
+    const size_t per = (size_t)nb * nc * 256;
+    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= per * R) return;
+    const int l = (int)(t / per);
+    const size_t e = t - (size_t)l * per;
+    const int v = (int)(e & 3), lane = (int)((e >> 2) & 63);
+    const size_t blk = e >> 8;
+    const int rb = (int)(blk / nc), kg = (int)(blk % nc);
+    const int row = 16 * rb + (lane & 15), k = 16 * kg + 4 * v + (lane >> 4);
+    float ev = 0.f, ov = 0.f;
+    if (row < n && k < n) {
+        const double s = tau[l];
+        ev = (float)gauss_even((row + 0.5) * d, (k + 0.5) * d, d, s);
+        ov = (float)gauss_odd((row + 0.5) * d, (k + 0.5) * d, d, s);
+    }
+    E[t] = ev;
+    O[t] = ov;
+}
+
+struct LrSwizzled {
+    const float* E[3];
+    const float* O[3];
+};
+
+typedef float lr_f32x4 __attribute__((ext_vector_type(4)));
+
+// F_q^{pl} for FP32 on MFMA.  Columns of axis q: even blocks of 16 hold the
+// two components p != q (2r columns), odd blocks component q (r columns); a
+// workgroup takes NE even and NO odd blocks (column group = grid z; blocks
+// past the last are zero and not written) and 4 row blocks of 16 (one per
+// wave; grid x over the three axes), node l = grid y.  Per 16 x 16 tile a
+// wave issues four MFMAs per block (K = 4 each): A from the swizzled matrix
+// (all tiles of a chunk in flight before the chunk's factor rows are staged),
+// B from LDS.  Accumulator layout: lane holds rows 4 (lane / 16) + v, column
+// lane % 16.  No control flow inside the product loop: idle waves compute on
+// a valid tile and do not store.
+template <int NE, int NO>
+__global__ void __launch_bounds__(256) k_lr_factors_mfma(int n1, int n2, int n3, int R, int r, LrSwizzled S,
+                                                         const float* __restrict__ U, float* __restrict__ FG) {
+    constexpr int NB = NE + NO;
+    __shared__ float Us[kMfChunk][NB * 16 + 1];
+    const int nb1 = (n1 + 15) / 16, nb2 = (n2 + 15) / 16, nb3 = (n3 + 15) / 16;
+    const int t1 = (nb1 + 3) / 4, t2 = (nb2 + 3) / 4;
+    const int bx = blockIdx.x, l = blockIdx.y, z = blockIdx.z;
+    const int q = bx < t1 ? 0 : bx < t1 + t2 ? 1 : 2;
+    const int tile = q == 0 ? bx : q == 1 ? bx - t1 : bx - t1 - t2;
+    const int n = q == 0 ? n1 : q == 1 ? n2 : n3;
+    const int nb = q == 0 ? nb1 : q == 1 ? nb2 : nb3;
+    const int nc = lr_sw_cols(n);
+    const size_t uoff = q == 0 ? 0 : q == 1 ? (size_t)3 * r * n1 : (size_t)3 * r * (n1 + n2);
+    const size_t foff = q == 0 ? 0 : q == 1 ? (size_t)6 * R * r * n1 : (size_t)6 * R * r * (n1 + n2);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int rb = tile * 4 + wave;
+    const bool live = rb < nb;
+    const int rbc = live ? rb : nb - 1;
+    const size_t per = (size_t)nb * nc * 256;
+    const float* Esw = S.E[q] + (size_t)l * per + (size_t)rbc * nc * 256 + lane * 4;
+    const float* Osw = S.O[q] + (size_t)l * per + (size_t)rbc * nc * 256 + lane * 4;
+    // (component, column) of block j, column c; -1 for padding
+    auto col_of = [&](int j, int c, int& p) {
+        if (j < NE) {
+            const int cc = 16 * (z * NE + j) + c;
+            if (cc >= 2 * r) return -1;
+            const int i = cc / r;
+            p = i < q ? i : i + 1;
+            return cc - i * r;
+        }
+        const int cc = 16 * (z * NO + j - NE) + c;
+        if (cc >= r) return -1;
+        p = q;
+        return cc;
+    };
+    lr_f32x4 acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = lr_f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < nc * 16; k0 += kMfChunk) {
+        lr_f32x4 aE[NE > 0 ? kMfGroups : 1], aO[NO > 0 ? kMfGroups : 1];
+#pragma unroll
+        for (int g = 0; g < kMfGroups; ++g) {
+            const size_t off = (size_t)((k0 >> 4) + g) * 256;
+            if constexpr (NE > 0) aE[g] = *(const lr_f32x4*)(Esw + off);
+            if constexpr (NO > 0) aO[g] = *(const lr_f32x4*)(Osw + off);
+        }
+        __syncthreads();
+        for (int idx = tid; idx < kMfChunk * NB * 16; idx += blockDim.x) {
+            const int kk = idx % kMfChunk, cl = idx / kMfChunk;
+            int p = 0;
+            const int s = col_of(cl >> 4, cl & 15, p);
+            const int k = k0 + kk;
+            Us[kk][cl] = (s >= 0 && k < n) ? U[uoff + (size_t)k + (size_t)n * (p * r + s)] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int g = 0; g < kMfGroups; ++g) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int kk = 16 * g + 4 * v + (lane >> 4);
+                float bv[NB];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) bv[j] = Us[kk][16 * j + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    float a;
+                    if constexpr (NE > 0) a = j < NE ? aE[g][v] : aO[NO > 0 ? g : 0][v];
+                    else a = aO[g][v];
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[j], acc[j], 0, 0, 0);
+                }
+            }
+        }
+    }
+    if (live) {
+        const size_t ld = (size_t)2 * n;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            int p = 0;
+            const int s = col_of(j, lane & 15, p);
+            if (s >= 0) {
+                float* col = FG + foff + ((size_t)(p * R + l) * r + s) * ld;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * rb + 4 * (lane >> 4) + v;
+                    if (row < n) col[row] = acc[j][v];
+                }
+            }
+        }
+    }
+}
+
+// Field factors from potential factors: G_q = -delta_q F_q (rows [n_q, 2 n_q)
+// of every column of FG), the difference stencils of the field, FP64 arithmetic.
+__global__ void __launch_bounds__(256) k_lr_grad(int n1, int n2, int n3, int R, int r, double h1, double h2,
+                                                 double h3, float* __restrict__ FG) {
+    const size_t cols = (size_t)3 * R * r;
+    const size_t c1 = cols * n1, c2 = cols * n2, c3 = cols * n3;
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= c1 + c2 + c3) return;
+    int n;
+    double h;
+    size_t foff;
+    if (t < c1) {
+        n = n1, h = h1, foff = 0;
+    } else if (t < c1 + c2) {
+        t -= c1;
+        n = n2, h = h2, foff = (size_t)6 * R * r * n1;
+    } else {
+        t -= c1 + c2;
+        n = n3, h = h3, foff = (size_t)6 * R * r * (n1 + n2);
+    }
+    const size_t col = t / n;
+    const int row = (int)(t - col * n);
+    float* F = FG + foff + col * 2 * n;
+    auto f = [&](int j) { return (double)F[j]; };
+    F[n + row] = (float)minus_diff(f, row, n, h);
+}
+
 // Energy, step 1: the Gram matrices Gamma_q = (U_q^a)^T X_q (r x r, X_q the
 // field factor G_q^{pl} when q = a, else the potential factor F_q^{pl}), one
 // workgroup per (a, p, l, q), blockIdx.x = ((a * 3 + p) * R + l) * 3 + q.
@@ -355,6 +530,16 @@ hipError_t launch_lr_axis(hipStream_t st, int n, double d, double h, int R, cons
     return hipGetLastError();
 }
 
+hipError_t launch_lr_axis_sw(hipStream_t st, int n, double d, int R, const double* tau, float* E, float* O) {
+    const size_t total = lr_swizzled_elems(n) * R;
+    hipLaunchKernelGGL(k_lr_axis_sw, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, d, R, tau, E, O);
+    return hipGetLastError();
+}
+
+size_t lr_swizzled_elems(int n) {
+    return (size_t)((n + 15) / 16) * lr_sw_cols(n) * 256;
+}
+
 size_t lr_gram_lds_bytes(int r) {
     return sizeof(double) * std::max<size_t>(2 * (size_t)(kLrStage / r + 1) * r, 256);
 }
@@ -368,13 +553,34 @@ size_t lr_contract_lds_bytes(int r, bool tucker) {
 // the factors and the dense field.  DE[q], DO[q]: stacked Gaussian matrices
 // of axis q ([R][n_q][2 n_q] column-major, ld 2 n_q).
 template <typename T>
-int lr_evaluate(void* handle, hipStream_t st, const int n[3], int R, int r, bool tucker, const T* core, const T* U,
-                const T* const DE[3], const T* const DO[3], const double* c, double alpha, T* FG, double* partials,
-                double* gram, T* H, T* W, size_t w_elems) {
+int lr_evaluate(void* handle, hipStream_t st, const int n[3], const double h[3], int R, int r, bool tucker,
+                const T* core, const T* U, const T* const DE[3], const T* const DO[3], const double* c, double alpha,
+                T* FG, double* partials, double* gram, T* H, T* W, size_t w_elems) {
     rocblas_handle hd = (rocblas_handle)handle;
     if (rocblas_set_stream(hd, st) != rocblas_status_success) return -1;
     const T one = 1, zero = 0;
-    {
+    if constexpr (sizeof(T) == 4) {  // FP32: swizzled matrices, MFMA, then the differences
+        LrSwizzled S;
+        for (int q = 0; q < 3; ++q) {
+            S.E[q] = (const float*)DE[q];
+            S.O[q] = (const float*)DO[q];
+        }
+        const int tiles = ((n[0] + 15) / 16 + 3) / 4 + ((n[1] + 15) / 16 + 3) / 4 + ((n[2] + 15) / 16 + 3) / 4;
+        const int nbE = (2 * r + 15) / 16, nbO = (r + 15) / 16;
+        if (r <= 8) {
+            hipLaunchKernelGGL((k_lr_factors_mfma<1, 1>), dim3(tiles, R, 1), dim3(256), 0, st, n[0], n[1], n[2], R, r,
+                               S, (const float*)U, (float*)FG);
+        } else {
+            const int groups = std::max((nbE + 1) / 2, nbO);
+            hipLaunchKernelGGL((k_lr_factors_mfma<2, 1>), dim3(tiles, R, groups), dim3(256), 0, st, n[0], n[1], n[2],
+                               R, r, S, (const float*)U, (float*)FG);
+        }
+        if (hipGetLastError() != hipSuccess) return -2;
+        const size_t total = (size_t)3 * R * r * (n[0] + n[1] + n[2]);
+        hipLaunchKernelGGL(k_lr_grad, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n[0], n[1], n[2], R, r,
+                           h[0], h[1], h[2], (float*)FG);
+        if (hipGetLastError() != hipSuccess) return -2;
+    } else {
         LrStacks<T> S;
         for (int q = 0; q < 3; ++q) {
             S.E[q] = DE[q];
@@ -438,11 +644,11 @@ int lr_evaluate(void* handle, hipStream_t st, const int n[3], int R, int r, bool
 
 template hipError_t launch_lr_axis<float>(hipStream_t, int, double, double, int, const double*, float*, float*);
 template hipError_t launch_lr_axis<double>(hipStream_t, int, double, double, int, const double*, double*, double*);
-template int lr_evaluate<float>(void*, hipStream_t, const int[3], int, int, bool, const float*, const float*,
-                                const float* const[3], const float* const[3], const double*, double, float*, double*,
-                                double*, float*, float*, size_t);
-template int lr_evaluate<double>(void*, hipStream_t, const int[3], int, int, bool, const double*, const double*,
-                                 const double* const[3], const double* const[3], const double*, double, double*,
-                                 double*, double*, double*, double*, size_t);
+template int lr_evaluate<float>(void*, hipStream_t, const int[3], const double[3], int, int, bool, const float*,
+                                const float*, const float* const[3], const float* const[3], const double*, double,
+                                float*, double*, double*, float*, float*, size_t);
+template int lr_evaluate<double>(void*, hipStream_t, const int[3], const double[3], int, int, bool, const double*,
+                                 const double*, const double* const[3], const double* const[3], const double*, double,
+                                 double*, double*, double*, double*, double*, size_t);
 
 }  // namespace demag

@@ -683,8 +683,9 @@ int setup_lr(demag_plan_s* p, hipStream_t st, double step) {
     alloc((void**)&g->c, R * sizeof(double), "weights");
     alloc((void**)&g->partials, 9 * (size_t)R * sizeof(double), "energy partials");
     for (int q = 0; q < 3; ++q) {
-        alloc(&g->DE[q], (size_t)R * 2 * n[q] * n[q] * sizeof(T), "Gaussian matrices");
-        alloc(&g->DO[q], (size_t)R * 2 * n[q] * n[q] * sizeof(T), "Gaussian matrices");
+        const size_t per = sizeof(T) == 4 ? lr_swizzled_elems(n[q]) : (size_t)2 * n[q] * n[q];
+        alloc(&g->DE[q], (size_t)R * per * sizeof(T), "Gaussian matrices");
+        alloc(&g->DO[q], (size_t)R * per * sizeof(T), "Gaussian matrices");
     }
     if (!rc && (hipMemcpy(g->tau, tau.data(), R * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
                 hipMemcpy(g->c, w.data(), R * sizeof(double), hipMemcpyHostToDevice) != hipSuccess))
@@ -692,7 +693,8 @@ int setup_lr(demag_plan_s* p, hipStream_t st, double step) {
     if (!rc) {
         hipError_t e = hipSuccess;
         for (int q = 0; q < 3 && e == hipSuccess; ++q)
-            e = launch_lr_axis<T>(st, n[q], dt[q], p->d[q], R, g->tau, (T*)g->DE[q], (T*)g->DO[q]);
+            e = sizeof(T) == 4 ? launch_lr_axis_sw(st, n[q], dt[q], R, g->tau, (float*)g->DE[q], (float*)g->DO[q])
+                               : launch_lr_axis<T>(st, n[q], dt[q], p->d[q], R, g->tau, (T*)g->DE[q], (T*)g->DO[q]);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = hip_fail(e, "low-rank tensor-grid setup");
     }
@@ -1347,12 +1349,12 @@ int demag_tg_lowrank_field(demag_plan_t p, int format, int rank, const void* cor
     if (p->dtype == DEMAG_F32) {
         const float* DE[3] = {(const float*)g->DE[0], (const float*)g->DE[1], (const float*)g->DE[2]};
         const float* DO[3] = {(const float*)g->DO[0], (const float*)g->DO[1], (const float*)g->DO[2]};
-        rc = lr_evaluate<float>(g->handle, st, p->n, g->R, rank, tucker, (const float*)core, (const float*)U, DE, DO,
+        rc = lr_evaluate<float>(g->handle, st, p->n, p->d, g->R, rank, tucker, (const float*)core, (const float*)U, DE, DO,
                                 g->c, Ms * hmax, (float*)FG, parts, g->gram, (float*)H, (float*)g->W, w_elems);
     } else {
         const double* DE[3] = {(const double*)g->DE[0], (const double*)g->DE[1], (const double*)g->DE[2]};
         const double* DO[3] = {(const double*)g->DO[0], (const double*)g->DO[1], (const double*)g->DO[2]};
-        rc = lr_evaluate<double>(g->handle, st, p->n, g->R, rank, tucker, (const double*)core, (const double*)U, DE,
+        rc = lr_evaluate<double>(g->handle, st, p->n, p->d, g->R, rank, tucker, (const double*)core, (const double*)U, DE,
                                  DO, g->c, Ms * hmax, (double*)FG, parts, g->gram, (double*)H, (double*)g->W,
                                  w_elems);
     }
