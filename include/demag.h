@@ -109,7 +109,8 @@ int demag_energy_async(demag_plan_t plan, const void* m, double Ms, double* E_de
 
 /* Copy the stored tensor spectrum (plan precision) to HOST memory `out`,
  * layout [Py/2+1][6][Kx][Pz/2+1], components xx yy zz xy xz yz, with the
- * factor -1/(Px Py Pz) folded in.  Synchronous. */
+ * factor -1/(Px Py Pz) folded in (device storage keeps the six components of
+ * a frequency side by side; the copy reorders).  Synchronous. */
 int demag_plan_spectrum(demag_plan_t plan, void* out);
 
 /* Recompute the FP64 real-space tensor octant N(o), o in [0,n), to HOST

@@ -125,7 +125,7 @@ hipError_t launch_tensor_embed(hipStream_t, int comp, int nx, int ny, int nz, in
                                const double* Noct, double* A);
 // Take the real part of the FFT'd component (B2 [Py][Kx][Pz], complex FP64)
 // on the octant ky <= Ly, kz <= Lz, scale, cast to T into
-// nhat [Ly+1][6][Kx][Lz+1].
+// nhat [Ly+1][Kx][Lz+1][6] (the six components of a frequency side by side).
 template <typename T>
 hipError_t launch_tensor_extract(hipStream_t, int comp, int Px, int Py, int Pz, int Kx, double scale,
                                  const cx<double>* B2, T* nhat);

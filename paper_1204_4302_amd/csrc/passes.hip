@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_y_fwd(const cx<T>* __restrict__
 // A workgroup takes ky' and its mirror Py - ky' together, so each tensor value
 // is read once.  Mirroring ky (kz) flips the sign of the components odd in y
 // (z): xy, yz (xz, yz).
-// grid (ceil(Kx/Tx), Ly + 1); B2 [3][Py][Kx][nz]; nhat [Ly+1][6][Kx][Lz+1].
+// grid (ceil(Kx/Tx), Ly + 1); B2 [3][Py][Kx][nz]; nhat [Ly+1][Kx][Lz+1][6].
 template <typename T, int E>
 __global__ void __launch_bounds__(kMaxThreads) k_z_conv(cx<T>* __restrict__ B2, const T* __restrict__ nhat, T Ms,
                                                       int nz, int Py, int Kx, int Tx, FftPlanDev pl,
@@ -141,17 +141,16 @@ __global__ void __launch_bounds__(kMaxThreads) k_z_conv(cx<T>* __restrict__ B2, 
     }
     __syncthreads();
     fft_lds<-1, E>(buf, B, P, pl, tw);
-    const size_t cs = (size_t)Kx * (Lz + 1);  // component stride in nhat
-    const T* nh0 = nhat + (size_t)kyp * 6 * cs;
+    const T* nh0 = nhat + (size_t)kyp * Kx * (Lz + 1) * 6;
     for (int e = tid; e < ns * tx * P; e += nthr) {
         int kz = e % P, r = e / P;
         int xi = r % tx, s = r / tx;
         int kzp = kz <= Lz ? kz : P - kz;
         T sz = kz > Lz ? T(-1) : T(1);
         T sy = s ? T(-1) : T(1);
-        const T* nh = nh0 + (size_t)(kx0 + xi) * (Lz + 1) + kzp;
-        T nxx = nh[0], nyy = nh[cs], nzz = nh[2 * cs];
-        T nxy = sy * nh[3 * cs], nxz = sz * nh[4 * cs], nyz = sy * sz * nh[5 * cs];
+        const T* nh = nh0 + ((size_t)(kx0 + xi) * (Lz + 1) + kzp) * 6;
+        T nxx = nh[0], nyy = nh[1], nzz = nh[2];
+        T nxy = sy * nh[3], nxz = sz * nh[4], nyz = sy * sz * nh[5];
         cx<T>* px = buf + ((s * 3 + 0) * tx + xi) * P + kz;
         cx<T>* py = buf + ((s * 3 + 1) * tx + xi) * P + kz;
         cx<T>* pz = buf + ((s * 3 + 2) * tx + xi) * P + kz;

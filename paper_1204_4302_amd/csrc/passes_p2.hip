@@ -174,6 +174,29 @@ __device__ __forceinline__ void bst(Buf b, unsigned off, cx<T> c) {
         __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), b.r, off, 0, 0);
     }
 }
+// The six tensor components of one frequency (stored side by side): FP32 as
+// three 2-dword loads, FP64 as three 4-dword loads (natural alignment: the
+// frequency stride is 24 resp. 48 bytes).
+template <typename T>
+__device__ __forceinline__ void bld6(Buf b, unsigned off, T* o) {
+    if constexpr (sizeof(T) == 4) {
+        typedef float f2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const f2 v = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(b.r, off + 8 * i, 0, 0));
+            o[2 * i] = (T)v.x;
+            o[2 * i + 1] = (T)v.y;
+        }
+    } else {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const d2 v = __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(b.r, off + 16 * i, 0, 0));
+            o[2 * i] = (T)v.x;
+            o[2 * i + 1] = (T)v.y;
+        }
+    }
+}
 // byte offset `base + d` of a lane's element, or an out-of-range offset when
 // the element is not valid (d is a compile-time constant after unrolling)
 __device__ __forceinline__ unsigned boff(bool valid, unsigned base, unsigned d) {
@@ -540,9 +563,10 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     // Tensor values of this thread's frequencies kz (forward output slots);
     // octant index kz' = kz for kz <= Lz, else P - kz; lanes outside the tile
     // read row 0 (their results are never stored).
-    const size_t cs = (size_t)Kx * (Lz + 1);  // component stride of the octant (elements)
-    const Buf bt = make_buf(nhat, (size_t)(Ly + 1) * 6 * cs * RB);
-    const unsigned trow = ok ? (unsigned)((((size_t)kyp * 6 * Kx + kx0 + xi) * (Lz + 1)) * RB) : 0u;
+    // octant [Ly+1][Kx][Lz+1][6]: the six components of a frequency side by side
+    constexpr unsigned FB = 6 * RB;  // bytes per frequency
+    const Buf bt = make_buf(nhat, (size_t)(Ly + 1) * Kx * (Lz + 1) * FB);
+    const unsigned trow = ok ? (unsigned)((((size_t)kyp * Kx + kx0 + xi) * (Lz + 1)) * FB) : 0u;
     T nt[LT::EPT][6];
     auto load_tensor = [&]() {
 #pragma unroll
@@ -551,13 +575,12 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
             if constexpr (kPow2) {
                 // kz = t + k TP; for k >= EPT/2, P - kz = (TP - 1 - t) + P - (k + 1) TP + 1
                 const int k = LT::F::slot_out(j);
-                off = k < LT::EPT / 2 ? trow + (t + k * LT::TP) * RB : trow + ((LT::TP - 1 - t) + P - (k + 1) * LT::TP + 1) * RB;
+                off = k < LT::EPT / 2 ? trow + (t + k * LT::TP) * FB : trow + ((LT::TP - 1 - t) + P - (k + 1) * LT::TP + 1) * FB;
             } else {
                 const int kz = LT::fout(t, j);
-                off = trow + (kz <= Lz ? kz : P - kz) * RB;
+                off = trow + (kz <= Lz ? kz : P - kz) * FB;
             }
-#pragma unroll
-            for (int q = 0; q < 6; ++q) nt[j][q] = bldr<T>(bt, off, (unsigned)(q * cs * RB));
+            bld6<T>(bt, off, nt[j]);
         }
     };
     if constexpr (kKeep) load_tensor();

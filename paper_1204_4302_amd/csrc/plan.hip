@@ -1127,7 +1127,18 @@ int demag_energy(demag_plan_t p, const void* m, double Ms, double* E_host, void*
 int demag_plan_spectrum(demag_plan_t p, void* out) {
     if (!p || !out) return fail(DEMAG_EINVAL, "NULL argument");
     HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(out, p->nhat, p->tensor_bytes, hipMemcpyDeviceToHost));
+    std::vector<unsigned char> dev(p->tensor_bytes);
+    HIP_TRY(hipMemcpy(dev.data(), p->nhat, p->tensor_bytes, hipMemcpyDeviceToHost));
+    // device [Ly+1][Kx][Lz+1][6] -> documented [Ly+1][6][Kx][Lz+1]
+    const size_t rb = p->dtype == DEMAG_F32 ? 4 : 8;
+    const size_t Ly1 = p->P[1] / 2 + 1, Kx = p->Kx, Lz1 = p->P[2] / 2 + 1;
+    unsigned char* o = (unsigned char*)out;
+    for (size_t ky = 0; ky < Ly1; ++ky)
+        for (size_t kx = 0; kx < Kx; ++kx)
+            for (size_t kz = 0; kz < Lz1; ++kz)
+                for (size_t c = 0; c < 6; ++c)
+                    std::memcpy(o + (((ky * 6 + c) * Kx + kx) * Lz1 + kz) * rb,
+                                dev.data() + (((ky * Kx + kx) * Lz1 + kz) * 6 + c) * rb, rb);
     return DEMAG_OK;
 }
 

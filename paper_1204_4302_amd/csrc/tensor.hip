@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(256) k_tensor_extract(int comp, int Py, int Pz
     const int Lx = Kx - 1;
     const bool oddx = comp == 3 || comp == 4, oddy = comp == 3 || comp == 5, oddz = comp == 4 || comp == 5;
     if ((oddx && kx == Lx) || (oddy && ky == Ly) || (oddz && kz == Lz)) v = 0.0;
-    nhat[(((size_t)ky * 6 + comp) * Kx + kx) * (Lz + 1) + kz] = (T)v;
+    nhat[(((size_t)ky * Kx + kx) * (Lz + 1) + kz) * 6 + comp] = (T)v;  // [Ly+1][Kx][Lz+1][6]
 }
 
 }  // namespace
