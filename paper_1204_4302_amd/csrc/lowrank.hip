@@ -16,9 +16,14 @@
 // potential is again a block-CP tensor whose factors cost R n_q^2 r each, and
 // no dense tensor is formed.  A difference operator along axis a acts on the
 // mode-a factor only, so the field component H_a = -d_a Phi is the same sum
-// with F_a replaced by G_a^{pl} = -delta_a F_a^{pl}; the difference matrices
-// are folded into the Gaussian matrices at set-up ([D; -delta D] stacked), so
-// one GEMM per (axis, component) gives both factors for all nodes.
+// with F_a replaced by G_a^{pl} = -delta_a F_a^{pl}.
+//
+// The factor product is a dense contraction: in FP32 it runs on MFMA
+// (v_mfma_f32_16x16x4f32) over Gaussian matrices stored in the instruction's
+// operand order, one launch for all axes, nodes and components, and the field
+// factors follow from a small difference kernel; in FP64 the difference rows
+// are folded into the matrices at set-up ([D; -delta D] stacked) and a VALU
+// kernel produces both factors from one pass over the matrices.
 //
 // The energy -mu0/2 Ms V sum_a <M_a, H_a> is a sum of inner products of
 // Tucker (CP) tensors, taken on the factors: with the r x r Gram matrices
