@@ -100,3 +100,50 @@ def test_cube_vortex_tucker_rank10():
     assert Edm == pytest.approx(2.189e-2, abs=0.0005e-2)
     assert E == pytest.approx(2.193e-2, abs=0.0005e-2)
     assert 4.0e-3 / 2 < h_err < 4.0e-3 * 2
+
+
+THIN = (80, 80, 8)
+THIN_CELL = (1 / 80, 1 / 80, 0.1 / 8)
+
+
+def _thin(fmt, core, factors, m):
+    from paper_1204_4302_amd import Plan
+    lr = Plan(THIN, THIN_CELL, torch.float64)
+    lr.tg_lowrank_prepare()
+    _, H, E = lr.tg_lowrank_field(fmt, core, factors, 1.0)
+    dm = Plan(THIN, THIN_CELL, torch.float64)
+    Hdm, Edm = dm.field_energy(_gpu(m), 1.0)
+    h_err = float(np.sqrt(((H - Hdm) ** 2).sum().item() / np.prod(THIN)))
+    return float(E) / MU0, float(Edm) / MU0, h_err  # energies in mu0 Ms^2 L^3, L = 1
+
+
+def test_thin_film_homogeneous_cp_rank1():
+    """Table thin_homo (1 x 1 x 0.1 film, 80 x 80 x 8, out of plane): TG
+    (CP r = 1) e printed as 4.025e-2 (DM 4.025e-2), field error 3.7e-3."""
+    m = inputs.uniform(THIN, (0, 0, 1))
+    core = np.zeros((3, 1))
+    core[2, 0] = 1.0
+    factors = [np.ones((3, 1, n)) for n in THIN]
+    E, Edm, h_err = _thin(1, _gpu(core), [_gpu(f) for f in factors], m)
+    print(f"thin_homo TG CP1: e {E:.4e} (paper 4.025e-2, DM {Edm:.4e}), relerr h {h_err:.2e} (paper 3.7e-3)")
+    assert Edm == pytest.approx(4.025e-2, abs=0.0005e-2)
+    assert E == pytest.approx(4.025e-2, abs=0.0005e-2)
+    assert 3.7e-3 / 2 < h_err < 3.7e-3 * 2
+
+
+def test_thin_film_vortex_tucker():
+    """Table thin_vortex: the vortex of eq. (config1) (r_c = 0.14) in the thin
+    film; TG e printed as 1.569e-3 (DM 1.569e-3), field error 2.9e-3.  The
+    table's "CP r = 1" cannot hold a vortex (not a separable state); a Tucker
+    rank 8 compression is used instead."""
+    from paper_1204_4302_amd import Plan
+    m = inputs.paper_vortex(THIN, THIN_CELL, rc=0.14)
+    plan = Plan(THIN, THIN_CELL, torch.float64)
+    _, init = inputs.lowrank(THIN, 0, 8, seed=81)
+    core, factors, relerr = plan.lowrank_compress(_gpu(m), 0, 8, 12, [_gpu(f) for f in init])
+    E, Edm, h_err = _thin(0, core, factors, m)
+    print(f"thin_vortex TG Tucker8: compression relerr {relerr:.2e}, e {E:.4e} (paper 1.569e-3, DM {Edm:.4e}), "
+          f"relerr h {h_err:.2e} (paper 2.9e-3)")
+    assert Edm == pytest.approx(1.569e-3, abs=0.0005e-3)
+    assert E == pytest.approx(1.569e-3, abs=0.0005e-3)
+    assert 2.9e-3 / 2 < h_err < 2.9e-3 * 2
