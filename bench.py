@@ -458,6 +458,11 @@ def bench(args):
                    "launch_shapes": "autotuned" if r32["tune_s"] is not None else "default",
                    "autotune_s": None if r32["tune_s"] is None else round(r32["tune_s"], 2)},
         "roofline": roofline,
+        # once per plan, not in the timed region: Newell tensor on the octant
+        # (FP64, three distance bands) and its spectrum (FP64 FFTs), stored in
+        # the plan precision
+        "setup": {"tensor_setup_ms": round(info["setup_us"] / 1e3, 2), "tensor_bytes": info["tensor_bytes"],
+                  "scratch_bytes": info["scratch_bytes"]},
     }
     if torch.float64 in results:
         r64 = results[torch.float64]
