@@ -62,7 +62,12 @@ typedef enum {
  * (Sec. 4: the constants depend on the geometry only and are computed once).
  * Runs on `setup_stream` and synchronises it.  Padded length per axis:
  * 2L, L the smallest 2^a 3^b 5^c >= n; 2L <= 4096 per axis, else
- * DEMAG_EUNSUPPORTED.  *out receives the plan (caller destroys it once). */
+ * DEMAG_EUNSUPPORTED.  Along z the fused Z pass holds a pencil and its mirror
+ * in one workgroup: powers of two up to 2048 (and 3 * 2^a up to 3072 in FP32)
+ * on the register kernels, other lengths when six pencils fit 64 KB (up to
+ * 1365 in FP32, 682 in FP64); longer z lengths are DEMAG_EUNSUPPORTED (put the
+ * longest axis along x or y).  *out receives the plan (caller destroys it
+ * once). */
 int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, double dy, double dz,
                       demag_dtype dtype, void* setup_stream);
 
@@ -75,7 +80,8 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
  *  "generic_kernels": 1 runs every pass on the generic (any-length)
  *             kernels, 0 (default) uses the compile-time power-of-two kernels
  *             on the axes whose padded length allows them; resets the launch
- *             shapes to their defaults.
+ *             shapes to their defaults.  DEMAG_EUNSUPPORTED (plan unchanged)
+ *             when the generic Z pass cannot hold the padded z length.
  *  "pass_timing": K > 0 records HIP events around every pass of the next
  *             evaluations on their own stream (a ring of K evaluations; 0 turns
  *             it off); read the averages with demag_plan_pass_times.

@@ -985,6 +985,21 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
     const size_t nB1 = 3ull * nz * Kx * ny, nB2 = 3ull * P[1] * Kx * nz;
     const size_t nH = (size_t)(P[1] / 2 + 1) * 6 * Kx * (P[2] / 2 + 1);
     p->cfg = default_cfgs(p);
+    if (!one_cfg_ok(p->cfg.zc, P[2], cb, 2)) {
+        // the register Z kernel holds a pencil and its mirror in one workgroup
+        // (2 P / 8 threads <= 512, i.e. P <= 2048, or 3 * 2^a in FP32); the LDS
+        // kernel holds six pencils (6 P complex values <= 64 KB)
+        const LaunchCfg g = cfg_zconv(P[2], Kx, cb);
+        if (!one_cfg_ok(g, P[2], cb, 2)) {
+            const int pz = P[2];
+            free_plan(p);
+            return fail(DEMAG_EUNSUPPORTED,
+                        "z axis: no fused Z pass for padded length %d in %s (register kernel: powers of two up to "
+                        "2048, and 3 * 2^a in FP32; LDS kernel: 6 P complex values within 64 KB)",
+                        pz, dtype == DEMAG_F32 ? "FP32" : "FP64");
+        }
+        p->cfg.zc = g;
+    }
     int rc = DEMAG_OK;
     auto alloc = [&](void** ptr, size_t bytes, const char* what) {
         if (rc) return;
@@ -1035,8 +1050,16 @@ int demag_plan_set_option(demag_plan_t p, const char* key, double value) {
         b.fg_cut = (int)value;
     } else if (!strcmp(key, "generic_kernels")) {
         if (value != 0 && value != 1) return fail(DEMAG_EINVAL, "generic_kernels must be 0 or 1");
+        const size_t cb = csize(p->dtype);
+        PassCfgs c = value == 1 ? generic_cfgs(p) : default_cfgs(p);
+        if (!one_cfg_ok(c.zc, p->P[2], cb, 2)) {
+            if (value == 1)
+                return fail(DEMAG_EUNSUPPORTED, "generic kernels: padded z length %d needs more than 64 KB of LDS",
+                            p->P[2]);
+            c.zc = cfg_zconv(p->P[2], p->Kx, cb);  // as at plan creation, where this fallback was verified
+        }
         HIP_TRY(hipDeviceSynchronize());
-        p->cfg = value == 1 ? generic_cfgs(p) : default_cfgs(p);
+        p->cfg = c;
         return DEMAG_OK;
     } else if (!strcmp(key, "pass_timing")) {
         if (!(value >= 0) || value != std::floor(value) || value > 1e6)
@@ -1157,7 +1180,8 @@ int demag_sp_prepare(demag_plan_t p, void* stream) {
     if (!p) return fail(DEMAG_EINVAL, "NULL plan");
     if (p->shat) return DEMAG_OK;
     const size_t cb = csize(p->dtype), rb = cb / 2;
-    if (!p2_z_supported(p->P[2], cb) || !p2_z_ranges_ok(p))
+    const LaunchCfg zs = p->cfg.zc.p2 ? p->cfg.zc : p2_zconv(p->P[2], p->Kx, cb);
+    if (!p2_z_supported(p->P[2], cb) || !p2_z_ranges_ok(p) || !p2_cfg_ok(zs, p->P[2], cb, 2))
         return fail(DEMAG_EUNSUPPORTED, "scalar-potential method: padded z length %d not supported in %s", p->P[2],
                     p->dtype == DEMAG_F32 ? "FP32" : "FP64");
     hipStream_t st = (hipStream_t)stream;
@@ -1175,7 +1199,7 @@ int demag_sp_prepare(demag_plan_t p, void* stream) {
         p->shat = nullptr;
         return rc;
     }
-    p->zs = p->cfg.zc.p2 ? p->cfg.zc : p2_zconv(p->P[2], p->Kx, cb);
+    p->zs = zs;
     return leave(p, st);
 }
 

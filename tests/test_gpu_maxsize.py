@@ -1,0 +1,62 @@
+"""The largest padded lengths the library takes: 2L = 4096 along x and y (the
+X and Y passes hold one pencil per thread group); along z the fused pass
+holds a pencil and its mirror in one workgroup, so the register kernel takes
+powers of two up to 2048 (and 3 * 2^a up to 3072 in FP32) and the LDS kernel
+lengths whose six pencils fit 64 KB; longer z lengths are refused at plan
+creation.  Each case is a thin grid so that the oracle's direct sum stays
+small: the whole field against the oracle, FP64 and FP32, forward and
+adjoint."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1204_4302_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
+CELL = (2e-9, 2e-9, 3e-9)
+RUNS = [((2048, 2, 2), None), ((2, 2048, 2), None), ((1536, 3, 2), None), ((2, 2, 1024), None),
+        ((3, 2, 1536), torch.float32), ((2, 2, 320), torch.float64)]
+
+
+@pytest.mark.parametrize("shape,only", RUNS, ids=lambda v: str(v))
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_max_padded_length(shape, only, dtype):
+    from paper_1204_4302_amd import Plan
+    if only is not None and dtype != only:
+        pytest.skip("length taken in the other precision only")
+    plan = Plan(shape, CELL, dtype)
+    info = plan.info()
+    m = inputs.random_unit(shape, 11)
+    mq = m.astype(np.float32).astype(np.float64) if dtype == torch.float32 else m
+    mg = torch.from_numpy(np.ascontiguousarray(m)).to("cuda", dtype)
+    H = plan.field(mg, 8e5).double().cpu().numpy()
+    gm = plan.adjoint(mg, 8e5).double().cpu().numpy()
+    o = oracle.Oracle(shape, CELL)
+    ref = o.field(mq, 8e5)
+    err = float(np.abs(H - ref).max() / np.abs(ref).max())
+    errT = float(np.abs(gm - ref).max() / np.abs(ref).max())  # A = A^T: the adjoint of m is the field of m
+    print(f"{shape} {dtype}: padded {info['Px']}x{info['Py']}x{info['Pz']}, field {err:.2e}, adjoint {errT:.2e}")
+    assert err <= TOL[dtype] and errT <= TOL[dtype]
+
+
+@pytest.mark.parametrize("shape,dtype", [((2, 2, 2048), torch.float32), ((2, 2, 2048), torch.float64),
+                                         ((3, 2, 1536), torch.float64), ((2, 2, 341), torch.float64)],
+                         ids=lambda v: str(v))
+def test_z_lengths_without_a_fused_pass_are_refused(shape, dtype):
+    """Refused at plan creation (a host-side check; nothing is launched)."""
+    from paper_1204_4302_amd import Plan
+    from paper_1204_4302_amd._lib import DemagError
+    with pytest.raises(DemagError, match="EUNSUPPORTED"):
+        Plan(shape, CELL, dtype)
+
+
+def test_generic_kernels_refused_where_their_z_pass_does_not_fit():
+    from paper_1204_4302_amd import Plan
+    from paper_1204_4302_amd._lib import DemagError
+    plan = Plan((2, 2, 1024), CELL, torch.float64)  # padded z 2048: register kernel only
+    with pytest.raises(DemagError, match="EUNSUPPORTED"):
+        plan.set_option("generic_kernels", 1)
+    plan.set_option("generic_kernels", 0)
