@@ -120,6 +120,7 @@ def bench_sp(args, torch, np, m_np, dm_value):
     e_sp = float(e_sp.cpu())
     out = {"value": round(k / secs, 2), "unit": "evals/s", "ms_per_eval": round(1e3 * secs / k, 4),
            "modelled_bytes_per_eval": nbytes, "achieved_GBs": round(nbytes * k / secs / 1e9, 1),
+           "roofline": hbm_roofline(nbytes * k, secs, "whole SP evaluation (all six kernels)"),
            "bytes_per_kernel": pb, "speedup_over_dm": round(k / secs / dm_value, 3),
            "vortex_energy_rel_diff_vs_dm": abs(e_sp - e_dm) / abs(e_dm),
            "step": "one SP field evaluation with energy (potential by FFT convolution, finite-difference gradient)"}
@@ -151,6 +152,7 @@ def bench_llg(args, torch, np, dm_value):
     nbytes = 2 * field + 4 * vec + 5 * vec  # two fields, predictor (m, H -> k1, m*), corrector (m, H, k1, m* -> m)
     out = {"value": round(k / secs, 2), "unit": "Heun steps/s", "ms_per_step": round(1e3 * secs / k, 4),
            "modelled_bytes_per_step": nbytes, "achieved_GBs": round(nbytes * k / secs / 1e9, 1),
+           "roofline": hbm_roofline(nbytes * k, secs, "whole Heun step (two field evaluations, two update kernels)"),
            "field_evals_per_s": round(2 * k / secs, 1),
            "step": "one explicit Heun step of the LLG equation (alpha 0.5, dt 1e-13 s, H_ext 5e4 A/m along z, "
                    "Gaussian vortex start), demag field by DM"}
@@ -241,6 +243,8 @@ def bench_lowrank(args, torch, np, dm_value):
             "value": round(k / sc, 1), "unit": "evals/s", "ms_per_eval": round(1e3 * sc / k, 4),
             "speedup_over_dm": round(k / sc / dm_value, 2),
             "modelled_bytes_per_eval": nbytes, "achieved_GBs": round(nbytes * k / sc / 1e9, 1),
+            "roofline": hbm_roofline(nbytes * k, sc, "whole compressed evaluation (factors, differences, "
+                                                     "Gram matrices, contraction, sum)"),
             "magnetization_values": stored, "dense_values": 3 * n1 * n2 * n3,
             "with_dense_field": {"value": round(kd / sd, 2), "unit": "evals/s", "ms_per_eval": round(1e3 * sd / kd, 3),
                                  "expansion_gemm_flops": 2 * 3 * n1 * n2 * n3 * 3 * R * rank},
@@ -261,6 +265,14 @@ def bench_lowrank(args, torch, np, dm_value):
                            "sweeps": sweeps, "seconds": round(secs, 4), "relerr": relerr}
     plan.close()
     return out
+
+
+def hbm_roofline(nbytes, seconds, what):
+    """HBM roofline of a leg measured as a whole (modelled bytes over the
+    measured time of the leg's step, every kernel of the step included)."""
+    achieved = nbytes / seconds / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "over": what}
 
 
 def read_traffic():
@@ -365,6 +377,7 @@ def bench_batch(args, torch, np):
            "graph_batches_per_s": round(k / t_graph, 2), "graph_grid_evals_per_s": round(96 * k / t_graph, 1),
            "sequential_batches_per_s": round(k / t_seq, 2), "speedup_graph_over_sequential": round(t_seq / t_graph, 3),
            "modelled_bytes_per_batch": nbytes, "graph_achieved_GBs": round(nbytes * k / t_graph / 1e9, 1),
+           "roofline": hbm_roofline(nbytes * k, t_graph, "whole batch replay (96 grids, five passes each)"),
            "launch_shapes": "autotuned per group" if tune_s is not None else "default", "autotune_s": tune_s}
     batch.close()
     for p in plans:
