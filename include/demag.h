@@ -64,9 +64,9 @@ typedef enum {
  * 2L, L the smallest 2^a 3^b 5^c >= n; 2L <= 4096 per axis, else
  * DEMAG_EUNSUPPORTED.  Along z the fused Z pass holds a pencil and its mirror
  * in one workgroup: powers of two up to 2048 (and 3 * 2^a up to 3072 in FP32)
- * on the register kernels, other lengths when six pencils fit 64 KB (up to
- * 1365 in FP32, 682 in FP64); longer z lengths are DEMAG_EUNSUPPORTED (put the
- * longest axis along x or y).  *out receives the plan (caller destroys it
+ * on the register kernels, other lengths up to 1365 (six pencils in one
+ * workgroup); longer z lengths are DEMAG_EUNSUPPORTED (put the longest axis
+ * along x or y).  *out receives the plan (caller destroys it
  * once). */
 int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, double dy, double dz,
                       demag_dtype dtype, void* setup_stream);

@@ -331,7 +331,14 @@ hipError_t launch_z_conv(const LaunchCfg& lc, hipStream_t st, cx<T>* B2, const T
                          const FftPlanDev& pl, const cx<T>* tw, const BatchIO& bio) {
     dim3 grid((Kx + lc.t0 - 1) / lc.t0, Py / 2 + 1, bio.count);
     size_t lds = (size_t)6 * lc.t0 * pl.P * sizeof(cx<T>);
-#define CALL(EE) hipLaunchKernelGGL((k_z_conv<T, EE>), grid, dim3(lc.threads), lds, st, B2, nhat, Ms, nz, Py, Kx, lc.t0, pl, tw, bio)
+    // dynamic LDS above 64 KB must be allowed per kernel before its launch
+#define CALL(EE)                                                                                                   \
+    if (lds > 65536) {                                                                                             \
+        hipError_t e_ = hipFuncSetAttribute((const void*)&k_z_conv<T, EE>,                                         \
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                 \
+        if (e_ != hipSuccess) return e_;                                                                           \
+    }                                                                                                              \
+    hipLaunchKernelGGL((k_z_conv<T, EE>), grid, dim3(lc.threads), lds, st, B2, nhat, Ms, nz, Py, Kx, lc.t0, pl, tw, bio)
     DEMAG_E_SWITCH(lc.E, CALL)
 #undef CALL
     return hipGetLastError();

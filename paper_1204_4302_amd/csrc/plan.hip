@@ -358,7 +358,11 @@ bool one_cfg_ok(const LaunchCfg& c, int P, size_t cb, int kind) {
     if (c.p2) return p2_cfg_ok(c, P, cb, kind);
     if (kind == 0) return cfg_ok(c, (c.t0 + 1) / 2, P, cb) && c.t0 % 2 == 0;
     if (kind == 1) return cfg_ok(c, (long)c.t0 * c.t1, P, cb);
-    return cfg_ok(c, 6L * c.t0, P, cb);
+    // the generic fused Z pass may use the whole LDS of a workgroup (its
+    // launcher raises the per-kernel limit): six pencils of the tile
+    const long pencils = 6L * c.t0;
+    return c.E > 0 && c.threads > 0 && c.threads <= kMaxThreads && c.threads % 64 == 0 &&
+           (long)c.threads * c.E >= pencils * P && (size_t)pencils * P * cb <= g_p2_lds;
 }
 
 bool plan_cfgs_ok(const demag_plan_s* p, const PassCfgs& c) {
@@ -988,14 +992,14 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
     if (!one_cfg_ok(p->cfg.zc, P[2], cb, 2)) {
         // the register Z kernel holds a pencil and its mirror in one workgroup
         // (2 P / 8 threads <= 512, i.e. P <= 2048, or 3 * 2^a in FP32); the LDS
-        // kernel holds six pencils (6 P complex values <= 64 KB)
+        // kernel holds six pencils (6 P complex values within a workgroup's LDS)
         const LaunchCfg g = cfg_zconv(P[2], Kx, cb);
         if (!one_cfg_ok(g, P[2], cb, 2)) {
             const int pz = P[2];
             free_plan(p);
             return fail(DEMAG_EUNSUPPORTED,
                         "z axis: no fused Z pass for padded length %d in %s (register kernel: powers of two up to "
-                        "2048, and 3 * 2^a in FP32; LDS kernel: 6 P complex values within 64 KB)",
+                        "2048, and 3 * 2^a in FP32; LDS kernel: 6 P complex values within a workgroup's LDS)",
                         pz, dtype == DEMAG_F32 ? "FP32" : "FP64");
         }
         p->cfg.zc = g;
@@ -1054,7 +1058,7 @@ int demag_plan_set_option(demag_plan_t p, const char* key, double value) {
         PassCfgs c = value == 1 ? generic_cfgs(p) : default_cfgs(p);
         if (!one_cfg_ok(c.zc, p->P[2], cb, 2)) {
             if (value == 1)
-                return fail(DEMAG_EUNSUPPORTED, "generic kernels: padded z length %d needs more than 64 KB of LDS",
+                return fail(DEMAG_EUNSUPPORTED, "generic kernels: padded z length %d needs more LDS than a workgroup has",
                             p->P[2]);
             c.zc = cfg_zconv(p->P[2], p->Kx, cb);  // as at plan creation, where this fallback was verified
         }
