@@ -62,11 +62,11 @@ typedef enum {
  * (Sec. 4: the constants depend on the geometry only and are computed once).
  * Runs on `setup_stream` and synchronises it.  Padded length per axis:
  * 2L, L the smallest 2^a 3^b 5^c >= n; 2L <= 4096 per axis, else
- * DEMAG_EUNSUPPORTED.  Along z the fused Z pass holds a pencil and its mirror
- * in one workgroup: powers of two up to 2048 (and 3 * 2^a up to 3072 in FP32)
- * on the register kernels, other lengths up to 1365 (six pencils in one
- * workgroup); longer z lengths are DEMAG_EUNSUPPORTED (put the longest axis
- * along x or y).  *out receives the plan (caller destroys it
+ * DEMAG_EUNSUPPORTED.  Along z the fused Z pass runs on the register kernels
+ * for powers of two up to 4096 (a pencil and its mirror per workgroup up to
+ * 2048, one pencil per workgroup at 4096) and, in FP32, 3 * 2^a up to 3072;
+ * other lengths up to 1365 (six pencils in one workgroup); longer z lengths
+ * are DEMAG_EUNSUPPORTED (put the longest axis along x or y).  *out receives the plan (caller destroys it
  * once). */
 int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, double dy, double dz,
                       demag_dtype dtype, void* setup_stream);

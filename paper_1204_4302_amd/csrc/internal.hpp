@@ -99,14 +99,16 @@ template <typename T>
 hipError_t launch_y_inv_p2(int lgTz, int lgTx, hipStream_t, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
                            int C, int P, const cx<T>* twt, const BatchIO& bio = BatchIO());
 template <typename T>
-hipError_t launch_z_conv_p2(int lgTx, hipStream_t, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx, int P,
-                            const cx<T>* twt, const BatchIO& bio = BatchIO());
+// rows: 2 = a row ky' and its mirror Py - ky' per workgroup (the default),
+// 1 = one row per workgroup (lengths whose pair exceeds kP2MaxThreadsZ)
+hipError_t launch_z_conv_p2(int lgTx, int rows, hipStream_t, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx,
+                            int P, const cx<T>* twt, const BatchIO& bio = BatchIO());
 
 // scalar-potential method: fused Z pass (3 components in, Ms phi out in
 // component 0 of B2), register-kernel lengths only
 template <typename T>
-hipError_t launch_z_sp_p2(int lgTx, hipStream_t, cx<T>* B2, const T* shat, T Ms, int nz, int Py, int Kx, int P,
-                          const cx<T>* twt);
+hipError_t launch_z_sp_p2(int lgTx, int rows, hipStream_t, cx<T>* B2, const T* shat, T Ms, int nz, int Py, int Kx,
+                          int P, const cx<T>* twt);
 
 // ---- tensor setup (FP64) ----------------------------------------------------
 struct TensorBands {

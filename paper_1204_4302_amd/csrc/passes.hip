@@ -279,19 +279,33 @@ __global__ void __launch_bounds__(kMaxThreads) k_x_inv(const cx<T>* __restrict__
     }
 }
 
-// Deterministic FP64 sum of the partials (fixed order), scaled.
-__global__ void __launch_bounds__(256) k_energy_reduce(const double* __restrict__ partials, int n, double scale,
-                                                       double* __restrict__ out) {
-    __shared__ double red[256];
+// Deterministic FP64 sum of the partials (fixed order), scaled.  Thread i
+// sums partials i, i + 1024, ... in that order; each iteration issues its
+// four loads before the first add, so the latency of a few thousand partials
+// is paid about once rather than once per element.
+constexpr int kReduceThreads = 1024;
+__global__ void __launch_bounds__(kReduceThreads) k_energy_reduce(const double* __restrict__ partials, int n,
+                                                                  double scale, double* __restrict__ out) {
+    __shared__ double red[kReduceThreads];
+    const int tid = threadIdx.x;
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) s += partials[i];
-    red[threadIdx.x] = s;
+    for (int base = 0; base < n; base += 4 * kReduceThreads) {
+        double a[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * kReduceThreads + tid;
+            a[u] = i < n ? partials[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += a[u];
+    }
+    red[tid] = s;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    for (int w = kReduceThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = scale * red[0];
+    if (tid == 0) out[0] = scale * red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -380,7 +394,7 @@ hipError_t launch_x_inv(const LaunchCfg& lc, hipStream_t st, const cx<T>* in, T*
 }
 
 hipError_t launch_energy_reduce(hipStream_t st, const double* partials, int n, double scale, double* out) {
-    hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, st, partials, n, scale, out);
+    hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(kReduceThreads), 0, st, partials, n, scale, out);
     return hipGetLastError();
 }
 

@@ -505,7 +505,10 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) ky_inv(const cx<T>* __res
 // at (kx0 + xi, ky_s), ky_0 = ky', ky_1 = Py - ky'; each thread keeps all
 // three components in registers, so the tensor product needs no exchange and
 // the forward output slots hand over to the inverse input slots in registers.
-// 1-D grid of ceil(Kx/Tx) * (Py/2 + 1) tiles, block 2 * Tx * TP.
+// Paired form (rows = 2): 1-D grid of ceil(Kx/Tx) * (Py/2 + 1) tiles, block
+// 2 * Tx * TP; a tile's two rows share the tensor octant row ky'.  Split form
+// (rows = 1, for lengths whose pair would exceed the workgroup): one row ky
+// per tile, ceil(Kx/Tx) * Py tiles, block Tx * TP, s = (ky > Py/2).
 // Every B2 and tensor access is a raw buffer access (one resource per B2
 // component, one for the tensor octant with the component in the scalar
 // offset); the host guarantees that each range is below kOob.
@@ -524,8 +527,8 @@ __host__ __device__ constexpr bool z_keep_twiddles() {
 
 template <typename T, int P>
 __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2, const T* __restrict__ nhat, T Ms, int nz,
-                                                int Py, int Kx, int lgTx, int nxcd, const cx<T>* __restrict__ twt,
-                                                BatchIO bio) {
+                                                int Py, int Kx, int lgTx, int rows, int nxcd,
+                                                const cx<T>* __restrict__ twt, BatchIO bio) {
     using LT = p2::Len<P>;
     constexpr bool kPow2 = p2::is_pow2(P);
     constexpr bool kKeep = z_keep_twiddles<T, P>();
@@ -535,16 +538,26 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     const int tid = threadIdx.x;
     const int g = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
     const int Tx = 1 << lgTx, Ly = Py >> 1;
-    const int xi = g & (Tx - 1), s = g >> lgTx;
+    const int xi = g & (Tx - 1);
     const int nxt = (Kx + Tx - 1) >> lgTx;
     int gb;
     const int tile = batch_tile(xcd_tile(nxcd), bio, &gb);
     if (bio.in) B2 = (cx<T>*)bio.out[gb];
-    const int kx0 = (tile % nxt) << lgTx, kyp = tile / nxt;
+    const int kx0 = (tile % nxt) << lgTx;
     const int tx = min(Tx, Kx - kx0);
-    const int ns = (kyp == 0 || kyp == Ly) ? 1 : 2;
-    const bool ok = s < ns && xi < tx;
-    const int ky = s ? Py - kyp : kyp;
+    int s, kyp, ky;
+    bool ok;
+    if (rows == 2) {
+        s = g >> lgTx;
+        kyp = tile / nxt;
+        ok = s < ((kyp == 0 || kyp == Ly) ? 1 : 2) && xi < tx;
+        ky = s ? Py - kyp : kyp;
+    } else {
+        ky = tile / nxt;
+        s = ky > Ly;
+        kyp = s ? Py - ky : ky;
+        ok = xi < tx;
+    }
     const size_t cstride = (size_t)Py * Kx * nz;  // component stride of B2 (elements)
     const Buf bc[3] = {make_buf(B2, cstride * CB), make_buf(B2 + cstride, cstride * CB),
                        make_buf(B2 + 2 * cstride, cstride * CB)};
@@ -646,7 +659,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
 // access and register budget as in kz_conv.
 template <typename T, int P>
 __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, const T* __restrict__ shat, T Ms,
-                                                        int nz, int Py, int Kx, int lgTx, int nxcd,
+                                                        int nz, int Py, int Kx, int lgTx, int rows, int nxcd,
                                                         const cx<T>* __restrict__ twt) {
     using LT = p2::Len<P>;
     constexpr bool kPow2 = p2::is_pow2(P);
@@ -657,14 +670,24 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
     const int tid = threadIdx.x;
     const int g = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
     const int Tx = 1 << lgTx, Ly = Py >> 1;
-    const int xi = g & (Tx - 1), s = g >> lgTx;
+    const int xi = g & (Tx - 1);
     const int nxt = (Kx + Tx - 1) >> lgTx;
     const int tile = xcd_tile(nxcd);
-    const int kx0 = (tile % nxt) << lgTx, kyp = tile / nxt;
+    const int kx0 = (tile % nxt) << lgTx;
     const int tx = min(Tx, Kx - kx0);
-    const int ns = (kyp == 0 || kyp == Ly) ? 1 : 2;
-    const bool ok = s < ns && xi < tx;
-    const int ky = s ? Py - kyp : kyp;
+    int s, kyp, ky;
+    bool ok;
+    if (rows == 2) {
+        s = g >> lgTx;
+        kyp = tile / nxt;
+        ok = s < ((kyp == 0 || kyp == Ly) ? 1 : 2) && xi < tx;
+        ky = s ? Py - kyp : kyp;
+    } else {
+        ky = tile / nxt;
+        s = ky > Ly;
+        kyp = s ? Py - ky : ky;
+        ok = xi < tx;
+    }
     const size_t cstride = (size_t)Py * Kx * nz;
     const Buf bc[3] = {make_buf(B2, cstride * CB), make_buf(B2 + cstride, cstride * CB),
                        make_buf(B2 + 2 * cstride, cstride * CB)};
@@ -879,17 +902,17 @@ hipError_t launch_y_inv_p2(int lgTz, int lgTx, hipStream_t st, const cx<T>* in, 
 }
 
 template <typename T>
-hipError_t launch_z_conv_p2(int lgTx, hipStream_t st, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx, int P,
-                            const cx<T>* twt, const BatchIO& bio) {
+hipError_t launch_z_conv_p2(int lgTx, int rows, hipStream_t st, cx<T>* B2, const T* nhat, T Ms, int nz, int Py,
+                            int Kx, int P, const cx<T>* twt, const BatchIO& bio) {
     if (!twt) return hipErrorInvalidValue;
-    if (!p2_z_supported(P, sizeof(cx<T>))) return hipErrorInvalidValue;
-    const int G = 2 << lgTx;
-    dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * (Py / 2 + 1) * bio.count));
+    if (!p2_z_supported(P, sizeof(cx<T>)) || (rows != 1 && rows != 2)) return hipErrorInvalidValue;
+    const int G = rows << lgTx;
+    dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * (rows == 2 ? Py / 2 + 1 : Py) * bio.count));
     const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
 #define CALL(PP) \
     if (hipError_t e_ = allow_lds(&kz_conv<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((kz_conv<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, kXcds, twt, \
-                       bio)
+    hipLaunchKernelGGL((kz_conv<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, rows, kXcds, \
+                       twt, bio)
     if constexpr (sizeof(T) == 4) {
         DEMAG_P2_SWITCH(P, CALL)
     } else {  // FP64 lengths 3 * 2^a would not fit the registers: generic kernels
@@ -903,16 +926,16 @@ hipError_t launch_z_conv_p2(int lgTx, hipStream_t st, cx<T>* B2, const T* nhat, 
 }
 
 template <typename T>
-hipError_t launch_z_sp_p2(int lgTx, hipStream_t st, cx<T>* B2, const T* shat, T Ms, int nz, int Py, int Kx, int P,
-                          const cx<T>* twt) {
+hipError_t launch_z_sp_p2(int lgTx, int rows, hipStream_t st, cx<T>* B2, const T* shat, T Ms, int nz, int Py,
+                          int Kx, int P, const cx<T>* twt) {
     if (!twt) return hipErrorInvalidValue;
-    if (!p2_z_supported(P, sizeof(cx<T>))) return hipErrorInvalidValue;
-    const int G = 2 << lgTx;
-    dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * (Py / 2 + 1)));
+    if (!p2_z_supported(P, sizeof(cx<T>)) || (rows != 1 && rows != 2)) return hipErrorInvalidValue;
+    const int G = rows << lgTx;
+    dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * (rows == 2 ? Py / 2 + 1 : Py)));
     const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
 #define CALL(PP) \
     if (hipError_t e_ = allow_lds(&kz_sp<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((kz_sp<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, shat, Ms, nz, Py, Kx, lgTx, kXcds, twt)
+    hipLaunchKernelGGL((kz_sp<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, shat, Ms, nz, Py, Kx, lgTx, rows, kXcds, twt)
     if constexpr (sizeof(T) == 4) {
         DEMAG_P2_SWITCH(P, CALL)
     } else {
@@ -952,9 +975,10 @@ std::vector<cx<T>> p2_thread_twiddles(int P, const std::vector<cx<T>>& tw) {
                                            const cx<T>*, const BatchIO&);                                          \
     template hipError_t launch_y_inv_p2<T>(int, int, hipStream_t, const cx<T>*, cx<T>*, int, int, int, int, int,  \
                                            const cx<T>*, const BatchIO&);                                          \
-    template hipError_t launch_z_conv_p2<T>(int, hipStream_t, cx<T>*, const T*, T, int, int, int, int,            \
+    template hipError_t launch_z_conv_p2<T>(int, int, hipStream_t, cx<T>*, const T*, T, int, int, int, int,       \
                                             const cx<T>*, const BatchIO&);                                         \
-    template hipError_t launch_z_sp_p2<T>(int, hipStream_t, cx<T>*, const T*, T, int, int, int, int, const cx<T>*);
+    template hipError_t launch_z_sp_p2<T>(int, int, hipStream_t, cx<T>*, const T*, T, int, int, int, int,          \
+                                          const cx<T>*);
 
 DEMAG_P2_INSTANTIATE(float)
 DEMAG_P2_INSTANTIATE(double)

@@ -317,22 +317,27 @@ LaunchCfg p2_zconv(int P, int Kx, size_t cbytes, int target = 64) {
     LaunchCfg c;
     c.p2 = 1;
     const int TP = p2_threads_per_pencil(P);
-    int lgTx = std::max(0, ilog2i(std::max(1, target / (2 * TP))));
+    // t1 = ky rows per workgroup: a row and its mirror (2) unless that pair
+    // of pencils would exceed the workgroup, then one row (1)
+    const int rows = 2 * TP <= kP2MaxThreadsZ ? 2 : 1;
+    int lgTx = std::max(0, ilog2i(std::max(1, target / (rows * TP))));
     lgTx = std::min(lgTx, pow2_ceil_log(Kx));
     while (lgTx > 0 &&
-           ((size_t)p2_slab_elems(P) << (lgTx + 1)) * cbytes + p2_z_twiddle_lds_bytes(P, cbytes) > g_p2_lds - 256)
+           ((size_t)p2_slab_elems(P) * (rows << lgTx)) * cbytes + p2_z_twiddle_lds_bytes(P, cbytes) > g_p2_lds - 256)
         --lgTx;
-    while (lgTx > 0 && (2 * TP << lgTx) > kP2MaxThreadsZ) --lgTx;
+    while (lgTx > 0 && (rows * TP << lgTx) > kP2MaxThreadsZ) --lgTx;
     c.t0 = lgTx;
-    c.threads = 2 * TP << lgTx;
+    c.t1 = rows;
+    c.threads = rows * TP << lgTx;
     return c;
 }
 
 bool p2_cfg_ok(const LaunchCfg& c, int P, size_t cbytes, int kind /*0 rows, 1 pencils, 2 z*/) {
     if (!p2_supported(P) || c.t0 < 0 || c.t1 < 0 || c.t0 > 12 || c.t1 > 12) return false;
     const long TP = p2_threads_per_pencil(P);
-    long pencils = kind == 0 ? (1L << (c.t0 - 1)) : kind == 1 ? (1L << (c.t0 + c.t1)) : (2L << c.t0);
+    long pencils = kind == 0 ? (1L << (c.t0 - 1)) : kind == 1 ? (1L << (c.t0 + c.t1)) : ((long)c.t1 << c.t0);
     if (kind == 0 && c.t0 < 1) return false;
+    if (kind == 2 && c.t1 != 1 && c.t1 != 2) return false;
     long threads = pencils * TP;
     long maxthr = kind == 2 ? kP2MaxThreadsZ : p2_max_threads(P);
     if (kind == 2 && !p2_z_supported(P, cbytes)) return false;
@@ -753,7 +758,7 @@ hipError_t launch_pass(demag_plan_s* p, int which, const LaunchCfg& lc, hipStrea
         return lc.p2 ? launch_y_fwd_p2<T>(lc.t1, lc.t0, st, B1, B2, ny, nz, Kx, 3, Py, tty, bio)
                      : launch_y_fwd<T>(lc, st, B1, B2, ny, nz, Kx, nz, 3, p->fp[1], twy, bio);
     case 2:
-        return lc.p2 ? launch_z_conv_p2<T>(lc.t0, st, B2, (const T*)p->nhat, (T)Ms, nz, Py, Kx, Pz, ttz, bio)
+        return lc.p2 ? launch_z_conv_p2<T>(lc.t0, lc.t1, st, B2, (const T*)p->nhat, (T)Ms, nz, Py, Kx, Pz, ttz, bio)
                      : launch_z_conv<T>(lc, st, B2, (const T*)p->nhat, (T)Ms, nz, Py, Kx, p->fp[2], twz, bio);
     case 3:
         return lc.p2 ? launch_y_inv_p2<T>(lc.t1, lc.t0, st, B2, B1, ny, nz, Kx, 3, Py, tty, bio)
@@ -811,7 +816,7 @@ int run_sp_field(demag_plan_s* p, const T* m, double Ms, T* H, double* E_dev, hi
     const PassCfgs& c = p->cfg;
     HIP_TRY(launch_pass<T>(p, 0, c.xf, st, m, Ms, nullptr, nullptr, nullptr, 0));
     HIP_TRY(launch_pass<T>(p, 1, c.yf, st, nullptr, Ms, nullptr, nullptr, nullptr, 0));
-    HIP_TRY(launch_z_sp_p2<T>(p->zs.t0, st, B2, (const T*)p->shat, (T)Ms, nz, Py, Kx, Pz, (const cx<T>*)p->twt[2]));
+    HIP_TRY(launch_z_sp_p2<T>(p->zs.t0, p->zs.t1, st, B2, (const T*)p->shat, (T)Ms, nz, Py, Kx, Pz, (const cx<T>*)p->twt[2]));
     const LaunchCfg& yi = c.yi;
     HIP_TRY(yi.p2 ? launch_y_inv_p2<T>(yi.t1, yi.t0, st, B2, B1, ny, nz, Kx, 1, Py, (const cx<T>*)p->twt[1])
                   : launch_y_inv<T>(yi, st, B2, B1, ny, nz, Kx, 1, p->fp[1], (const cx<T>*)p->tw[1]));
@@ -1545,7 +1550,7 @@ void add_p2_candidates(const demag_plan_s* p, int kind, std::vector<LaunchCfg>& 
     const size_t cb = csize(p->dtype);
     const int TP = p2_threads_per_pencil(P);
     for (int a = 0; a <= 10; ++a)
-        for (int b = 0; b <= (kind == 1 ? 10 : 0); ++b) {
+        for (int b = kind == 2 ? 1 : 0; b <= (kind == 1 ? 10 : kind == 2 ? 2 : 0); ++b) {
             LaunchCfg c;
             c.p2 = 1;
             if (kind == 0) {
@@ -1560,7 +1565,8 @@ void add_p2_candidates(const demag_plan_s* p, int kind, std::vector<LaunchCfg>& 
             } else {
                 if (a > pow2_ceil_log(p->Kx)) continue;
                 c.t0 = a;
-                c.threads = 2 * TP << a;
+                c.t1 = b;  // ky rows per workgroup
+                c.threads = b * TP << a;
             }
             if (c.threads < 64 && c.threads < TP * 2) continue;
             if (p2_cfg_ok(c, P, cb, kind)) out.push_back(c);
@@ -1583,7 +1589,7 @@ std::string cache_key(const demag_plan_s* p) {
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
     arch = arch.substr(0, arch.find(':'));
     char b[160];
-    snprintf(b, sizeof b, "v3|%s|%s|%d,%d,%d", arch.c_str(), p->dtype == DEMAG_F32 ? "f32" : "f64", p->n[0],
+    snprintf(b, sizeof b, "v4|%s|%s|%d,%d,%d", arch.c_str(), p->dtype == DEMAG_F32 ? "f32" : "f64", p->n[0],
              p->n[1], p->n[2]);
     return b;
 }
@@ -1595,7 +1601,7 @@ std::map<std::string, std::string> read_cache(const char* path) {
     std::string line;
     while (std::getline(f, line)) {
         auto sp = line.find(' ');
-        if (sp == std::string::npos || line.rfind("v3|", 0) != 0) continue;
+        if (sp == std::string::npos || line.rfind("v4|", 0) != 0) continue;
         m[line.substr(0, sp)] = line.substr(sp + 1);
     }
     return m;

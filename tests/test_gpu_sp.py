@@ -64,6 +64,7 @@ SHAPES = [
     ((24, 17, 3), (1.95e-9, 1.95e-9, 0.75e-9), 8e5),  # 48, 36 (generic), 6 = 3 * 2
     ((47, 11, 23), (2e-9, 2e-9, 3e-9), 1.4e6),     # 96, 24, 48: 3 * 2^a, ragged
     ((29, 61, 11), (2e-9, 2e-9, 3e-9), 1.4e6),     # 60 (generic), 128, 24
+    ((3, 3, 2039), (2e-9, 2e-9, 3e-9), 1.4e6),     # z 4096: one pencil row per Z workgroup, ragged
 ]
 
 
