@@ -315,6 +315,23 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __res
     }
     const int y0 = yt << lgTy, z = zc % nz, c = zc / nz;
     const int ty = min(Ty, ny - y0);
+    const size_t rowbase = (((size_t)c * nz + z) * ny + y0 + 2 * p) * (size_t)nx;
+    const bool ok0 = 2 * p < ty, ok1 = 2 * p + 1 < ty;
+    // energy: the magnetization at this thread's outputs, loaded first so that
+    // its latency overlaps the transposition and the transform
+    T m0[LT::EPT], m1[LT::EPT];
+    if (m) {
+        const gptr<const T> msrc = gmem(ok0 ? m + rowbase : m);  // rows past the tile read m[0], discarded
+#pragma unroll
+        for (int j = 0; j < LT::EPT; ++j) {
+            const int k = LT::iout_k(j);
+            const int x = t + k * LT::TP;
+            if (k < LT::EPT / 2) {
+                m0[j] = gldr_if(msrc, x, ok0 && x < nx);
+                m1[j] = gldr_if(msrc, x + nx, ok1 && x < nx);
+            }
+        }
+    }
     // pair q = tid mod Bp, frequencies k = tid / Bp + i TP: every load of the
     // thread is issued before the first LDS write
     {
@@ -353,10 +370,7 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __res
 #pragma unroll
     for (int j = 0; j < LT::EPT; ++j) v[j] = slab[LT::iin_slab(pt, t, j)];
     run_fft<T, P, +1>(v, slab, t, tws);
-    const size_t rowbase = (((size_t)c * nz + z) * ny + y0 + 2 * p) * (size_t)nx;
     const gptr<T> dst = out ? gmem(out + rowbase) : nullptr;
-    const gptr<const T> msrc = m ? gmem(m + rowbase) : nullptr;
-    const bool ok0 = 2 * p < ty, ok1 = 2 * p + 1 < ty;
     double acc = 0.0;
 #pragma unroll
     for (int j = 0; j < LT::EPT; ++j) {
@@ -365,12 +379,12 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __res
         if (k < LT::EPT / 2 && x < nx) {  // the discarded half is never written
             if (ok0) {
                 const T h = v[j].re;
-                if (msrc) acc += (double)(msrc[x] * h);
+                if (m) acc += (double)(m0[j] * h);
                 if (dst) dst[x] = accumulate ? dst[x] + h : h;
             }
             if (ok1) {
                 const T h = v[j].im;
-                if (msrc) acc += (double)(msrc[x + nx] * h);
+                if (m) acc += (double)(m1[j] * h);
                 if (dst) dst[x + nx] = accumulate ? dst[x + nx] + h : h;
             }
         }

@@ -1616,12 +1616,25 @@ bool parse_cfgs(const std::string& s, PassCfgs& c) {
            cfg_parse(a[4], c.xi);
 }
 
+// Time of a whole evaluation with candidate `lc` in pass `which` and the
+// plan's current shapes elsewhere.  A pass timed alone in a loop finds its
+// working set (up to a few hundred MB) still in the last-level cache, which
+// the other passes of an evaluation evict; inside the whole sequence each pass
+// meets the cache state it has in use, and the effect of its shape on the
+// passes around it is counted too.
 template <typename T>
 int time_pass(demag_plan_s* p, int which, const LaunchCfg& lc, hipStream_t st, const T* m, T* H, float* ms_out) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    auto launch = [&]() { return launch_pass<T>(p, which, lc, st, m, 1.0, H, nullptr, nullptr, 0); };
+    PassCfgs c = p->cfg;
+    LaunchCfg* slot[5] = {&c.xf, &c.yf, &c.zc, &c.yi, &c.xi};
+    *slot[which] = lc;
+    auto launch = [&]() {
+        for (int w = 0; w < 5; ++w)
+            if (hipError_t e = launch_pass<T>(p, w, pass_cfg(c, w), st, m, 1.0, H, nullptr, nullptr, 0)) return e;
+        return hipSuccess;
+    };
     hipError_t err = hipSuccess;
     for (int r = 0; r < 3 && err == hipSuccess; ++r) err = launch();
     const int reps = 10;
