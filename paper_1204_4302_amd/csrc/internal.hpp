@@ -205,9 +205,12 @@ template <typename T>
 hipError_t launch_llg_correct(hipStream_t, size_t N, T* m, const T* H2, const T* k1, const T* ms,
                               const double hext[3], double g, double alpha, double dt);
 
-// H = -grad phi (d = cell edges), optional energy partials m.H, one per (y, z) row.
+// H = -grad phi (d = cell edges), optional energy partials m.H, one per
+// workgroup; *nparts (if given) receives their count, at most
+// sp_gradient_tiles(nx, ny, nz, 1).
 template <typename T>
 hipError_t launch_sp_gradient(hipStream_t, int nx, int ny, int nz, const double d[3], const T* phi, T* H,
-                              const T* m, double* partials);
+                              const T* m, double* partials, int* nparts);
+long sp_gradient_tiles(int nx, int ny, int nz, int zc);
 
 }  // namespace demag

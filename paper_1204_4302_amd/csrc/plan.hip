@@ -544,10 +544,12 @@ int run_tg_field(demag_plan_s* p, const T* m, double Ms, T* H, double* E_dev, hi
                                    (const T* const*)g->Y1k, (T* const*)g->Y2k, B3, (T*)g->Y1, (T*)g->Y2, phi,
                                    Ms * hmax);
     if (rc) return fail(DEMAG_EHIP, "tensor-grid GEMM failed (%d)", rc);
-    HIP_TRY(launch_sp_gradient<T>(st, nx, ny, nz, p->d, phi, Hout, E_dev ? m : nullptr, E_dev ? p->partials : nullptr));
+    int nparts = 0;
+    HIP_TRY(launch_sp_gradient<T>(st, nx, ny, nz, p->d, phi, Hout, E_dev ? m : nullptr, E_dev ? p->partials : nullptr,
+                                  &nparts));
     if (E_dev) {
         const double V = p->d[0] * p->d[1] * p->d[2];
-        HIP_TRY(launch_energy_reduce(st, p->partials, ny * nz, -0.5 * kMu0 * Ms * V, E_dev));
+        HIP_TRY(launch_energy_reduce(st, p->partials, nparts, -0.5 * kMu0 * Ms * V, E_dev));
     }
     return DEMAG_OK;
 }
@@ -825,10 +827,12 @@ int run_sp_field(demag_plan_s* p, const T* m, double Ms, T* H, double* E_dev, hi
                                        (const cx<T>*)p->twt[0])
                   : launch_x_inv<T>(xi, st, B1, phi, nullptr, nullptr, nx, ny, nz, Kx, 1, 0, p->fp[0],
                                     (const cx<T>*)p->tw[0]));
-    HIP_TRY(launch_sp_gradient<T>(st, nx, ny, nz, p->d, phi, Hout, E_dev ? m : nullptr, E_dev ? p->partials : nullptr));
+    int nparts = 0;
+    HIP_TRY(launch_sp_gradient<T>(st, nx, ny, nz, p->d, phi, Hout, E_dev ? m : nullptr, E_dev ? p->partials : nullptr,
+                                  &nparts));
     if (E_dev) {
         const double V = p->d[0] * p->d[1] * p->d[2];
-        HIP_TRY(launch_energy_reduce(st, p->partials, ny * nz, -0.5 * kMu0 * Ms * V, E_dev));
+        HIP_TRY(launch_energy_reduce(st, p->partials, nparts, -0.5 * kMu0 * Ms * V, E_dev));
     }
     return DEMAG_OK;
 }
@@ -1021,7 +1025,8 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
     alloc(&p->B1, nB1 * cb, "spectrum scratch B1");
     alloc(&p->B2, nB2 * cb, "spectrum scratch B2");
     alloc(&p->nhat, nH * rb, "tensor spectrum");
-    p->npartials = 3 * nz * ((ny + 1) / 2);  // upper bound: X-inverse tiles of >= 2 rows
+    // upper bound: X-inverse tiles of >= 2 rows; gradient workgroups (SP, TG)
+    p->npartials = (int)std::max<long>(3L * nz * ((ny + 1) / 2), sp_gradient_tiles(nx, ny, nz, 1));
     alloc((void**)&p->partials, (size_t)p->npartials * sizeof(double), "energy partials");
     alloc((void**)&p->e_dev, sizeof(double), "energy scalar");
     p->scratch_bytes = (nB1 + nB2) * cb;

@@ -18,6 +18,9 @@
 // S_a is odd in axis a and even in the others; its transform is imaginary.
 // The spectrum stored is Im(S^) on the octant with +1/(Px Py Pz) folded in,
 // layout [Py/2+1][3][Kx][Pz/2+1].
+#include <algorithm>
+#include <climits>
+
 #include "internal.hpp"
 #include "newell.hpp"
 
@@ -197,46 +200,133 @@ __global__ void __launch_bounds__(256) k_sp_extract(int a, int Py, int Pz, int K
 }
 
 // ---- field: H = -grad phi (eq. (field)) ---------------------------------------
-// -d phi / d axis at index i of n along an axis (stride s, spacing h): central
-// inside, second-order one-sided on the faces, first order for n = 2, 0 for n = 1.
+// -d phi / d axis at index i of n from the five values around it (pm2 at
+// i - 2 ... p2 at i + 2; only those inside the grid are used), r2h = 1/(2h):
+// central inside, second-order one-sided on the faces, first order for n = 2,
+// 0 for n = 1; chosen by selects, so that a face needs no branch.
 template <typename T>
-__device__ __forceinline__ T minus_d(const T* __restrict__ p, int i, int n, long s, T h) {
-    if (n == 1) return T(0);
-    if (n == 2) return i == 0 ? -(p[s] - p[0]) / h : -(p[0] - p[-s]) / h;
-    if (i == 0) return -(T(-3) * p[0] + T(4) * p[s] - p[2 * s]) / (T(2) * h);
-    if (i == n - 1) return -(T(3) * p[0] - T(4) * p[-s] + p[-2 * s]) / (T(2) * h);
-    return -(p[s] - p[-s]) / (T(2) * h);
+__device__ __forceinline__ T minus_d5(T pm2, T pm1, T p0, T p1, T p2, int i, int n, T r2h) {
+    const T central = -(p1 - pm1) * r2h;
+    const T first = -(T(-3) * p0 + T(4) * p1 - p2) * r2h;  // i = 0
+    const T last = -(T(3) * p0 - T(4) * pm1 + pm2) * r2h;  // i = n - 1
+    const T two = i == 0 ? -(p1 - p0) * (T(2) * r2h) : -(p0 - pm1) * (T(2) * r2h);
+    const T d = i == 0 ? first : i == n - 1 ? last : central;
+    return n == 1 ? T(0) : n == 2 ? two : d;
 }
 
-// One workgroup per (y, z) row; optional energy partial sum m.H per row (FP64).
+// Tiled gradient.  A workgroup owns a kGX x kGY cell tile of a z-chunk
+// [z0, z0 + zc); thread (lx, ly) owns x = x0 + lx and the rows y0 + ly + 4 r
+// (r < kGR) and walks z with phi at z - 2 ... z + 2 of its cells in registers
+// (each plane is read once, three planes ahead of its use).  The plane's tile
+// with a two-cell halo in x and y is staged in LDS, double-buffered, one
+// barrier per plane; every stencil, the one-sided ones of the faces included,
+// then reads LDS and registers only.  Addresses: a workgroup-uniform plane
+// pointer plus a 32-bit in-plane offset per lane; a lane with nothing to load
+// reads its plane's first cell and discards it.  Optional energy: one FP64
+// partial of m.H per workgroup.
+constexpr int kGX = 64, kGR = 4, kGY = 4 * kGR, kGH = 2;
+
 template <typename T>
-__global__ void __launch_bounds__(256) k_sp_gradient(int nx, int ny, int nz, T dx, T dy, T dz,
+__global__ void __launch_bounds__(256) k_sp_gradient(int nx, int ny, int nz, int zc, T dx, T dy, T dz,
                                                      const T* __restrict__ phi, T* __restrict__ H,
                                                      const T* __restrict__ m, double* __restrict__ partials) {
+    constexpr int TW = kGX + 2 * kGH, TH = kGY + 2 * kGH;
+    __shared__ T tile[2][TH][TW];
     __shared__ double red[4];
-    const int row = blockIdx.x, y = row % ny, z = row / ny;
-    const size_t N = (size_t)nx * ny * nz;
-    const size_t base = ((size_t)z * ny + y) * nx;
+    const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+    const int ntx = (nx + kGX - 1) / kGX, nty = (ny + kGY - 1) / kGY;
+    const int bx = blockIdx.x % ntx, by = (blockIdx.x / ntx) % nty, bz = blockIdx.x / (ntx * nty);
+    const int x0 = bx * kGX, y0 = by * kGY, z0 = bz * zc, z1 = min(nz, z0 + zc);
+    const int x = x0 + lx;
+    const size_t sxy = (size_t)nx * ny, N = sxy * nz;
+    auto plane = [&](const T* a, int zz) { return a + (size_t)min(max(zz, 0), nz - 1) * sxy; };
+    auto ld = [&](const T* a, int zz, unsigned off, bool valid) {
+        const T v = plane(a, zz)[off];
+        return valid ? v : T(0);
+    };
+    bool ok[kGR];
+    unsigned oc[kGR];
+#pragma unroll
+    for (int r = 0; r < kGR; ++r) {
+        const int y = y0 + ly + 4 * r;
+        ok[r] = x < nx && y < ny;
+        oc[r] = ok[r] ? (unsigned)y * (unsigned)nx + (unsigned)x : 0u;
+    }
+    // halo: rows y0 - 2, y0 - 1, y0 + kGY, y0 + kGY + 1 (one per ly, column x);
+    // columns x0 - 2, x0 - 1, x0 + kGX, x0 + kGX + 1 (ly = 0: lx / 16, row y0 + lx % 16)
+    const int hry = ly < 2 ? y0 - kGH + ly : y0 + kGY + (ly - 2);
+    const bool hrv = x < nx && hry >= 0 && hry < ny;
+    const unsigned ohr = hrv ? (unsigned)hry * (unsigned)nx + (unsigned)x : 0u;
+    const int hrt = ly < 2 ? ly : kGY + kGH + (ly - 2);  // its tile row
+    const int hk = lx >> 4;
+    const int hcx = hk < 2 ? x0 - kGH + hk : x0 + kGX + (hk - 2), hcy = y0 + (lx & 15);
+    const bool hcv = ly == 0 && hcx >= 0 && hcx < nx && hcy < ny;
+    const unsigned ohc = hcv ? (unsigned)hcy * (unsigned)nx + (unsigned)hcx : 0u;
+    const int hct = hk < 2 ? hk : kGX + kGH + (hk - 2);  // its tile column
+    T w[5][kGR];  // phi at z - 2 ... z + 2
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+        for (int r = 0; r < kGR; ++r) {
+            const int zz = z0 - 2 + k;
+            w[k][r] = ld(phi, zz, oc[r], ok[r] && zz >= 0 && zz < nz);
+        }
+    T hr = ld(phi, z0, ohr, hrv), hc = ld(phi, z0, ohc, hcv);
+    const T rx = T(1) / (T(2) * dx), ry = T(1) / (T(2) * dy), rz = T(1) / (T(2) * dz);
+    const int tx = lx + kGH;
     double acc = 0.0;
-    for (int x = threadIdx.x; x < nx; x += blockDim.x) {
-        const size_t i = base + x;
-        const T hx = minus_d(phi + i, x, nx, 1, dx);
-        const T hy = minus_d(phi + i, y, ny, (long)nx, dy);
-        const T hz = minus_d(phi + i, z, nz, (long)nx * ny, dz);
-        H[i] = hx;
-        H[N + i] = hy;
-        H[2 * N + i] = hz;
-        if (m) acc += (double)(m[i] * hx) + (double)(m[N + i] * hy) + (double)(m[2 * N + i] * hz);
+    for (int z = z0; z < z1; ++z) {
+        const int b = (z - z0) & 1;
+#pragma unroll
+        for (int r = 0; r < kGR; ++r) tile[b][ly + 4 * r + kGH][tx] = w[2][r];
+        tile[b][hrt][tx] = hr;
+        if (ly == 0) tile[b][(lx & 15) + kGH][hct] = hc;
+        // the values of later planes, in flight while this plane is differenced
+        T wn[kGR];
+#pragma unroll
+        for (int r = 0; r < kGR; ++r) wn[r] = ld(phi, z + 3, oc[r], ok[r] && z + 3 < nz);
+        const T hrn = ld(phi, z + 1, ohr, hrv && z + 1 < z1), hcn = ld(phi, z + 1, ohc, hcv && z + 1 < z1);
+        T mv[kGR][3];
+        if (m) {
+#pragma unroll
+            for (int r = 0; r < kGR; ++r)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) mv[r][a] = plane(m + a * N, z)[oc[r]];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kGR; ++r) {
+            const int ty = ly + 4 * r + kGH, y = y0 + ly + 4 * r;
+            const T c = w[2][r];
+            const T hxv = minus_d5(tile[b][ty][tx - 2], tile[b][ty][tx - 1], c, tile[b][ty][tx + 1], tile[b][ty][tx + 2],
+                                   x, nx, rx);
+            const T hyv = minus_d5(tile[b][ty - 2][tx], tile[b][ty - 1][tx], c, tile[b][ty + 1][tx], tile[b][ty + 2][tx],
+                                   y, ny, ry);
+            const T hzv = minus_d5(w[0][r], w[1][r], c, w[3][r], w[4][r], z, nz, rz);
+            if (ok[r]) {
+                T* hz = H + (size_t)z * sxy;
+                hz[oc[r]] = hxv;
+                hz[N + oc[r]] = hyv;
+                hz[2 * N + oc[r]] = hzv;
+                if (m) acc += (double)(mv[r][0] * hxv) + (double)(mv[r][1] * hyv) + (double)(mv[r][2] * hzv);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kGR; ++r) {
+            w[0][r] = w[1][r];
+            w[1][r] = w[2][r];
+            w[2][r] = w[3][r];
+            w[3][r] = w[4][r];
+            w[4][r] = wn[r];
+        }
+        hr = hrn;
+        hc = hcn;
     }
     if (partials) {
         for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+        if (lx == 0) red[ly] = acc;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) s += red[w];
-            partials[row] = s;
-        }
+        if (threadIdx.x == 0) partials[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
     }
 }
 
@@ -281,20 +371,35 @@ hipError_t launch_sp_extract(hipStream_t st, int a, int Py, int Pz, int Kx, doub
     return hipGetLastError();
 }
 
+long sp_gradient_tiles(int nx, int ny, int nz, int zc) {
+    return (long)((nx + kGX - 1) / kGX) * ((ny + kGY - 1) / kGY) * ((nz + zc - 1) / zc);
+}
+
+// z-chunk: the longest (up to 16 planes) that still gives about 1024
+// workgroups, so that the device is filled and each chunk reuses its planes
+int sp_gradient_zc(int nx, int ny, int nz) {
+    int zc = 16;
+    while (zc > 1 && sp_gradient_tiles(nx, ny, nz, zc) < 1024) zc >>= 1;
+    return std::min(zc, std::max(nz, 1));
+}
+
 template <typename T>
 hipError_t launch_sp_gradient(hipStream_t st, int nx, int ny, int nz, const double d[3], const T* phi, T* H,
-                              const T* m, double* partials) {
-    const int threads = nx >= 256 ? 256 : nx >= 128 ? 128 : 64;
-    hipLaunchKernelGGL((k_sp_gradient<T>), dim3((unsigned)ny * nz), dim3(threads), 0, st, nx, ny, nz, (T)d[0],
-                       (T)d[1], (T)d[2], phi, H, m, partials);
+                              const T* m, double* partials, int* nparts) {
+    const int zc = sp_gradient_zc(nx, ny, nz);
+    const long tiles = sp_gradient_tiles(nx, ny, nz, zc);
+    if (tiles > INT_MAX) return hipErrorInvalidValue;
+    if (nparts) *nparts = (int)tiles;
+    hipLaunchKernelGGL((k_sp_gradient<T>), dim3((unsigned)tiles), dim3(256), 0, st, nx, ny, nz, zc, (T)d[0], (T)d[1],
+                       (T)d[2], phi, H, m, partials);
     return hipGetLastError();
 }
 
 template hipError_t launch_sp_extract<float>(hipStream_t, int, int, int, int, double, const cx<double>*, float*);
 template hipError_t launch_sp_extract<double>(hipStream_t, int, int, int, int, double, const cx<double>*, double*);
 template hipError_t launch_sp_gradient<float>(hipStream_t, int, int, int, const double[3], const float*, float*,
-                                              const float*, double*);
+                                              const float*, double*, int*);
 template hipError_t launch_sp_gradient<double>(hipStream_t, int, int, int, const double[3], const double*, double*,
-                                               const double*, double*);
+                                               const double*, double*, int*);
 
 }  // namespace demag
