@@ -80,6 +80,21 @@ constexpr int kP2MaxThreadsZ = 512;     // fused Z pass (three pencils per threa
 // buffer offsets: one B2 component and the whole octant must each span fewer
 // bytes than this (larger shapes run the generic Z pass).
 constexpr size_t kP2BufLimit = 0xFFFFF000u;
+
+// One-thread-per-element launches over `total` elements in pieces of at most
+// kLaunchPiece work-items (a 1-D grid holds fewer than 2^32 work-items, and
+// set-up arrays of a large padded grid hold more elements): launch(base,
+// blocks) enqueues the piece starting at element `base`.
+constexpr size_t kLaunchPiece = size_t(1) << 30;
+template <typename F>
+hipError_t launch_pieces(size_t total, unsigned threads, F&& launch) {
+    for (size_t base = 0; base < total; base += kLaunchPiece) {
+        const size_t n = total - base < kLaunchPiece ? total - base : kLaunchPiece;
+        launch(base, (unsigned)((n + threads - 1) / threads));
+        if (hipError_t e = hipGetLastError()) return e;
+    }
+    return hipSuccess;
+}
 // The p2 kernels read their twiddles from a thread-major table: the values of
 // tw (exp(-2 pi i t / P), t < P) rearranged so that the threads of one pencil
 // load consecutive entries.  Empty if P is not a supported power of two.

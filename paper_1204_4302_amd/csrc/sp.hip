@@ -94,10 +94,11 @@ __device__ double point_gap(const double R[3], const double dt[3]) {
 }
 
 // Near and far bands: one thread per octant offset.
-__global__ void __launch_bounds__(256) k_sp_pointwise(int nx, int ny, int nz, double dt0, double dt1, double dt2,
-                                                      double far_cut, int fg_cut, double* __restrict__ Soct) {
+__global__ void __launch_bounds__(256) k_sp_pointwise(size_t base, int nx, int ny, int nz, double dt0, double dt1,
+                                                      double dt2, double far_cut, int fg_cut,
+                                                      double* __restrict__ Soct) {
     const size_t ncell = (size_t)nx * ny * nz;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t t = base + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ncell) return;
     const int ox = (int)(t % nx), oy = (int)((t / nx) % ny), oz = (int)(t / ((size_t)nx * ny));
     const double dt[3] = {dt0, dt1, dt2};
@@ -115,12 +116,12 @@ __global__ void __launch_bounds__(256) k_sp_pointwise(int nx, int ny, int nz, do
 
 // Mid band: one 64-lane workgroup per offset of the bounding box
 // [0,bx) x [0,by) x [0,bz); offsets outside the band return at once.
-__global__ void __launch_bounds__(64) k_sp_mid(int nx, int ny, int nz, int bx, int by, double dt0, double dt1,
+__global__ void __launch_bounds__(64) k_sp_mid(long base, int nx, int ny, int nz, int bx, int by, double dt0, double dt1,
                                                double dt2, double far_cut, int fg_cut, int q, int max_panels,
                                                const double* __restrict__ gl_x, const double* __restrict__ gl_w,
                                                double* __restrict__ Soct) {
-    const int b = blockIdx.x;
-    const int ox = b % bx, oy = (b / bx) % by, oz = b / (bx * by);
+    const long b = base + blockIdx.x;
+    const int ox = (int)(b % bx), oy = (int)((b / bx) % by), oz = (int)(b / ((long)bx * by));
     if (ox >= nx || oy >= ny || oz >= nz) return;
     const double dt[3] = {dt0, dt1, dt2};
     const double R[3] = {ox * dt0, oy * dt1, oz * dt2};
@@ -168,10 +169,10 @@ __device__ __forceinline__ bool unpad_sp(int i, int n, int P, int* o) {
 }
 
 // component a of the octant mirrored into the P-periodic array (odd in axis a)
-__global__ void __launch_bounds__(256) k_sp_embed(int a, int nx, int ny, int nz, int Px, int Py, int Pz,
+__global__ void __launch_bounds__(256) k_sp_embed(size_t base, int a, int nx, int ny, int nz, int Px, int Py, int Pz,
                                                   const double* __restrict__ Soct, double* __restrict__ A) {
     const size_t total = (size_t)Px * Py * Pz;
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t t = base + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     const int x = (int)(t % Px), y = (int)((t / Px) % Py), z = (int)(t / ((size_t)Px * Py));
     int o[3];
@@ -187,11 +188,11 @@ __global__ void __launch_bounds__(256) k_sp_embed(int a, int nx, int ny, int nz,
 // Im of the transform on the octant, scaled; the transform of a function odd
 // in axis a vanishes on that axis's Nyquist plane: stored as an exact zero.
 template <typename T>
-__global__ void __launch_bounds__(256) k_sp_extract(int a, int Py, int Pz, int Kx, double scale,
+__global__ void __launch_bounds__(256) k_sp_extract(size_t base, int a, int Py, int Pz, int Kx, double scale,
                                                     const cx<double>* __restrict__ B2, T* __restrict__ shat) {
     const int Ly = Py / 2, Lz = Pz / 2;
     const size_t total = (size_t)(Ly + 1) * Kx * (Lz + 1);
-    const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t t = base + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     const int kz = (int)(t % (Lz + 1)), kx = (int)((t / (Lz + 1)) % Kx), ky = (int)(t / ((size_t)(Lz + 1) * Kx));
     double v = B2[((size_t)ky * Kx + kx) * Pz + kz].im * scale;
@@ -335,21 +336,20 @@ __global__ void __launch_bounds__(256) k_sp_gradient(int nx, int ny, int nz, int
 hipError_t launch_sp_kernel_octant(hipStream_t st, int nx, int ny, int nz, const double dt[3], const TensorBands& tb,
                                    const double* gl_x_dev, const double* gl_w_dev, double* Soct) {
     const size_t ncell = (size_t)nx * ny * nz;
-    hipLaunchKernelGGL(k_sp_pointwise, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, nx, ny, nz, dt[0],
-                       dt[1], dt[2], tb.far_cut, tb.fg_cut, Soct);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_pieces(ncell, 256, [&](size_t base, unsigned blocks) {
+        hipLaunchKernelGGL(k_sp_pointwise, dim3(blocks), dim3(256), 0, st, base, nx, ny, nz, dt[0], dt[1], dt[2],
+                           tb.far_cut, tb.fg_cut, Soct);
+    });
     if (e != hipSuccess) return e;
-    int bx = nx, by = ny, bz = nz;
-    const int lim[3] = {(int)ceil(tb.far_cut / dt[0]) + 1, (int)ceil(tb.far_cut / dt[1]) + 1,
-                        (int)ceil(tb.far_cut / dt[2]) + 1};
-    bx = bx < lim[0] ? bx : lim[0];
-    by = by < lim[1] ? by : lim[1];
-    bz = bz < lim[2] ? bz : lim[2];
+    // (in floating point: far_cut / dt may exceed the int range)
+    auto box = [&](int n, double d) { return (int)std::min<double>(n, ceil(tb.far_cut / d) + 1.0); };
+    const int bx = box(nx, dt[0]), by = box(ny, dt[1]), bz = box(nz, dt[2]);
     const long nb = (long)bx * by * bz;
-    if (nb > 0 && tb.far_cut > 0) {
-        hipLaunchKernelGGL(k_sp_mid, dim3((unsigned)nb), dim3(64), 0, st, nx, ny, nz, bx, by, dt[0], dt[1], dt[2],
-                           tb.far_cut, tb.fg_cut, tb.gl_q, tb.max_panels, gl_x_dev, gl_w_dev, Soct);
-        e = hipGetLastError();
+    if (nb > 0 && tb.far_cut > 0) {  // one 64-lane workgroup per offset of the box
+        e = launch_pieces((size_t)nb * 64, 64, [&](size_t base, unsigned blocks) {
+            hipLaunchKernelGGL(k_sp_mid, dim3(blocks), dim3(64), 0, st, (long)(base / 64), nx, ny, nz, bx, by, dt[0],
+                               dt[1], dt[2], tb.far_cut, tb.fg_cut, tb.gl_q, tb.max_panels, gl_x_dev, gl_w_dev, Soct);
+        });
     }
     return e;
 }
@@ -357,18 +357,18 @@ hipError_t launch_sp_kernel_octant(hipStream_t st, int nx, int ny, int nz, const
 hipError_t launch_sp_embed(hipStream_t st, int a, int nx, int ny, int nz, int Px, int Py, int Pz, const double* Soct,
                            double* A) {
     const size_t total = (size_t)Px * Py * Pz;
-    hipLaunchKernelGGL(k_sp_embed, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, nx, ny, nz, Px, Py, Pz,
-                       Soct, A);
-    return hipGetLastError();
+    return launch_pieces(total, 256, [&](size_t base, unsigned blocks) {
+        hipLaunchKernelGGL(k_sp_embed, dim3(blocks), dim3(256), 0, st, base, a, nx, ny, nz, Px, Py, Pz, Soct, A);
+    });
 }
 
 template <typename T>
 hipError_t launch_sp_extract(hipStream_t st, int a, int Py, int Pz, int Kx, double scale, const cx<double>* B2,
                              T* shat) {
     const size_t total = (size_t)(Py / 2 + 1) * Kx * (Pz / 2 + 1);
-    hipLaunchKernelGGL((k_sp_extract<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, Py, Pz, Kx,
-                       scale, B2, shat);
-    return hipGetLastError();
+    return launch_pieces(total, 256, [&](size_t base, unsigned blocks) {
+        hipLaunchKernelGGL((k_sp_extract<T>), dim3(blocks), dim3(256), 0, st, base, a, Py, Pz, Kx, scale, B2, shat);
+    });
 }
 
 long sp_gradient_tiles(int nx, int ny, int nz, int zc) {

@@ -11,6 +11,8 @@
 //   3. (plan runtime) the same X/Y/Z FFT passes in FP64;
 //   4. the real part on the spectral octant, with -1/(Px Py Pz) folded in,
 //      cast to the plan's precision.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "newell.hpp"
 
@@ -24,10 +26,11 @@ __device__ __forceinline__ bool in_far(int ox, int oy, int oz, const double* dt,
 }
 
 // Near and far bands: one thread per octant offset.
-__global__ void __launch_bounds__(256) k_tensor_pointwise(int nx, int ny, int nz, double dt0, double dt1, double dt2,
-                                                          double far_cut, int fg_cut, double* __restrict__ Noct) {
+__global__ void __launch_bounds__(256) k_tensor_pointwise(size_t base, int nx, int ny, int nz, double dt0, double dt1,
+                                                          double dt2, double far_cut, int fg_cut,
+                                                          double* __restrict__ Noct) {
     const size_t ncell = (size_t)nx * ny * nz;
-    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t t = base + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= ncell) return;
     int ox = (int)(t % nx), oy = (int)((t / nx) % ny), oz = (int)(t / ((size_t)nx * ny));
     const double dt[3] = {dt0, dt1, dt2};
@@ -45,12 +48,12 @@ __global__ void __launch_bounds__(256) k_tensor_pointwise(int nx, int ny, int nz
 
 // Mid band: one 64-lane workgroup per offset of the bounding box
 // [0,bx) x [0,by) x [0,bz); offsets outside the band return at once.
-__global__ void __launch_bounds__(64) k_tensor_mid(int nx, int ny, int nz, int bx, int by, double dt0, double dt1,
+__global__ void __launch_bounds__(64) k_tensor_mid(long base, int nx, int ny, int nz, int bx, int by, double dt0, double dt1,
                                                    double dt2, double far_cut, int fg_cut, int q, int max_panels,
                                                    const double* __restrict__ gl_x, const double* __restrict__ gl_w,
                                                    double* __restrict__ Noct) {
-    const int b = blockIdx.x;
-    const int ox = b % bx, oy = (b / bx) % by, oz = b / (bx * by);
+    const long b = base + blockIdx.x;
+    const int ox = (int)(b % bx), oy = (int)((b / bx) % by), oz = (int)(b / ((long)bx * by));
     if (ox >= nx || oy >= ny || oz >= nz) return;
     const double dt[3] = {dt0, dt1, dt2};
     if (max(ox, max(oy, oz)) <= fg_cut || in_far(ox, oy, oz, dt, far_cut)) return;
@@ -89,10 +92,11 @@ __device__ __forceinline__ bool unpad(int i, int n, int P, int* o) {
     return false;
 }
 
-__global__ void __launch_bounds__(256) k_tensor_embed(int comp, int nx, int ny, int nz, int Px, int Py, int Pz,
-                                                      const double* __restrict__ Noct, double* __restrict__ A) {
+__global__ void __launch_bounds__(256) k_tensor_embed(size_t base, int comp, int nx, int ny, int nz, int Px, int Py,
+                                                      int Pz, const double* __restrict__ Noct,
+                                                      double* __restrict__ A) {
     const size_t total = (size_t)Px * Py * Pz;
-    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t t = base + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     int x = (int)(t % Px), y = (int)((t / Px) % Py), z = (int)(t / ((size_t)Px * Py));
     int ox, oy, oz;
@@ -109,11 +113,11 @@ __global__ void __launch_bounds__(256) k_tensor_embed(int comp, int nx, int ny, 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_tensor_extract(int comp, int Py, int Pz, int Kx, double scale,
+__global__ void __launch_bounds__(256) k_tensor_extract(size_t base, int comp, int Py, int Pz, int Kx, double scale,
                                                         const cx<double>* __restrict__ B2, T* __restrict__ nhat) {
     const int Ly = Py / 2, Lz = Pz / 2;
     const size_t total = (size_t)(Ly + 1) * Kx * (Lz + 1);
-    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t t = base + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     int kz = (int)(t % (Lz + 1)), kx = (int)((t / (Lz + 1)) % Kx), ky = (int)(t / ((size_t)(Lz + 1) * Kx));
     double v = B2[((size_t)ky * Kx + kx) * Pz + kz].re * scale;
@@ -132,22 +136,22 @@ __global__ void __launch_bounds__(256) k_tensor_extract(int comp, int Py, int Pz
 hipError_t launch_tensor_octant(hipStream_t st, int nx, int ny, int nz, const double dt[3], const TensorBands& tb,
                                 const double* gl_x_dev, const double* gl_w_dev, double* Noct) {
     const size_t ncell = (size_t)nx * ny * nz;
-    hipLaunchKernelGGL(k_tensor_pointwise, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, st, nx, ny, nz,
-                       dt[0], dt[1], dt[2], tb.far_cut, tb.fg_cut, Noct);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_pieces(ncell, 256, [&](size_t base, unsigned blocks) {
+        hipLaunchKernelGGL(k_tensor_pointwise, dim3(blocks), dim3(256), 0, st, base, nx, ny, nz, dt[0], dt[1], dt[2],
+                           tb.far_cut, tb.fg_cut, Noct);
+    });
     if (e != hipSuccess) return e;
     // bounding box of the mid band: |o_k| dt_k < far_cut
-    int bx = nx, by = ny, bz = nz;
-    const int lim[3] = {(int)ceil(tb.far_cut / dt[0]) + 1, (int)ceil(tb.far_cut / dt[1]) + 1,
-                        (int)ceil(tb.far_cut / dt[2]) + 1};
-    bx = bx < lim[0] ? bx : lim[0];
-    by = by < lim[1] ? by : lim[1];
-    bz = bz < lim[2] ? bz : lim[2];
+    // (in floating point: far_cut / dt may exceed the int range)
+    auto box = [&](int n, double d) { return (int)std::min<double>(n, ceil(tb.far_cut / d) + 1.0); };
+    const int bx = box(nx, dt[0]), by = box(ny, dt[1]), bz = box(nz, dt[2]);
     const long nb = (long)bx * by * bz;
-    if (nb > 0 && tb.far_cut > 0) {
-        hipLaunchKernelGGL(k_tensor_mid, dim3((unsigned)nb), dim3(64), 0, st, nx, ny, nz, bx, by, dt[0], dt[1],
-                           dt[2], tb.far_cut, tb.fg_cut, tb.gl_q, tb.max_panels, gl_x_dev, gl_w_dev, Noct);
-        e = hipGetLastError();
+    if (nb > 0 && tb.far_cut > 0) {  // one 64-lane workgroup per offset of the box
+        e = launch_pieces((size_t)nb * 64, 64, [&](size_t base, unsigned blocks) {
+            hipLaunchKernelGGL(k_tensor_mid, dim3(blocks), dim3(64), 0, st, (long)(base / 64), nx, ny, nz, bx, by,
+                               dt[0], dt[1], dt[2], tb.far_cut, tb.fg_cut, tb.gl_q, tb.max_panels, gl_x_dev, gl_w_dev,
+                               Noct);
+        });
     }
     return e;
 }
@@ -155,9 +159,9 @@ hipError_t launch_tensor_octant(hipStream_t st, int nx, int ny, int nz, const do
 hipError_t launch_tensor_embed(hipStream_t st, int comp, int nx, int ny, int nz, int Px, int Py, int Pz,
                                const double* Noct, double* A) {
     const size_t total = (size_t)Px * Py * Pz;
-    hipLaunchKernelGGL(k_tensor_embed, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, comp, nx, ny, nz, Px,
-                       Py, Pz, Noct, A);
-    return hipGetLastError();
+    return launch_pieces(total, 256, [&](size_t base, unsigned blocks) {
+        hipLaunchKernelGGL(k_tensor_embed, dim3(blocks), dim3(256), 0, st, base, comp, nx, ny, nz, Px, Py, Pz, Noct, A);
+    });
 }
 
 template <typename T>
@@ -165,9 +169,10 @@ hipError_t launch_tensor_extract(hipStream_t st, int comp, int Px, int Py, int P
                                  const cx<double>* B2, T* nhat) {
     (void)Px;
     const size_t total = (size_t)(Py / 2 + 1) * Kx * (Pz / 2 + 1);
-    hipLaunchKernelGGL((k_tensor_extract<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, comp, Py, Pz,
-                       Kx, scale, B2, nhat);
-    return hipGetLastError();
+    return launch_pieces(total, 256, [&](size_t base, unsigned blocks) {
+        hipLaunchKernelGGL((k_tensor_extract<T>), dim3(blocks), dim3(256), 0, st, base, comp, Py, Pz, Kx, scale, B2,
+                           nhat);
+    });
 }
 
 template hipError_t launch_tensor_extract<float>(hipStream_t, int, int, int, int, int, double, const cx<double>*,
