@@ -66,7 +66,14 @@ typedef enum {
  * for powers of two up to 4096 (a pencil and its mirror per workgroup up to
  * 2048, one pencil per workgroup at 4096) and, in FP32, 3 * 2^a up to 3072;
  * other lengths up to 1365 (six pencils in one workgroup); longer z lengths
- * are DEMAG_EUNSUPPORTED (put the longest axis along x or y).  *out receives the plan (caller destroys it
+ * are DEMAG_EUNSUPPORTED (put the longest axis along x or y).  The register
+ * Z kernels address a spectrum component (ny' Kx nz complex values, ny' the
+ * padded y length, Kx = nx' / 2 + 1, nx' the padded x length) with 32-bit
+ * offsets: above 4 GB per component the generic kernel is used, so z lengths
+ * above 1365 need smaller x-y extents.  Device memory
+ * bounds the grid: about 96 bytes per cell for an FP32 plan (192 in FP64)
+ * plus about 240 bytes per cell of FP64 set-up scratch while this call runs
+ * (DEMAG_ENOMEM when it cannot be allocated).  *out receives the plan (caller destroys it
  * once). */
 int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, double dy, double dz,
                       demag_dtype dtype, void* setup_stream);

@@ -42,6 +42,10 @@ int fail(int code, const char* fmt, ...) {
 }
 
 int hip_fail(hipError_t e, const char* what) {
+    if (e == hipErrorOutOfMemory) {  // an allocation, e.g. set-up scratch: not a device fault
+        (void)hipGetLastError();
+        return fail(DEMAG_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    }
     return fail(DEMAG_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 

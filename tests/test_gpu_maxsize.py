@@ -62,3 +62,19 @@ def test_generic_kernels_refused_where_their_z_pass_does_not_fit():
     with pytest.raises(DemagError, match="EUNSUPPORTED"):
         plan.set_option("generic_kernels", 1)
     plan.set_option("generic_kernels", 0)
+
+
+def test_plan_beyond_device_memory_is_enomem():
+    """2048 x 2048 x 512 cells in FP64 need about 310 GB for the two spectrum
+    buffers alone (B1 103 GB, B2 206 GB), more than the device holds: plan
+    creation reports DEMAG_ENOMEM (an allocation failure, nothing is
+    launched), and the device stays usable."""
+    from paper_1204_4302_amd import Plan
+    from paper_1204_4302_amd._lib import DemagError
+    with pytest.raises(DemagError, match="ENOMEM"):
+        Plan((2048, 2048, 512), CELL, torch.float64)
+    plan = Plan((8, 8, 8), CELL, torch.float64)  # the next plan works
+    m = torch.from_numpy(inputs.random_unit((8, 8, 8), 3)).to("cuda", torch.float64)
+    H = plan.field(m, 8e5).cpu().numpy()
+    ref = oracle.Oracle((8, 8, 8), CELL).field(inputs.random_unit((8, 8, 8), 3), 8e5)
+    assert np.abs(H - ref).max() <= 1e-12 * np.abs(ref).max()
