@@ -338,6 +338,65 @@ def cpu_baseline(m, target_seconds, Href32, Href64):
     return base, err
 
 
+def bench_rocfft_reference(args, torch, np, m_np):
+    """Informational, not a target: the same forward DM field written with
+    torch.fft (rocFFT) -- the padded magnetization transformed whole, the
+    product with the plan's tensor spectrum (mirrored from its octant with the
+    parity signs: xy, yz odd in ky; xz, yz odd in kz) as separate tensor
+    operations, the inverse transform and the crop -- against the plan's own
+    forward field on the same input.  Checked against the plan's field first."""
+    from paper_1204_4302_amd import Plan
+    plan = Plan(SHAPE, CELL, torch.float32)
+    if not args.no_autotune:
+        plan.autotune()
+    i = plan.info()
+    Px, Py, Pz = i["Px"], i["Py"], i["Pz"]
+    nx, ny, nz = SHAPE
+    S = torch.from_numpy(plan.spectrum()).cuda()  # [Py/2+1][6][Kx][Pz/2+1]
+    ky = torch.arange(Py, device="cuda")
+    kz = torch.arange(Pz, device="cuda")
+    iy = torch.where(ky <= Py // 2, ky, Py - ky)
+    iz = torch.where(kz <= Pz // 2, kz, Pz - kz)
+    full = S[iy][..., iz].permute(1, 3, 0, 2).contiguous()  # [6][Pz][Py][Kx]
+    sy = torch.where(ky <= Py // 2, 1.0, -1.0).view(1, Py, 1)
+    sz = torch.where(kz <= Pz // 2, 1.0, -1.0).view(Pz, 1, 1)
+    for c in (3, 5):
+        full[c] *= sy
+    for c in (4, 5):
+        full[c] *= sz
+    nxx, nyy, nzz, nxy, nxz, nyz = full
+    m = torch.from_numpy(m_np).to("cuda", torch.float32)
+    mp = torch.zeros((3, Pz, Py, Px), device="cuda")
+    out = torch.empty_like(m)
+
+    def step():
+        mp[:, :nz, :ny, :nx] = m
+        M = torch.fft.rfftn(mp, dim=(1, 2, 3))
+        Hh = torch.stack((nxx * M[0] + nxy * M[1] + nxz * M[2], nxy * M[0] + nyy * M[1] + nyz * M[2],
+                          nxz * M[0] + nyz * M[1] + nzz * M[2]))
+        h = torch.fft.irfftn(Hh, s=(Pz, Py, Px), dim=(1, 2, 3), norm="forward")
+        torch.mul(h[:, :nz, :ny, :nx], MS, out=out)
+
+    step()
+    ref = plan.field(m, MS)
+    err = float(((out - ref).abs().max() / ref.abs().max()).item())
+    H = torch.empty_like(m)
+    k = args.rocfft_steps
+    for _ in range(3):
+        step()
+        plan.field(m, MS, out=H)
+    t_ref = run_steps(step, k, torch)
+    t_dm = run_steps(lambda: plan.field(m, MS, out=H), k, torch)
+    plan.close()
+    del full, mp, out, ref
+    torch.cuda.empty_cache()
+    return {"value": round(k / t_ref, 1), "unit": "evals/s", "ms_per_eval": round(1e3 * t_ref / k, 4),
+            "dm_forward_evals_per_s": round(k / t_dm, 1), "speedup_dm_over_rocfft": round(t_ref / t_dm, 2),
+            "rel_err_vs_dm": err,
+            "note": "informational, not a target: forward field with torch.fft (rocFFT) on the padded grid and "
+                    "the plan's tensor spectrum, vs the plan's forward field (no energy, no adjoint)"}
+
+
 BATCH_SIZES = [(32, 32, 32), (64, 64, 16), (96, 48, 8), (128, 128, 4), (48, 48, 48)]
 
 
@@ -495,6 +554,9 @@ def bench(args):
     if args.llg_steps > 0:
         out["llg"] = bench_llg(args, torch, np, value)
         print(f"# llg: {out['llg']}", file=sys.stderr, flush=True)
+    if args.rocfft_steps > 0:
+        out["rocfft_reference"] = bench_rocfft_reference(args, torch, np, m_np)
+        print(f"# rocfft_reference: {out['rocfft_reference']}", file=sys.stderr, flush=True)
     if args.tg_steps > 0:
         out["tg"] = bench_tg(args, torch, np, m_np, value)
         print(f"# tg: {out['tg']}", file=sys.stderr, flush=True)
@@ -607,6 +669,8 @@ def main():
     ap.add_argument("--tg-steps", type=int, default=10, help="tensor-grid evaluations (0: skip)")
     ap.add_argument("--llg-steps", type=int, default=100, help="LLG Heun steps (0: skip)")
     ap.add_argument("--lowrank-steps", type=int, default=200, help="low-rank TG evaluations (0: skip)")
+    ap.add_argument("--rocfft-steps", type=int, default=30,
+                    help="informational torch.fft (rocFFT) forward fields beside the plan's (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
