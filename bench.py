@@ -352,18 +352,7 @@ def bench_rocfft_reference(args, torch, np, m_np):
     i = plan.info()
     Px, Py, Pz = i["Px"], i["Py"], i["Pz"]
     nx, ny, nz = SHAPE
-    S = torch.from_numpy(plan.spectrum()).cuda()  # [Py/2+1][6][Kx][Pz/2+1]
-    ky = torch.arange(Py, device="cuda")
-    kz = torch.arange(Pz, device="cuda")
-    iy = torch.where(ky <= Py // 2, ky, Py - ky)
-    iz = torch.where(kz <= Pz // 2, kz, Pz - kz)
-    full = S[iy][..., iz].permute(1, 3, 0, 2).contiguous()  # [6][Pz][Py][Kx]
-    sy = torch.where(ky <= Py // 2, 1.0, -1.0).view(1, Py, 1)
-    sz = torch.where(kz <= Pz // 2, 1.0, -1.0).view(Pz, 1, 1)
-    for c in (3, 5):
-        full[c] *= sy
-    for c in (4, 5):
-        full[c] *= sz
+    full = torch.from_numpy(mirrored_spectrum(np, plan.spectrum(), Py, Pz)).cuda()  # [6][Pz][Py][Kx]
     nxx, nyy, nzz, nxy, nxz, nyz = full
     m = torch.from_numpy(m_np).to("cuda", torch.float32)
     mp = torch.zeros((3, Pz, Py, Px), device="cuda")
@@ -395,6 +384,57 @@ def bench_rocfft_reference(args, torch, np, m_np):
             "rel_err_vs_dm": err,
             "note": "informational, not a target: forward field with torch.fft (rocFFT) on the padded grid and "
                     "the plan's tensor spectrum, vs the plan's forward field (no energy, no adjoint)"}
+
+
+def mirrored_spectrum(np, S, Py, Pz):
+    """[6][Pz][Py][Kx] from the stored octant [Py/2+1][6][Kx][Pz/2+1] (numpy):
+    xy, yz odd in ky; xz, yz odd in kz."""
+    ky, kz = np.arange(Py), np.arange(Pz)
+    full = S[np.where(ky <= Py // 2, ky, Py - ky)][..., np.where(kz <= Pz // 2, kz, Pz - kz)]
+    full = np.ascontiguousarray(full.transpose(1, 3, 0, 2))
+    sy = np.where(ky <= Py // 2, 1.0, -1.0)[None, :, None]
+    sz = np.where(kz <= Pz // 2, 1.0, -1.0)[:, None, None]
+    for c in (3, 5):
+        full[c] *= sy
+    for c in (4, 5):
+        full[c] *= sz
+    return full
+
+
+def cpu_fft_reference(args, np, m_np, plan64, H64):
+    """Informational, not a target: the forward DM field on the host with
+    scipy.fft in FP64 on the host's threads (the padded magnetization
+    transformed whole, the product with the plan's FP64 tensor spectrum, the
+    inverse, the crop); best of a few evaluations; checked against the plan's
+    FP64 field.  The like-for-like (O(N log N)) CPU counterpart of the GPU
+    path, where the oracle baseline is the O(N^2) definition."""
+    import scipy.fft
+    i = plan64.info()
+    Px, Py, Pz = i["Px"], i["Py"], i["Pz"]
+    nx, ny, nz = SHAPE
+    full = mirrored_spectrum(np, plan64.spectrum(), Py, Pz)
+    nxx, nyy, nzz, nxy, nxz, nyz = full
+    workers = min(len(os.sched_getaffinity(0)), int(os.environ.get("OMP_NUM_THREADS", "16") or 16))
+
+    def ev():
+        mp = np.zeros((3, Pz, Py, Px))
+        mp[:, :nz, :ny, :nx] = m_np
+        M = scipy.fft.rfftn(mp, axes=(1, 2, 3), workers=workers)
+        Hh = np.stack((nxx * M[0] + nxy * M[1] + nxz * M[2], nxy * M[0] + nyy * M[1] + nyz * M[2],
+                       nxz * M[0] + nyz * M[1] + nzz * M[2]))
+        h = scipy.fft.irfftn(Hh, s=(Pz, Py, Px), axes=(1, 2, 3), norm="forward", workers=workers)
+        return MS * h[:, :nz, :ny, :nx]
+
+    best, h = None, None
+    for _ in range(max(1, args.cpu_fft_evals)):
+        t0 = time.perf_counter()
+        h = ev()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    err = float(np.max(np.abs(h - H64)) / np.max(np.abs(H64)))
+    return {"value": round(1.0 / best, 3), "unit": "evals/s", "cores": workers, "kind": "scipy.fft FP64 host",
+            "rel_err_vs_gpu_f64": err,
+            "note": "informational: forward field only, best of %d evaluations" % max(1, args.cpu_fft_evals)}
 
 
 BATCH_SIZES = [(32, 32, 32), (64, 64, 16), (96, 48, 8), (128, 128, 4), (48, 48, 48)]
@@ -568,6 +608,9 @@ def bench(args):
         base, err = cpu_baseline(m_np, args.cpu_seconds, r32["H"], H64)
         out["cpu_baseline"] = base
         out.setdefault("accuracy", {})["vs_oracle_sampled"] = err
+        if args.cpu_fft_evals > 0 and torch.float64 in results:
+            out["cpu_fft_reference"] = cpu_fft_reference(args, np, m_np, results[torch.float64]["plan"], H64)
+            print(f"# cpu_fft_reference: {out['cpu_fft_reference']}", file=sys.stderr, flush=True)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
@@ -669,6 +712,8 @@ def main():
     ap.add_argument("--tg-steps", type=int, default=10, help="tensor-grid evaluations (0: skip)")
     ap.add_argument("--llg-steps", type=int, default=100, help="LLG Heun steps (0: skip)")
     ap.add_argument("--lowrank-steps", type=int, default=200, help="low-rank TG evaluations (0: skip)")
+    ap.add_argument("--cpu-fft-evals", type=int, default=2,
+                    help="informational host scipy.fft FP64 forward fields (0: skip)")
     ap.add_argument("--rocfft-steps", type=int, default=30,
                     help="informational torch.fft (rocFFT) forward fields beside the plan's (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
