@@ -170,7 +170,15 @@ hipError_t launch_tg_stack3(hipStream_t, int n3, int R, const double* c, const T
 template <typename T>
 int tg_potential(void* handle, hipStream_t st, int n1, int n2, int n3, int R, const T* m, const T* D1E,
                  const T* D1O, const T* const* D2p[3], const T* const* Y1k, T* const* Y2k, const T* const B3[3], T* Y1,
-                 T* Y2, T* phi, double alpha);
+                 T* Y2, T* phi, double alpha, int sol1 = 0, int sol2 = 0, int sol3 = 0);
+// rocBLAS solutions for the three GEMMs of tg_potential, chosen by timing on
+// the given buffers (Mp: a mode-1 input; Y1, Y2 (behind Y2k) and phi are
+// overwritten); 0 (the default) for FP64 or when no faster solution agrees
+// with the default's result.
+template <typename T>
+int tg_tune(void* handle, hipStream_t st, int n1, int n2, int n3, int R, const T* D1, const T* Mp, T* Y1,
+            const T* const* Y1k, const T* const* D2k, T* const* Y2k, T* Y2, const T* B3, T* phi, int* sol1, int* sol2,
+            int* sol3);
 
 // ---- low-rank tensor grid (lowrank.hip) ---------------------------------------
 // Stacked Gaussian matrices of one axis for every node: [R][2n x n] column-major,

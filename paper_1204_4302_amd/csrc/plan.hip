@@ -158,6 +158,7 @@ struct TGState {
     void *Y1 = nullptr, *Y2 = nullptr;
     void **Y1k = nullptr, **Y2k = nullptr, **D2kE = nullptr, **D2kO = nullptr;
     size_t bytes = 0;
+    int sol1 = 0, sol2 = 0, sol3 = 0;  // rocBLAS solutions of the mode-product GEMMs (0: the default)
 };
 
 // Low-rank tensor-grid state (after demag_tg_lowrank_prepare): nodes,
@@ -546,7 +547,7 @@ int run_tg_field(demag_plan_s* p, const T* m, double Ms, T* H, double* E_dev, hi
     const double hmax = std::max(p->d[0], std::max(p->d[1], p->d[2]));
     const int rc = tg_potential<T>(g->handle, st, nx, ny, nz, g->R, m, (const T*)g->D1E, (const T*)g->D1O, D2p,
                                    (const T* const*)g->Y1k, (T* const*)g->Y2k, B3, (T*)g->Y1, (T*)g->Y2, phi,
-                                   Ms * hmax);
+                                   Ms * hmax, g->sol1, g->sol2, g->sol3);
     if (rc) return fail(DEMAG_EHIP, "tensor-grid GEMM failed (%d)", rc);
     int nparts = 0;
     HIP_TRY(launch_sp_gradient<T>(st, nx, ny, nz, p->d, phi, Hout, E_dev ? m : nullptr, E_dev ? p->partials : nullptr,
@@ -639,6 +640,18 @@ int setup_tg(demag_plan_s* p, hipStream_t st, double step) {
         rocblas_handle h = nullptr;
         if (rocblas_create_handle(&h) != rocblas_status_success) rc = fail(DEMAG_EHIP, "rocblas_create_handle failed");
         g->handle = h;
+    }
+    if (!rc) {
+        // the mode-1 and mode-3 GEMMs' rocBLAS solutions, timed on the plan's buffers: a
+        // mode-1 input and Y2 filled with a finite pattern (bytes 0x3C: 0.0115 in FP32) in
+        // the plan's B1 scratch and in Y2, the plan's B2 scratch as the mode-3 output
+        if (hipMemsetAsync(g->Y2, 0x3C, (size_t)R * N * sz, st) != hipSuccess ||
+            hipMemsetAsync(p->B1, 0x3C, N * sz, st) != hipSuccess)
+            rc = fail(DEMAG_EHIP, "tuning fill");
+        if (!rc && tg_tune<T>(g->handle, st, n1, n2, n3, R, (const T*)g->D1E, (const T*)p->B1, (T*)g->Y1,
+                              (const T* const*)g->Y1k, (const T* const*)g->D2kE, (T* const*)g->Y2k, (T*)g->Y2,
+                              (const T*)g->B3E, (T*)p->B2, &g->sol1, &g->sol2, &g->sol3))
+            rc = fail(DEMAG_EHIP, "tensor-grid GEMM tuning failed");
     }
     return rc;
 }

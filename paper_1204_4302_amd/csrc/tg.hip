@@ -20,8 +20,10 @@
 //     mode 2: Y2[l](:,:,k) = Y1[l](:,:,k) D_2[l]^T   (pointer-batched over l, k)
 //     mode 3: Phi += [Y2[0] .. Y2[R-1]] [c_l D_3[l]^T stacked]  (one GEMM, K = R n3)
 // The field is the finite-difference gradient of the SP method.
+#define ROCBLAS_BETA_FEATURES_API  // rocblas_gemm_ex_get_solutions: the mode-3 solution is chosen by timing
 #include <rocblas/rocblas.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -107,10 +109,199 @@ template hipError_t launch_tg_stack3<double>(hipStream_t, int, int, const double
 // [n3][R n3] stacked mode-3 factors with c_l folded in; Y1, Y2 [R][N]
 // scratch; Y1k/Y2k/D2p device pointer arrays for the mode-2 batch (R n3
 // entries each; D2p per component).  alpha = Ms h_max.
+namespace {
+
+// mode 3: phi (M x N) = al Y2 (M x K) B3 (K x N) + be phi, column-major; FP32
+// with rocBLAS solution `sol` (0: rocBLAS's default choice).
+rocblas_status mode3(rocblas_handle h, int M, int N, int K, const float* al, const float* A, const float* B,
+                     const float* be, float* C, int sol) {
+    if (sol == 0) return gemm(h, rocblas_operation_none, rocblas_operation_none, M, N, K, al, A, M, B, K, be, C, M);
+    return rocblas_gemm_ex(h, rocblas_operation_none, rocblas_operation_none, M, N, K, al, A, rocblas_datatype_f32_r, M,
+                           B, rocblas_datatype_f32_r, K, be, C, rocblas_datatype_f32_r, M, C, rocblas_datatype_f32_r, M,
+                           rocblas_datatype_f32_r, rocblas_gemm_algo_solution_index, sol, 0);
+}
+rocblas_status mode3(rocblas_handle h, int M, int N, int K, const double* al, const double* A, const double* B,
+                     const double* be, double* C, int) {
+    return gemm(h, rocblas_operation_none, rocblas_operation_none, M, N, K, al, A, M, B, K, be, C, M);
+}
+
+// mode 1: Y1[l] (n1 x n2 n3) = D1[l] (n1 x n1) Mp (n1 x n2 n3) for l < R (Mp
+// shared: stride 0); FP32 with rocBLAS solution `sol` (0: the default).
+rocblas_status mode1(rocblas_handle h, int n1, int nc, int R, const float* D1, const float* Mp, float* Y1, int sol) {
+    const float one = 1, zero = 0;
+    const rocblas_stride sD = (rocblas_stride)n1 * n1, sY = (rocblas_stride)n1 * nc;
+    if (sol == 0)
+        return gemm_sb(h, rocblas_operation_none, rocblas_operation_none, n1, nc, n1, &one, D1, n1, sD, Mp, n1, 0,
+                       &zero, Y1, n1, sY, R);
+    return rocblas_gemm_strided_batched_ex(h, rocblas_operation_none, rocblas_operation_none, n1, nc, n1, &one, D1,
+                                           rocblas_datatype_f32_r, n1, sD, Mp, rocblas_datatype_f32_r, n1, 0, &zero,
+                                           Y1, rocblas_datatype_f32_r, n1, sY, Y1, rocblas_datatype_f32_r, n1, sY, R,
+                                           rocblas_datatype_f32_r, rocblas_gemm_algo_solution_index, sol, 0);
+}
+rocblas_status mode1(rocblas_handle h, int n1, int nc, int R, const double* D1, const double* Mp, double* Y1, int) {
+    const double one = 1, zero = 0;
+    return gemm_sb(h, rocblas_operation_none, rocblas_operation_none, n1, nc, n1, &one, D1, n1,
+                   (rocblas_stride)n1 * n1, Mp, n1, 0, &zero, Y1, n1, (rocblas_stride)n1 * nc, R);
+}
+
+// mode 2: Y2[l](:,:,k) (n1 x n2) = Y1[l](:,:,k) (n1 x n2) D2[l]^T for the
+// `batch` (l, k) pairs of the pointer arrays; FP32 with rocBLAS solution `sol`
+// (0: the default).
+rocblas_status mode2(rocblas_handle h, int n1, int n2, int batch, const float* const* Y1k, const float* const* D2,
+                     float* const* Y2k, int sol) {
+    const float one = 1, zero = 0;
+    if (sol == 0)
+        return gemm_b(h, rocblas_operation_none, rocblas_operation_transpose, n1, n2, n2, &one, Y1k, n1, D2, n2,
+                      &zero, Y2k, n1, batch);
+    return rocblas_gemm_batched_ex(h, rocblas_operation_none, rocblas_operation_transpose, n1, n2, n2, &one, Y1k,
+                                   rocblas_datatype_f32_r, n1, D2, rocblas_datatype_f32_r, n2, &zero, Y2k,
+                                   rocblas_datatype_f32_r, n1, (void*)Y2k, rocblas_datatype_f32_r, n1, batch,
+                                   rocblas_datatype_f32_r, rocblas_gemm_algo_solution_index, sol, 0);
+}
+rocblas_status mode2(rocblas_handle h, int n1, int n2, int batch, const double* const* Y1k, const double* const* D2,
+                     double* const* Y2k, int) {
+    const double one = 1, zero = 0;
+    return gemm_b(h, rocblas_operation_none, rocblas_operation_transpose, n1, n2, n2, &one, Y1k, n1, D2, n2, &zero,
+                  Y2k, n1, batch);
+}
+
+// Of the candidate solutions `sols` (each run by run(sol); 0 is rocBLAS's
+// default), the fastest that beats the default and whose first `cmp` output
+// values agree with the default's to 1e-5 (relative max-norm: no solution of
+// reduced precision is taken); 0 if none.  Each candidate is timed once (one
+// warm-up, three runs); a candidate that cannot run the problem is skipped.
+template <typename RunF>
+int pick_solution(hipStream_t st, const std::vector<rocblas_int>& sols, RunF run, const float* out, size_t cmp,
+                  int* best) {
+    *best = 0;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -3;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return -3;
+    }
+    auto time_sol = [&](int sol, float* ms) {
+        if (run(sol) != rocblas_status_success) return false;
+        if (hipEventRecord(e0, st) != hipSuccess) return false;
+        for (int r = 0; r < 3; ++r)
+            if (run(sol) != rocblas_status_success) return false;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return false;
+        return hipEventElapsedTime(ms, e0, e1) == hipSuccess;
+    };
+    std::vector<std::pair<float, int>> times;
+    float t0 = 0;
+    int rc = time_sol(0, &t0) ? 0 : -4;
+    for (size_t i = 0; i < sols.size() && !rc; ++i) {
+        float t = 0;
+        if (sols[i] != 0 && time_sol(sols[i], &t)) times.push_back({t, sols[i]});
+        (void)hipGetLastError();
+    }
+    std::sort(times.begin(), times.end());
+    std::vector<float> ref(cmp), got(cmp);
+    if (!rc && (run(0) != rocblas_status_success ||
+                hipMemcpyAsync(ref.data(), out, sizeof(float) * cmp, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipStreamSynchronize(st) != hipSuccess))
+        rc = -5;
+    double scale = 0;
+    for (float v : ref) scale = std::max(scale, (double)std::fabs(v));
+    for (size_t i = 0; i < times.size() && i < 8 && !rc && times[i].first < t0; ++i) {
+        if (run(times[i].second) != rocblas_status_success) continue;
+        if (hipMemcpyAsync(got.data(), out, sizeof(float) * cmp, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            rc = -5;
+            break;
+        }
+        double err = 0;
+        for (size_t j = 0; j < cmp; ++j) err = std::max(err, (double)std::fabs(got[j] - ref[j]));
+        if (scale > 0 && err <= 1e-5 * scale) {
+            *best = times[i].second;
+            break;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return rc;
+}
+
+}  // namespace
+
+// rocBLAS's default choice pads its tiles for some of the mode products'
+// shapes (mode 3 is skinny: N = n3 against M = n1 n2 and K = R n3); every
+// solution rocBLAS offers for each of the three GEMMs is timed once on the
+// plan's buffers and the fastest that agrees with the default is kept
+// (pick_solution).  Mode 2 runs after mode 1 and before mode 3, so that each
+// reads the previous one's output.  FP64 keeps the defaults.
+template <>
+int tg_tune<float>(void* handle, hipStream_t st, int n1, int n2, int n3, int R, const float* D1, const float* Mp,
+                   float* Y1, const float* const* Y1k, const float* const* D2k, float* const* Y2k, float* Y2,
+                   const float* B3, float* phi, int* sol1, int* sol2, int* sol3) {
+    *sol1 = *sol2 = *sol3 = 0;
+    rocblas_handle h = (rocblas_handle)handle;
+    if (rocblas_set_stream(h, st) != rocblas_status_success) return -1;
+    const float one = 1, zero = 0;
+    const int nc = n2 * n3, M = n1 * n2, K = R * n3;
+    std::vector<rocblas_int> sols;
+    rocblas_int count = 0;
+    // mode 1
+    const rocblas_stride sD = (rocblas_stride)n1 * n1, sY = (rocblas_stride)n1 * nc;
+    auto list1 = [&](rocblas_int* arr) {
+        return rocblas_gemm_strided_batched_ex_get_solutions(
+            h, rocblas_operation_none, rocblas_operation_none, n1, nc, n1, &one, D1, rocblas_datatype_f32_r, n1, sD, Mp,
+            rocblas_datatype_f32_r, n1, 0, &zero, Y1, rocblas_datatype_f32_r, n1, sY, Y1, rocblas_datatype_f32_r, n1, sY,
+            R, rocblas_datatype_f32_r, rocblas_gemm_algo_solution_index, 0, arr, &count);
+    };
+    int rc = 0;
+    if (list1(nullptr) == rocblas_status_success && count > 0) {
+        sols.assign((size_t)count, 0);
+        if (list1(sols.data()) == rocblas_status_success)
+            rc = pick_solution(st, sols, [&](int sol) { return mode1(h, n1, nc, R, D1, Mp, Y1, sol); }, Y1,
+                               std::min<size_t>((size_t)R * n1 * nc, (size_t)1 << 22), sol1);
+    }
+    if (rc) return rc;
+    // mode 2
+    count = 0;
+    const int nb = R * n3;
+    auto list2 = [&](rocblas_int* arr) {
+        return rocblas_gemm_batched_ex_get_solutions(
+            h, rocblas_operation_none, rocblas_operation_transpose, n1, n2, n2, &one, Y1k, rocblas_datatype_f32_r, n1,
+            D2k, rocblas_datatype_f32_r, n2, &zero, Y2k, rocblas_datatype_f32_r, n1, (void*)Y2k, rocblas_datatype_f32_r, n1,
+            nb, rocblas_datatype_f32_r, rocblas_gemm_algo_solution_index, 0, arr, &count);
+    };
+    if (list2(nullptr) == rocblas_status_success && count > 0) {
+        sols.assign((size_t)count, 0);
+        if (list2(sols.data()) == rocblas_status_success)
+            rc = pick_solution(st, sols, [&](int sol) { return mode2(h, n1, n2, nb, Y1k, D2k, Y2k, sol); }, Y2,
+                               std::min<size_t>((size_t)nb * n1 * n2, (size_t)1 << 22), sol2);
+    }
+    if (rc) return rc;
+    // mode 3
+    count = 0;
+    auto list3 = [&](rocblas_int* arr) {
+        return rocblas_gemm_ex_get_solutions(h, rocblas_operation_none, rocblas_operation_none, M, n3, K, &one, Y2,
+                                             rocblas_datatype_f32_r, M, B3, rocblas_datatype_f32_r, K, &zero, phi,
+                                             rocblas_datatype_f32_r, M, phi, rocblas_datatype_f32_r, M,
+                                             rocblas_datatype_f32_r, rocblas_gemm_algo_solution_index, 0, arr, &count);
+    };
+    if (list3(nullptr) == rocblas_status_success && count > 0) {
+        sols.assign((size_t)count, 0);
+        if (list3(sols.data()) == rocblas_status_success)
+            rc = pick_solution(st, sols, [&](int sol) { return mode3(h, M, n3, K, &one, Y2, B3, &zero, phi, sol); },
+                               phi, std::min<size_t>((size_t)M * n3, (size_t)1 << 22), sol3);
+    }
+    return rc;
+}
+template <>
+int tg_tune<double>(void*, hipStream_t, int, int, int, int, const double*, const double*, double*,
+                    const double* const*, const double* const*, double* const*, double*, const double*, double*,
+                    int* sol1, int* sol2, int* sol3) {
+    *sol1 = *sol2 = *sol3 = 0;
+    return 0;
+}
+
 template <typename T>
 int tg_potential(void* handle, hipStream_t st, int n1, int n2, int n3, int R, const T* m, const T* D1E,
                  const T* D1O, const T* const* D2p[3], const T* const* Y1k, T* const* Y2k, const T* const B3[3], T* Y1,
-                 T* Y2, T* phi, double alpha) {
+                 T* Y2, T* phi, double alpha, int sol1, int sol2, int sol3) {
     rocblas_handle h = (rocblas_handle)handle;
     if (rocblas_set_stream(h, st) != rocblas_status_success) return -1;
     const size_t N = (size_t)n1 * n2 * n3;
@@ -118,17 +309,12 @@ int tg_potential(void* handle, hipStream_t st, int n1, int n2, int n3, int R, co
     for (int p = 0; p < 3; ++p) {
         const T* D1 = p == 0 ? D1O : D1E;
         // mode 1: Y1[l] (n1 x n2 n3) = D1[l] (n1 x n1) M_p (n1 x n2 n3)
-        if (gemm_sb(h, rocblas_operation_none, rocblas_operation_none, n1, n2 * n3, n1, &one, D1, n1,
-                    (rocblas_stride)n1 * n1, m + (size_t)p * N, n1, 0, &zero, Y1, n1, (rocblas_stride)N, R) !=
-            rocblas_status_success)
-            return -2;
+        if (mode1(h, n1, n2 * n3, R, D1, m + (size_t)p * N, Y1, sol1) != rocblas_status_success) return -2;
         // mode 2: Y2[l](:,:,k) (n1 x n2) = Y1[l](:,:,k) (n1 x n2) D2[l]^T
-        if (gemm_b(h, rocblas_operation_none, rocblas_operation_transpose, n1, n2, n2, &one, Y1k, n1, D2p[p], n2,
-                   &zero, Y2k, n1, R * n3) != rocblas_status_success)
-            return -3;
+        if (mode2(h, n1, n2, R * n3, Y1k, D2p[p], Y2k, sol2) != rocblas_status_success) return -3;
         // mode 3 and the node sum: phi (n1 n2 x n3) (+)= alpha Y2 (n1 n2 x R n3) B3[p] (R n3 x n3)
-        if (gemm(h, rocblas_operation_none, rocblas_operation_none, n1 * n2, n3, R * n3, &al, Y2, n1 * n2, B3[p],
-                 R * n3, p == 0 ? &zero : &one, phi, n1 * n2) != rocblas_status_success)
+        if (mode3(h, n1 * n2, n3, R * n3, &al, Y2, B3[p], p == 0 ? &zero : &one, phi, sol3) !=
+            rocblas_status_success)
             return -4;
     }
     (void)Y1;
@@ -137,9 +323,9 @@ int tg_potential(void* handle, hipStream_t st, int n1, int n2, int n3, int R, co
 
 template int tg_potential<float>(void*, hipStream_t, int, int, int, int, const float*, const float*, const float*,
                                  const float* const* [3], const float* const*, float* const*, const float* const[3],
-                                 float*, float*, float*, double);
+                                 float*, float*, float*, double, int, int, int);
 template int tg_potential<double>(void*, hipStream_t, int, int, int, int, const double*, const double*,
                                   const double*, const double* const* [3], const double* const*, double* const*,
-                                  const double* const[3], double*, double*, double*, double);
+                                  const double* const[3], double*, double*, double*, double, int, int, int);
 
 }  // namespace demag
