@@ -19,7 +19,9 @@
 //     mode 1: Y1[l] = D_1[l] M_p                (strided-batched over l)
 //     mode 2: Y2[l](:,:,k) = Y1[l](:,:,k) D_2[l]^T   (pointer-batched over l, k)
 //     mode 3: Phi += [Y2[0] .. Y2[R-1]] [c_l D_3[l]^T stacked]  (one GEMM, K = R n3)
-// The field is the finite-difference gradient of the SP method.
+// In FP32 each of the three runs the rocBLAS solution chosen for its shape
+// when the method is prepared (tg_tune).  The field is the finite-difference
+// gradient of the SP method.
 #define ROCBLAS_BETA_FEATURES_API  // rocblas_gemm_ex_get_solutions: the mode-3 solution is chosen by timing
 #include <rocblas/rocblas.h>
 
