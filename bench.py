@@ -736,8 +736,8 @@ def main():
         summarize_profile(args.summarize_profile, args.out or "/dev/stdout", args.command, args.match)
         return 0
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(this build measures the one-GPU path only)", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU and measures the one-GPU path only; --gpus {args.gpus} "
+              "is not supported", file=sys.stderr)
         return 2
     if args.copy_calibration:
         import torch
