@@ -168,7 +168,9 @@ def bench_tg(args, torch, np, m_np, dm_value):
     same workload, FP32: potential by GEMMs (MFMA), field by differences."""
     from paper_1204_4302_amd import Plan
     plan = Plan(SHAPE, CELL, torch.float32)
-    plan.tg_prepare()
+    t0 = time.perf_counter()
+    plan.tg_prepare()  # matrices, scratch, and the timed choice of the GEMMs' rocBLAS solutions
+    prepare_s = time.perf_counter() - t0
     info = plan.tg_info()
     m = torch.from_numpy(m_np).to("cuda", torch.float32)
     H = torch.empty_like(m)
@@ -184,7 +186,7 @@ def bench_tg(args, torch, np, m_np, dm_value):
     tflops = info["flops_per_eval"] * k / secs / 1e12
     out = {"value": round(k / secs, 2), "unit": "evals/s", "ms_per_eval": round(1e3 * secs / k, 3),
            "sinc_nodes": info["nodes"], "flops_per_eval": info["flops_per_eval"],
-           "scratch_bytes": info["scratch_bytes"],
+           "scratch_bytes": info["scratch_bytes"], "prepare_s": round(prepare_s, 2),
            "roofline": {"bound": "mfma", "achieved": round(tflops, 1), "peak": MFMA_FP32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(tflops / MFMA_FP32_PEAK_TFLOPS, 4),
                         "note": "mode-product GEMM flops over the whole evaluation (gradient included in the time)"},
