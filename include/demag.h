@@ -179,7 +179,7 @@ int demag_llg_heun(demag_plan_t plan, void* m, double Ms, double alpha, double g
  * (2 R N values; R nodes, about 75 in FP32 and 125 in FP64 at 256 x 256 x 64);
  * in FP32 it also times the rocBLAS solutions of the three GEMM shapes on
  * these buffers and keeps, per shape, the fastest whose result agrees with
- * rocBLAS's default to 1e-5 (about a second at 256 x 256 x 64; the plan's
+ * rocBLAS's default to 1e-5 (preparation takes about 2 s at 256 x 256 x 64; the plan's
  * spectrum scratch is overwritten); synchronous; idempotent; DEMAG_ENOMEM if
  * the scratch does not fit. */
 int demag_tg_prepare(demag_plan_t plan, void* stream);
