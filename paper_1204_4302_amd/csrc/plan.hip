@@ -425,13 +425,13 @@ struct SetupBufs {
     double* glx = nullptr;
     double* glw = nullptr;
     ~SetupBufs() {
-        hipFree(Noct);
-        hipFree(A);
-        hipFree(B1);
-        hipFree(B2);
-        for (auto t : tw) hipFree(t);
-        hipFree(glx);
-        hipFree(glw);
+        (void)hipFree(Noct);
+        (void)hipFree(A);
+        (void)hipFree(B1);
+        (void)hipFree(B2);
+        for (auto t : tw) (void)hipFree(t);
+        (void)hipFree(glx);
+        (void)hipFree(glw);
     }
 };
 
@@ -634,8 +634,8 @@ int setup_tg(demag_plan_s* p, hipStream_t st, double step) {
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = hip_fail(e, "tensor-grid setup");
     }
-    hipFree(D3E);
-    hipFree(D3O);
+    (void)hipFree(D3E);
+    (void)hipFree(D3O);
     if (!rc) {
         rocblas_handle h = nullptr;
         if (rocblas_create_handle(&h) != rocblas_status_success) rc = fail(DEMAG_EHIP, "rocblas_create_handle failed");
@@ -668,7 +668,7 @@ void free_tg(TGState* g) {
     if (g->handle) rocblas_destroy_handle((rocblas_handle)g->handle);
     for (void* q : {(void*)g->tau, (void*)g->c, g->D1E, g->D1O, g->D2E, g->D2O, g->B3E, g->B3O, g->Y1, g->Y2,
                     (void*)g->Y1k, (void*)g->Y2k, (void*)g->D2kE, (void*)g->D2kO})
-        hipFree(q);
+        (void)hipFree(q);
     delete g;
 }
 
@@ -677,7 +677,7 @@ void free_lr(LRState* g) {
     if (g->handle) rocblas_destroy_handle((rocblas_handle)g->handle);
     for (void* q : {(void*)g->tau, (void*)g->c, g->DE[0], g->DE[1], g->DE[2], g->DO[0], g->DO[1], g->DO[2],
                     (void*)g->partials, (void*)g->gram, g->W})
-        hipFree(q);
+        (void)hipFree(q);
     delete g;
 }
 
@@ -735,19 +735,19 @@ int setup_lr(demag_plan_s* p, hipStream_t st, double step) {
 }
 
 void free_plan(demag_plan_s* p) {
-    for (auto t : p->tw) hipFree(t);
-    for (auto t : p->twt) hipFree(t);
-    hipFree(p->nhat);
-    hipFree(p->shat);
+    for (auto t : p->tw) (void)hipFree(t);
+    for (auto t : p->twt) (void)hipFree(t);
+    (void)hipFree(p->nhat);
+    (void)hipFree(p->shat);
     free_tg(p->tg);
     free_lr(p->lr);
     if (p->als_handle) rocblas_destroy_handle((rocblas_handle)p->als_handle);
-    hipFree(p->B1);
-    hipFree(p->B2);
-    hipFree(p->partials);
-    hipFree(p->e_dev);
-    if (p->done) hipEventDestroy(p->done);
-    for (auto e : p->tev) hipEventDestroy(e);
+    (void)hipFree(p->B1);
+    (void)hipFree(p->B2);
+    (void)hipFree(p->partials);
+    (void)hipFree(p->e_dev);
+    if (p->done) (void)hipEventDestroy(p->done);
+    for (auto e : p->tev) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -945,7 +945,7 @@ int run_compress(demag_plan_s* p, hipStream_t st, int format, int r, int sweeps,
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = hip_fail(e, "ALS compression");
     }
-    hipFree(buf);
+    (void)hipFree(buf);
     if (rc) return rc;
     if (flag)
         return fail(DEMAG_EINVAL, "a Gram matrix of the factors is not positive definite (rank %d above the "
@@ -1096,7 +1096,7 @@ int demag_plan_set_option(demag_plan_t p, const char* key, double value) {
         if (!(value >= 0) || value != std::floor(value) || value > 1e6)
             return fail(DEMAG_EINVAL, "pass_timing must be an integer in [0, 1e6]");
         HIP_TRY(hipDeviceSynchronize());
-        for (auto e : p->tev) hipEventDestroy(e);
+        for (auto e : p->tev) (void)hipEventDestroy(e);
         p->tev.assign((size_t)value * kPassMarks, nullptr);
         for (auto& e : p->tev) HIP_TRY(hipEventCreate(&e));
         p->tcap = (int)value;
@@ -1116,7 +1116,7 @@ int demag_plan_set_option(demag_plan_t p, const char* key, double value) {
 
 int demag_plan_destroy(demag_plan_t p) {
     if (!p) return fail(DEMAG_EINVAL, "NULL plan");
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     free_plan(p);
     return DEMAG_OK;
 }
@@ -1226,7 +1226,7 @@ int demag_sp_prepare(demag_plan_t p, void* stream) {
     }
     rc = p->dtype == DEMAG_F32 ? setup_sp_spectrum<float>(p, st) : setup_sp_spectrum<double>(p, st);
     if (rc) {
-        hipFree(p->shat);
+        (void)hipFree(p->shat);
         p->shat = nullptr;
         return rc;
     }
@@ -1375,7 +1375,7 @@ int demag_tg_lowrank_field(demag_plan_t p, int format, int rank, const void* cor
         const size_t want = std::min<size_t>((size_t)p->n[2] * per_slice, std::max(p->lr_cap, per_slice));
         if (want != g->w_bytes && (want > g->w_bytes || g->w_bytes > std::max(p->lr_cap, per_slice))) {
             HIP_TRY(hipDeviceSynchronize());  // the old scratch may still be in use
-            hipFree(g->W);
+            (void)hipFree(g->W);
             g->bytes -= g->w_bytes;
             g->W = nullptr;
             g->w_bytes = 0;
@@ -1393,7 +1393,7 @@ int demag_tg_lowrank_field(demag_plan_t p, int format, int rank, const void* cor
         const size_t want = (size_t)27 * g->R * rank * rank * sizeof(double);
         if (want > g->gram_bytes) {
             HIP_TRY(hipDeviceSynchronize());  // the old buffer may still be in use
-            hipFree(g->gram);
+            (void)hipFree(g->gram);
             g->bytes -= g->gram_bytes;
             g->gram = nullptr;
             g->gram_bytes = 0;
@@ -1670,8 +1670,8 @@ int time_pass(demag_plan_s* p, int which, const LaunchCfg& lc, hipStream_t st, c
         if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
         best = std::min(best, ms / reps);
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (err != hipSuccess) return hip_fail(err, "autotune timing");
     *ms_out = best;
     return DEMAG_OK;
@@ -1704,8 +1704,8 @@ int autotune_impl(demag_plan_s* p, hipStream_t st) {
         }
         *slot[which] = bestc;
     }
-    hipFree(m);
-    hipFree(H);
+    (void)hipFree(m);
+    (void)hipFree(H);
     return rc;
 }
 
@@ -1788,8 +1788,8 @@ int enqueue_group(const BatchGroup& grp, double Ms, hipStream_t st) {
 // Record every group's launches into the batch's graph (replacing an earlier
 // one): groups on up to kBranches forked capture streams, joined at the end.
 int record_graph(demag_batch_s* b) {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
     int rc = DEMAG_OK;
@@ -1809,17 +1809,23 @@ int record_graph(demag_batch_s* b) {
         else
             capturing = true;
     }
+    // the fork and join of the capture streams: a failed record or wait would
+    // leave a dependency out of the graph, so each is checked
+    auto chk = [&](hipError_t e, const char* what) {
+        if (!rc && e != hipSuccess) rc = hip_fail(e, what);
+    };
     if (!rc) {
-        hipEventRecord(ev[kBranches], cs[0]);
-        for (int k = 1; k < nb; ++k) hipStreamWaitEvent(cs[k], ev[kBranches], 0);
+        chk(hipEventRecord(ev[kBranches], cs[0]), "hipEventRecord (capture fork)");
+        for (int k = 1; k < nb; ++k)
+            chk(hipStreamWaitEvent(cs[k], ev[kBranches], 0), "hipStreamWaitEvent (capture fork)");
         for (size_t gi = 0; gi < b->groups.size() && !rc; ++gi) {
             const BatchGroup& g = b->groups[gi];
             rc = g.lead->dtype == DEMAG_F32 ? enqueue_group<float>(g, b->Ms, cs[gi % nb])
                                             : enqueue_group<double>(g, b->Ms, cs[gi % nb]);
         }
         for (int k = 1; k < nb; ++k) {
-            hipEventRecord(ev[k], cs[k]);
-            hipStreamWaitEvent(cs[0], ev[k], 0);
+            chk(hipEventRecord(ev[k], cs[k]), "hipEventRecord (capture join)");
+            chk(hipStreamWaitEvent(cs[0], ev[k], 0), "hipStreamWaitEvent (capture join)");
         }
     }
     if (capturing) {
@@ -1831,10 +1837,10 @@ int record_graph(demag_batch_s* b) {
             rc = fail(DEMAG_EHIP, "hipGraphInstantiate failed");
     }
     for (int k = 0; k < nb; ++k) {
-        if (cs[k]) hipStreamDestroy(cs[k]);
-        if (ev[k]) hipEventDestroy(ev[k]);
+        if (cs[k]) (void)hipStreamDestroy(cs[k]);
+        if (ev[k]) (void)hipEventDestroy(ev[k]);
     }
-    if (ev[kBranches]) hipEventDestroy(ev[kBranches]);
+    if (ev[kBranches]) (void)hipEventDestroy(ev[kBranches]);
     return rc;
 }
 
@@ -1878,8 +1884,8 @@ int tune_group(BatchGroup& g, hipStream_t st) {
         }
         *slot[w] = bestc;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (err != hipSuccess) return hip_fail(err, "batch autotune timing");
     return DEMAG_OK;
 }
@@ -1941,10 +1947,10 @@ extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans,
     }
     if (!rc) rc = record_graph(b);
     if (rc) {
-        if (b->exec) hipGraphExecDestroy(b->exec);
-        if (b->graph) hipGraphDestroy(b->graph);
-        if (b->done) hipEventDestroy(b->done);
-        hipFree(b->dev_lists);
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        if (b->done) (void)hipEventDestroy(b->done);
+        (void)hipFree(b->dev_lists);
         delete b;
         return rc;
     }
@@ -1993,13 +1999,13 @@ extern "C" int demag_batch_launch(demag_batch_t b, void* stream) {
 
 extern "C" int demag_batch_destroy(demag_batch_t b) {
     if (!b) return fail(DEMAG_EINVAL, "NULL batch");
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     for (auto p : b->plans)  // the replays are complete: drop the reference to the batch's event
         if (p->busy == b->done) p->busy = nullptr;
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
-    if (b->done) hipEventDestroy(b->done);
-    hipFree(b->dev_lists);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->done) (void)hipEventDestroy(b->done);
+    (void)hipFree(b->dev_lists);
     delete b;
     return DEMAG_OK;
 }

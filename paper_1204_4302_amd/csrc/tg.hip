@@ -179,7 +179,7 @@ int pick_solution(hipStream_t st, const std::vector<rocblas_int>& sols, RunF run
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -3;
     if (hipEventCreate(&e1) != hipSuccess) {
-        hipEventDestroy(e0);
+        (void)hipEventDestroy(e0);
         return -3;
     }
     auto time_sol = [&](int sol, float* ms) {
@@ -220,8 +220,8 @@ int pick_solution(hipStream_t st, const std::vector<rocblas_int>& sols, RunF run
             break;
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     return rc;
 }
 
@@ -233,6 +233,9 @@ int pick_solution(hipStream_t st, const std::vector<rocblas_int>& sols, RunF run
 // plan's buffers and the fastest that agrees with the default is kept
 // (pick_solution).  Mode 2 runs after mode 1 and before mode 3, so that each
 // reads the previous one's output.  FP64 keeps the defaults.
+// rocBLAS marks its solution listing as a beta interface (deprecation attribute)
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wdeprecated-declarations"
 template <>
 int tg_tune<float>(void* handle, hipStream_t st, int n1, int n2, int n3, int R, const float* D1, const float* Mp,
                    float* Y1, const float* const* Y1k, const float* const* D2k, float* const* Y2k, float* Y2,
@@ -292,6 +295,7 @@ int tg_tune<float>(void* handle, hipStream_t st, int n1, int n2, int n3, int R, 
     }
     return rc;
 }
+#pragma clang diagnostic pop
 template <>
 int tg_tune<double>(void*, hipStream_t, int, int, int, int, const double*, const double*, double*,
                     const double* const*, const double* const*, double* const*, double*, const double*, double*,
