@@ -581,9 +581,14 @@ def bench(args):
     if torch.float64 in results:
         r64 = results[torch.float64]
         v64 = 2 * r64["steps"] / r64["secs"]
+        i64 = r64["info"]
+        pb64 = pass_bytes(SHAPE, i64["Px"], i64["Py"], i64["Pz"], i64["Kx"], 8)
+        step64 = 2 * sum(pb64.values()) + 3 * nx * ny * nz * 8  # as the FP32 step, 8-byte reals
         out["fp64"] = {"value": round(v64, 2), "unit": "evals/s",
                        "ms_per_step": round(1e3 * r64["secs"] / r64["steps"], 4),
-                       "speedup_fp32_over_fp64": round(value / v64, 3)}
+                       "speedup_fp32_over_fp64": round(value / v64, 3),
+                       "roofline": hbm_roofline(step64 * r64["steps"], r64["secs"],
+                                                "whole FP64 step (modelled bytes of both evaluations)")}
         H64 = r64["H"]
         out["accuracy"] = {"f32_vs_f64_gpu_field": float(np.max(np.abs(r32["H"] - H64)) / np.max(np.abs(H64))),
                            "f32_vs_f64_gpu_energy": abs(r32["E"] - r64["E"]) / abs(r64["E"])}
