@@ -109,9 +109,11 @@ __device__ __forceinline__ cx<T> gld_if(gptr<const cx<T>> p, size_t i, bool vali
     const cx<T> v = gld(p, valid ? i : 0);
     return valid ? v : czero<T>();
 }
+// (real values: the magnetization, read once per evaluation, is loaded
+// non-temporally, so that it does not displace the spectrum in the caches)
 template <typename T>
 __device__ __forceinline__ T gldr_if(gptr<const T> p, size_t i, bool valid) {
-    const T v = p[valid ? i : 0];
+    const T v = __builtin_nontemporal_load(&p[valid ? i : 0]);
     return valid ? v : T(0);
 }
 
@@ -380,12 +382,18 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __res
             if (ok0) {
                 const T h = v[j].re;
                 if (m) acc += (double)(m0[j] * h);
-                if (dst) dst[x] = accumulate ? dst[x] + h : h;
+                if (dst) {  // the field is not read again by the evaluation: streamed unless accumulating
+                    if (accumulate) dst[x] = dst[x] + h;
+                    else __builtin_nontemporal_store(h, &dst[x]);
+                }
             }
             if (ok1) {
                 const T h = v[j].im;
                 if (m) acc += (double)(m1[j] * h);
-                if (dst) dst[x + nx] = accumulate ? dst[x + nx] + h : h;
+                if (dst) {
+                    if (accumulate) dst[x + nx] = dst[x + nx] + h;
+                    else __builtin_nontemporal_store(h, &dst[x + nx]);
+                }
             }
         }
     }
