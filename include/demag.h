@@ -101,7 +101,13 @@ int demag_plan_destroy(demag_plan_t plan);
  * nx ny nz Px Py Pz Kx dtype scratch_bytes tensor_bytes setup_us 0... */
 int demag_plan_info(demag_plan_t plan, int64_t* info);
 
-/* H = -Ms N * m  (Sec. 3.1 eq. (demag)); asynchronous on `stream`. */
+/* H = -Ms N * m  (Sec. 3.1 eq. (demag)); asynchronous on `stream`.
+ * demag_field, demag_field_adjoint, demag_field_energy and
+ * demag_energy_async record only kernels (no memset, no synchronisation) and
+ * may be captured into a HIP graph by stream capture: while `stream` is
+ * capturing, the plan's busy tracking and pass timing are skipped; a replay
+ * reads the buffers given at capture.  (A plan must still not run two
+ * evaluations at once.) */
 int demag_field(demag_plan_t plan, const void* m, double Ms, void* H, void* stream);
 
 /* Adjoint (transpose) of m -> H applied to a cotangent gH:

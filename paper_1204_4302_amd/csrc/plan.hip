@@ -794,12 +794,21 @@ const LaunchCfg& pass_cfg(const PassCfgs& c, int which) {
     return *slot[which];
 }
 
+// The caller's stream is being captured into a graph: the plan's busy
+// tracking (an event query, an event record) and its pass timing stay out of
+// the capture.
+bool stream_capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
+
 // one evaluation: X-R2C -> Y -> Z (x N) -> Y^-1 -> X-C2R (+ energy)
 template <typename T>
 int run_field(demag_plan_s* p, const PassCfgs& c, const T* m, double Ms, T* H, const T* m_energy, double* E_dev,
               int accumulate, hipStream_t st) {
     hipEvent_t* mark = nullptr;
-    if (p->tcap > 0 && !p->capturing) mark = &p->tev[(size_t)(p->tcount % p->tcap) * kPassMarks];
+    if (p->tcap > 0 && !p->capturing && !stream_capturing(st))
+        mark = &p->tev[(size_t)(p->tcount % p->tcap) * kPassMarks];
     double* partials = E_dev ? p->partials : nullptr;
     const T* me = E_dev ? m_energy : nullptr;
     for (int which = 0; which < 5; ++which) {
@@ -865,7 +874,7 @@ int dispatch_field(demag_plan_s* p, const void* m, double Ms, void* H, double* E
 // One plan on one stream at a time: refuse a call on another stream while
 // the plan's previous work is still pending.
 int enter(demag_plan_s* p, hipStream_t st) {
-    if (p->capturing) return DEMAG_OK;
+    if (p->capturing || stream_capturing(st)) return DEMAG_OK;
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
     if (cur != p->device) return fail(DEMAG_ESTATE, "plan was created on device %d, current device is %d", p->device, cur);
@@ -879,7 +888,7 @@ int enter(demag_plan_s* p, hipStream_t st) {
 }
 
 int leave(demag_plan_s* p, hipStream_t st) {
-    if (p->capturing) return DEMAG_OK;
+    if (p->capturing || stream_capturing(st)) return DEMAG_OK;
     HIP_TRY(hipEventRecord(p->done, st));
     p->busy = p->done;
     p->last_stream = st;
