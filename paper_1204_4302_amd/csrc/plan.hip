@@ -1873,7 +1873,16 @@ int tune_group(BatchGroup& g, hipStream_t st) {
         float best = 1e30f;
         LaunchCfg bestc = *slot[w];
         for (const auto& lc : cand[w]) {
-            auto launch = [&]() { return launch_pass<T>(p, w, lc, st, nullptr, 1.0, nullptr, nullptr, nullptr, 0, io[w]); };
+            // the group's whole evaluation with the candidate in pass w (as the
+            // plan autotuner: the cache state of the real sequence)
+            auto launch = [&]() {
+                for (int ww = 0; ww < 5; ++ww) {
+                    const LaunchCfg& c = ww == w ? lc : *slot[ww];
+                    if (hipError_t e = launch_pass<T>(p, ww, c, st, nullptr, 1.0, nullptr, nullptr, nullptr, 0, io[ww]))
+                        return e;
+                }
+                return hipSuccess;
+            };
             for (int r = 0; r < 2 && err == hipSuccess; ++r) err = launch();
             float t_best = 1e30f;
             for (int trial = 0; trial < 3 && err == hipSuccess; ++trial) {
