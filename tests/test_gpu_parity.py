@@ -220,3 +220,20 @@ def test_sentinels_around_output():
     plan.field(to_gpu(inputs.random_unit(shape, 2), torch.float32), Ms, out=H)
     torch.cuda.synchronize()
     assert torch.all(buf[:1024] == 12345.0) and torch.all(buf[1024 + n:] == 12345.0)
+
+
+@pytest.mark.parametrize("shape,cell", [((16, 16, 8), (10e-9, 10e-9, 1e-9)), ((24, 6, 4), (1e-9, 1e-9, 10e-9)),
+                                        ((48, 48, 4), (5e-9, 5e-9, 0.5e-9))], ids=lambda v: str(v))
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_flat_and_elongated_cells_vs_oracle(shape, cell, dtype):
+    """Cells with a 10:1 and a 1:10 aspect ratio: the tensor's distance bands
+    (reduced units of the largest edge; far-field series beyond 40 of them,
+    Gauss-Legendre in between) against the binary128 oracle tensor."""
+    o = get_oracle(shape, cell)
+    plan = get_plan(shape, cell, dtype)
+    m = inputs.random_unit(shape, 5)
+    ref = o.field(quantised(m, dtype), 8e5)
+    H = plan.field(to_gpu(m, dtype), 8e5).double().cpu().numpy()
+    err = float(np.abs(H - ref).max() / np.abs(ref).max())
+    print(f"{shape} {cell} {dtype}: {err:.2e}")
+    assert err <= (1e-12 if dtype == torch.float64 else 1e-5)
