@@ -237,3 +237,21 @@ def test_flat_and_elongated_cells_vs_oracle(shape, cell, dtype):
     err = float(np.abs(H - ref).max() / np.abs(ref).max())
     print(f"{shape} {cell} {dtype}: {err:.2e}")
     assert err <= (1e-12 if dtype == torch.float64 else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_cell_scale_invariance(dtype):
+    """The tensor depends on the cell's shape only (lengths reduced by the
+    largest edge): cells scaled by 2^10 (exact in binary, so the reduced edges
+    are the same numbers) give the same field bit for bit, and an energy
+    larger by exactly the volume ratio 2^30."""
+    from paper_1204_4302_amd import Plan
+    shape = (24, 17, 3)
+    small = (1.95e-9, 1.95e-9, 0.75e-9)
+    big = tuple(c * 1024 for c in small)
+    m = to_gpu(inputs.random_unit(shape, 9), dtype)
+    H1, E1 = Plan(shape, small, dtype).field_energy(m, 8e5)
+    H2, E2 = Plan(shape, big, dtype).field_energy(m, 8e5)
+    assert torch.equal(H1, H2)
+    print(f"{dtype}: energy ratio {float(E2) / float(E1)!r}")
+    assert float(E2) == float(E1) * 2.0 ** 30
