@@ -1,0 +1,55 @@
+"""The plan autotuner and its cache file (DEMAG_AUTOTUNE_CACHE): a tuned plan
+writes its launch shapes under a key of version, architecture, precision and
+grid; a second plan of that key reads them back without tuning; a corrupt
+entry is ignored (tuned again and rewritten).  Launch shapes group pencils into
+tiles but do not change any pencil's arithmetic, so the field is the same bit
+for bit whatever the shapes."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1204_4302_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = (64, 48, 16)
+CELL = (2e-9, 2e-9, 3e-9)
+
+
+def _entries(path):
+    with open(path) as f:
+        return [ln.split() for ln in f if ln.strip()]
+
+
+def test_autotune_cache_round_trip_and_shapes_do_not_change_the_field(tmp_path, monkeypatch):
+    from paper_1204_4302_amd import Plan
+    cache = str(tmp_path / "tune.cache")
+    monkeypatch.setenv("DEMAG_AUTOTUNE_CACHE", cache)
+    m = torch.from_numpy(np.ascontiguousarray(inputs.random_unit(SHAPE, 12))).to("cuda", torch.float32)
+    default = Plan(SHAPE, CELL, torch.float32)
+    H_default = default.field(m, 8e5)
+    tuned = Plan(SHAPE, CELL, torch.float32)
+    tuned.autotune()
+    assert os.path.exists(cache)
+    rows = _entries(cache)
+    assert len(rows) == 1 and rows[0][0].startswith("v4|") and rows[0][0].endswith("|f32|64,48,16")
+    assert len(rows[0]) == 6  # key and the five passes' shapes
+    H_tuned = tuned.field(m, 8e5)
+    assert torch.equal(H_tuned, H_default)
+    # a second plan of the same key reads the shapes back
+    again = Plan(SHAPE, CELL, torch.float32)
+    again.autotune()
+    assert again.describe() == tuned.describe()
+    assert _entries(cache) == rows
+    # a corrupt entry is ignored: tuned again, rewritten valid
+    with open(cache, "w") as f:
+        f.write(rows[0][0] + " garbage 1,2,3 x y z\n")
+    fresh = Plan(SHAPE, CELL, torch.float32)
+    fresh.autotune()
+    rows2 = _entries(cache)
+    assert len(rows2) == 1 and rows2[0][0] == rows[0][0] and len(rows2[0]) == 6
+    assert torch.equal(fresh.field(m, 8e5), H_default)
+    for p in (default, tuned, again, fresh):
+        p.close()
