@@ -109,6 +109,13 @@ __device__ __forceinline__ cx<T> gld_if(gptr<const cx<T>> p, size_t i, bool vali
     const cx<T> v = gld(p, valid ? i : 0);
     return valid ? v : czero<T>();
 }
+// The same for a spectrum that its last reader takes: loaded non-temporally.
+template <typename T>
+__device__ __forceinline__ cx<T> gld_last_if(gptr<const cx<T>> p, size_t i, bool valid) {
+    const typename vec2<T>::type v =
+        __builtin_nontemporal_load(&((gptr<const typename vec2<T>::type>)p)[valid ? i : 0]);
+    return valid ? mk(v.x, v.y) : czero<T>();
+}
 // (real values: the magnetization, read once per evaluation, is loaded
 // non-temporally, so that it does not displace the spectrum in the caches)
 template <typename T>
@@ -496,7 +503,7 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) ky_inv(const cx<T>* __res
         const size_t step = (size_t)LT::TP * Kx * nz;
         cx<T> ld[LT::EPT];
 #pragma unroll
-        for (int i = 0; i < LT::EPT; ++i) ld[i] = gld_if(src, i * step, okj);
+        for (int i = 0; i < LT::EPT; ++i) ld[i] = gld_last_if(src, i * step, okj);
         cx<T>* pj = lds + ((zj << lgTx) + xj) * LT::PS;
         const int pk = LT::pad(ky0);
 #pragma unroll
