@@ -296,6 +296,46 @@ def read_traffic():
         return None
 
 
+def device_copy_rates(torch):
+    """Context for the HBM fractions: a plain device-to-device copy (torch
+    copy_) of 512 MiB and 2 GiB on the same GPU in the same run, bytes read
+    plus bytes written per second (median of 10 after 3 warm-ups)."""
+    out = {}
+    for label, nbytes in (("512MiB", 512 << 20), ("2GiB", 2 << 30)):
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        ts = []
+        for r in range(13):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            if r >= 3:
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+        ts.sort()
+        out[label] = round(2 * nbytes / ts[len(ts) // 2] / 1e9, 1)
+        del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
+def settle(step, torch, seconds):
+    """Run `step` back to back for about `seconds` before the warm-up steps.
+    Measured on MI355X: after an idle spell the step time falls from about
+    0.76 to 0.61 ms over its first ~30 repetitions (the GPU's clocks ramp up
+    under sustained load), so a few warm-up steps alone leave a short timed
+    region inside the ramp."""
+    if seconds <= 0:
+        return
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        for _ in range(10):
+            step()
+        torch.cuda.synchronize()
+
+
 def run_steps(step, k, torch):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -518,13 +558,18 @@ def bench(args):
             plan.field_energy(m, MS, out=H, E_out=E)
             plan.adjoint(gH, MS, out=gm)
 
+        settle(step, torch, args.settle)
         for _ in range(args.warmup):
             step()
-        timing = dtype == torch.float32 and not args.no_pass_timing
-        if timing:
-            plan.set_option("pass_timing", 2 * steps)
+        # the timed region runs without instrumentation; the per-pass times
+        # come from a second, separately recorded region of the same length
         secs = run_steps(step, steps, torch)
-        passes, nrec = plan.pass_times() if timing else ({}, 0)
+        passes, nrec = {}, 0
+        if dtype == torch.float32 and not args.no_pass_timing:
+            plan.set_option("pass_timing", 2 * steps)
+            run_steps(step, steps, torch)
+            passes, nrec = plan.pass_times()
+            plan.set_option("pass_timing", 0)
         print(f"# {dtype} launch: {plan.describe()}", file=sys.stderr, flush=True)
         results[dtype] = {"plan": plan, "secs": secs, "steps": steps, "H": H.double().cpu().numpy(), "tune_s": tune_s,
                           "E": float(E.cpu()), "passes": passes, "nrec": nrec, "info": plan.info()}
@@ -536,7 +581,7 @@ def bench(args):
     ms_step = 1e3 * r32["secs"] / r32["steps"]
     value = 2 * r32["steps"] / r32["secs"]
 
-    # roofline of the dominant pass, from the live per-pass events
+    # roofline of the dominant pass, from the per-pass events of the second region
     pb = pass_bytes(SHAPE, info["Px"], info["Py"], info["Pz"], info["Kx"], 4)
     passes = r32["passes"]
     roofline = None
@@ -547,10 +592,13 @@ def bench(args):
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": read_traffic() if dom == "z_conv" else None,
                     "bytes_per_launch": pb[dom], "avg_launch_ms": round(passes[dom], 5),
-                    "pass_ms": {k: round(v, 5) for k, v in passes.items()}}
+                    "pass_ms": {k: round(v, 5) for k, v in passes.items()},
+                    "pass_ms_region": f"separate region of {r32['steps']} steps with per-pass HIP events "
+                                      "(the timed region runs without them)"}
         # the whole step against HBM: modelled bytes of all passes of both evaluations
         step_bytes = 2 * sum(pb.values()) + 3 * nx * ny * nz * 4  # + m read by the energy epilogue
         roofline["step_achieved_GBs"] = round(step_bytes / (ms_step * 1e-3) / 1e9, 1)
+        roofline["device_copy_GBs"] = device_copy_rates(torch)
 
     out = {
         "metric": "demag field evals/s at 256x256x64 FP32 (fwd+adjoint), achieved HBM GB/s, vs FP64",
@@ -570,6 +618,7 @@ def bench(args):
                    "padded": [info["Px"], info["Py"], info["Pz"]], "parallelism": "none (1 GPU)",
                    "launch": r32["plan"].describe(),
                    "launch_shapes": "autotuned" if r32["tune_s"] is not None else "default",
+                   "settle_s": args.settle,
                    "autotune_s": None if r32["tune_s"] is None else round(r32["tune_s"], 2)},
         "roofline": roofline,
         # once per plan, not in the timed region: Newell tensor on the octant
@@ -723,6 +772,8 @@ def main():
                     help="informational host scipy.fft FP64 forward fields (0: skip)")
     ap.add_argument("--rocfft-steps", type=int, default=30,
                     help="informational torch.fft (rocFFT) forward fields beside the plan's (0: skip)")
+    ap.add_argument("--settle", type=float, default=0.15,
+                    help="seconds of back-to-back steps before the warm-up steps (clock ramp; 0: none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",

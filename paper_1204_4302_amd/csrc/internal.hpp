@@ -140,9 +140,9 @@ hipError_t launch_tensor_octant(hipStream_t, int nx, int ny, int nz, const doubl
 // A [Pz][Py][Px] (zero in the padding gap), with the parity signs.
 hipError_t launch_tensor_embed(hipStream_t, int comp, int nx, int ny, int nz, int Px, int Py, int Pz,
                                const double* Noct, double* A);
-// Take the real part of the FFT'd component (B2 [Py][Kx][Pz], complex FP64)
+// Take the real part of the FFT'd component (B2 [Kx][Py][Pz], complex FP64)
 // on the octant ky <= Ly, kz <= Lz, scale, cast to T into
-// nhat [Ly+1][Kx][Lz+1][6] (the six components of a frequency side by side).
+// nhat [Kx][Ly+1][Lz+1][6] (the six components of a frequency side by side).
 template <typename T>
 hipError_t launch_tensor_extract(hipStream_t, int comp, int Px, int Py, int Pz, int Kx, double scale,
                                  const cx<double>* B2, T* nhat);
@@ -155,7 +155,7 @@ hipError_t launch_sp_kernel_octant(hipStream_t, int nx, int ny, int nz, const do
 // Component a mirrored into A [Pz][Py][Px] (odd in axis a, zero in the gap).
 hipError_t launch_sp_embed(hipStream_t, int a, int nx, int ny, int nz, int Px, int Py, int Pz, const double* Soct,
                            double* A);
-// Im of the FFT'd component on the octant, scaled, into shat [Ly+1][3][Kx][Lz+1].
+// Im of the FFT'd component on the octant, scaled, into shat [Kx][Ly+1][3][Lz+1].
 template <typename T>
 hipError_t launch_sp_extract(hipStream_t, int a, int Py, int Pz, int Kx, double scale, const cx<double>* B2,
                              T* shat);

@@ -10,7 +10,7 @@
 //
 //   m   [C][nz][ny][nx]  real
 //   B1  [C][nz][Kx][ny]  complex   Kx = Px/2 + 1     (after X-R2C / Y-inverse)
-//   B2  [C][Py][Kx][Zs]  complex   Zs = nz (field)   (after Y / fused Z)
+//   B2  [C][Kx][Py][Zs]  complex   Zs = nz (field)   (after Y / fused Z)
 //   H   [C][nz][ny][nx]  real
 //
 // X-R2C transforms two real rows at once as one complex pencil (even row in
@@ -74,14 +74,14 @@ __global__ void __launch_bounds__(kMaxThreads) k_x_fwd(const T* __restrict__ in,
 
 // ---------------------------------------------------------------------------
 // Y forward: y-pencils (contiguous) -> ky, written with z fastest.
-// grid (ceil(Kx/Tx), ceil(Zr/Tz), C); in [C][Zr][Kx][Yin]; out [C][Py][Kx][Zs].
+// grid (ceil(Zr/Tz), ceil(Kx/Tx), C); in [C][Zr][Kx][Yin]; out [C][Kx][Py][Zs].
 template <typename T, int E>
 __global__ void __launch_bounds__(kMaxThreads) k_y_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                      int Yin, int Zr, int Kx, int Zs, int Tx, int Tz, int C,
                                                      FftPlanDev pl, const cx<T>* __restrict__ tw, BatchIO bio) {
     cx<T>* buf = lds_buf<T>();
     const int P = pl.P, tid = threadIdx.x, nthr = blockDim.x;
-    const int kx0 = blockIdx.x * Tx, z0 = blockIdx.y * Tz, c = blockIdx.z % C, g = blockIdx.z / C;
+    const int kx0 = blockIdx.y * Tx, z0 = blockIdx.x * Tz, c = blockIdx.z % C, g = blockIdx.z / C;
     if (bio.in) {
         in = (const cx<T>*)bio.in[g];
         out = (cx<T>*)bio.out[g];
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_y_fwd(const cx<T>* __restrict__
     for (int e = tid; e < P * B; e += nthr) {
         int zi = e % tz, r = e / tz;
         int xi = r % tx, ky = r / tx;
-        out[(((size_t)c * P + ky) * Kx + kx0 + xi) * (size_t)Zs + z0 + zi] = buf[(zi * tx + xi) * P + ky];
+        out[(((size_t)c * Kx + kx0 + xi) * P + ky) * (size_t)Zs + z0 + zi] = buf[(zi * tx + xi) * P + ky];
     }
 }
 
@@ -114,14 +114,14 @@ __global__ void __launch_bounds__(kMaxThreads) k_y_fwd(const cx<T>* __restrict__
 // A workgroup takes ky' and its mirror Py - ky' together, so each tensor value
 // is read once.  Mirroring ky (kz) flips the sign of the components odd in y
 // (z): xy, yz (xz, yz).
-// grid (ceil(Kx/Tx), Ly + 1); B2 [3][Py][Kx][nz]; nhat [Ly+1][Kx][Lz+1][6].
+// grid (Ly + 1, ceil(Kx/Tx)); B2 [3][Kx][Py][nz]; nhat [Kx][Ly+1][Lz+1][6].
 template <typename T, int E>
 __global__ void __launch_bounds__(kMaxThreads) k_z_conv(cx<T>* __restrict__ B2, const T* __restrict__ nhat, T Ms,
                                                       int nz, int Py, int Kx, int Tx, FftPlanDev pl,
                                                       const cx<T>* __restrict__ tw, BatchIO bio) {
     cx<T>* buf = lds_buf<T>();
     const int P = pl.P, Lz = P >> 1, Ly = Py >> 1, tid = threadIdx.x, nthr = blockDim.x;
-    const int kx0 = blockIdx.x * Tx, kyp = blockIdx.y;
+    const int kx0 = blockIdx.y * Tx, kyp = blockIdx.x;
     if (bio.in) B2 = (cx<T>*)bio.out[blockIdx.z];
     const int tx = min(Tx, Kx - kx0);
     const int ns = (kyp == 0 || kyp == Ly) ? 1 : 2;
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_z_conv(cx<T>* __restrict__ B2, 
         int sc = p / tx, xi = p - sc * tx;
         int s = sc / 3, comp = sc - s * 3;
         int ky = s ? Py - kyp : kyp;
-        buf[p * P + zz] = B2[(((size_t)comp * Py + ky) * Kx + kx0 + xi) * (size_t)nz + zz];
+        buf[p * P + zz] = B2[(((size_t)comp * Kx + kx0 + xi) * Py + ky) * (size_t)nz + zz];
     }
     const int pad = P - nz;
     for (int e = tid; e < B * pad; e += nthr) {
@@ -141,14 +141,13 @@ __global__ void __launch_bounds__(kMaxThreads) k_z_conv(cx<T>* __restrict__ B2, 
     }
     __syncthreads();
     fft_lds<-1, E>(buf, B, P, pl, tw);
-    const T* nh0 = nhat + (size_t)kyp * Kx * (Lz + 1) * 6;
     for (int e = tid; e < ns * tx * P; e += nthr) {
         int kz = e % P, r = e / P;
         int xi = r % tx, s = r / tx;
         int kzp = kz <= Lz ? kz : P - kz;
         T sz = kz > Lz ? T(-1) : T(1);
         T sy = s ? T(-1) : T(1);
-        const T* nh = nh0 + ((size_t)(kx0 + xi) * (Lz + 1) + kzp) * 6;
+        const T* nh = nhat + (((size_t)(kx0 + xi) * (Ly + 1) + kyp) * (Lz + 1) + kzp) * 6;
         T nxx = nh[0], nyy = nh[1], nzz = nh[2];
         T nxy = sy * nh[3], nxz = sz * nh[4], nyz = sy * sz * nh[5];
         cx<T>* px = buf + ((s * 3 + 0) * tx + xi) * P + kz;
@@ -166,36 +165,36 @@ __global__ void __launch_bounds__(kMaxThreads) k_z_conv(cx<T>* __restrict__ B2, 
         int sc = p / tx, xi = p - sc * tx;
         int s = sc / 3, comp = sc - s * 3;
         int ky = s ? Py - kyp : kyp;
-        B2[(((size_t)comp * Py + ky) * Kx + kx0 + xi) * (size_t)nz + zz] = buf[p * P + zz];
+        B2[(((size_t)comp * Kx + kx0 + xi) * Py + ky) * (size_t)nz + zz] = buf[p * P + zz];
     }
 }
 
 // Plain forward z-FFT of full-length pencils, in place (tensor setup).
-// grid (ceil(Kx/Tx), Py); B2 [Py][Kx][P].
+// grid (ceil(Py/Ty), Kx); B2 [Kx][Py][P]: Ty consecutive pencils (kx, ky0 ..).
 template <typename T, int E>
-__global__ void __launch_bounds__(kMaxThreads) k_z_fwd(cx<T>* __restrict__ B2, int Kx, int Tx, FftPlanDev pl,
+__global__ void __launch_bounds__(kMaxThreads) k_z_fwd(cx<T>* __restrict__ B2, int Py, int Ty, FftPlanDev pl,
                                                      const cx<T>* __restrict__ tw) {
     cx<T>* buf = lds_buf<T>();
     const int P = pl.P, tid = threadIdx.x, nthr = blockDim.x;
-    const int kx0 = blockIdx.x * Tx, ky = blockIdx.y;
-    const int tx = min(Tx, Kx - kx0);
-    cx<T>* base = B2 + ((size_t)ky * Kx + kx0) * (size_t)P;
-    for (int e = tid; e < tx * P; e += nthr) buf[e] = base[e];
+    const int ky0 = blockIdx.x * Ty, kx = blockIdx.y;
+    const int ty = min(Ty, Py - ky0);
+    cx<T>* base = B2 + ((size_t)kx * Py + ky0) * (size_t)P;
+    for (int e = tid; e < ty * P; e += nthr) buf[e] = base[e];
     __syncthreads();
-    fft_lds<-1, E>(buf, tx, P, pl, tw);
-    for (int e = tid; e < tx * P; e += nthr) base[e] = buf[e];
+    fft_lds<-1, E>(buf, ty, P, pl, tw);
+    for (int e = tid; e < ty * P; e += nthr) base[e] = buf[e];
 }
 
 // ---------------------------------------------------------------------------
 // Y inverse: ky -> first ny outputs, written y-fastest.
-// grid (ceil(Kx/Tx), ceil(nz/Tz), C); in [C][Py][Kx][nz]; out [C][nz][Kx][ny].
+// grid (ceil(nz/Tz), ceil(Kx/Tx), C); in [C][Kx][Py][nz]; out [C][nz][Kx][ny].
 template <typename T, int E>
 __global__ void __launch_bounds__(kMaxThreads) k_y_inv(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                      int ny, int nz, int Kx, int Tx, int Tz, int C, FftPlanDev pl,
                                                      const cx<T>* __restrict__ tw, BatchIO bio) {
     cx<T>* buf = lds_buf<T>();
     const int P = pl.P, tid = threadIdx.x, nthr = blockDim.x;
-    const int kx0 = blockIdx.x * Tx, z0 = blockIdx.y * Tz, c = blockIdx.z % C, g = blockIdx.z / C;
+    const int kx0 = blockIdx.y * Tx, z0 = blockIdx.x * Tz, c = blockIdx.z % C, g = blockIdx.z / C;
     if (bio.in) {
         in = (const cx<T>*)bio.in[g];
         out = (cx<T>*)bio.out[g];
@@ -205,7 +204,7 @@ __global__ void __launch_bounds__(kMaxThreads) k_y_inv(const cx<T>* __restrict__
     for (int e = tid; e < P * B; e += nthr) {
         int zi = e % tz, r = e / tz;
         int xi = r % tx, ky = r / tx;
-        buf[(zi * tx + xi) * P + ky] = in[(((size_t)c * P + ky) * Kx + kx0 + xi) * (size_t)nz + z0 + zi];
+        buf[(zi * tx + xi) * P + ky] = in[(((size_t)c * Kx + kx0 + xi) * P + ky) * (size_t)nz + z0 + zi];
     }
     __syncthreads();
     fft_lds<+1, E>(buf, B, P, pl, tw);
@@ -332,7 +331,7 @@ hipError_t launch_x_fwd(const LaunchCfg& lc, hipStream_t st, const T* in, cx<T>*
 template <typename T>
 hipError_t launch_y_fwd(const LaunchCfg& lc, hipStream_t st, const cx<T>* in, cx<T>* out, int Yin, int Zr, int Kx,
                         int Zs, int C, const FftPlanDev& pl, const cx<T>* tw, const BatchIO& bio) {
-    dim3 grid((Kx + lc.t0 - 1) / lc.t0, (Zr + lc.t1 - 1) / lc.t1, C * bio.count);
+    dim3 grid((Zr + lc.t1 - 1) / lc.t1, (Kx + lc.t0 - 1) / lc.t0, C * bio.count);
     size_t lds = (size_t)lc.t0 * lc.t1 * pl.P * sizeof(cx<T>);
 #define CALL(EE) hipLaunchKernelGGL((k_y_fwd<T, EE>), grid, dim3(lc.threads), lds, st, in, out, Yin, Zr, Kx, Zs, lc.t0, lc.t1, C, pl, tw, bio)
     DEMAG_E_SWITCH(lc.E, CALL)
@@ -343,7 +342,7 @@ hipError_t launch_y_fwd(const LaunchCfg& lc, hipStream_t st, const cx<T>* in, cx
 template <typename T>
 hipError_t launch_z_conv(const LaunchCfg& lc, hipStream_t st, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx,
                          const FftPlanDev& pl, const cx<T>* tw, const BatchIO& bio) {
-    dim3 grid((Kx + lc.t0 - 1) / lc.t0, Py / 2 + 1, bio.count);
+    dim3 grid(Py / 2 + 1, (Kx + lc.t0 - 1) / lc.t0, bio.count);
     size_t lds = (size_t)6 * lc.t0 * pl.P * sizeof(cx<T>);
     // dynamic LDS above 64 KB must be allowed per kernel before its launch
 #define CALL(EE)                                                                                                   \
@@ -361,9 +360,9 @@ hipError_t launch_z_conv(const LaunchCfg& lc, hipStream_t st, cx<T>* B2, const T
 template <typename T>
 hipError_t launch_z_fwd(const LaunchCfg& lc, hipStream_t st, cx<T>* B2, int Py, int Kx, const FftPlanDev& pl,
                         const cx<T>* tw) {
-    dim3 grid((Kx + lc.t0 - 1) / lc.t0, Py, 1);
+    dim3 grid((Py + lc.t0 - 1) / lc.t0, Kx, 1);
     size_t lds = (size_t)lc.t0 * pl.P * sizeof(cx<T>);
-#define CALL(EE) hipLaunchKernelGGL((k_z_fwd<T, EE>), grid, dim3(lc.threads), lds, st, B2, Kx, lc.t0, pl, tw)
+#define CALL(EE) hipLaunchKernelGGL((k_z_fwd<T, EE>), grid, dim3(lc.threads), lds, st, B2, Py, lc.t0, pl, tw)
     DEMAG_E_SWITCH(lc.E, CALL)
 #undef CALL
     return hipGetLastError();
@@ -372,7 +371,7 @@ hipError_t launch_z_fwd(const LaunchCfg& lc, hipStream_t st, cx<T>* B2, int Py, 
 template <typename T>
 hipError_t launch_y_inv(const LaunchCfg& lc, hipStream_t st, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
                         int C, const FftPlanDev& pl, const cx<T>* tw, const BatchIO& bio) {
-    dim3 grid((Kx + lc.t0 - 1) / lc.t0, (nz + lc.t1 - 1) / lc.t1, C * bio.count);
+    dim3 grid((nz + lc.t1 - 1) / lc.t1, (Kx + lc.t0 - 1) / lc.t0, C * bio.count);
     size_t lds = (size_t)lc.t0 * lc.t1 * pl.P * sizeof(cx<T>);
 #define CALL(EE) hipLaunchKernelGGL((k_y_inv<T, EE>), grid, dim3(lc.threads), lds, st, in, out, ny, nz, Kx, lc.t0, lc.t1, C, pl, tw, bio)
     DEMAG_E_SWITCH(lc.E, CALL)

@@ -1,7 +1,7 @@
 // The five passes of one field evaluation for power-of-two padded lengths
 // (compile-time P), on the register-resident FFT of fft_reg.hpp.  Same data
 // layouts and arithmetic as the generic passes (passes.hip):
-//   m [C][nz][ny][nx] -> B1 [C][nz][Kx][ny] -> B2 [C][Py][Kx][nz] -> (x Nhat)
+//   m [C][nz][ny][nx] -> B1 [C][nz][Kx][ny] -> B2 [C][Kx][Py][nz] -> (x Nhat)
 //   -> B2 -> B1 -> H [C][nz][ny][nx].
 // The side of a pass whose pencils are contiguous in memory moves directly
 // between HBM and registers (input positions of the first stage, output
@@ -132,6 +132,62 @@ __device__ __forceinline__ void gst(gptr<cx<T>> p, size_t i, cx<T> c) {
     ((gptr<typename vec2<T>::type>)p)[i] = v;
 }
 
+// 16-byte vectors of reals: VR = 4 floats or 2 doubles.
+template <typename T>
+__host__ __device__ constexpr int vr() { return 16 / (int)sizeof(T); }
+template <typename T>
+struct vecN {
+    typedef T type __attribute__((ext_vector_type(16 / sizeof(T))));
+};
+// X-C2R moves rows as 16-byte vectors when each thread's contiguous share of
+// the kept half (EPT/2 positions) is a whole number of them.
+template <typename T, int P>
+__host__ __device__ constexpr bool vec_rows() {
+    return p2::Len<P>::EPT >= 8 && (p2::Len<P>::EPT / 2) % vr<T>() == 0;
+}
+// Row vector at real index x (a multiple of VR; rows start 16-byte aligned),
+// zero if not valid (the load then goes to p[0]); non-temporal: the
+// magnetization is read once per evaluation.
+template <typename T>
+__device__ __forceinline__ typename vecN<T>::type gldv_nt_if(gptr<const T> p, int x, bool valid) {
+    using V = typename vecN<T>::type;
+    const V v = __builtin_nontemporal_load((gptr<const V>)(p + (valid ? x : 0)));
+    return valid ? v : V{};
+}
+// Two adjacent complex values c0, c1 at p[i], p[i + 1] (i even; FP32: one
+// 16-byte store).
+template <typename T>
+__device__ __forceinline__ void gst2(gptr<cx<T>> p, size_t i, cx<T> c0, cx<T> c1) {
+    if constexpr (sizeof(T) == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        f4 v;
+        v.x = c0.re;
+        v.y = c0.im;
+        v.z = c1.re;
+        v.w = c1.im;
+        *(gptr<f4>)(p + i) = v;
+    } else {
+        gst(p, i, c0);
+        gst(p, i + 1, c1);
+    }
+}
+// ... and the matching load (FP32: one 16-byte load); zero if not valid.
+template <typename T>
+__device__ __forceinline__ void gld2_if(gptr<const cx<T>> p, size_t i, bool valid, cx<T>& c0, cx<T>& c1) {
+    if constexpr (sizeof(T) == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 v = *(gptr<const f4>)(p + (valid ? i : 0));
+        c0 = valid ? mk(v.x, v.y) : czero<T>();
+        c1 = valid ? mk(v.z, v.w) : czero<T>();
+    } else {
+        c0 = gld_if(p, i, valid);
+        c1 = gld_if(p, i + 1, valid);
+    }
+}
+// Order a pencil's slab accesses among its own threads (see p2::pencil_sync).
+template <int P>
+__device__ __forceinline__ void pencil_sync_p() { p2::pencil_sync<p2::Len<P>::TP>(); }
+
 // Raw buffer access: a resource (base address and byte range, uniform across
 // the wavefront, so held in scalar registers) plus a 32-bit per-lane byte
 // offset, with compile-time parts folded into the instruction's immediate.
@@ -215,6 +271,12 @@ __device__ __forceinline__ unsigned boff(bool valid, unsigned base, unsigned d) 
 // ---------------------------------------------------------------------------
 // X forward (R2C of two rows per complex pencil).  1-D grid of
 // ceil(ny/Ty) * nz * C (* batch) tiles, block (Ty/2) * TP threads.
+// Output: thread (pair q, frequency k) forms X_even[k] and X_odd[k] of rows
+// 2q and 2q+1 from one pair of slab reads and, when ny is even (rows 2q and
+// 2q+1 then lie side by side in B1 and are both inside the tile or both
+// outside), writes them with one 16-byte store (FP32).  (Loading the rows as
+// 16-byte vectors staged through the slab measured slower than the direct
+// first-stage loads.)
 template <typename T, int P>
 __global__ void __launch_bounds__(xy_max_threads<P>()) kx_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, int nx, int ny,
                                                int nz, int lgTy, int nxcd, const cx<T>* __restrict__ twt,
@@ -259,40 +321,38 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_fwd(const T* __restric
     for (int j = 0; j < LT::EPT; ++j) slab[LT::fout_slab(pt, t, j)] = v[j];
     __syncthreads();
     // spectra of the two rows: X_even = (Z_k + conj Z_{P-k})/2, X_odd = (Z_k - conj Z_{P-k})/(2i),
-    // written y-contiguous
-    const gptr<cx<T>> dst = gmem(out + ((size_t)c * nz + z) * (size_t)Kx * ny + y0);
-    if constexpr (LT::TP >= 2) {
-        // nthr = (Ty/2) TP is a multiple of Ty: each thread keeps one row y
-        constexpr int KS = LT::TP / 2, KN = (Kx + KS - 1) / KS;
-        const int y = tid & (Ty - 1), k0 = tid >> lgTy;
-        if (y < ty) {
-            const cx<T>* pen = lds + (y >> 1) * LT::PS;
-            cx<T> r[KN];
+    // written y-contiguous; thread (q, k0 + i TP), q = tid mod (Ty/2)
+    constexpr int KI = (Kx + LT::TP - 1) / LT::TP;
+    const int lgB = lgTy - 1;
+    const int q = tid & ((1 << lgB) - 1), k0 = tid >> lgB;
+    const bool okq0 = 2 * q < ty, okq1 = 2 * q + 1 < ty;
+    if (okq0) {
+        const cx<T>* pen = lds + q * LT::PS;
+        cx<T> xe[KI], xo[KI];
 #pragma unroll
-            for (int i = 0; i < KN; ++i) {
-                const int k = k0 + i * KS;
-                if (k < Kx) {
-                    const cx<T> a = pen[LT::pad(k)], b = pen[LT::pad(k == 0 ? 0 : P - k)];
-                    r[i] = (y & 1) ? mk(T(0.5) * (a.im + b.im), T(0.5) * (b.re - a.re))
-                                   : mk(T(0.5) * (a.re + b.re), T(0.5) * (a.im - b.im));
-                }
-            }
-            const gptr<cx<T>> dy = dst + y;
-#pragma unroll
-            for (int i = 0; i < KN; ++i) {
-                const int k = k0 + i * KS;
-                if (k < Kx) gst(dy, k * ny, r[i]);
+        for (int i = 0; i < KI; ++i) {
+            const int k = k0 + i * LT::TP;
+            if (i + 1 < KI || k < Kx) {
+                const cx<T> a = pen[LT::pad(k)], b = pen[LT::pad(k == 0 ? 0 : P - k)];
+                xe[i] = mk(T(0.5) * (a.re + b.re), T(0.5) * (a.im - b.im));
+                xo[i] = mk(T(0.5) * (a.im + b.im), T(0.5) * (b.re - a.re));
             }
         }
-    } else {
-        for (int e = tid; e < (Kx << lgTy); e += nthr) {
-            const int y = e & (Ty - 1), k = e >> lgTy;
-            if (y < ty) {
-                const cx<T>* pen = lds + (y >> 1) * LT::PS;
-                const cx<T> a = pen[LT::pad(k)], b = pen[LT::pad(k == 0 ? 0 : P - k)];
-                gst(dst, (size_t)k * ny + y,
-                    (y & 1) ? mk(T(0.5) * (a.im + b.im), T(0.5) * (b.re - a.re))
-                            : mk(T(0.5) * (a.re + b.re), T(0.5) * (a.im - b.im)));
+        const gptr<cx<T>> dst = gmem(out + ((size_t)c * nz + z) * (size_t)Kx * ny + y0 + 2 * q);
+        if ((ny & 1) == 0) {  // okq1 == okq0
+#pragma unroll
+            for (int i = 0; i < KI; ++i) {
+                const int k = k0 + i * LT::TP;
+                if (i + 1 < KI || k < Kx) gst2(dst, (size_t)k * ny, xe[i], xo[i]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < KI; ++i) {
+                const int k = k0 + i * LT::TP;
+                if (i + 1 < KI || k < Kx) {
+                    gst(dst, (size_t)k * ny, xe[i]);
+                    if (okq1) gst(dst, (size_t)k * ny + 1, xo[i]);
+                }
             }
         }
     }
@@ -301,13 +361,26 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_fwd(const T* __restric
 // ---------------------------------------------------------------------------
 // X inverse (C2R of two rows per pencil), first nx outputs, optional
 // accumulate and energy partial (one FP64 value per workgroup).
+//
+// Input: thread (pair q, frequency k) loads B1 at rows 2q and 2q+1 -- one
+// 16-byte load (FP32) when ny is even -- and writes the packed pencil
+// Z_k = X_even[k] + i X_odd[k] and its mirror to the slab.  Output: when nx is
+// a multiple of the 16-byte vector width, the pencil's kept half goes through
+// its slab once more so that each thread holds the contiguous positions
+// [HALF t, HALF t + HALF) of both rows and writes them (and reads m for the
+// energy) as 16-byte vectors (FP32); otherwise each thread writes the
+// positions its last stage holds.
 template <typename T, int P>
 __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __restrict__ in, T* __restrict__ out,
                                                const T* __restrict__ m, double* __restrict__ partials, int nx,
                                                int ny, int nz, int lgTy, int accumulate, int nxcd,
                                                const cx<T>* __restrict__ twt, BatchIO bio) {
     using LT = p2::Len<P>;
+    using V = typename vecN<T>::type;
     constexpr int Kx = P / 2 + 1, Lx = P / 2;
+    // (FP64 keeps the direct output: its registers would spill)
+    constexpr bool kVec = vec_rows<T, P>() && sizeof(T) == 4;
+    constexpr int HALF = LT::EPT / 2, VR = vr<T>(), NV = kVec ? HALF / VR : 1;
     __shared__ double red[16];
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -326,18 +399,30 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __res
     const int ty = min(Ty, ny - y0);
     const size_t rowbase = (((size_t)c * nz + z) * ny + y0 + 2 * p) * (size_t)nx;
     const bool ok0 = 2 * p < ty, ok1 = 2 * p + 1 < ty;
+    const bool vec = kVec && nx % VR == 0;  // uniform
     // energy: the magnetization at this thread's outputs, loaded first so that
     // its latency overlaps the transposition and the transform
     T m0[LT::EPT], m1[LT::EPT];
+    V mv0[NV], mv1[NV];
     if (m) {
         const gptr<const T> msrc = gmem(ok0 ? m + rowbase : m);  // rows past the tile read m[0], discarded
+        if (vec) {
+            const gptr<const T> msrc1 = gmem(ok1 ? m + rowbase + nx : m);
 #pragma unroll
-        for (int j = 0; j < LT::EPT; ++j) {
-            const int k = LT::iout_k(j);
-            const int x = t + k * LT::TP;
-            if (k < LT::EPT / 2) {
-                m0[j] = gldr_if(msrc, x, ok0 && x < nx);
-                m1[j] = gldr_if(msrc, x + nx, ok1 && x < nx);
+            for (int u = 0; u < NV; ++u) {
+                const int x = HALF * t + VR * u;
+                mv0[u] = gldv_nt_if(msrc, x, ok0 && x < nx);
+                mv1[u] = gldv_nt_if(msrc1, x, ok1 && x < nx);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < LT::EPT; ++j) {
+                const int k = LT::iout_k(j);
+                const int x = t + k * LT::TP;
+                if (k < LT::EPT / 2) {
+                    m0[j] = gldr_if(msrc, x, ok0 && x < nx);
+                    m1[j] = gldr_if(msrc, x + nx, ok1 && x < nx);
+                }
             }
         }
     }
@@ -348,19 +433,28 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __res
         const int q = tid & (Bp - 1), k0 = tid >> lgB;
         const bool okq0 = 2 * q < ty, okq1 = 2 * q + 1 < ty;
         const cx<T>* qb = in + ((size_t)c * nz + z) * (size_t)Kx * ny + y0 + 2 * q;
-        const gptr<const cx<T>> s0 = gmem(okq0 ? qb : in), s1 = gmem(okq1 ? qb + 1 : in);
         cx<T> xe[KI], xo[KI];
+        if ((ny & 1) == 0) {  // rows 2q, 2q+1 side by side, okq1 == okq0
+            const gptr<const cx<T>> s0 = gmem(okq0 ? qb : in);
 #pragma unroll
-        for (int i = 0; i < KI; ++i) {
-            const int k = k0 + i * LT::TP;
-            xe[i] = gld_if(s0, (size_t)k * ny, k < Kx && okq0);
-            xo[i] = gld_if(s1, (size_t)k * ny, k < Kx && okq1);
+            for (int i = 0; i < KI; ++i) {
+                const int k = k0 + i * LT::TP;
+                gld2_if(s0, (size_t)k * ny, (i + 1 < KI || k < Kx) && okq0, xe[i], xo[i]);
+            }
+        } else {
+            const gptr<const cx<T>> s0 = gmem(okq0 ? qb : in), s1 = gmem(okq1 ? qb + 1 : in);
+#pragma unroll
+            for (int i = 0; i < KI; ++i) {
+                const int k = k0 + i * LT::TP;
+                xe[i] = gld_if(s0, (size_t)k * ny, (i + 1 < KI || k < Kx) && okq0);
+                xo[i] = gld_if(s1, (size_t)k * ny, (i + 1 < KI || k < Kx) && okq1);
+            }
         }
         cx<T>* pq = lds + q * LT::PS;
 #pragma unroll
         for (int i = 0; i < KI; ++i) {
             const int k = k0 + i * LT::TP;
-            if (k < Kx) {
+            if (i + 1 < KI || k < Kx) {
                 cx<T> a = xe[i], b = xo[i];
                 if (k == 0 || k == Lx) {  // C2R ignores the imaginary parts of DC and Nyquist
                     a.im = T(0);
@@ -381,25 +475,71 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __res
     run_fft<T, P, +1>(v, slab, t, tws);
     const gptr<T> dst = out ? gmem(out + rowbase) : nullptr;
     double acc = 0.0;
+    if (vec) {
+        // the kept half through the slab: position x of row 2p (re) and 2p+1 (im)
+        pencil_sync_p<P>();
 #pragma unroll
-    for (int j = 0; j < LT::EPT; ++j) {
-        const int k = LT::iout_k(j);
-        const int x = t + k * LT::TP;
-        if (k < LT::EPT / 2 && x < nx) {  // the discarded half is never written
-            if (ok0) {
-                const T h = v[j].re;
-                if (m) acc += (double)(m0[j] * h);
-                if (dst) {  // the field is not read again by the evaluation: streamed unless accumulating
-                    if (accumulate) dst[x] = dst[x] + h;
-                    else __builtin_nontemporal_store(h, &dst[x]);
+        for (int j = 0; j < LT::EPT; ++j) {
+            const int k = LT::iout_k(j);
+            if (k < LT::EPT / 2) slab[LT::pad(t + k * LT::TP)] = v[j];
+        }
+        pencil_sync_p<P>();
+#pragma unroll
+        for (int u = 0; u < NV; ++u) {
+            const int x = HALF * t + VR * u;
+            V h0, h1;
+#pragma unroll
+            for (int e = 0; e < VR; ++e) {
+                const cx<T> w = slab[LT::pad(x + e)];
+                h0[e] = w.re;
+                h1[e] = w.im;
+            }
+            if (x < nx) {  // whole vectors: nx is a multiple of VR
+                if (ok0) {
+                    if (m) {
+#pragma unroll
+                        for (int e = 0; e < VR; ++e) acc += (double)(mv0[u][e] * h0[e]);
+                    }
+                    if (dst) {  // the field is not read again by the evaluation: streamed unless accumulating
+                        const gptr<V> d0 = (gptr<V>)(dst + x);
+                        if (accumulate) *d0 = *d0 + h0;
+                        else __builtin_nontemporal_store(h0, d0);
+                    }
+                }
+                if (ok1) {
+                    if (m) {
+#pragma unroll
+                        for (int e = 0; e < VR; ++e) acc += (double)(mv1[u][e] * h1[e]);
+                    }
+                    if (dst) {
+                        const gptr<V> d1 = (gptr<V>)(dst + nx + x);
+                        if (accumulate) *d1 = *d1 + h1;
+                        else __builtin_nontemporal_store(h1, d1);
+                    }
                 }
             }
-            if (ok1) {
-                const T h = v[j].im;
-                if (m) acc += (double)(m1[j] * h);
-                if (dst) {
-                    if (accumulate) dst[x + nx] = dst[x + nx] + h;
-                    else __builtin_nontemporal_store(h, &dst[x + nx]);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < LT::EPT; ++j) {
+            const int k = LT::iout_k(j);
+            const int x = t + k * LT::TP;
+            if (k < LT::EPT / 2 && x < nx) {  // the discarded half is never written
+                if (ok0) {
+                    const T h = v[j].re;
+                    if (m) acc += (double)(m0[j] * h);
+                    if (dst) {
+                        if (accumulate) dst[x] = dst[x] + h;
+                        else __builtin_nontemporal_store(h, &dst[x]);
+                    }
+                }
+                if (ok1) {
+                    const T h = v[j].im;
+                    if (m) acc += (double)(m1[j] * h);
+                    if (dst) {
+                        if (accumulate) dst[x + nx] = dst[x + nx] + h;
+                        else __builtin_nontemporal_store(h, &dst[x + nx]);
+                    }
                 }
             }
         }
@@ -419,11 +559,15 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __res
 // ---------------------------------------------------------------------------
 // Y forward.  Tile Tz x Tx pencils (z, kx); pencil p = zi * Tx + xi.
 // 1-D grid of ceil(nz/Tz) * ceil(Kx/Tx) * C tiles, block Tz * Tx * TP.
+//
+// FP32 with an even nz and z tiles of at least two: each thread writes two
+// adjacent z pencils at a frequency with one 16-byte store (the strided side).
 template <typename T, int P>
 __global__ void __launch_bounds__(xy_max_threads<P>()) ky_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
                                                int nz, int Kx, int lgTz, int lgTx, int nxcd,
                                                const cx<T>* __restrict__ twt, BatchIO bio) {
     using LT = p2::Len<P>;
+    constexpr bool kVec = sizeof(T) == 4 && LT::EPT >= 8;
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x;
     const int p = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
@@ -456,19 +600,38 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) ky_fwd(const cx<T>* __res
 #pragma unroll
     for (int j = 0; j < LT::EPT; ++j) slab[LT::fout_slab(pt, t, j)] = v[j];
     __syncthreads();
-    // (zj, xj) = tid mod (Tz Tx), ky = tid / (Tz Tx) + i TP; z-contiguous runs
     const int lgB = lgTz + lgTx;
-    const int zj = tid & (Tz - 1), xj = (tid >> lgTz) & (Tx - 1), ky0 = tid >> lgB;
-    if (zj < tz && xj < tx) {
-        const cx<T>* pj = lds + ((zj << lgTx) + xj) * LT::PS;
-        const int pk = LT::pad(ky0);
-        cx<T> r[LT::EPT];
+    const size_t step = (size_t)LT::TP * nz;  // B2 offset of TP frequencies ky
+    if (kVec && lgTz >= 1 && (nz & 1) == 0) {
+        // pair (zq, xj) = tid mod (Tz/2 Tx) writes pencils z0 + 2 zq and z0 + 2 zq + 1
+        // (both inside the tile or both outside: tz is even), ky = tid / (Tz/2 Tx) + i 2 TP
+        const int zq = tid & ((Tz >> 1) - 1), xj = (tid >> (lgTz - 1)) & (Tx - 1), ky0 = tid >> (lgB - 1);
+        if (2 * zq < tz && xj < tx) {
+            const cx<T>* pj = lds + (((2 * zq) << lgTx) + xj) * LT::PS;
+            const int pk = LT::pad(ky0);
+            cx<T> lo[LT::EPT / 2], hi[LT::EPT / 2];
 #pragma unroll
-        for (int i = 0; i < LT::EPT; ++i) r[i] = pj[LT::pad_add(pk, ky0, i * LT::TP)];
-        const gptr<cx<T>> dst = gmem(out + (((size_t)c * P + ky0) * Kx + kx0 + xj) * (size_t)nz + z0 + zj);
-        const size_t step = (size_t)LT::TP * Kx * nz;
+            for (int i = 0; i < LT::EPT / 2; ++i) {
+                lo[i] = pj[LT::pad_add(pk, ky0, 2 * i * LT::TP)];
+                hi[i] = pj[Tx * LT::PS + LT::pad_add(pk, ky0, 2 * i * LT::TP)];
+            }
+            const gptr<cx<T>> dst = gmem(out + (((size_t)c * Kx + kx0 + xj) * P + ky0) * (size_t)nz + z0 + 2 * zq);
 #pragma unroll
-        for (int i = 0; i < LT::EPT; ++i) gst(dst, i * step, r[i]);
+            for (int i = 0; i < LT::EPT / 2; ++i) gst2(dst, 2 * i * step, lo[i], hi[i]);
+        }
+    } else {
+        // (zj, xj) = tid mod (Tz Tx), ky = tid / (Tz Tx) + i TP; z-contiguous runs
+        const int zj = tid & (Tz - 1), xj = (tid >> lgTz) & (Tx - 1), ky0 = tid >> lgB;
+        if (zj < tz && xj < tx) {
+            const cx<T>* pj = lds + ((zj << lgTx) + xj) * LT::PS;
+            const int pk = LT::pad(ky0);
+            cx<T> r[LT::EPT];
+#pragma unroll
+            for (int i = 0; i < LT::EPT; ++i) r[i] = pj[LT::pad_add(pk, ky0, i * LT::TP)];
+            const gptr<cx<T>> dst = gmem(out + (((size_t)c * Kx + kx0 + xj) * P + ky0) * (size_t)nz + z0 + zj);
+#pragma unroll
+            for (int i = 0; i < LT::EPT; ++i) gst(dst, i * step, r[i]);
+        }
     }
 }
 
@@ -499,8 +662,8 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) ky_inv(const cx<T>* __res
         const int zj = tid & (Tz - 1), xj = (tid >> lgTz) & (Tx - 1), ky0 = tid >> lgB;
         const bool okj = zj < tz && xj < tx;
         const gptr<const cx<T>> src =
-            gmem(okj ? in + (((size_t)c * P + ky0) * Kx + kx0 + xj) * (size_t)nz + z0 + zj : in);
-        const size_t step = (size_t)LT::TP * Kx * nz;
+            gmem(okj ? in + (((size_t)c * Kx + kx0 + xj) * P + ky0) * (size_t)nz + z0 + zj : in);
+        const size_t step = (size_t)LT::TP * nz;  // B2 offset of TP frequencies ky
         cx<T> ld[LT::EPT];
 #pragma unroll
         for (int i = 0; i < LT::EPT; ++i) ld[i] = gld_last_if(src, i * step, okj);
@@ -568,21 +731,22 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     const int g = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
     const int Tx = 1 << lgTx, Ly = Py >> 1;
     const int xi = g & (Tx - 1);
-    const int nxt = (Kx + Tx - 1) >> lgTx;
     int gb;
     const int tile = batch_tile(xcd_tile(nxcd), bio, &gb);
     if (bio.in) B2 = (cx<T>*)bio.out[gb];
-    const int kx0 = (tile % nxt) << lgTx;
+    // rows of one kx tile are consecutive tiles (B2 and the octant are kx-major)
+    const int nrow = rows == 2 ? Ly + 1 : Py;
+    const int kx0 = (tile / nrow) << lgTx;
     const int tx = min(Tx, Kx - kx0);
     int s, kyp, ky;
     bool ok;
     if (rows == 2) {
         s = g >> lgTx;
-        kyp = tile / nxt;
+        kyp = tile % nrow;
         ok = s < ((kyp == 0 || kyp == Ly) ? 1 : 2) && xi < tx;
         ky = s ? Py - kyp : kyp;
     } else {
-        ky = tile / nxt;
+        ky = tile % nrow;
         s = ky > Ly;
         kyp = s ? Py - ky : ky;
         ok = xi < tx;
@@ -591,7 +755,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     const Buf bc[3] = {make_buf(B2, cstride * CB), make_buf(B2 + cstride, cstride * CB),
                        make_buf(B2 + 2 * cstride, cstride * CB)};
     // byte offset of this lane's first element; zz = t + k TP adds k TP CB
-    const unsigned row = (unsigned)((((size_t)ky * Kx + kx0 + xi) * nz + t) * CB);
+    const unsigned row = (unsigned)((((size_t)(kx0 + xi) * Py + ky) * nz + t) * CB);
     cx<T> v[3][LT::EPT];
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
@@ -605,10 +769,10 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     // Tensor values of this thread's frequencies kz (forward output slots);
     // octant index kz' = kz for kz <= Lz, else P - kz; lanes outside the tile
     // read row 0 (their results are never stored).
-    // octant [Ly+1][Kx][Lz+1][6]: the six components of a frequency side by side
+    // octant [Kx][Ly+1][Lz+1][6]: the six components of a frequency side by side
     constexpr unsigned FB = 6 * RB;  // bytes per frequency
-    const Buf bt = make_buf(nhat, (size_t)(Ly + 1) * Kx * (Lz + 1) * FB);
-    const unsigned trow = ok ? (unsigned)((((size_t)kyp * Kx + kx0 + xi) * (Lz + 1)) * FB) : 0u;
+    const Buf bt = make_buf(nhat, (size_t)Kx * (Ly + 1) * (Lz + 1) * FB);
+    const unsigned trow = ok ? (unsigned)((((size_t)(kx0 + xi) * (Ly + 1) + kyp) * (Lz + 1)) * FB) : 0u;
     T nt[LT::EPT][6];
     auto load_tensor = [&]() {
 #pragma unroll
@@ -681,7 +845,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
 // Fused Z pass of the scalar-potential method (Sec. 3.1, eq. (convolution)):
 // per (kx, ky) the three component pencils are transformed along z, combined
 // with the kernel spectrum S^_a = i s_a (s_a real: Im of the transform of the
-// odd kernel, octant [Py/2+1][3][Kx][Pz/2+1], +1/(Px Py Pz) folded in) into
+// odd kernel, octant [Kx][Py/2+1][3][Pz/2+1], +1/(Px Py Pz) folded in) into
 // phi^ = i sum_a s_a M^_a, transformed back, and Ms phi (first nz outputs) is
 // written in place to component 0 of B2.  Parity signs: s_y odd in ky (s = 1
 // groups), s_z odd in kz; s_x needs none (kx <= Px/2).  Tiles, groups, buffer
@@ -700,19 +864,20 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
     const int g = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
     const int Tx = 1 << lgTx, Ly = Py >> 1;
     const int xi = g & (Tx - 1);
-    const int nxt = (Kx + Tx - 1) >> lgTx;
     const int tile = xcd_tile(nxcd);
-    const int kx0 = (tile % nxt) << lgTx;
+    // rows of one kx tile are consecutive tiles (B2 and the octant are kx-major)
+    const int nrow = rows == 2 ? Ly + 1 : Py;
+    const int kx0 = (tile / nrow) << lgTx;
     const int tx = min(Tx, Kx - kx0);
     int s, kyp, ky;
     bool ok;
     if (rows == 2) {
         s = g >> lgTx;
-        kyp = tile / nxt;
+        kyp = tile % nrow;
         ok = s < ((kyp == 0 || kyp == Ly) ? 1 : 2) && xi < tx;
         ky = s ? Py - kyp : kyp;
     } else {
-        ky = tile / nxt;
+        ky = tile % nrow;
         s = ky > Ly;
         kyp = s ? Py - ky : ky;
         ok = xi < tx;
@@ -720,7 +885,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
     const size_t cstride = (size_t)Py * Kx * nz;
     const Buf bc[3] = {make_buf(B2, cstride * CB), make_buf(B2 + cstride, cstride * CB),
                        make_buf(B2 + 2 * cstride, cstride * CB)};
-    const unsigned row = (unsigned)((((size_t)ky * Kx + kx0 + xi) * nz + t) * CB);
+    const unsigned row = (unsigned)((((size_t)(kx0 + xi) * Py + ky) * nz + t) * CB);
     cx<T> v[3][LT::EPT];
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
@@ -731,9 +896,9 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
             v[comp][j] = k < LT::EPT / 2 ? bld<T>(bc[comp], boff(ok && zz < nz, row, k * LT::TP * CB)) : czero<T>();
         }
     }
-    const size_t cs = (size_t)Kx * (Lz + 1);  // component stride of the spectrum octant
-    const Buf bt = make_buf(shat, (size_t)(Ly + 1) * 3 * cs * RB);
-    const unsigned trow = ok ? (unsigned)((((size_t)kyp * 3 * Kx + kx0 + xi) * (Lz + 1)) * RB) : 0u;
+    const size_t cs = (size_t)(Lz + 1);  // component stride of the spectrum octant
+    const Buf bt = make_buf(shat, (size_t)Kx * (Ly + 1) * 3 * cs * RB);
+    const unsigned trow = ok ? (unsigned)((((size_t)(kx0 + xi) * (Ly + 1) + kyp) * 3 * (Lz + 1)) * RB) : 0u;
     T sk[LT::EPT][3];
     auto load_kernel = [&]() {
 #pragma unroll

@@ -471,7 +471,7 @@ int setup_spectrum(demag_plan_s* p, hipStream_t st) {
     }
     const size_t cb = sizeof(cx<double>);
     LaunchCfg xf = cfg_rows(Px, Py, cb), yf = cfg_pencils(Py, Kx, Pz, cb), zf;
-    zf.t0 = (int)std::max<long>(1, std::min<long>(Kx, 2048 / Pz));
+    zf.t0 = (int)std::max<long>(1, std::min<long>(Py, 2048 / Pz));  // ky pencils per workgroup
     zf.E = pick_E((long)zf.t0 * Pz, zf.threads);
     const double scale = -1.0 / ((double)Px * Py * Pz);
     for (int comp = 0; comp < 6; ++comp) {
@@ -519,7 +519,7 @@ int setup_sp_spectrum(demag_plan_s* p, hipStream_t st) {
     }
     const size_t cb = sizeof(cx<double>);
     LaunchCfg xf = cfg_rows(Px, Py, cb), yf = cfg_pencils(Py, Kx, Pz, cb), zf;
-    zf.t0 = (int)std::max<long>(1, std::min<long>(Kx, 2048 / Pz));
+    zf.t0 = (int)std::max<long>(1, std::min<long>(Py, 2048 / Pz));  // ky pencils per workgroup
     zf.E = pick_E((long)zf.t0 * Pz, zf.threads);
     const double h = std::max(p->d[0], std::max(p->d[1], p->d[2]));
     const double scale = h / ((double)Px * Py * Pz);
@@ -1192,7 +1192,7 @@ int demag_plan_spectrum(demag_plan_t p, void* out) {
     HIP_TRY(hipDeviceSynchronize());
     std::vector<unsigned char> dev(p->tensor_bytes);
     HIP_TRY(hipMemcpy(dev.data(), p->nhat, p->tensor_bytes, hipMemcpyDeviceToHost));
-    // device [Ly+1][Kx][Lz+1][6] -> documented [Ly+1][6][Kx][Lz+1]
+    // device [Kx][Ly+1][Lz+1][6] -> documented [Ly+1][6][Kx][Lz+1]
     const size_t rb = p->dtype == DEMAG_F32 ? 4 : 8;
     const size_t Ly1 = p->P[1] / 2 + 1, Kx = p->Kx, Lz1 = p->P[2] / 2 + 1;
     unsigned char* o = (unsigned char*)out;
@@ -1201,7 +1201,7 @@ int demag_plan_spectrum(demag_plan_t p, void* out) {
             for (size_t kz = 0; kz < Lz1; ++kz)
                 for (size_t c = 0; c < 6; ++c)
                     std::memcpy(o + (((ky * 6 + c) * Kx + kx) * Lz1 + kz) * rb,
-                                dev.data() + (((ky * Kx + kx) * Lz1 + kz) * 6 + c) * rb, rb);
+                                dev.data() + (((kx * Ly1 + ky) * Lz1 + kz) * 6 + c) * rb, rb);
     return DEMAG_OK;
 }
 

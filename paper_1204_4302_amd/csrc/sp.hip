@@ -17,7 +17,7 @@
 //         uniform cell (d^2/12, d^4/80, d^6/448) over beta!.
 // S_a is odd in axis a and even in the others; its transform is imaginary.
 // The spectrum stored is Im(S^) on the octant with +1/(Px Py Pz) folded in,
-// layout [Py/2+1][3][Kx][Pz/2+1].
+// layout [Kx][Py/2+1][3][Pz/2+1].
 #include <algorithm>
 #include <climits>
 
@@ -194,10 +194,11 @@ __global__ void __launch_bounds__(256) k_sp_extract(size_t base, int a, int Py, 
     const size_t total = (size_t)(Ly + 1) * Kx * (Lz + 1);
     const size_t t = base + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    const int kz = (int)(t % (Lz + 1)), kx = (int)((t / (Lz + 1)) % Kx), ky = (int)(t / ((size_t)(Lz + 1) * Kx));
-    double v = B2[((size_t)ky * Kx + kx) * Pz + kz].im * scale;
+    const int kz = (int)(t % (Lz + 1)), ky = (int)((t / (Lz + 1)) % (Ly + 1)),
+              kx = (int)(t / ((size_t)(Lz + 1) * (Ly + 1)));
+    double v = B2[((size_t)kx * Py + ky) * Pz + kz].im * scale;  // B2 [Kx][Py][Pz]
     if ((a == 0 && kx == Kx - 1) || (a == 1 && ky == Ly) || (a == 2 && kz == Lz)) v = 0.0;
-    shat[(((size_t)ky * 3 + a) * Kx + kx) * (Lz + 1) + kz] = (T)v;
+    shat[(((size_t)kx * (Ly + 1) + ky) * 3 + a) * (Lz + 1) + kz] = (T)v;  // [Kx][Ly+1][3][Lz+1]
 }
 
 // ---- field: H = -grad phi (eq. (field)) ---------------------------------------

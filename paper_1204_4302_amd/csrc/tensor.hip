@@ -119,8 +119,8 @@ __global__ void __launch_bounds__(256) k_tensor_extract(size_t base, int comp, i
     const size_t total = (size_t)(Ly + 1) * Kx * (Lz + 1);
     size_t t = base + (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
-    int kz = (int)(t % (Lz + 1)), kx = (int)((t / (Lz + 1)) % Kx), ky = (int)(t / ((size_t)(Lz + 1) * Kx));
-    double v = B2[((size_t)ky * Kx + kx) * Pz + kz].re * scale;
+    int kz = (int)(t % (Lz + 1)), ky = (int)((t / (Lz + 1)) % (Ly + 1)), kx = (int)(t / ((size_t)(Lz + 1) * (Ly + 1)));
+    double v = B2[((size_t)kx * Py + ky) * Pz + kz].re * scale;  // B2 [Kx][Py][Pz]
     // A component odd in an axis has an exactly zero transform on that axis's
     // Nyquist plane (its samples at o and P - o cancel, and the sample at P/2
     // is zero); store the exact zero rather than the transform's rounding.
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(256) k_tensor_extract(size_t base, int comp, i
     const int Lx = Kx - 1;
     const bool oddx = comp == 3 || comp == 4, oddy = comp == 3 || comp == 5, oddz = comp == 4 || comp == 5;
     if ((oddx && kx == Lx) || (oddy && ky == Ly) || (oddz && kz == Lz)) v = 0.0;
-    nhat[(((size_t)ky * Kx + kx) * (Lz + 1) + kz) * 6 + comp] = (T)v;  // [Ly+1][Kx][Lz+1][6]
+    nhat[t * 6 + comp] = (T)v;  // [Kx][Ly+1][Lz+1][6]
 }
 
 }  // namespace
