@@ -19,8 +19,10 @@ constexpr int kMaxThreads = 256;  // workgroup size bound of every pass kernel
 //
 // p2 = 1 selects the compile-time register kernels (passes_p2.hip; lengths
 // 2^a and 3 * 2^a); then
-// t0, t1 are log2 of the tile extents (X: Ty; Y: Tx, Tz; Z: Tx) and the
-// workgroup size follows from them (pencils x threads per pencil).
+// t0, t1 are log2 of the tile extents (X: Ty; Y: Tx, Tz) and the workgroup
+// size follows from them (pencils x threads per pencil); for the Z pass t0 is
+// log2 of the consecutive ky' rows of one kx per tile and t1 the rows per
+// group (2: a row with its mirror, 1: single rows).
 struct LaunchCfg {
     int threads = 256;
     int E = 16;

@@ -693,14 +693,18 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) ky_inv(const cx<T>* __res
 }
 
 // ---------------------------------------------------------------------------
-// Fused Z pass.  Group g = s * Tx + xi handles the three component pencils
-// at (kx0 + xi, ky_s), ky_0 = ky', ky_1 = Py - ky'; each thread keeps all
-// three components in registers, so the tensor product needs no exchange and
-// the forward output slots hand over to the inverse input slots in registers.
-// Paired form (rows = 2): 1-D grid of ceil(Kx/Tx) * (Py/2 + 1) tiles, block
-// 2 * Tx * TP; a tile's two rows share the tensor octant row ky'.  Split form
-// (rows = 1, for lengths whose pair would exceed the workgroup): one row ky
-// per tile, ceil(Kx/Tx) * Py tiles, block Tx * TP, s = (ky > Py/2).
+// Fused Z pass.  A tile is Tx consecutive rows of one kx (B2 and the tensor
+// octant are kx-major, so its pencils and tensor rows are contiguous runs, and
+// consecutive tiles continue them).  Group g = s * Tx + xi handles the three
+// component pencils at (kx, ky_s), ky_0 = ky' = r0 + xi, ky_1 = Py - ky'; each
+// thread keeps all three components in registers, so the tensor product needs
+// no exchange and the forward output slots hand over to the inverse input
+// slots in registers.  Paired form (rows = 2): 1-D grid of
+// Kx * ceil((Py/2 + 1)/Tx) tiles, block 2 * Tx * TP; a row and its mirror share
+// the tensor octant row ky' (ky' = 0 and Py/2 have no mirror).  Split form
+// (rows = 1, for lengths whose pair would exceed the workgroup): rows ky =
+// r0 + xi of the whole range, Kx * ceil(Py/Tx) tiles, block Tx * TP,
+// s = (ky > Py/2).
 // Every B2 and tensor access is a raw buffer access (one resource per B2
 // component, one for the tensor octant with the component in the scalar
 // offset); the host guarantees that each range is below kOob.
@@ -734,28 +738,27 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     int gb;
     const int tile = batch_tile(xcd_tile(nxcd), bio, &gb);
     if (bio.in) B2 = (cx<T>*)bio.out[gb];
-    // rows of one kx tile are consecutive tiles (B2 and the octant are kx-major)
-    const int nrow = rows == 2 ? Ly + 1 : Py;
-    const int kx0 = (tile / nrow) << lgTx;
-    const int tx = min(Tx, Kx - kx0);
+    // a tile: Tx consecutive rows ky' (and their mirrors) of one kx
+    const int nrow = rows == 2 ? (Ly + Tx) >> lgTx : (Py + Tx - 1) >> lgTx;
+    const int kx = tile / nrow, r0 = (tile % nrow) << lgTx;
     int s, kyp, ky;
     bool ok;
     if (rows == 2) {
         s = g >> lgTx;
-        kyp = tile % nrow;
-        ok = s < ((kyp == 0 || kyp == Ly) ? 1 : 2) && xi < tx;
+        kyp = r0 + xi;
+        ok = kyp <= Ly && (s == 0 || (kyp != 0 && kyp != Ly));
         ky = s ? Py - kyp : kyp;
     } else {
-        ky = tile % nrow;
+        ky = r0 + xi;
+        ok = ky < Py;
         s = ky > Ly;
         kyp = s ? Py - ky : ky;
-        ok = xi < tx;
     }
     const size_t cstride = (size_t)Py * Kx * nz;  // component stride of B2 (elements)
     const Buf bc[3] = {make_buf(B2, cstride * CB), make_buf(B2 + cstride, cstride * CB),
                        make_buf(B2 + 2 * cstride, cstride * CB)};
     // byte offset of this lane's first element; zz = t + k TP adds k TP CB
-    const unsigned row = (unsigned)((((size_t)(kx0 + xi) * Py + ky) * nz + t) * CB);
+    const unsigned row = (unsigned)((((size_t)kx * Py + ky) * nz + t) * CB);
     cx<T> v[3][LT::EPT];
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
@@ -772,7 +775,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     // octant [Kx][Ly+1][Lz+1][6]: the six components of a frequency side by side
     constexpr unsigned FB = 6 * RB;  // bytes per frequency
     const Buf bt = make_buf(nhat, (size_t)Kx * (Ly + 1) * (Lz + 1) * FB);
-    const unsigned trow = ok ? (unsigned)((((size_t)(kx0 + xi) * (Ly + 1) + kyp) * (Lz + 1)) * FB) : 0u;
+    const unsigned trow = ok ? (unsigned)((((size_t)kx * (Ly + 1) + kyp) * (Lz + 1)) * FB) : 0u;
     T nt[LT::EPT][6];
     auto load_tensor = [&]() {
 #pragma unroll
@@ -865,27 +868,26 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
     const int Tx = 1 << lgTx, Ly = Py >> 1;
     const int xi = g & (Tx - 1);
     const int tile = xcd_tile(nxcd);
-    // rows of one kx tile are consecutive tiles (B2 and the octant are kx-major)
-    const int nrow = rows == 2 ? Ly + 1 : Py;
-    const int kx0 = (tile / nrow) << lgTx;
-    const int tx = min(Tx, Kx - kx0);
+    // a tile: Tx consecutive rows ky' (and their mirrors) of one kx
+    const int nrow = rows == 2 ? (Ly + Tx) >> lgTx : (Py + Tx - 1) >> lgTx;
+    const int kx = tile / nrow, r0 = (tile % nrow) << lgTx;
     int s, kyp, ky;
     bool ok;
     if (rows == 2) {
         s = g >> lgTx;
-        kyp = tile % nrow;
-        ok = s < ((kyp == 0 || kyp == Ly) ? 1 : 2) && xi < tx;
+        kyp = r0 + xi;
+        ok = kyp <= Ly && (s == 0 || (kyp != 0 && kyp != Ly));
         ky = s ? Py - kyp : kyp;
     } else {
-        ky = tile % nrow;
+        ky = r0 + xi;
+        ok = ky < Py;
         s = ky > Ly;
         kyp = s ? Py - ky : ky;
-        ok = xi < tx;
     }
     const size_t cstride = (size_t)Py * Kx * nz;
     const Buf bc[3] = {make_buf(B2, cstride * CB), make_buf(B2 + cstride, cstride * CB),
                        make_buf(B2 + 2 * cstride, cstride * CB)};
-    const unsigned row = (unsigned)((((size_t)(kx0 + xi) * Py + ky) * nz + t) * CB);
+    const unsigned row = (unsigned)((((size_t)kx * Py + ky) * nz + t) * CB);
     cx<T> v[3][LT::EPT];
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
@@ -898,7 +900,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
     }
     const size_t cs = (size_t)(Lz + 1);  // component stride of the spectrum octant
     const Buf bt = make_buf(shat, (size_t)Kx * (Ly + 1) * 3 * cs * RB);
-    const unsigned trow = ok ? (unsigned)((((size_t)(kx0 + xi) * (Ly + 1) + kyp) * 3 * (Lz + 1)) * RB) : 0u;
+    const unsigned trow = ok ? (unsigned)((((size_t)kx * (Ly + 1) + kyp) * 3 * (Lz + 1)) * RB) : 0u;
     T sk[LT::EPT][3];
     auto load_kernel = [&]() {
 #pragma unroll
@@ -1101,7 +1103,7 @@ hipError_t launch_z_conv_p2(int lgTx, int rows, hipStream_t st, cx<T>* B2, const
     if (!twt) return hipErrorInvalidValue;
     if (!p2_z_supported(P, sizeof(cx<T>)) || (rows != 1 && rows != 2)) return hipErrorInvalidValue;
     const int G = rows << lgTx;
-    dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * (rows == 2 ? Py / 2 + 1 : Py) * bio.count));
+    dim3 grid((unsigned)(Kx * ((rows == 2 ? Py / 2 + (1 << lgTx) : Py + (1 << lgTx) - 1) >> lgTx) * bio.count));
     const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
 #define CALL(PP) \
     if (hipError_t e_ = allow_lds(&kz_conv<T, PP>, lds)) return e_; \
@@ -1125,7 +1127,7 @@ hipError_t launch_z_sp_p2(int lgTx, int rows, hipStream_t st, cx<T>* B2, const T
     if (!twt) return hipErrorInvalidValue;
     if (!p2_z_supported(P, sizeof(cx<T>)) || (rows != 1 && rows != 2)) return hipErrorInvalidValue;
     const int G = rows << lgTx;
-    dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * (rows == 2 ? Py / 2 + 1 : Py)));
+    dim3 grid((unsigned)(Kx * ((rows == 2 ? Py / 2 + (1 << lgTx) : Py + (1 << lgTx) - 1) >> lgTx)));
     const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
 #define CALL(PP) \
     if (hipError_t e_ = allow_lds(&kz_sp<T, PP>, lds)) return e_; \

@@ -318,7 +318,7 @@ LaunchCfg p2_pencils(int P, int Kx, int nz, size_t cbytes, int target = 1024) {
     return c;
 }
 
-LaunchCfg p2_zconv(int P, int Kx, size_t cbytes, int target = 64) {
+LaunchCfg p2_zconv(int P, int Py, size_t cbytes, int target = 64) {
     LaunchCfg c;
     c.p2 = 1;
     const int TP = p2_threads_per_pencil(P);
@@ -326,7 +326,7 @@ LaunchCfg p2_zconv(int P, int Kx, size_t cbytes, int target = 64) {
     // of pencils would exceed the workgroup, then one row (1)
     const int rows = 2 * TP <= kP2MaxThreadsZ ? 2 : 1;
     int lgTx = std::max(0, ilog2i(std::max(1, target / (rows * TP))));
-    lgTx = std::min(lgTx, pow2_ceil_log(Kx));
+    lgTx = std::min(lgTx, pow2_ceil_log(Py / 2 + 1));
     while (lgTx > 0 &&
            ((size_t)p2_slab_elems(P) * (rows << lgTx)) * cbytes + p2_z_twiddle_lds_bytes(P, cbytes) > g_p2_lds - 256)
         --lgTx;
@@ -391,7 +391,7 @@ PassCfgs default_cfgs(const demag_plan_s* p) {
     c.xi = c.xf;
     c.yf = p2_supported(p->P[1]) ? p2_pencils(p->P[1], p->Kx, p->n[2], cb) : cfg_pencils(p->P[1], p->Kx, p->n[2], cb);
     c.yi = c.yf;
-    c.zc = p2_z_supported(p->P[2], cb) && p2_z_ranges_ok(p) ? p2_zconv(p->P[2], p->Kx, cb)
+    c.zc = p2_z_supported(p->P[2], cb) && p2_z_ranges_ok(p) ? p2_zconv(p->P[2], p->P[1], cb)
                                                              : cfg_zconv(p->P[2], p->Kx, cb);
     return c;
 }
@@ -1220,7 +1220,7 @@ int demag_sp_prepare(demag_plan_t p, void* stream) {
     if (!p) return fail(DEMAG_EINVAL, "NULL plan");
     if (p->shat) return DEMAG_OK;
     const size_t cb = csize(p->dtype), rb = cb / 2;
-    const LaunchCfg zs = p->cfg.zc.p2 ? p->cfg.zc : p2_zconv(p->P[2], p->Kx, cb);
+    const LaunchCfg zs = p->cfg.zc.p2 ? p->cfg.zc : p2_zconv(p->P[2], p->P[1], cb);
     if (!p2_z_supported(p->P[2], cb) || !p2_z_ranges_ok(p) || !p2_cfg_ok(zs, p->P[2], cb, 2))
         return fail(DEMAG_EUNSUPPORTED, "scalar-potential method: padded z length %d not supported in %s", p->P[2],
                     p->dtype == DEMAG_F32 ? "FP32" : "FP64");
@@ -1594,9 +1594,9 @@ void add_p2_candidates(const demag_plan_s* p, int kind, std::vector<LaunchCfg>& 
                 c.t1 = b;
                 c.threads = TP << (a + b);
             } else {
-                if (a > pow2_ceil_log(p->Kx)) continue;
-                c.t0 = a;
-                c.t1 = b;  // ky rows per workgroup
+                if (a > pow2_ceil_log(p->P[1] / 2 + 1)) continue;
+                c.t0 = a;  // log2 of the consecutive ky' rows of a tile
+                c.t1 = b;  // 2: each row with its mirror, 1: single rows
                 c.threads = b * TP << a;
             }
             if (c.threads < 64 && c.threads < TP * 2) continue;
