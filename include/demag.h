@@ -170,6 +170,22 @@ int demag_sp_kernel(demag_plan_t plan, double* out);
  * allocated.  Asynchronous on `stream`. */
 int demag_llg_heun(demag_plan_t plan, void* m, double Ms, double alpha, double gamma, double hx, double hy, double hz,
                    double dt, int nsteps, void* work, void* stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * steps as demag_llg_heun with the 9 nx ny nz-value workspace taken from a
+ * static device array of the library instead of a `work` argument.  The array
+ * holds DEMAG_LLG_STATIC_SCRATCH_BYTES (64 MiB) on every GPU the library runs
+ * on, from the library's load until the process ends; a plan whose workspace
+ * would exceed it (9 N sizeof(real) bytes: N up to 1,864,135 cells in FP32,
+ * 932,067 in FP64) gets DEMAG_EINVAL.  The call allocates nothing (no
+ * hipMalloc, hipFree or allocating library routine).  All calls on one GPU
+ * share the array and it keeps the last call's contents (none need to start at
+ * zero); calls that overlap on one GPU -- on different streams, or replays of
+ * graphs that captured it -- race and must be ordered by the caller.
+ * Asynchronous on `stream`. */
+#define DEMAG_LLG_STATIC_SCRATCH_BYTES (64ull << 20)
+int demag_llg_heun_static(demag_plan_t plan, void* m, double Ms, double alpha, double gamma, double hx, double hy,
+                          double hz, double dt, int nsteps, void* stream);
 
 /* ---- Tensor-grid method (TG, dense), Sec. 3.2 eqs. (transform), (gausspot),
  * (sumpot), (Dmat), (gs) -----------------------------------------------------

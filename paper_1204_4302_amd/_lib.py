@@ -42,6 +42,7 @@ SIGNATURES = {
     "demag_sp_field_energy": (_I, [_P, _P, _D, _P, _P, _P]),
     "demag_sp_kernel": (_I, [_P, _P]),
     "demag_llg_heun": (_I, [_P, _P, _D, _D, _D, _D, _D, _D, _D, _I, _P, _P]),
+    "demag_llg_heun_static": (_I, [_P, _P, _D, _D, _D, _D, _D, _D, _D, _I, _P]),
     "demag_tg_prepare": (_I, [_P, _P]),
     "demag_tg_field": (_I, [_P, _P, _D, _P, _P]),
     "demag_tg_field_energy": (_I, [_P, _P, _D, _P, _P, _P]),

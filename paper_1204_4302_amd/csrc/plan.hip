@@ -19,6 +19,7 @@
 #include <map>
 #include <sstream>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "../../include/demag.h"
@@ -898,6 +899,70 @@ int leave(demag_plan_s* p, hipStream_t st) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
 
+// LLG Heun steps (Sec. 2) on the workspace `work` (9 N values of the plan
+// precision: H, k1, the predictor; nothing is allocated).
+int llg_heun_impl(demag_plan_s* p, void* m, double Ms, double alpha, double gamma, double hx, double hy, double hz,
+                  double dt, int nsteps, void* work, void* stream) {
+    if (!p || !m || !work) return fail(DEMAG_EINVAL, "NULL plan, m or work");
+    if (!std::isfinite(Ms) || !(alpha >= 0) || !std::isfinite(alpha) || !(gamma > 0) || !std::isfinite(gamma) ||
+        !std::isfinite(hx) || !std::isfinite(hy) || !std::isfinite(hz) || !(dt > 0) || !std::isfinite(dt) || nsteps < 0)
+        return fail(DEMAG_EINVAL, "need finite Ms, alpha >= 0, gamma > 0, finite H_ext, dt > 0, nsteps >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    const size_t N = (size_t)p->n[0] * p->n[1] * p->n[2];
+    const double hext[3] = {hx, hy, hz};
+    const double g = gamma / (1.0 + alpha * alpha);
+    auto steps = [&](auto proto) -> int {
+        using T = decltype(proto);
+        T* mm = (T*)m;
+        T* H = (T*)work;
+        T* k1 = H + 3 * N;
+        T* ms = k1 + 3 * N;
+        for (int s = 0; s < nsteps; ++s) {
+            int r = run_field<T>(p, p->cfg, mm, Ms, H, nullptr, nullptr, 0, st);
+            if (r) return r;
+            HIP_TRY(launch_llg_predict<T>(st, N, mm, H, hext, g, alpha, dt, k1, ms));
+            r = run_field<T>(p, p->cfg, ms, Ms, H, nullptr, nullptr, 0, st);
+            if (r) return r;
+            HIP_TRY(launch_llg_correct<T>(st, N, mm, H, k1, ms, hext, g, alpha, dt));
+        }
+        return DEMAG_OK;
+    };
+    rc = p->dtype == DEMAG_F32 ? steps(float()) : steps(double());
+    if (rc) return rc;
+    return leave(p, st);
+}
+
+// Workspace of demag_llg_heun_static, for callers that cannot allocate: a
+// file-scope device array, which every GPU the library runs on holds from the
+// library's load until the process ends.  In host code its name stands for
+// the symbol only; its device address comes from hipGetSymbolAddress, looked
+// up once per device (with that device current) and kept.  Nothing in it
+// needs to start at zero (each step writes H, k1 and the predictor before
+// reading them); calls on one device share it, so calls that overlap race.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DEMAG_EUNSUPPORTED, "device %d beyond the static scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(DEMAG_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DEMAG_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1277,35 +1342,22 @@ int demag_sp_kernel(demag_plan_t p, double* out) {
 
 int demag_llg_heun(demag_plan_t p, void* m, double Ms, double alpha, double gamma, double hx, double hy, double hz,
                    double dt, int nsteps, void* work, void* stream) {
-    if (!p || !m || !work) return fail(DEMAG_EINVAL, "NULL plan, m or work");
-    if (!std::isfinite(Ms) || !(alpha >= 0) || !std::isfinite(alpha) || !(gamma > 0) || !std::isfinite(gamma) ||
-        !std::isfinite(hx) || !std::isfinite(hy) || !std::isfinite(hz) || !(dt > 0) || !std::isfinite(dt) || nsteps < 0)
-        return fail(DEMAG_EINVAL, "need finite Ms, alpha >= 0, gamma > 0, finite H_ext, dt > 0, nsteps >= 0");
-    hipStream_t st = (hipStream_t)stream;
-    int rc = enter(p, st);
-    if (rc) return rc;
+    if (!work) return fail(DEMAG_EINVAL, "NULL work");
+    return llg_heun_impl(p, m, Ms, alpha, gamma, hx, hy, hz, dt, nsteps, work, stream);
+}
+
+int demag_llg_heun_static(demag_plan_t p, void* m, double Ms, double alpha, double gamma, double hx, double hy,
+                          double hz, double dt, int nsteps, void* stream) {
+    if (!p) return fail(DEMAG_EINVAL, "NULL plan");
     const size_t N = (size_t)p->n[0] * p->n[1] * p->n[2];
-    const double hext[3] = {hx, hy, hz};
-    const double g = gamma / (1.0 + alpha * alpha);
-    auto steps = [&](auto proto) -> int {
-        using T = decltype(proto);
-        T* mm = (T*)m;
-        T* H = (T*)work;
-        T* k1 = H + 3 * N;
-        T* ms = k1 + 3 * N;
-        for (int s = 0; s < nsteps; ++s) {
-            int r = run_field<T>(p, p->cfg, mm, Ms, H, nullptr, nullptr, 0, st);
-            if (r) return r;
-            HIP_TRY(launch_llg_predict<T>(st, N, mm, H, hext, g, alpha, dt, k1, ms));
-            r = run_field<T>(p, p->cfg, ms, Ms, H, nullptr, nullptr, 0, st);
-            if (r) return r;
-            HIP_TRY(launch_llg_correct<T>(st, N, mm, H, k1, ms, hext, g, alpha, dt));
-        }
-        return DEMAG_OK;
-    };
-    rc = p->dtype == DEMAG_F32 ? steps(float()) : steps(double());
+    const size_t need = 9 * N * (p->dtype == DEMAG_F32 ? sizeof(float) : sizeof(double));
+    if (need > kStaticScratchBytes)
+        return fail(DEMAG_EINVAL, "workspace of %zu bytes exceeds the static scratch (%zu bytes); use demag_llg_heun",
+                    need, kStaticScratchBytes);
+    void* work = nullptr;
+    const int rc = static_scratch(&work);
     if (rc) return rc;
-    return leave(p, st);
+    return llg_heun_impl(p, m, Ms, alpha, gamma, hx, hy, hz, dt, nsteps, work, stream);
 }
 
 int demag_tg_prepare(demag_plan_t p, void* stream) {
