@@ -10,7 +10,7 @@ shared object with ctypes and marshals numpy arrays.
 Functions and the passages they follow (Abert et al., arXiv:1204.4302):
 
 * ``tensor``      -- cell-averaged demagnetization tensor N for homogeneously
-                     magnetized cells (Sec. 4.1, "Homogeneously Magnetized
+                     magnetized cells (Sec. 5.1, "Homogeneously Magnetized
                      Cube"; closed forms of Newell et al. 1993, which the paper
                      cites only by property).
 * ``field``       -- H = -Ms N * m as a plain sum, Sec. 3.1 eq. (demag).

@@ -14,7 +14,7 @@
  *      H_i = -Ms * sum_j N(r_i - r_j) m_j          (every cell j, j = i included)
  *
  * with N the cell-averaged demagnetization tensor of homogeneously magnetized
- * cuboid cells (Sec. 4.1: the tensor assumes homogeneously magnetized cells and
+ * cuboid cells (Sec. 5.1: the tensor assumes homogeneously magnetized cells and
  * the field is averaged over each cell).  The paper names this tensor but does
  * not print it; the closed forms used here are those of Newell, Williams and
  * Dunlop (J. Geophys. Res. 98, 1993): N is (1/(4 pi V)) times the 27-point

@@ -2,7 +2,7 @@
 // cells, in FP64, for one integer cell offset o (device math for the setup).
 //
 // The paper uses the tensor of homogeneously magnetized cells whose field is
-// averaged over each cell (Sec. 4.1) without printing it.  Three routes to the
+// averaged over each cell (Sec. 5.1) without printing it.  Three routes to the
 // same quantity, chosen per offset by distance:
 //
 //  near  (Chebyshev distance <= fg_cut): the closed form of Newell, Williams
