@@ -106,8 +106,10 @@ int demag_plan_info(demag_plan_t plan, int64_t* info);
  * demag_energy_async record only kernels (no memset, no synchronisation) and
  * may be captured into a HIP graph by stream capture: while `stream` is
  * capturing, the plan's busy tracking and pass timing are skipped; a replay
- * reads the buffers given at capture.  (A plan must still not run two
- * evaluations at once.) */
+ * reads the buffers given at capture.  Replays of such a graph are outside the
+ * plan's busy tracking (DEMAG_ESTATE cannot see them): they use the plan's
+ * scratch like any call, so the caller must order them against every other
+ * call on the plan and must not run two at once. */
 int demag_field(demag_plan_t plan, const void* m, double Ms, void* H, void* stream);
 
 /* Adjoint (transpose) of m -> H applied to a cotangent gH:
@@ -120,6 +122,16 @@ int demag_field_adjoint(demag_plan_t plan, const void* gH, double Ms, void* gm, 
  * E_dev, a DEVICE double receiving E = -(mu0/2) Ms V sum m.H (Sec. 2).
  * FP32 plans form m.H in FP32 and accumulate in FP64.  Asynchronous. */
 int demag_field_energy(demag_plan_t plan, const void* m, double Ms, void* H, double* E_dev, void* stream);
+
+/* Gradient of the energy of Sec. 2 with respect to m, from the field H that
+ * demag_field / demag_field_energy returned for that m: E is quadratic in m
+ * and the grid operator is symmetric, so dE/dm = -mu0 Ms V H (no further
+ * convolution).  gm (+)= gE * dE/dm, gE = *gE_dev (a DEVICE double, the
+ * cotangent of E; NULL means 1); accumulate = 0 overwrites gm, 1 adds to it.
+ * H and gm: device [3][nz][ny][nx] in the plan precision, distinct buffers.
+ * Asynchronous. */
+int demag_energy_gradient(demag_plan_t plan, const void* H, double Ms, const double* gE_dev, void* gm, int accumulate,
+                          void* stream);
 
 /* Energy only, result to a HOST double; synchronises `stream`. */
 int demag_energy(demag_plan_t plan, const void* m, double Ms, double* E_host, void* stream);

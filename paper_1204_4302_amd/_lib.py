@@ -30,6 +30,7 @@ SIGNATURES = {
     "demag_field_energy": (_I, [_P, _P, _D, _P, _P, _P]),
     "demag_energy": (_I, [_P, _P, _D, ctypes.POINTER(_D), _P]),
     "demag_energy_async": (_I, [_P, _P, _D, _P, _P]),
+    "demag_energy_gradient": (_I, [_P, _P, _D, _P, _P, _I, _P]),
     "demag_plan_spectrum": (_I, [_P, _P]),
     "demag_plan_tensor": (_I, [_P, _P]),
     "demag_plan_describe": (_I, [_P, ctypes.c_char_p, _I]),

@@ -60,6 +60,9 @@ hipError_t launch_x_inv(const LaunchCfg&, hipStream_t, const cx<T>* in, T* out, 
                         int ny, int nz, int Kx, int C, int accumulate, const FftPlanDev&, const cx<T>* tw,
                         const BatchIO& bio = BatchIO());
 hipError_t launch_energy_reduce(hipStream_t, const double* partials, int n, double scale, double* out);
+// gm (+)= gE c H over n values (gE: device scalar, NULL = 1): the energy gradient.
+template <typename T>
+hipError_t launch_energy_grad(hipStream_t, size_t n, const T* H, const double* gE, double c, T* gm, int accumulate);
 
 // lengths 2^a and 3 * 2^a (2 <= P <= 4096): compile-time instances
 // compile-time register kernels ("p2" family): lengths 2^a and 3 * 2^a up to

@@ -307,6 +307,18 @@ __global__ void __launch_bounds__(kReduceThreads) k_energy_reduce(const double* 
     if (tid == 0) out[0] = scale * red[0];
 }
 
+// Energy gradient (Sec. 2): E = -(mu0/2) Ms V sum m.H(m) is quadratic in m
+// and the grid operator is symmetric, so dE/dm = -mu0 Ms V H(m); with the
+// cotangent gE (device scalar, NULL = 1), gm (+)= gE c H, c = -mu0 Ms V.
+template <typename T>
+__global__ void __launch_bounds__(256) k_energy_grad(size_t n, const T* __restrict__ H,
+                                                     const double* __restrict__ gE, double c, T* __restrict__ gm,
+                                                     int accumulate) {
+    const T s = (T)(gE ? gE[0] * c : c);
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        gm[i] = accumulate ? gm[i] + s * H[i] : s * H[i];
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers (E dispatch).
 #define DEMAG_E_SWITCH(E, CALL)                              \
@@ -397,6 +409,14 @@ hipError_t launch_energy_reduce(hipStream_t st, const double* partials, int n, d
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_energy_grad(hipStream_t st, size_t n, const T* H, const double* gE, double c, T* gm, int accumulate) {
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL((k_energy_grad<T>), dim3((unsigned)blocks), dim3(256), 0, st, n, H, gE, c, gm, accumulate);
+    return hipGetLastError();
+}
+
 #define DEMAG_INSTANTIATE(T)                                                                                      \
     template hipError_t launch_x_fwd<T>(const LaunchCfg&, hipStream_t, const T*, cx<T>*, int, int, int, int, int, \
                                         const FftPlanDev&, const cx<T>*, const BatchIO&);                         \
@@ -409,7 +429,8 @@ hipError_t launch_energy_reduce(hipStream_t st, const double* partials, int n, d
     template hipError_t launch_y_inv<T>(const LaunchCfg&, hipStream_t, const cx<T>*, cx<T>*, int, int, int, int,  \
                                         const FftPlanDev&, const cx<T>*, const BatchIO&);                         \
     template hipError_t launch_x_inv<T>(const LaunchCfg&, hipStream_t, const cx<T>*, T*, const T*, double*, int,  \
-                                        int, int, int, int, int, const FftPlanDev&, const cx<T>*, const BatchIO&);
+                                        int, int, int, int, int, const FftPlanDev&, const cx<T>*, const BatchIO&); \
+    template hipError_t launch_energy_grad<T>(hipStream_t, size_t, const T*, const double*, double, T*, int);
 
 DEMAG_INSTANTIATE(float)
 DEMAG_INSTANTIATE(double)

@@ -709,16 +709,26 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) ky_inv(const cx<T>* __res
 // component, one for the tensor octant with the component in the scalar
 // offset); the host guarantees that each range is below kOob.
 //
-// Register budget.  FP32 power-of-two lengths load the tensor values of all
-// the thread's frequencies together with the data, before the transforms, so
-// that their latency overlaps, and keep the thread's twiddles in registers for
-// all six transforms.  FP64 (twice the registers) and lengths 3 * 2^a (three
-// times the slots) load the tensor after the forward transforms and read the
-// twiddles per transform from the workgroup's LDS copy of the table (from
-// memory if it is larger than kP2TwLdsMax), which keeps them in registers.
+// Register budget.  FP32 power-of-two lengths keep the thread's twiddles in
+// registers for all six transforms; in the paired form the tile's tensor rows
+// are copied into LDS with 16-byte loads issued together with the data loads,
+// and each frequency's six values are read from LDS right before its product
+// (the split form at 4096 loads them into registers up front).  FP64 (twice
+// the registers) and lengths 3 * 2^a (three times the slots) load the tensor
+// after the forward transforms and read the twiddles per transform from the
+// workgroup's LDS copy of the table (from memory if it is larger than
+// kP2TwLdsMax), which keeps them in registers.
 template <typename T, int P>
 __host__ __device__ constexpr bool z_keep_twiddles() {
     return sizeof(T) == 4 && p2::is_pow2(P);
+}
+// The same lengths in the paired form stage the tile's tensor rows in LDS
+// (one contiguous run of the kx-major octant) instead of loading each
+// frequency's six values into registers up front: 142 -> 97 VGPRs at P = 128
+// (3 -> 4 waves per SIMD), fused Z pass 109 -> 100 us at 256x256x64.
+template <typename T>
+bool z_stages_tensor(int P) {
+    return sizeof(T) == 4 && p2::is_pow2(P) && 2 * p2_threads_per_pencil(P) <= kP2MaxThreadsZ;
 }
 
 template <typename T, int P>
@@ -792,7 +802,34 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
             bld6<T>(bt, off, nt[j]);
         }
     };
-    if constexpr (kKeep) load_tensor();
+    constexpr bool kStage = kKeep && kPow2 && 2 * LT::TP <= kP2MaxThreadsZ;  // paired form only
+    // kStage: the tile's octant rows (kx, r0 .. r0 + Tx - 1) are one contiguous
+    // run; it is copied into LDS (after the slabs) with 16-byte loads from a
+    // 16-byte-aligned start, and each frequency's six values are read from there
+    // right before its product.
+    const T* tls = nullptr;
+    unsigned tmis = 0;
+    if constexpr (kStage) {
+        const int nthr = blockDim.x;
+        const int G = rows << lgTx;
+        const unsigned tb0 = (unsigned)((((size_t)kx * (Ly + 1) + r0) * (Lz + 1)) * FB);
+        const unsigned tal = tb0 & ~15u;
+        tmis = tb0 - tal;
+        const unsigned nbytes = (unsigned)min(Tx, Ly + 1 - r0) * (Lz + 1) * FB + tmis;
+        constexpr int NCH = ((Lz + 1) * (int)FB + 16 + 32 * LT::TP - 1) / (32 * LT::TP);
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        u4 ch[NCH];
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) ch[q] = __builtin_amdgcn_raw_buffer_load_b128(bt.r, tal + (unsigned)(tid + q * nthr) * 16u, 0, 0);
+        u4* dstl = (u4*)(lds + G * LT::PS);
+#pragma unroll
+        for (int q = 0; q < NCH; ++q)
+            if ((unsigned)(tid + q * nthr) * 16u < nbytes) dstl[tid + q * nthr] = ch[q];
+        __syncthreads();
+        tls = (const T*)((const unsigned char*)(lds + G * LT::PS) + tmis) + (size_t)xi * (Lz + 1) * 6;
+    } else if constexpr (kKeep) {
+        load_tensor();
+    }
     cx<T>* slab = lds + g * LT::PS;
     const cx<T>* twsrc = twt;
     if constexpr (!kKeep) {
@@ -818,6 +855,18 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         bool negz;
         if constexpr (kPow2) negz = LT::F::slot_out(j) >= LT::EPT / 2;
         else negz = LT::fout(t, j) > Lz;
+        if constexpr (kStage) {
+            const int k = LT::F::slot_out(j);
+            const int kzp = k < LT::EPT / 2 ? t + k * LT::TP : (LT::TP - 1 - t) + P - (k + 1) * LT::TP + 1;
+            typedef T t2 __attribute__((ext_vector_type(2)));
+            const t2* e = (const t2*)(tls + kzp * 6);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const t2 u = e[i];
+                nt[j][2 * i] = u.x;
+                nt[j][2 * i + 1] = u.y;
+            }
+        }
         const T nxx = nt[j][0], nyy = nt[j][1], nzz = nt[j][2];
         const T nxy = sy * nt[j][3];
         const T nxz = negz ? -nt[j][4] : nt[j][4];
@@ -1102,9 +1151,11 @@ hipError_t launch_z_conv_p2(int lgTx, int rows, hipStream_t st, cx<T>* B2, const
                             int Kx, int P, const cx<T>* twt, const BatchIO& bio) {
     if (!twt) return hipErrorInvalidValue;
     if (!p2_z_supported(P, sizeof(cx<T>)) || (rows != 1 && rows != 2)) return hipErrorInvalidValue;
+    if (rows != (2 * p2_threads_per_pencil(P) <= kP2MaxThreadsZ ? 2 : 1)) return hipErrorInvalidValue;
     const int G = rows << lgTx;
     dim3 grid((unsigned)(Kx * ((rows == 2 ? Py / 2 + (1 << lgTx) : Py + (1 << lgTx) - 1) >> lgTx) * bio.count));
-    const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
+    size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
+    if (z_stages_tensor<T>(P)) lds += ((size_t)(1 << lgTx) * (P / 2 + 1) * 6 + 4) * sizeof(T);
 #define CALL(PP) \
     if (hipError_t e_ = allow_lds(&kz_conv<T, PP>, lds)) return e_; \
     hipLaunchKernelGGL((kz_conv<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, rows, kXcds, \

@@ -209,7 +209,6 @@ struct demag_plan_s {
     hipEvent_t busy = nullptr;  // marks the plan's last enqueued work: `done`, or its batch's event
     hipStream_t last_stream = nullptr;
     bool used = false;
-    bool capturing = false;
     // optional pass timing: kPassMarks events per evaluation in a ring of tcap slots
     std::vector<hipEvent_t> tev;
     int tcap = 0;
@@ -343,7 +342,7 @@ bool p2_cfg_ok(const LaunchCfg& c, int P, size_t cbytes, int kind /*0 rows, 1 pe
     const long TP = p2_threads_per_pencil(P);
     long pencils = kind == 0 ? (1L << (c.t0 - 1)) : kind == 1 ? (1L << (c.t0 + c.t1)) : ((long)c.t1 << c.t0);
     if (kind == 0 && c.t0 < 1) return false;
-    if (kind == 2 && c.t1 != 1 && c.t1 != 2) return false;
+    if (kind == 2 && c.t1 != (2 * TP <= kP2MaxThreadsZ ? 2 : 1)) return false;
     long threads = pencils * TP;
     long maxthr = kind == 2 ? kP2MaxThreadsZ : p2_max_threads(P);
     if (kind == 2 && !p2_z_supported(P, cbytes)) return false;
@@ -808,7 +807,7 @@ template <typename T>
 int run_field(demag_plan_s* p, const PassCfgs& c, const T* m, double Ms, T* H, const T* m_energy, double* E_dev,
               int accumulate, hipStream_t st) {
     hipEvent_t* mark = nullptr;
-    if (p->tcap > 0 && !p->capturing && !stream_capturing(st))
+    if (p->tcap > 0 && !stream_capturing(st))
         mark = &p->tev[(size_t)(p->tcount % p->tcap) * kPassMarks];
     double* partials = E_dev ? p->partials : nullptr;
     const T* me = E_dev ? m_energy : nullptr;
@@ -875,7 +874,7 @@ int dispatch_field(demag_plan_s* p, const void* m, double Ms, void* H, double* E
 // One plan on one stream at a time: refuse a call on another stream while
 // the plan's previous work is still pending.
 int enter(demag_plan_s* p, hipStream_t st) {
-    if (p->capturing || stream_capturing(st)) return DEMAG_OK;
+    if (stream_capturing(st)) return DEMAG_OK;
     int cur = 0;
     HIP_TRY(hipGetDevice(&cur));
     if (cur != p->device) return fail(DEMAG_ESTATE, "plan was created on device %d, current device is %d", p->device, cur);
@@ -889,7 +888,7 @@ int enter(demag_plan_s* p, hipStream_t st) {
 }
 
 int leave(demag_plan_s* p, hipStream_t st) {
-    if (p->capturing || stream_capturing(st)) return DEMAG_OK;
+    if (stream_capturing(st)) return DEMAG_OK;
     HIP_TRY(hipEventRecord(p->done, st));
     p->busy = p->done;
     p->last_stream = st;
@@ -1239,6 +1238,22 @@ int demag_field_energy(demag_plan_t p, const void* m, double Ms, void* H, double
 
 int demag_energy_async(demag_plan_t p, const void* m, double Ms, double* E_dev, void* stream) {
     return demag_field_energy(p, m, Ms, nullptr, E_dev, stream);
+}
+
+int demag_energy_gradient(demag_plan_t p, const void* H, double Ms, const double* gE_dev, void* gm, int accumulate,
+                          void* stream) {
+    if (!p || !H || !gm) return fail(DEMAG_EINVAL, "NULL plan, H or gm");
+    if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
+    if (H == gm) return fail(DEMAG_EINVAL, "H and gm must be distinct buffers");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = enter(p, st);
+    if (rc) return rc;
+    const size_t n = 3ull * p->n[0] * p->n[1] * p->n[2];
+    const double c = -kMu0 * Ms * p->d[0] * p->d[1] * p->d[2];
+    HIP_TRY(p->dtype == DEMAG_F32
+                ? launch_energy_grad<float>(st, n, (const float*)H, gE_dev, c, (float*)gm, accumulate ? 1 : 0)
+                : launch_energy_grad<double>(st, n, (const double*)H, gE_dev, c, (double*)gm, accumulate ? 1 : 0));
+    return leave(p, st);
 }
 
 int demag_energy(demag_plan_t p, const void* m, double Ms, double* E_host, void* stream) {
@@ -1634,6 +1649,8 @@ void add_p2_candidates(const demag_plan_s* p, int kind, std::vector<LaunchCfg>& 
     const int TP = p2_threads_per_pencil(P);
     for (int a = 0; a <= 10; ++a)
         for (int b = kind == 2 ? 1 : 0; b <= (kind == 1 ? 10 : kind == 2 ? 2 : 0); ++b) {
+            // the fused Z pass pairs each row with its mirror whenever the pair fits a workgroup
+            if (kind == 2 && b != (2 * TP <= kP2MaxThreadsZ ? 2 : 1)) continue;
             LaunchCfg c;
             c.p2 = 1;
             if (kind == 0) {
@@ -1742,9 +1759,19 @@ template <typename T>
 int autotune_impl(demag_plan_s* p, hipStream_t st) {
     const size_t nvec = 3ull * p->n[0] * p->n[1] * p->n[2];
     T *m = nullptr, *H = nullptr;
-    HIP_TRY(hipMalloc(&m, nvec * sizeof(T)));
-    HIP_TRY(hipMalloc(&H, nvec * sizeof(T)));
-    HIP_TRY(hipMemsetAsync(m, 0, nvec * sizeof(T), st));
+    auto release = [&]() {
+        (void)hipFree(m);
+        (void)hipFree(H);
+    };
+    if (hipMalloc(&m, nvec * sizeof(T)) != hipSuccess || hipMalloc(&H, nvec * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        release();
+        return fail(DEMAG_ENOMEM, "autotune: cannot allocate %zu bytes of input and output", 2 * nvec * sizeof(T));
+    }
+    if (hipError_t e = hipMemsetAsync(m, 0, nvec * sizeof(T), st)) {
+        release();
+        return hip_fail(e, "hipMemsetAsync");
+    }
     int rc = DEMAG_OK;
     std::vector<LaunchCfg> cand[5] = {candidates_rows(p), candidates_pencils(p), candidates_z(p),
                                       candidates_pencils(p), candidates_rows(p)};
@@ -1765,8 +1792,8 @@ int autotune_impl(demag_plan_s* p, hipStream_t st) {
         }
         *slot[which] = bestc;
     }
-    (void)hipFree(m);
-    (void)hipFree(H);
+    (void)hipStreamSynchronize(st);  // the timed launches have finished with m and H
+    release();
     return rc;
 }
 
@@ -1788,9 +1815,11 @@ extern "C" int demag_autotune(demag_plan_t p, void* stream) {
             return DEMAG_OK;
         }
     }
+    const PassCfgs before = p->cfg;  // shapes the plan has verified (defaults, generic_kernels, a cache)
     rc = p->dtype == DEMAG_F32 ? autotune_impl<float>(p, st) : autotune_impl<double>(p, st);
     if (rc) {
-        p->cfg = default_cfgs(p);
+        p->cfg = before;
+        (void)leave(p, st);  // the busy marker covers what was enqueued before the failure
         return rc;
     }
     if (path) {

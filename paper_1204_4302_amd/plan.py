@@ -155,6 +155,20 @@ class Plan:
                   self._ptr(H) if H is not None else None, ctypes.c_void_p(E.data_ptr()), _stream_ptr())
         return H, E
 
+    def energy_gradient(self, H: torch.Tensor, Ms: float, gE: torch.Tensor | None = None,
+                        out: torch.Tensor | None = None, accumulate: bool = False) -> torch.Tensor:
+        """gE * dE/dm = gE * (-mu0 Ms V H) from the field H of m (gE: a
+        one-element float64 CUDA tensor, None = 1)."""
+        self._check(H, "H")
+        gm = torch.empty_like(H) if out is None else out
+        self._check(gm, "out")
+        if gE is not None and (gE.dtype != torch.float64 or gE.device.type != "cuda" or gE.numel() != 1):
+            raise TypeError("gE must be a one-element float64 CUDA tensor")
+        _lib.call("demag_energy_gradient", self._h, self._ptr(H), float(Ms),
+                  ctypes.c_void_p(gE.data_ptr()) if gE is not None else None, self._ptr(gm),
+                  1 if accumulate else 0, _stream_ptr())
+        return gm
+
     # -- scalar-potential method (SP) ---------------------------------------
     def sp_prepare(self):
         """Build the SP kernel spectrum (synchronous, once)."""
@@ -403,20 +417,22 @@ class DemagField(torch.autograd.Function):
 
 
 class DemagEnergy(torch.autograd.Function):
-    """E = -(mu0/2) Ms V sum m.H; dE/dm = -mu0 Ms V H (the operator is
-    symmetric), so the backward needs no further convolution."""
+    """E = -(mu0/2) Ms V sum m.H; the backward hands the saved field and the
+    cotangent to demag_energy_gradient (dE/dm = -mu0 Ms V H: the operator is
+    symmetric, so no further convolution)."""
 
     @staticmethod
     def forward(ctx, m, plan: Plan, Ms: float):
         H, E = plan.field_energy(m.contiguous(), Ms)
         ctx.save_for_backward(H)
-        ctx.scale = -MU0 * float(Ms) * plan.volume
+        ctx.plan, ctx.Ms = plan, float(Ms)
         return E
 
     @staticmethod
     def backward(ctx, gE):
         (H,) = ctx.saved_tensors
-        return (gE.to(H.dtype) * ctx.scale) * H, None, None
+        g = gE.detach().to(device=H.device, dtype=torch.float64).contiguous()
+        return ctx.plan.energy_gradient(H, ctx.Ms, gE=g), None, None
 
 
 def demag_field(m, plan: Plan, Ms: float):

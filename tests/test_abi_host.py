@@ -69,6 +69,8 @@ def test_null_handles_rejected():
     assert lib.demag_batch_autotune(None, None) == -1
     assert lib.demag_sp_prepare(None, None) == -1
     assert lib.demag_llg_heun(None, None, 1.0, 0.1, 2.2e5, 0.0, 0.0, 0.0, 1e-13, 1, None, None) == -1
+    assert lib.demag_llg_heun_static(None, None, 1.0, 0.1, 2.2e5, 0.0, 0.0, 0.0, 1e-13, 1, None) == -1
+    assert lib.demag_energy_gradient(None, None, 1.0, None, None, 0, None) == -1
     assert lib.demag_sp_field(None, None, 1.0, None, None) == -1
     assert lib.demag_sp_field_energy(None, None, 1.0, None, None, None) == -1
     assert lib.demag_sp_kernel(None, None) == -1

@@ -18,9 +18,11 @@ pytestmark = pytest.mark.gpu
 
 TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
 CELL = (2e-9, 2e-9, 3e-9)
+# (the padded z lengths 640, 720 and 1200 run on the generic Z pass in both
+# precisions; padded z 3072 has a fused pass in FP32 only and is refused in FP64)
 RUNS = [((2048, 2, 2), None), ((2, 2048, 2), None), ((1536, 3, 2), None), ((2, 2, 1024), None),
         ((2, 2, 2048), None), ((3, 3, 2039), None), ((3, 2, 1536), torch.float32),
-        ((2, 2, 320), torch.float64), ((2, 2, 341), torch.float64), ((2, 2, 600), torch.float64)]
+        ((2, 2, 320), None), ((2, 2, 341), None), ((2, 2, 600), None)]
 
 
 @pytest.mark.parametrize("shape,only", RUNS, ids=lambda v: str(v))
@@ -28,7 +30,7 @@ RUNS = [((2048, 2, 2), None), ((2, 2048, 2), None), ((1536, 3, 2), None), ((2, 2
 def test_max_padded_length(shape, only, dtype):
     from paper_1204_4302_amd import Plan
     if only is not None and dtype != only:
-        pytest.skip("length taken in the other precision only")
+        pytest.skip("refused in this precision at plan creation (test_z_lengths_without_a_fused_pass_are_refused)")
     plan = Plan(shape, CELL, dtype)
     info = plan.info()
     m = inputs.random_unit(shape, 11)

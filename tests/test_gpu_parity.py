@@ -161,6 +161,105 @@ def test_spectrum_matches_fft_of_oracle_tensor():
         assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
 
 
+def _embedded(o, c, P):
+    """Component c of the oracle tensor octant mirrored into a P-periodic
+    array [Pz][Py][Px] with its parity signs (xy odd in x and y, xz in x and z,
+    yz in y and z), zero in the padding gap."""
+    Px, Py, Pz = P
+    nz, ny, nx = o.Noct.shape[1:]
+    par = [(0, 0, 0), (0, 0, 0), (0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+    A = np.zeros((Pz, Py, Px))
+    for sz in (1, -1):
+        for sy in (1, -1):
+            for sx in (1, -1):
+                sign = (sx if par[c][0] else 1) * (sy if par[c][1] else 1) * (sz if par[c][2] else 1)
+                A[np.ix_((sz * np.arange(nz)) % Pz, (sy * np.arange(ny)) % Py, (sx * np.arange(nx)) % Px)] = \
+                    sign * o.Noct[c]
+    return A
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_spectrum_equals_direct_dft(dtype):
+    """The FFT engine (radix-2/3/5 generic passes along x and y, register
+    kernel along z) against the DFT by its definition, sum_o A(o)
+    exp(-2 pi i k.o / P) as explicit products with the DFT matrices, on the
+    stored octant: the tensor spectrum of a 5-smooth grid (padded 30 x 18 x 8)."""
+    shape, cell = (15, 9, 4), (2e-9, 2e-9, 3e-9)
+    o = get_oracle(shape, cell)
+    plan = get_plan(shape, cell, dtype)
+    info = plan.info()
+    P = (info["Px"], info["Py"], info["Pz"])
+    assert P == (30, 18, 8)
+    Kx, S = info["Kx"], plan.spectrum()
+
+    def dft_matrix(n, keep):
+        k = np.arange(keep)[:, None]
+        t = np.arange(n)[None, :]
+        return np.exp(-2j * np.pi * ((k * t) % n) / n)  # exact angle reduction before exp
+
+    Wx, Wy, Wz = dft_matrix(P[0], Kx), dft_matrix(P[1], P[1] // 2 + 1), dft_matrix(P[2], P[2] // 2 + 1)
+    for c in range(6):
+        A = _embedded(o, c, P)
+        F = np.einsum("az,by,cx,zyx->abc", Wz, Wy, Wx, A)  # [kz][ky][kx]
+        ref = -F.real / (P[0] * P[1] * P[2])
+        got = S[:, c, :, :].transpose(2, 0, 1)
+        err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+        print(f"{dtype} component {c}: {err:.2e}")
+        assert err <= (1e-13 if dtype == torch.float64 else 3e-7)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("shape,generic", [((13, 7, 5), False), ((24, 17, 3), True)], ids=["x30", "generic_kernels"])
+def test_energy_vs_oracle_generic_x(dtype, shape, generic):
+    """The energy epilogue of the generic X-C2R kernel: a 5-smooth padded x
+    length (30), and a plan with generic_kernels = 1 on every pass."""
+    cell, Ms = (2e-9, 2e-9, 3e-9), 8e5
+    from paper_1204_4302_amd import Plan
+    o = get_oracle(shape, cell)
+    plan = Plan(shape, cell, dtype)
+    if generic:
+        plan.set_option("generic_kernels", 1)
+    assert "generic" in plan.describe().split()[-1] or not generic
+    for m in [inputs.random_unit(shape, 12), inputs.gaussian_vortex(shape, cell, 8e-9)]:
+        mq = quantised(m, dtype)
+        Href = o.field(mq, Ms)
+        ref = o.energy(mq, Href, Ms)
+        H, E = plan.field_energy(to_gpu(m, dtype), Ms)
+        scale = 0.5 * oracle.MU0 * Ms * o.volume * np.sum(np.abs(mq * Href))
+        tol = 1e-12 if dtype == torch.float64 else 1e-5
+        print(f"{shape} generic={generic} {dtype}: |dE|/scale {abs(float(E) - ref) / scale:.2e}")
+        assert abs(float(E) - ref) <= tol * scale
+        assert rel_err(H.double().cpu().numpy(), Href) <= (FP64_TOL if dtype == torch.float64 else FP32_TOL)
+    plan.close()
+
+
+def test_plan_busy_on_another_stream_is_estate():
+    """A plan runs on one stream at a time: a call on stream B while the
+    plan's work on stream A is still pending returns DEMAG_ESTATE (the work on
+    A is held back by a bounded spin kernel queued before it); once A has
+    drained, stream B may use the plan."""
+    from paper_1204_4302_amd import Plan
+    from paper_1204_4302_amd._lib import DemagError
+    shape, cell = (64, 32, 16), (2e-9, 2e-9, 3e-9)
+    plan = Plan(shape, cell, torch.float32)
+    m = to_gpu(inputs.random_unit(shape, 13), torch.float32)
+    H0 = plan.field(m, 8e5)
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(sa):
+        torch.cuda._sleep(100_000_000)  # bounded spin: a few tens of ms
+        plan.field(m, 8e5)
+    with torch.cuda.stream(sb):
+        with pytest.raises(DemagError, match="ESTATE"):
+            plan.field(m, 8e5)
+    sa.synchronize()
+    with torch.cuda.stream(sb):
+        H = plan.field(m, 8e5)
+    sb.synchronize()
+    assert torch.equal(H, H0)
+    plan.close()
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 def test_energy_vs_oracle(dtype):
     shape, cell, Ms = (24, 17, 3), (1.95e-9, 1.95e-9, 0.75e-9), 8e5
