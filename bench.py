@@ -509,6 +509,11 @@ def bench_batch(args, torch, np):
         batch.launch()
     t_seq = run_steps(seq, k, torch)
     t_graph = run_steps(batch.launch, k, torch)
+    # every member of the timed replays against its single-grid call (the
+    # group-tuned launch shapes may differ from the plans' own: FP32 rounding)
+    batch.launch()
+    torch.cuda.synchronize()
+    member_err = max(float((p.field(m, Ms) - h).abs().max() / h.abs().max()) for p, m, h in zip(plans, ms, hs))
     nbytes = 0
     for p in plans:
         i = p.info()
@@ -519,7 +524,8 @@ def bench_batch(args, torch, np):
            "sequential_batches_per_s": round(k / t_seq, 2), "speedup_graph_over_sequential": round(t_seq / t_graph, 3),
            "modelled_bytes_per_batch": nbytes, "graph_achieved_GBs": round(nbytes * k / t_graph / 1e9, 1),
            "roofline": hbm_roofline(nbytes * k, t_graph, "whole batch replay (96 grids, five passes each)"),
-           "launch_shapes": "autotuned per group" if tune_s is not None else "default", "autotune_s": tune_s}
+           "launch_shapes": "autotuned per group" if tune_s is not None else "default", "autotune_s": tune_s,
+           "members_max_rel_diff_vs_single_calls": member_err}
     batch.close()
     for p in plans:
         p.close()

@@ -92,6 +92,12 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
  *  "pass_timing": K > 0 records HIP events around every pass of the next
  *             evaluations on their own stream (a ring of K evaluations; 0 turns
  *             it off); read the averages with demag_plan_pass_times.
+ *  "radix_schedule": S = 0, 1 or 2 sets the radix schedule of every pass on
+ *             the register kernels whose length has schedule S (the others
+ *             take 0); launch shapes are kept.  The schedules of a length
+ *             2^a = 8^k r (same number of stages each): 0 = 8, ..., 8, r;
+ *             1 = 8, r, 8, ..., 8 (k >= 2, r = 2 or 4); 2 = 8, ..., 8, 4, 4
+ *             (k >= 2, r = 2).  demag_autotune searches them per pass.
  *  "lowrank_scratch": byte cap of the low-rank dense-expansion scratch
  *             (default 256 MB; at least one z slice is always held). */
 int demag_plan_set_option(demag_plan_t plan, const char* key, double value);
@@ -316,9 +322,10 @@ int demag_plan_describe(demag_plan_t plan, char* buf, int len);
  * the device and empties the ring. */
 int demag_plan_pass_times(demag_plan_t plan, double* ms, int64_t* count);
 
-/* Time the candidate launch shapes of every pass on this plan's buffers,
- * keep the fastest, and update the cache file named by $DEMAG_AUTOTUNE_CACHE
- * (if set).  Synchronous; clobbers the plan's scratch. */
+/* Time the candidate launch shapes and radix schedules of every pass on this
+ * plan's buffers, keep the fastest, and update the cache file named by
+ * $DEMAG_AUTOTUNE_CACHE (if set).  Synchronous; clobbers the plan's scratch.
+ * On failure the plan keeps the launch shapes it had. */
 int demag_autotune(demag_plan_t plan, void* stream);
 
 /* Batch: `count` independent field evaluations H_i = -Ms N_i * m_i (one per

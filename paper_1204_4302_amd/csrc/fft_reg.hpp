@@ -2,8 +2,8 @@
 //
 // A pencil of P complex values is held by TP = P / EPT threads, EPT = 8
 // values per thread (EPT = P for P < 8).  The transform is a Stockham
-// sequence of radix-8 stages followed by at most one radix-2 or radix-4 stage;
-// each stage works on registers, and consecutive stages exchange data through
+// sequence of radix-8, -4 and -2 stages in one of a few radix schedules (see
+// Fft); each stage works on registers, and consecutive stages exchange data through
 // the pencil's LDS slab (for pencils of up to 64 threads, i.e. P <= 512,
 // within one wavefront and without workgroup barriers).  LDS positions are padded
 // with one slot per eight (pad(i) = i + i/8) so that the strided writes of the
@@ -27,9 +27,32 @@ namespace p2 {
 
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
-template <int P>
+// Radix schedules of a power-of-two length P = 8^N8 r (r = 1, 2 or 4).  Stage
+// 0 is always radix 8 (it spans the thread's eight slots; the zero-skip of a
+// padded input reads half of them), and every schedule has the same number of
+// stages, i.e. of LDS exchanges:
+//   S = 0: 8, 8, ..., 8, r         (the remaining factor last)
+//   S = 1: 8, r, 8, ..., 8         (N8 >= 2, r > 1: the remaining factor second)
+//   S = 2: 8, ..., 8, 4, 4         (N8 >= 2, r = 2: the last 8 x 2 as 4 x 4)
+// They differ in the twiddles a thread holds per stage and in the butterflies'
+// arithmetic and register use; the autotuner chooses one per axis.
+__host__ __device__ constexpr int num_schedules(int P) {
+    const int L2 = ilog2(P), N8 = L2 / 3, r = 1 << (L2 % 3);
+    return 1 + (N8 >= 2 && r > 1 ? 1 : 0) + (N8 >= 2 && r == 2 ? 1 : 0);
+}
+// Radix of stage s of schedule S (stages: N8, plus one when r > 1).
+__host__ __device__ constexpr int schedule_radix(int P, int S, int s) {
+    const int L2 = ilog2(P), N8 = L2 / 3, r = 1 << (L2 % 3);
+    return S == 0 ? (s < N8 ? 8 : r) : S == 1 ? (s == 1 ? r : 8) : (s < N8 - 1 ? 8 : 4);
+}
+__host__ __device__ constexpr int schedule_stages(int P) {
+    return ilog2(P) / 3 + ((ilog2(P) % 3) ? 1 : 0);
+}
+
+template <int P, int S = 0>
 struct Fft {
     static_assert(P >= 2 && (P & (P - 1)) == 0, "power-of-two length");
+    static_assert(S >= 0 && S < num_schedules(P), "radix schedule of this length");
     static constexpr int L2 = ilog2(P);
     static constexpr int N8 = L2 / 3;
     static constexpr int RLAST = 1 << (L2 % 3);  // 1, 2 or 4
@@ -37,7 +60,7 @@ struct Fft {
     static constexpr int EPT = P >= 8 ? 8 : P;
     static constexpr int TP = P / EPT;
     static constexpr int LOG_TP = ilog2(TP);
-    __host__ __device__ static constexpr int radix(int s) { return s < N8 ? 8 : RLAST; }
+    __host__ __device__ static constexpr int radix(int s) { return schedule_radix(P, S, s); }
     __host__ __device__ static constexpr int ns(int s) { return s == 0 ? 1 : ns(s - 1) * radix(s - 1); }
     __host__ __device__ static constexpr int pad(int i) { return i + (i >> 3); }
     // pad(a + c) from pt = pad(a): exact when c is a multiple of 8, or when a
@@ -75,15 +98,15 @@ __device__ __forceinline__ void pencil_sync() {
 // transforms loads them once; the inverse uses their conjugates.  They are
 // read from a thread-major table, twt[((S-1) 7 + e) TP + t] (thread_twiddle
 // below), so that the threads of a pencil load consecutive addresses.
-template <int P, typename T>
+template <int P, typename T, int SCH = 0>
 struct Twiddles {
-    cx<T> w[Fft<P>::NST > 1 ? Fft<P>::NST : 1][7];
+    cx<T> w[Fft<P, SCH>::NST > 1 ? Fft<P, SCH>::NST : 1][7];
 
     __device__ __forceinline__ void load(int t, const cx<T>* __restrict__ twt) { load_from<1>(t, twt); }
 
     template <int S>
     __device__ __forceinline__ void load_from(int t, const cx<T>* __restrict__ twt) {
-        using F = Fft<P>;
+        using F = Fft<P, SCH>;
         if constexpr (S < F::NST) {
             constexpr int R = F::radix(S), NB = F::EPT / R;
 #pragma unroll
@@ -95,9 +118,9 @@ struct Twiddles {
 
 // Table position of entry [S][e] of thread t, and the index into tw[] it
 // holds; table_size() entries in all.  Host-side builder of the table.
-template <int P>
+template <int P, int SCH = 0>
 struct TwiddleTable {
-    using F = Fft<P>;
+    using F = Fft<P, SCH>;
     static constexpr int table_size() { return (F::NST > 1 ? F::NST - 1 : 1) * 7 * F::TP; }
     template <typename T>
     static void fill(const cx<T>* tw, cx<T>* twt) {
@@ -116,9 +139,9 @@ struct TwiddleTable {
 
 // LO: the transform's upper half of inputs (positions >= P/2, i.e. slots
 // j >= EPT/2 of the first stage, whose radix equals EPT) is zero and unread.
-template <int P, int S, int DIR, bool LO, typename T>
-__device__ __forceinline__ void stage_compute(cx<T>* v, const Twiddles<P, T>& tws) {
-    using F = Fft<P>;
+template <int P, int SCH, int S, int DIR, bool LO, typename T>
+__device__ __forceinline__ void stage_compute(cx<T>* v, const Twiddles<P, T, SCH>& tws) {
+    using F = Fft<P, SCH>;
     constexpr int R = F::radix(S), NS = F::ns(S), NB = F::EPT / R;
     if constexpr (S == 0 && LO) {
         static_assert(NB == 1 && NS == 1, "first stage spans the thread's slots");
@@ -140,10 +163,10 @@ __device__ __forceinline__ void stage_compute(cx<T>* v, const Twiddles<P, T>& tw
 }
 
 // Stage S and every later one.  Caller: slots hold stage-S inputs.
-template <int P, int S, int DIR, bool LO, typename T>
-__device__ __forceinline__ void stages_from(cx<T>* v, cx<T>* slab, int t, const Twiddles<P, T>& tws) {
-    using F = Fft<P>;
-    stage_compute<P, S, DIR, LO>(v, tws);
+template <int P, int SCH, int S, int DIR, bool LO, typename T>
+__device__ __forceinline__ void stages_from(cx<T>* v, cx<T>* slab, int t, const Twiddles<P, T, SCH>& tws) {
+    using F = Fft<P, SCH>;
+    stage_compute<P, SCH, S, DIR, LO>(v, tws);
     if constexpr (S + 1 < F::NST) {
         constexpr int R = F::radix(S), NS = F::ns(S), NB = F::EPT / R;
         // every thread of the pencil has consumed the slab's previous contents
@@ -166,7 +189,7 @@ __device__ __forceinline__ void stages_from(cx<T>* v, cx<T>* slab, int t, const 
         for (int i = 0; i < NB2; ++i)
 #pragma unroll
             for (int r = 0; r < R2; ++r) v[i * R2 + r] = slab[F::pad_add(pt, t, i * F::TP + r * (P / R2))];
-        stages_from<P, S + 1, DIR, LO>(v, slab, t, tws);
+        stages_from<P, SCH, S + 1, DIR, LO>(v, slab, t, tws);
     }
 }
 
@@ -175,16 +198,9 @@ __device__ __forceinline__ void stages_from(cx<T>* v, cx<T>* slab, int t, const 
 // caller orders any access by other threads (a workgroup barrier) before.
 // LO = true: input positions >= P/2 are zero (zero-padded data) and the slots
 // holding them are not read.
-template <int P, int DIR, bool LO = false, typename T>
-__device__ __forceinline__ void fft(cx<T>* v, cx<T>* slab, int t, const Twiddles<P, T>& tws) {
-    stages_from<P, 0, DIR, LO>(v, slab, t, tws);
-}
-
-template <int P, int DIR, bool LO = false, typename T>
-__device__ __forceinline__ void fft(cx<T>* v, cx<T>* slab, int t, const cx<T>* __restrict__ twt) {
-    Twiddles<P, T> tws;
-    tws.load(t, twt);
-    stages_from<P, 0, DIR, LO>(v, slab, t, tws);
+template <int P, int DIR, bool LO = false, typename T, int SCH>
+__device__ __forceinline__ void fft(cx<T>* v, cx<T>* slab, int t, const Twiddles<P, T, SCH>& tws) {
+    stages_from<P, SCH, 0, DIR, LO>(v, slab, t, tws);
 }
 
 // ---------------------------------------------------------------------------
@@ -206,12 +222,12 @@ __device__ __forceinline__ void fft(cx<T>* v, cx<T>* slab, int t, const cx<T>* _
 constexpr bool is_pow2(int v) { return v >= 1 && (v & (v - 1)) == 0; }
 constexpr bool reg_length(int P) { return P >= 2 && (is_pow2(P) || (P % 3 == 0 && P >= 6 && is_pow2(P / 3))); }
 
-template <int P, bool POW2 = is_pow2(P)>
+template <int P, int S = 0, bool POW2 = is_pow2(P)>
 struct Len;
 
-template <int P>
-struct Len<P, true> {
-    using F = Fft<P>;
+template <int P, int S>
+struct Len<P, S, true> {
+    using F = Fft<P, S>;
     static constexpr int EPT = F::EPT, TP = F::TP, LOG_TP = F::LOG_TP, PS = F::PS;
     __host__ __device__ static constexpr int pad(int i) { return F::pad(i); }
     __host__ __device__ static constexpr int pad_add(int pt, int a, int c) { return F::pad_add(pt, a, c); }
@@ -227,7 +243,7 @@ struct Len<P, true> {
         return -1;
     }
     template <typename T>
-    using Tw = Twiddles<P, T>;
+    using Tw = Twiddles<P, T, S>;
     template <int DIR, bool LO, typename T>
     __device__ static void fft(cx<T>* v, cx<T>* slab, int t, const Tw<T>& tw) {
         p2::fft<P, DIR, LO>(v, slab, t, tw);
@@ -239,10 +255,10 @@ struct Len<P, true> {
         tw.load(t, src);
         p2::fft<P, DIR, LO>(v, slab, t, tw);
     }
-    static constexpr int table_size() { return TwiddleTable<P>::table_size(); }
+    static constexpr int table_size() { return TwiddleTable<P, S>::table_size(); }
     template <typename T>
     static void fill(const cx<T>* tw, cx<T>* twt) {
-        TwiddleTable<P>::fill(tw, twt);
+        TwiddleTable<P, S>::fill(tw, twt);
     }
 };
 
@@ -255,9 +271,10 @@ struct Len<P, true> {
 // side) or k2 (frequency side).  The Q-transforms use the pencil's slab in
 // turn.  Twiddle table: the Q-transform's, then W_P^(m (t + k TPQ)) for m = 1,
 // 2 and k < EPTQ, thread-major.
-template <int P>
-struct Len<P, false> {
+template <int P, int S>
+struct Len<P, S, false> {
     static_assert(P % 3 == 0 && is_pow2(P / 3) && P >= 6, "length 3 * 2^a");
+    static_assert(S == 0, "lengths 3 * 2^a have one schedule");
     static constexpr int Q = P / 3;
     using FQ = Fft<Q>;
     static constexpr int EQ = FQ::EPT;

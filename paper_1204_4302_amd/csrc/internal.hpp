@@ -29,6 +29,7 @@ struct LaunchCfg {
     int t0 = 1;
     int t1 = 1;
     int p2 = 0;
+    int sched = 0;  // p2: radix schedule of the pass's length (p2::num_schedules); one per axis
 };
 
 // Several grids of one shape in one launch: per-grid device pointers of the
@@ -80,6 +81,7 @@ size_t p2_twiddle_lds_bytes(int P, size_t cbytes);
 size_t p2_z_twiddle_lds_bytes(int P, size_t cbytes);  // extra LDS of a fused Z launch
 extern int kXcds;                       // XCDs of the device: 8 on MI355X; 1 turns the swizzle off
 int p2_max_threads(int P);              // X and Y passes: 1024 (2^a) or 512 (3 * 2^a)
+int p2_num_schedules(int P);            // radix schedules of a register-kernel length (0: not one)
 constexpr int kP2MaxThreadsZ = 512;     // fused Z pass (three pencils per thread)
 // The register-kernel Z pass reaches B2 and the tensor octant through 32-bit
 // buffer offsets: one B2 component and the whole octant must each span fewer
@@ -103,32 +105,34 @@ hipError_t launch_pieces(size_t total, unsigned threads, F&& launch) {
 // The p2 kernels read their twiddles from a thread-major table: the values of
 // tw (exp(-2 pi i t / P), t < P) rearranged so that the threads of one pencil
 // load consecutive entries.  Empty if P is not a supported power of two.
+// (the table of radix schedule `sched`; every launcher below takes the
+// schedule of its length and the table built for it)
 template <typename T>
-std::vector<cx<T>> p2_thread_twiddles(int P, const std::vector<cx<T>>& tw);
+std::vector<cx<T>> p2_thread_twiddles(int P, int sched, const std::vector<cx<T>>& tw);
 template <typename T>
-hipError_t launch_x_fwd_p2(int lgTy, hipStream_t, const T* in, cx<T>* out, int nx, int ny, int nz, int C, int P,
-                           const cx<T>* twt, const BatchIO& bio = BatchIO());
+hipError_t launch_x_fwd_p2(int lgTy, int sched, hipStream_t, const T* in, cx<T>* out, int nx, int ny, int nz, int C,
+                           int P, const cx<T>* twt, const BatchIO& bio = BatchIO());
 template <typename T>
-hipError_t launch_x_inv_p2(int lgTy, hipStream_t, const cx<T>* in, T* out, const T* m, double* partials, int nx,
-                           int ny, int nz, int C, int accumulate, int P, const cx<T>* twt,
+hipError_t launch_x_inv_p2(int lgTy, int sched, hipStream_t, const cx<T>* in, T* out, const T* m, double* partials,
+                           int nx, int ny, int nz, int C, int accumulate, int P, const cx<T>* twt,
                            const BatchIO& bio = BatchIO());
 template <typename T>
-hipError_t launch_y_fwd_p2(int lgTz, int lgTx, hipStream_t, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
-                           int C, int P, const cx<T>* twt, const BatchIO& bio = BatchIO());
+hipError_t launch_y_fwd_p2(int lgTz, int lgTx, int sched, hipStream_t, const cx<T>* in, cx<T>* out, int ny, int nz,
+                           int Kx, int C, int P, const cx<T>* twt, const BatchIO& bio = BatchIO());
 template <typename T>
-hipError_t launch_y_inv_p2(int lgTz, int lgTx, hipStream_t, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
-                           int C, int P, const cx<T>* twt, const BatchIO& bio = BatchIO());
+hipError_t launch_y_inv_p2(int lgTz, int lgTx, int sched, hipStream_t, const cx<T>* in, cx<T>* out, int ny, int nz,
+                           int Kx, int C, int P, const cx<T>* twt, const BatchIO& bio = BatchIO());
 template <typename T>
-// rows: 2 = a row ky' and its mirror Py - ky' per workgroup (the default),
-// 1 = one row per workgroup (lengths whose pair exceeds kP2MaxThreadsZ)
-hipError_t launch_z_conv_p2(int lgTx, int rows, hipStream_t, cx<T>* B2, const T* nhat, T Ms, int nz, int Py, int Kx,
-                            int P, const cx<T>* twt, const BatchIO& bio = BatchIO());
+// rows: 2 = a row ky' and its mirror Py - ky' per workgroup (lengths whose
+// pair fits kP2MaxThreadsZ), 1 = one row per workgroup (the others)
+hipError_t launch_z_conv_p2(int lgTx, int rows, int sched, hipStream_t, cx<T>* B2, const T* nhat, T Ms, int nz,
+                            int Py, int Kx, int P, const cx<T>* twt, const BatchIO& bio = BatchIO());
 
 // scalar-potential method: fused Z pass (3 components in, Ms phi out in
 // component 0 of B2), register-kernel lengths only
 template <typename T>
-hipError_t launch_z_sp_p2(int lgTx, int rows, hipStream_t, cx<T>* B2, const T* shat, T Ms, int nz, int Py, int Kx,
-                          int P, const cx<T>* twt);
+hipError_t launch_z_sp_p2(int lgTx, int rows, int sched, hipStream_t, cx<T>* B2, const T* shat, T Ms, int nz, int Py,
+                          int Kx, int P, const cx<T>* twt);
 
 // ---- tensor setup (FP64) ----------------------------------------------------
 struct TensorBands {

@@ -71,11 +71,12 @@ __device__ __forceinline__ const cx<T>* twiddle_source(cx<T>* lds, int npencils,
     }
 }
 
-// One transform of a pencil with this thread's twiddles loaded from `src`
-// (thread-major table, in LDS or global memory).
-template <typename T, int P, int DIR, bool LO = false>
+// One transform of a pencil (length traits LT: length and radix schedule)
+// with this thread's twiddles loaded from `src` (thread-major table, in LDS or
+// global memory).
+template <typename LT, int DIR, bool LO = false, typename T>
 __device__ __forceinline__ void run_fft(cx<T>* v, cx<T>* slab, int t, const cx<T>* __restrict__ src) {
-    p2::Len<P>::template fft_src<DIR, LO>(v, slab, t, src);
+    LT::template fft_src<DIR, LO>(v, slab, t, src);
 }
 
 // Workgroup size bound of the X and Y kernels: 1024 threads for power-of-two
@@ -277,11 +278,11 @@ __device__ __forceinline__ unsigned boff(bool valid, unsigned base, unsigned d) 
 // outside), writes them with one 16-byte store (FP32).  (Loading the rows as
 // 16-byte vectors staged through the slab measured slower than the direct
 // first-stage loads.)
-template <typename T, int P>
+template <typename T, int P, int S>
 __global__ void __launch_bounds__(xy_max_threads<P>()) kx_fwd(const T* __restrict__ in, cx<T>* __restrict__ out, int nx, int ny,
                                                int nz, int lgTy, int nxcd, const cx<T>* __restrict__ twt,
                                                BatchIO bio) {
-    using LT = p2::Len<P>;
+    using LT = p2::Len<P, S>;
     constexpr int Kx = P / 2 + 1;
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -314,7 +315,7 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_fwd(const T* __restric
     cx<T>* slab = lds + p * LT::PS;
     const cx<T>* tws = twiddle_source<T, P>(lds, nthr >> LT::LOG_TP, twt, tid, nthr);
     if constexpr (tw_in_lds<T, P>()) __syncthreads();
-    run_fft<T, P, -1, true>(v, slab, t, tws);
+    run_fft<LT, -1, true>(v, slab, t, tws);
     __syncthreads();
     const int pt = LT::pad(t);
 #pragma unroll
@@ -370,12 +371,12 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_fwd(const T* __restric
 // [HALF t, HALF t + HALF) of both rows and writes them (and reads m for the
 // energy) as 16-byte vectors (FP32); otherwise each thread writes the
 // positions its last stage holds.
-template <typename T, int P>
+template <typename T, int P, int S>
 __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __restrict__ in, T* __restrict__ out,
                                                const T* __restrict__ m, double* __restrict__ partials, int nx,
                                                int ny, int nz, int lgTy, int accumulate, int nxcd,
                                                const cx<T>* __restrict__ twt, BatchIO bio) {
-    using LT = p2::Len<P>;
+    using LT = p2::Len<P, S>;
     using V = typename vecN<T>::type;
     constexpr int Kx = P / 2 + 1, Lx = P / 2;
     // (FP64 keeps the direct output: its registers would spill)
@@ -472,7 +473,7 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __res
     const int pt = LT::pad(t);
 #pragma unroll
     for (int j = 0; j < LT::EPT; ++j) v[j] = slab[LT::iin_slab(pt, t, j)];
-    run_fft<T, P, +1>(v, slab, t, tws);
+    run_fft<LT, +1>(v, slab, t, tws);
     const gptr<T> dst = out ? gmem(out + rowbase) : nullptr;
     double acc = 0.0;
     if (vec) {
@@ -562,11 +563,11 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) kx_inv(const cx<T>* __res
 //
 // FP32 with an even nz and z tiles of at least two: each thread writes two
 // adjacent z pencils at a frequency with one 16-byte store (the strided side).
-template <typename T, int P>
+template <typename T, int P, int S>
 __global__ void __launch_bounds__(xy_max_threads<P>()) ky_fwd(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
                                                int nz, int Kx, int lgTz, int lgTx, int nxcd,
                                                const cx<T>* __restrict__ twt, BatchIO bio) {
-    using LT = p2::Len<P>;
+    using LT = p2::Len<P, S>;
     constexpr bool kVec = sizeof(T) == 4 && LT::EPT >= 8;
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x;
@@ -594,7 +595,7 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) ky_fwd(const cx<T>* __res
     cx<T>* slab = lds + p * LT::PS;
     const cx<T>* tws = twiddle_source<T, P>(lds, (int)blockDim.x >> LT::LOG_TP, twt, tid, blockDim.x);
     if constexpr (tw_in_lds<T, P>()) __syncthreads();
-    run_fft<T, P, -1, true>(v, slab, t, tws);
+    run_fft<LT, -1, true>(v, slab, t, tws);
     __syncthreads();
     const int pt = LT::pad(t);
 #pragma unroll
@@ -637,11 +638,11 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) ky_fwd(const cx<T>* __res
 
 // ---------------------------------------------------------------------------
 // Y inverse: first ny outputs, written y-contiguous.
-template <typename T, int P>
+template <typename T, int P, int S>
 __global__ void __launch_bounds__(xy_max_threads<P>()) ky_inv(const cx<T>* __restrict__ in, cx<T>* __restrict__ out, int ny,
                                                int nz, int Kx, int lgTz, int lgTx, int nxcd,
                                                const cx<T>* __restrict__ twt, BatchIO bio) {
-    using LT = p2::Len<P>;
+    using LT = p2::Len<P, S>;
     cx<T>* lds = lds_base<T>();
     const int tid = threadIdx.x;
     const int p = tid >> LT::LOG_TP, t = tid & (LT::TP - 1);
@@ -679,7 +680,7 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) ky_inv(const cx<T>* __res
     const int pt = LT::pad(t);
 #pragma unroll
     for (int j = 0; j < LT::EPT; ++j) v[j] = slab[LT::iin_slab(pt, t, j)];
-    run_fft<T, P, +1>(v, slab, t, tws);
+    run_fft<LT, +1>(v, slab, t, tws);
     const int xi = p & (Tx - 1), zi = p >> lgTx;
     if (xi < tx && zi < tz) {
         const gptr<cx<T>> dst = gmem(out + (((size_t)c * nz + z0 + zi) * Kx + kx0 + xi) * (size_t)ny);
@@ -731,11 +732,11 @@ bool z_stages_tensor(int P) {
     return sizeof(T) == 4 && p2::is_pow2(P) && 2 * p2_threads_per_pencil(P) <= kP2MaxThreadsZ;
 }
 
-template <typename T, int P>
+template <typename T, int P, int S>
 __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2, const T* __restrict__ nhat, T Ms, int nz,
                                                 int Py, int Kx, int lgTx, int rows, int nxcd,
                                                 const cx<T>* __restrict__ twt, BatchIO bio) {
-    using LT = p2::Len<P>;
+    using LT = p2::Len<P, S>;
     constexpr bool kPow2 = p2::is_pow2(P);
     constexpr bool kKeep = z_keep_twiddles<T, P>();
     constexpr int Lz = P / 2;
@@ -841,7 +842,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
         if constexpr (kKeep) LT::template fft<-1, true>(v[comp], slab, t, tws);
-        else run_fft<T, P, -1, true>(v[comp], slab, t, twsrc);
+        else run_fft<LT, -1, true>(v[comp], slab, t, twsrc);
     }
     if constexpr (!kKeep) load_tensor();
     // H^ = Nhat(kx, ky, kz) M^ (Ms applied at the store).  Octant lookup with
@@ -882,7 +883,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
 #pragma unroll
         for (int j = 0; j < LT::EPT; ++j) w[j] = v[comp][LT::fwd_slot_of_iin(j)];
         if constexpr (kKeep) LT::template fft<+1, false>(w, slab, t, tws);
-        else run_fft<T, P, +1>(w, slab, t, twsrc);
+        else run_fft<LT, +1>(w, slab, t, twsrc);
 #pragma unroll
         for (int j = 0; j < LT::EPT; ++j) {
             const int k = LT::iout_k(j);
@@ -902,11 +903,11 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
 // written in place to component 0 of B2.  Parity signs: s_y odd in ky (s = 1
 // groups), s_z odd in kz; s_x needs none (kx <= Px/2).  Tiles, groups, buffer
 // access and register budget as in kz_conv.
-template <typename T, int P>
+template <typename T, int P, int S>
 __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, const T* __restrict__ shat, T Ms,
                                                         int nz, int Py, int Kx, int lgTx, int rows, int nxcd,
                                                         const cx<T>* __restrict__ twt) {
-    using LT = p2::Len<P>;
+    using LT = p2::Len<P, S>;
     constexpr bool kPow2 = p2::is_pow2(P);
     constexpr bool kKeep = z_keep_twiddles<T, P>();
     constexpr int Lz = P / 2;
@@ -978,7 +979,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
         if constexpr (kKeep) LT::template fft<-1, true>(v[comp], slab, t, tws);
-        else run_fft<T, P, -1, true>(v[comp], slab, t, twsrc);
+        else run_fft<LT, -1, true>(v[comp], slab, t, twsrc);
     }
     if constexpr (!kKeep) load_kernel();
     const T sy = s ? T(-1) : T(1);
@@ -996,7 +997,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
 #pragma unroll
     for (int j = 0; j < LT::EPT; ++j) w[j] = v[0][LT::fwd_slot_of_iin(j)];
     if constexpr (kKeep) LT::template fft<+1, false>(w, slab, t, tws);
-    else run_fft<T, P, +1>(w, slab, t, twsrc);
+    else run_fft<LT, +1>(w, slab, t, twsrc);
 #pragma unroll
     for (int j = 0; j < LT::EPT; ++j) {
         const int k = LT::iout_k(j);
@@ -1050,6 +1051,20 @@ hipError_t allow_lds(K kernel, size_t lds) {
         DEMAG_P2_CASES_3POW2(CALL)                                                                 \
     default: return hipErrorInvalidValue;                                                          \
     }
+// The radix schedule `sched` of length PP as a compile-time instance (CALLS(PP, S)).
+#define DEMAG_P2_SCHED(PP, CALLS)                                                                  \
+    switch (sched) {                                                                               \
+    case 0: CALLS(PP, 0); break;                                                                   \
+    case 1:                                                                                        \
+        if constexpr (p2::is_pow2(PP) && p2::num_schedules(PP) > 1) { CALLS(PP, 1); }              \
+        else { return hipErrorInvalidValue; }                                                      \
+        break;                                                                                     \
+    case 2:                                                                                        \
+        if constexpr (p2::is_pow2(PP) && p2::num_schedules(PP) > 2) { CALLS(PP, 2); }              \
+        else { return hipErrorInvalidValue; }                                                      \
+        break;                                                                                     \
+    default: return hipErrorInvalidValue;                                                          \
+    }
 
 int kXcds = 8;  // XCDs of the device (workgroup swizzle); set by the plan runtime
 
@@ -1063,6 +1078,7 @@ int p2_threads_per_pencil(int P) {
 }
 int p2_slab_elems(int P) { return (P + (P >> 3)) + 1; }
 int p2_max_threads(int P) { return p2::is_pow2(P) ? 1024 : 512; }  // xy_max_threads
+int p2_num_schedules(int P) { return p2_supported(P) && p2::is_pow2(P) ? p2::num_schedules(P) : (p2_supported(P) ? 1 : 0); }
 static size_t table_entries(int P) {
     switch (P) {
 #define TS(PP) \
@@ -1083,72 +1099,80 @@ size_t p2_z_twiddle_lds_bytes(int P, size_t cbytes) {
 }
 
 template <typename T>
-hipError_t launch_x_fwd_p2(int lgTy, hipStream_t st, const T* in, cx<T>* out, int nx, int ny, int nz, int C, int P,
-                           const cx<T>* twt, const BatchIO& bio) {
+hipError_t launch_x_fwd_p2(int lgTy, int sched, hipStream_t st, const T* in, cx<T>* out, int nx, int ny, int nz, int C,
+                           int P, const cx<T>* twt, const BatchIO& bio) {
     if (!twt) return hipErrorInvalidValue;
     const int Bp = 1 << (lgTy - 1);
     dim3 grid((unsigned)(((ny + (1 << lgTy) - 1) >> lgTy) * nz * C * bio.count));
     const size_t lds = (size_t)Bp * p2_slab_elems(P) * sizeof(cx<T>) + p2_twiddle_lds_bytes(P, sizeof(cx<T>));
-#define CALL(PP) \
-    if (hipError_t e_ = allow_lds(&kx_fwd<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((kx_fwd<T, PP>), grid, dim3(Bp * tpp<PP>()), lds, st, in, out, nx, ny, nz, lgTy, kXcds, twt, \
+#define CALLS(PP, SS) \
+    if (hipError_t e_ = allow_lds(&kx_fwd<T, PP, SS>, lds)) return e_; \
+    hipLaunchKernelGGL((kx_fwd<T, PP, SS>), grid, dim3(Bp * tpp<PP>()), lds, st, in, out, nx, ny, nz, lgTy, kXcds, twt, \
                        bio)
+#define CALL(PP) DEMAG_P2_SCHED(PP, CALLS)
     DEMAG_P2_SWITCH(P, CALL)
 #undef CALL
+#undef CALLS
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_x_inv_p2(int lgTy, hipStream_t st, const cx<T>* in, T* out, const T* m, double* partials, int nx,
-                           int ny, int nz, int C, int accumulate, int P, const cx<T>* twt, const BatchIO& bio) {
+hipError_t launch_x_inv_p2(int lgTy, int sched, hipStream_t st, const cx<T>* in, T* out, const T* m, double* partials,
+                           int nx, int ny, int nz, int C, int accumulate, int P, const cx<T>* twt, const BatchIO& bio) {
     if (!twt) return hipErrorInvalidValue;
     const int Bp = 1 << (lgTy - 1);
     dim3 grid((unsigned)(((ny + (1 << lgTy) - 1) >> lgTy) * nz * C * bio.count));
     const size_t lds = (size_t)Bp * p2_slab_elems(P) * sizeof(cx<T>) + p2_twiddle_lds_bytes(P, sizeof(cx<T>));
-#define CALL(PP)                                                                                            \
-    if (hipError_t e_ = allow_lds(&kx_inv<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((kx_inv<T, PP>), grid, dim3(Bp * tpp<PP>()), lds, st, in, out, m, partials, nx, ny, nz, \
+#define CALLS(PP, SS)                                                                                       \
+    if (hipError_t e_ = allow_lds(&kx_inv<T, PP, SS>, lds)) return e_; \
+    hipLaunchKernelGGL((kx_inv<T, PP, SS>), grid, dim3(Bp * tpp<PP>()), lds, st, in, out, m, partials, nx, ny, nz, \
                        lgTy, accumulate, kXcds, twt, bio)
+#define CALL(PP) DEMAG_P2_SCHED(PP, CALLS)
     DEMAG_P2_SWITCH(P, CALL)
 #undef CALL
+#undef CALLS
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_y_fwd_p2(int lgTz, int lgTx, hipStream_t st, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
-                           int C, int P, const cx<T>* twt, const BatchIO& bio) {
+hipError_t launch_y_fwd_p2(int lgTz, int lgTx, int sched, hipStream_t st, const cx<T>* in, cx<T>* out, int ny, int nz,
+                           int Kx, int C, int P, const cx<T>* twt, const BatchIO& bio) {
     if (!twt) return hipErrorInvalidValue;
     const int B = 1 << (lgTz + lgTx);
     dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * ((nz + (1 << lgTz) - 1) >> lgTz) * C * bio.count));
     const size_t lds = (size_t)B * p2_slab_elems(P) * sizeof(cx<T>) + p2_twiddle_lds_bytes(P, sizeof(cx<T>));
-#define CALL(PP) \
-    if (hipError_t e_ = allow_lds(&ky_fwd<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((ky_fwd<T, PP>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, twt, \
-                       bio)
+#define CALLS(PP, SS) \
+    if (hipError_t e_ = allow_lds(&ky_fwd<T, PP, SS>, lds)) return e_; \
+    hipLaunchKernelGGL((ky_fwd<T, PP, SS>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, \
+                       twt, bio)
+#define CALL(PP) DEMAG_P2_SCHED(PP, CALLS)
     DEMAG_P2_SWITCH(P, CALL)
 #undef CALL
+#undef CALLS
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_y_inv_p2(int lgTz, int lgTx, hipStream_t st, const cx<T>* in, cx<T>* out, int ny, int nz, int Kx,
-                           int C, int P, const cx<T>* twt, const BatchIO& bio) {
+hipError_t launch_y_inv_p2(int lgTz, int lgTx, int sched, hipStream_t st, const cx<T>* in, cx<T>* out, int ny, int nz,
+                           int Kx, int C, int P, const cx<T>* twt, const BatchIO& bio) {
     if (!twt) return hipErrorInvalidValue;
     const int B = 1 << (lgTz + lgTx);
     dim3 grid((unsigned)(((Kx + (1 << lgTx) - 1) >> lgTx) * ((nz + (1 << lgTz) - 1) >> lgTz) * C * bio.count));
     const size_t lds = (size_t)B * p2_slab_elems(P) * sizeof(cx<T>) + p2_twiddle_lds_bytes(P, sizeof(cx<T>));
-#define CALL(PP) \
-    if (hipError_t e_ = allow_lds(&ky_inv<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((ky_inv<T, PP>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, twt, \
-                       bio)
+#define CALLS(PP, SS) \
+    if (hipError_t e_ = allow_lds(&ky_inv<T, PP, SS>, lds)) return e_; \
+    hipLaunchKernelGGL((ky_inv<T, PP, SS>), grid, dim3(B * tpp<PP>()), lds, st, in, out, ny, nz, Kx, lgTz, lgTx, kXcds, \
+                       twt, bio)
+#define CALL(PP) DEMAG_P2_SCHED(PP, CALLS)
     DEMAG_P2_SWITCH(P, CALL)
 #undef CALL
+#undef CALLS
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_z_conv_p2(int lgTx, int rows, hipStream_t st, cx<T>* B2, const T* nhat, T Ms, int nz, int Py,
-                            int Kx, int P, const cx<T>* twt, const BatchIO& bio) {
+hipError_t launch_z_conv_p2(int lgTx, int rows, int sched, hipStream_t st, cx<T>* B2, const T* nhat, T Ms, int nz,
+                            int Py, int Kx, int P, const cx<T>* twt, const BatchIO& bio) {
     if (!twt) return hipErrorInvalidValue;
     if (!p2_z_supported(P, sizeof(cx<T>)) || (rows != 1 && rows != 2)) return hipErrorInvalidValue;
     if (rows != (2 * p2_threads_per_pencil(P) <= kP2MaxThreadsZ ? 2 : 1)) return hipErrorInvalidValue;
@@ -1156,10 +1180,11 @@ hipError_t launch_z_conv_p2(int lgTx, int rows, hipStream_t st, cx<T>* B2, const
     dim3 grid((unsigned)(Kx * ((rows == 2 ? Py / 2 + (1 << lgTx) : Py + (1 << lgTx) - 1) >> lgTx) * bio.count));
     size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
     if (z_stages_tensor<T>(P)) lds += ((size_t)(1 << lgTx) * (P / 2 + 1) * 6 + 4) * sizeof(T);
-#define CALL(PP) \
-    if (hipError_t e_ = allow_lds(&kz_conv<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((kz_conv<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, rows, kXcds, \
-                       twt, bio)
+#define CALLS(PP, SS) \
+    if (hipError_t e_ = allow_lds(&kz_conv<T, PP, SS>, lds)) return e_; \
+    hipLaunchKernelGGL((kz_conv<T, PP, SS>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, rows, \
+                       kXcds, twt, bio)
+#define CALL(PP) DEMAG_P2_SCHED(PP, CALLS)
     if constexpr (sizeof(T) == 4) {
         DEMAG_P2_SWITCH(P, CALL)
     } else {  // FP64 lengths 3 * 2^a would not fit the registers: generic kernels
@@ -1169,20 +1194,23 @@ hipError_t launch_z_conv_p2(int lgTx, int rows, hipStream_t st, cx<T>* B2, const
         }
     }
 #undef CALL
+#undef CALLS
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_z_sp_p2(int lgTx, int rows, hipStream_t st, cx<T>* B2, const T* shat, T Ms, int nz, int Py,
-                          int Kx, int P, const cx<T>* twt) {
+hipError_t launch_z_sp_p2(int lgTx, int rows, int sched, hipStream_t st, cx<T>* B2, const T* shat, T Ms, int nz,
+                          int Py, int Kx, int P, const cx<T>* twt) {
     if (!twt) return hipErrorInvalidValue;
     if (!p2_z_supported(P, sizeof(cx<T>)) || (rows != 1 && rows != 2)) return hipErrorInvalidValue;
     const int G = rows << lgTx;
     dim3 grid((unsigned)(Kx * ((rows == 2 ? Py / 2 + (1 << lgTx) : Py + (1 << lgTx) - 1) >> lgTx)));
     const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
-#define CALL(PP) \
-    if (hipError_t e_ = allow_lds(&kz_sp<T, PP>, lds)) return e_; \
-    hipLaunchKernelGGL((kz_sp<T, PP>), grid, dim3(G * tpp<PP>()), lds, st, B2, shat, Ms, nz, Py, Kx, lgTx, rows, kXcds, twt)
+#define CALLS(PP, SS) \
+    if (hipError_t e_ = allow_lds(&kz_sp<T, PP, SS>, lds)) return e_; \
+    hipLaunchKernelGGL((kz_sp<T, PP, SS>), grid, dim3(G * tpp<PP>()), lds, st, B2, shat, Ms, nz, Py, Kx, lgTx, rows, \
+                       kXcds, twt)
+#define CALL(PP) DEMAG_P2_SCHED(PP, CALLS)
     if constexpr (sizeof(T) == 4) {
         DEMAG_P2_SWITCH(P, CALL)
     } else {
@@ -1192,18 +1220,30 @@ hipError_t launch_z_sp_p2(int lgTx, int rows, hipStream_t st, cx<T>* B2, const T
         }
     }
 #undef CALL
+#undef CALLS
     return hipGetLastError();
 }
 
+// The table of length P and schedule S (nothing for a schedule the length has not).
+template <typename T, int P, int S>
+void fill_table(const std::vector<cx<T>>& tw, std::vector<cx<T>>& out) {
+    if constexpr (S == 0 || (p2::is_pow2(P) && S < p2::num_schedules(P))) {
+        using LT = p2::Len<P, S>;
+        out.resize(LT::table_size());
+        LT::fill(tw.data(), out.data());
+    }
+}
+
 template <typename T>
-std::vector<cx<T>> p2_thread_twiddles(int P, const std::vector<cx<T>>& tw) {
+std::vector<cx<T>> p2_thread_twiddles(int P, int sched, const std::vector<cx<T>>& tw) {
     std::vector<cx<T>> out;
-    if ((int)tw.size() != P) return out;
+    if ((int)tw.size() != P || sched < 0 || sched >= p2_num_schedules(P)) return out;
     switch (P) {
-#define FILL(PP)                                                      \
-    case PP:                                                          \
-        out.resize(p2::Len<PP>::table_size());                        \
-        p2::Len<PP>::fill(tw.data(), out.data());                     \
+#define FILL(PP)                                                         \
+    case PP:                                                             \
+        if (sched == 0) fill_table<T, PP, 0>(tw, out);                   \
+        else if (sched == 1) fill_table<T, PP, 1>(tw, out);              \
+        else fill_table<T, PP, 2>(tw, out);                              \
         break;
         FILL(2) FILL(4) FILL(8) FILL(16) FILL(32) FILL(64) FILL(128) FILL(256) FILL(512) FILL(1024) FILL(2048) FILL(4096)
         FILL(6) FILL(12) FILL(24) FILL(48) FILL(96) FILL(192) FILL(384) FILL(768) FILL(1536) FILL(3072)
@@ -1214,22 +1254,22 @@ std::vector<cx<T>> p2_thread_twiddles(int P, const std::vector<cx<T>>& tw) {
 }
 
 #define DEMAG_P2_INSTANTIATE(T)                                                                                    \
-    template hipError_t launch_x_fwd_p2<T>(int, hipStream_t, const T*, cx<T>*, int, int, int, int, int,           \
+    template hipError_t launch_x_fwd_p2<T>(int, int, hipStream_t, const T*, cx<T>*, int, int, int, int, int,      \
                                            const cx<T>*, const BatchIO&);                                          \
-    template hipError_t launch_x_inv_p2<T>(int, hipStream_t, const cx<T>*, T*, const T*, double*, int, int, int,  \
-                                           int, int, int, const cx<T>*, const BatchIO&);                           \
-    template hipError_t launch_y_fwd_p2<T>(int, int, hipStream_t, const cx<T>*, cx<T>*, int, int, int, int, int,  \
-                                           const cx<T>*, const BatchIO&);                                          \
-    template hipError_t launch_y_inv_p2<T>(int, int, hipStream_t, const cx<T>*, cx<T>*, int, int, int, int, int,  \
-                                           const cx<T>*, const BatchIO&);                                          \
-    template hipError_t launch_z_conv_p2<T>(int, int, hipStream_t, cx<T>*, const T*, T, int, int, int, int,       \
+    template hipError_t launch_x_inv_p2<T>(int, int, hipStream_t, const cx<T>*, T*, const T*, double*, int, int,  \
+                                           int, int, int, int, const cx<T>*, const BatchIO&);                      \
+    template hipError_t launch_y_fwd_p2<T>(int, int, int, hipStream_t, const cx<T>*, cx<T>*, int, int, int, int, \
+                                           int, const cx<T>*, const BatchIO&);                                     \
+    template hipError_t launch_y_inv_p2<T>(int, int, int, hipStream_t, const cx<T>*, cx<T>*, int, int, int, int, \
+                                           int, const cx<T>*, const BatchIO&);                                     \
+    template hipError_t launch_z_conv_p2<T>(int, int, int, hipStream_t, cx<T>*, const T*, T, int, int, int, int,  \
                                             const cx<T>*, const BatchIO&);                                         \
-    template hipError_t launch_z_sp_p2<T>(int, int, hipStream_t, cx<T>*, const T*, T, int, int, int, int,          \
+    template hipError_t launch_z_sp_p2<T>(int, int, int, hipStream_t, cx<T>*, const T*, T, int, int, int, int,    \
                                           const cx<T>*);
 
 DEMAG_P2_INSTANTIATE(float)
 DEMAG_P2_INSTANTIATE(double)
-template std::vector<cx<float>> p2_thread_twiddles<float>(int, const std::vector<cx<float>>&);
-template std::vector<cx<double>> p2_thread_twiddles<double>(int, const std::vector<cx<double>>&);
+template std::vector<cx<float>> p2_thread_twiddles<float>(int, int, const std::vector<cx<float>>&);
+template std::vector<cx<double>> p2_thread_twiddles<double>(int, int, const std::vector<cx<double>>&);
 
 }  // namespace demag

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/demag.h"
+#include "fft_reg.hpp"
 #include "internal.hpp"
 
 using namespace demag;
@@ -187,7 +188,7 @@ struct demag_plan_s {
     int L[3], P[3], Kx;
     FftPlanDev fp[3];
     void* tw[3] = {nullptr, nullptr, nullptr};
-    void* twt[3] = {nullptr, nullptr, nullptr};  // thread-major twiddles of power-of-two axes
+    void* twt[3][3] = {};  // thread-major twiddles of register-kernel axes, per radix schedule
     void* nhat = nullptr;
     void* shat = nullptr;  // scalar-potential kernel spectrum (after demag_sp_prepare)
     TGState* tg = nullptr; // tensor-grid state (after demag_tg_prepare)
@@ -339,6 +340,7 @@ LaunchCfg p2_zconv(int P, int Py, size_t cbytes, int target = 64) {
 
 bool p2_cfg_ok(const LaunchCfg& c, int P, size_t cbytes, int kind /*0 rows, 1 pencils, 2 z*/) {
     if (!p2_supported(P) || c.t0 < 0 || c.t1 < 0 || c.t0 > 12 || c.t1 > 12) return false;
+    if (c.sched < 0 || c.sched >= p2_num_schedules(P)) return false;
     const long TP = p2_threads_per_pencil(P);
     long pencils = kind == 0 ? (1L << (c.t0 - 1)) : kind == 1 ? (1L << (c.t0 + c.t1)) : ((long)c.t1 << c.t0);
     if (kind == 0 && c.t0 < 1) return false;
@@ -736,7 +738,8 @@ int setup_lr(demag_plan_s* p, hipStream_t st, double step) {
 
 void free_plan(demag_plan_s* p) {
     for (auto t : p->tw) (void)hipFree(t);
-    for (auto t : p->twt) (void)hipFree(t);
+    for (auto& axis : p->twt)
+        for (auto t : axis) (void)hipFree(t);
     (void)hipFree(p->nhat);
     (void)hipFree(p->shat);
     free_tg(p->tg);
@@ -766,24 +769,27 @@ hipError_t launch_pass(demag_plan_s* p, int which, const LaunchCfg& lc, hipStrea
     const auto* twx = (const cx<T>*)p->tw[0];
     const auto* twy = (const cx<T>*)p->tw[1];
     const auto* twz = (const cx<T>*)p->tw[2];
-    const auto* ttx = (const cx<T>*)p->twt[0];
-    const auto* tty = (const cx<T>*)p->twt[1];
-    const auto* ttz = (const cx<T>*)p->twt[2];
+    const int sc = lc.p2 && lc.sched >= 0 && lc.sched < 3 ? lc.sched : 0;
+    const auto* ttx = (const cx<T>*)p->twt[0][sc];
+    const auto* tty = (const cx<T>*)p->twt[1][sc];
+    const auto* ttz = (const cx<T>*)p->twt[2][sc];
     switch (which) {
     case 0:
-        return lc.p2 ? launch_x_fwd_p2<T>(lc.t0, st, m, B1, nx, ny, nz, 3, Px, ttx, bio)
+        return lc.p2 ? launch_x_fwd_p2<T>(lc.t0, lc.sched, st, m, B1, nx, ny, nz, 3, Px, ttx, bio)
                      : launch_x_fwd<T>(lc, st, m, B1, nx, ny, nz, Kx, 3, p->fp[0], twx, bio);
     case 1:
-        return lc.p2 ? launch_y_fwd_p2<T>(lc.t1, lc.t0, st, B1, B2, ny, nz, Kx, 3, Py, tty, bio)
+        return lc.p2 ? launch_y_fwd_p2<T>(lc.t1, lc.t0, lc.sched, st, B1, B2, ny, nz, Kx, 3, Py, tty, bio)
                      : launch_y_fwd<T>(lc, st, B1, B2, ny, nz, Kx, nz, 3, p->fp[1], twy, bio);
     case 2:
-        return lc.p2 ? launch_z_conv_p2<T>(lc.t0, lc.t1, st, B2, (const T*)p->nhat, (T)Ms, nz, Py, Kx, Pz, ttz, bio)
+        return lc.p2 ? launch_z_conv_p2<T>(lc.t0, lc.t1, lc.sched, st, B2, (const T*)p->nhat, (T)Ms, nz, Py, Kx, Pz,
+                                           ttz, bio)
                      : launch_z_conv<T>(lc, st, B2, (const T*)p->nhat, (T)Ms, nz, Py, Kx, p->fp[2], twz, bio);
     case 3:
-        return lc.p2 ? launch_y_inv_p2<T>(lc.t1, lc.t0, st, B2, B1, ny, nz, Kx, 3, Py, tty, bio)
+        return lc.p2 ? launch_y_inv_p2<T>(lc.t1, lc.t0, lc.sched, st, B2, B1, ny, nz, Kx, 3, Py, tty, bio)
                      : launch_y_inv<T>(lc, st, B2, B1, ny, nz, Kx, 3, p->fp[1], twy, bio);
     default:
-        return lc.p2 ? launch_x_inv_p2<T>(lc.t0, st, B1, H, me, partials, nx, ny, nz, 3, accumulate, Px, ttx, bio)
+        return lc.p2 ? launch_x_inv_p2<T>(lc.t0, lc.sched, st, B1, H, me, partials, nx, ny, nz, 3, accumulate, Px, ttx,
+                                          bio)
                      : launch_x_inv<T>(lc, st, B1, H, me, partials, nx, ny, nz, Kx, 3, accumulate, p->fp[0], twx,
                                        bio);
     }
@@ -844,13 +850,15 @@ int run_sp_field(demag_plan_s* p, const T* m, double Ms, T* H, double* E_dev, hi
     const PassCfgs& c = p->cfg;
     HIP_TRY(launch_pass<T>(p, 0, c.xf, st, m, Ms, nullptr, nullptr, nullptr, 0));
     HIP_TRY(launch_pass<T>(p, 1, c.yf, st, nullptr, Ms, nullptr, nullptr, nullptr, 0));
-    HIP_TRY(launch_z_sp_p2<T>(p->zs.t0, p->zs.t1, st, B2, (const T*)p->shat, (T)Ms, nz, Py, Kx, Pz, (const cx<T>*)p->twt[2]));
+    HIP_TRY(launch_z_sp_p2<T>(p->zs.t0, p->zs.t1, p->zs.sched, st, B2, (const T*)p->shat, (T)Ms, nz, Py, Kx, Pz,
+                              (const cx<T>*)p->twt[2][p->zs.sched]));
     const LaunchCfg& yi = c.yi;
-    HIP_TRY(yi.p2 ? launch_y_inv_p2<T>(yi.t1, yi.t0, st, B2, B1, ny, nz, Kx, 1, Py, (const cx<T>*)p->twt[1])
+    HIP_TRY(yi.p2 ? launch_y_inv_p2<T>(yi.t1, yi.t0, yi.sched, st, B2, B1, ny, nz, Kx, 1, Py,
+                                       (const cx<T>*)p->twt[1][yi.sched])
                   : launch_y_inv<T>(yi, st, B2, B1, ny, nz, Kx, 1, p->fp[1], (const cx<T>*)p->tw[1]));
     const LaunchCfg& xi = c.xi;
-    HIP_TRY(xi.p2 ? launch_x_inv_p2<T>(xi.t0, st, B1, phi, nullptr, nullptr, nx, ny, nz, 1, 0, Px,
-                                       (const cx<T>*)p->twt[0])
+    HIP_TRY(xi.p2 ? launch_x_inv_p2<T>(xi.t0, xi.sched, st, B1, phi, nullptr, nullptr, nx, ny, nz, 1, 0, Px,
+                                       (const cx<T>*)p->twt[0][xi.sched])
                   : launch_x_inv<T>(xi, st, B1, phi, nullptr, nullptr, nx, ny, nz, Kx, 1, 0, p->fp[0],
                                     (const cx<T>*)p->tw[0]));
     int nparts = 0;
@@ -1126,7 +1134,8 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
             using T = decltype(proto);
             const std::vector<cx<T>> tw = twiddles<T>(P[k]);
             int r = upload(&p->tw[k], tw);
-            if (!r && p2_supported(P[k])) r = upload(&p->twt[k], p2_thread_twiddles<T>(P[k], tw));
+            for (int sc = 0; !r && sc < p2_num_schedules(P[k]); ++sc)
+                r = upload(&p->twt[k][sc], p2_thread_twiddles<T>(P[k], sc, tw));
             return r;
         };
         for (int k = 0; k < 3 && !rc; ++k) rc = dtype == DEMAG_F32 ? tables(float(), k) : tables(double(), k);
@@ -1174,6 +1183,15 @@ int demag_plan_set_option(demag_plan_t p, const char* key, double value) {
         for (auto& e : p->tev) HIP_TRY(hipEventCreate(&e));
         p->tcap = (int)value;
         p->tcount = 0;
+        return DEMAG_OK;
+    } else if (!strcmp(key, "radix_schedule")) {
+        if (value != 0 && value != 1 && value != 2) return fail(DEMAG_EINVAL, "radix_schedule must be 0, 1 or 2");
+        HIP_TRY(hipDeviceSynchronize());
+        LaunchCfg* slot[5] = {&p->cfg.xf, &p->cfg.yf, &p->cfg.zc, &p->cfg.yi, &p->cfg.xi};
+        for (int w = 0; w < 5; ++w) {
+            const int P = p->P[w == 0 || w == 4 ? 0 : w == 2 ? 2 : 1];
+            if (slot[w]->p2) slot[w]->sched = (int)value < p2_num_schedules(P) ? (int)value : 0;
+        }
         return DEMAG_OK;
     } else if (!strcmp(key, "lowrank_scratch")) {
         if (!(value >= 0) || value > 1e15) return fail(DEMAG_EINVAL, "lowrank_scratch must be in [0, 1e15] bytes");
@@ -1558,10 +1576,20 @@ int demag_plan_describe(demag_plan_t p, char* buf, int len) {
     for (int w = 0; w < 5; ++w) {
         const LaunchCfg& c = pass_cfg(p->cfg, w);
         char b[160];
-        if (c.p2)
-            snprintf(b, sizeof b, "%s:pow2(threads=%d,log2 tiles=%d,%d) ", names[w], c.threads, c.t0, c.t1);
-        else
+        if (c.p2) {
+            const int P = p->P[w == 0 || w == 4 ? 0 : w == 2 ? 2 : 1];
+            std::string rad;
+            if (p2_num_schedules(P) > 1 || (P & (P - 1)) == 0) {
+                for (int st = 0; st < p2::schedule_stages(P); ++st)
+                    rad += (st ? "." : "") + std::to_string(p2::schedule_radix(P, c.sched, st));
+            } else {
+                rad = "3x" + std::to_string(P / 3);
+            }
+            snprintf(b, sizeof b, "%s:pow2(threads=%d,log2 tiles=%d,%d,radix=%s) ", names[w], c.threads, c.t0, c.t1,
+                     rad.c_str());
+        } else {
             snprintf(b, sizeof b, "%s:generic(threads=%d,E=%d,tiles=%d,%d) ", names[w], c.threads, c.E, c.t0, c.t1);
+        }
         out += b;
     }
     if (!out.empty()) out.pop_back();
@@ -1669,18 +1697,21 @@ void add_p2_candidates(const demag_plan_s* p, int kind, std::vector<LaunchCfg>& 
                 c.threads = b * TP << a;
             }
             if (c.threads < 64 && c.threads < TP * 2) continue;
-            if (p2_cfg_ok(c, P, cb, kind)) out.push_back(c);
+            for (int sc = 0; sc < p2_num_schedules(P); ++sc) {  // every radix schedule of the length
+                c.sched = sc;
+                if (p2_cfg_ok(c, P, cb, kind)) out.push_back(c);
+            }
         }
 }
 
 std::string cfg_str(const LaunchCfg& c) {
     char b[64];
-    snprintf(b, sizeof b, "%d,%d,%d,%d,%d", c.threads, c.E, c.t0, c.t1, c.p2);
+    snprintf(b, sizeof b, "%d,%d,%d,%d,%d,%d", c.threads, c.E, c.t0, c.t1, c.p2, c.sched);
     return b;
 }
 
 bool cfg_parse(const std::string& s, LaunchCfg& c) {
-    return sscanf(s.c_str(), "%d,%d,%d,%d,%d", &c.threads, &c.E, &c.t0, &c.t1, &c.p2) == 5;
+    return sscanf(s.c_str(), "%d,%d,%d,%d,%d,%d", &c.threads, &c.E, &c.t0, &c.t1, &c.p2, &c.sched) == 6;
 }
 
 std::string cache_key(const demag_plan_s* p) {
@@ -1689,19 +1720,20 @@ std::string cache_key(const demag_plan_s* p) {
     if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) arch = prop.gcnArchName;
     arch = arch.substr(0, arch.find(':'));
     char b[160];
-    snprintf(b, sizeof b, "v4|%s|%s|%d,%d,%d", arch.c_str(), p->dtype == DEMAG_F32 ? "f32" : "f64", p->n[0],
+    snprintf(b, sizeof b, "v5|%s|%s|%d,%d,%d", arch.c_str(), p->dtype == DEMAG_F32 ? "f32" : "f64", p->n[0],
              p->n[1], p->n[2]);
     return b;
 }
 
-// Cache file: one line per plan key, "key xf yf zc yi xi" (each a,b,c,d).
+// Cache file: one line per plan key, "key xf yf zc yi xi" (each
+// threads,E,t0,t1,p2,sched).
 std::map<std::string, std::string> read_cache(const char* path) {
     std::map<std::string, std::string> m;
     std::ifstream f(path);
     std::string line;
     while (std::getline(f, line)) {
         auto sp = line.find(' ');
-        if (sp == std::string::npos || line.rfind("v4|", 0) != 0) continue;
+        if (sp == std::string::npos || line.rfind("v5|", 0) != 0) continue;
         m[line.substr(0, sp)] = line.substr(sp + 1);
     }
     return m;

@@ -54,6 +54,37 @@ def test_batch_equals_single_calls_and_replays_repeat():
     batch.close()
 
 
+def test_batch_of_96_members_equal_single_calls():
+    """The 96-grid workload itself (seeded sizes, m seeds 4000 + g): every
+    member of one graph replay equals its single-grid call bit for bit, and
+    one member of each shape matches the oracle at sampled cells (FP32 bar
+    1e-5)."""
+    from paper_1204_4302_amd import Batch
+    shapes, plans, ms, hs = build(96)
+    assert len(set(shapes)) == len(SIZES)
+    batch = Batch(plans, ms, hs, MS)
+    for h in hs:
+        h.fill_(float("nan"))
+    batch.launch()
+    torch.cuda.synchronize()
+    for p, m, h in zip(plans, ms, hs):
+        assert torch.equal(p.field(m, MS), h)
+    checked = set()
+    for g, s in enumerate(shapes):
+        if s in checked:
+            continue
+        checked.add(s)
+        t = inputs.sample_targets(s, 256, 5)
+        ref = oracle.Oracle(s, CELL).field_targets(ms[g].double().cpu().numpy(), MS, t)
+        got = hs[g].double().cpu().numpy().reshape(3, -1)[:, t]
+        err = float(np.abs(got - ref).max() / np.abs(ref).max())
+        print(f"grid {g} {s}: {err:.2e}")
+        assert err <= 1e-5
+    batch.close()
+    for p in plans:
+        p.close()
+
+
 def test_batch_autotune_keeps_results():
     """Group-tuned launch shapes may swap kernel families (rounding differs),
     so members are checked against single calls to FP32 rounding; replays of
