@@ -79,6 +79,8 @@ int p2_slab_elems(int P);
 constexpr size_t kP2TwLdsMax = 8192;
 size_t p2_twiddle_lds_bytes(int P, size_t cbytes);
 size_t p2_z_twiddle_lds_bytes(int P, size_t cbytes);  // extra LDS of a fused Z launch
+// dynamic LDS of a fused Z launch: slabs, twiddle table, tensor staging
+size_t p2_z_lds_bytes(int P, int rows, int lgTx, size_t cbytes);
 extern int kXcds;                       // XCDs of the device: 8 on MI355X; 1 turns the swizzle off
 int p2_max_threads(int P);              // X and Y passes: 1024 (2^a) or 512 (3 * 2^a)
 int p2_num_schedules(int P);            // radix schedules of a register-kernel length (0: not one)

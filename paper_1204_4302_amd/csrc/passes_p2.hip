@@ -711,25 +711,31 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) ky_inv(const cx<T>* __res
 // offset); the host guarantees that each range is below kOob.
 //
 // Register budget.  FP32 power-of-two lengths keep the thread's twiddles in
-// registers for all six transforms; in the paired form the tile's tensor rows
-// are copied into LDS with 16-byte loads issued together with the data loads,
-// and each frequency's six values are read from LDS right before its product
-// (the split form at 4096 loads them into registers up front).  FP64 (twice
-// the registers) and lengths 3 * 2^a (three times the slots) load the tensor
-// after the forward transforms and read the twiddles per transform from the
+// registers for all six transforms; FP64 (twice the registers) and lengths
+// 3 * 2^a (three times the slots) read them per transform from the
 // workgroup's LDS copy of the table (from memory if it is larger than
-// kP2TwLdsMax), which keeps them in registers.
+// kP2TwLdsMax).  Power-of-two lengths in the paired form copy the tile's
+// tensor rows into LDS with 16-byte loads issued together with the data loads
+// and read each frequency's six values from LDS right before its product; the
+// split form at 4096 (FP32) loads them into registers up front, and the other
+// lengths load them after the forward transforms.
 template <typename T, int P>
 __host__ __device__ constexpr bool z_keep_twiddles() {
     return sizeof(T) == 4 && p2::is_pow2(P);
 }
-// The same lengths in the paired form stage the tile's tensor rows in LDS
-// (one contiguous run of the kx-major octant) instead of loading each
-// frequency's six values into registers up front: 142 -> 97 VGPRs at P = 128
-// (3 -> 4 waves per SIMD), fused Z pass 109 -> 100 us at 256x256x64.
-template <typename T>
-bool z_stages_tensor(int P) {
-    return sizeof(T) == 4 && p2::is_pow2(P) && 2 * p2_threads_per_pencil(P) <= kP2MaxThreadsZ;
+// For power-of-two lengths in the paired form the tile's tensor rows (one
+// contiguous run of the kx-major octant) are staged in LDS and each
+// frequency's six values are read right before its product, instead of
+// holding all of the thread's tensor values in registers: FP32 P = 128
+// 142 -> 97 VGPRs (3 -> 4 waves per SIMD), fused Z pass 109 -> 100 us at
+// 256x256x64; FP64 P = 128 182 -> 165 VGPRs, 220 -> 210 us.  (For lengths
+// 3 * 2^a, whose threads hold 24 frequencies, the staging measured slower:
+// the 96-grid batch 499 -> 527 us.)  The staging area follows the slabs and
+// the LDS copy of the twiddle table, 16-byte aligned.
+template <typename T, int P>
+__host__ __device__ constexpr size_t z_stage_offset(int G) {
+    const size_t tw = z_keep_twiddles<T, P>() || !tw_in_lds<T, P>() ? 0 : p2::Len<P>::table_size() * sizeof(cx<T>);
+    return ((size_t)G * p2::Len<P>::PS * sizeof(cx<T>) + tw + 15) & ~(size_t)15;
 }
 
 template <typename T, int P, int S>
@@ -803,7 +809,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
             bld6<T>(bt, off, nt[j]);
         }
     };
-    constexpr bool kStage = kKeep && kPow2 && 2 * LT::TP <= kP2MaxThreadsZ;  // paired form only
+    constexpr bool kStage = kPow2 && 2 * LT::TP <= kP2MaxThreadsZ;  // power-of-two lengths, paired form
     // kStage: the tile's octant rows (kx, r0 .. r0 + Tx - 1) are one contiguous
     // run; it is copied into LDS (after the slabs) with 16-byte loads from a
     // 16-byte-aligned start, and each frequency's six values are read from there
@@ -822,12 +828,13 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         u4 ch[NCH];
 #pragma unroll
         for (int q = 0; q < NCH; ++q) ch[q] = __builtin_amdgcn_raw_buffer_load_b128(bt.r, tal + (unsigned)(tid + q * nthr) * 16u, 0, 0);
-        u4* dstl = (u4*)(lds + G * LT::PS);
+        unsigned char* sbase = (unsigned char*)lds + z_stage_offset<T, P>(G);
+        u4* dstl = (u4*)sbase;
 #pragma unroll
         for (int q = 0; q < NCH; ++q)
             if ((unsigned)(tid + q * nthr) * 16u < nbytes) dstl[tid + q * nthr] = ch[q];
         __syncthreads();
-        tls = (const T*)((const unsigned char*)(lds + G * LT::PS) + tmis) + (size_t)xi * (Lz + 1) * 6;
+        tls = (const T*)(sbase + tmis) + (size_t)xi * (Lz + 1) * 6;
     } else if constexpr (kKeep) {
         load_tensor();
     }
@@ -844,7 +851,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         if constexpr (kKeep) LT::template fft<-1, true>(v[comp], slab, t, tws);
         else run_fft<LT, -1, true>(v[comp], slab, t, twsrc);
     }
-    if constexpr (!kKeep) load_tensor();
+    if constexpr (!kKeep && !kStage) load_tensor();
     // H^ = Nhat(kx, ky, kz) M^ (Ms applied at the store).  Octant lookup with
     // parity signs: xy, yz odd in ky (negative for ky > Ly, i.e. s = 1); xz, yz
     // odd in kz, negative for kz > Lz.  For power-of-two lengths that is slot
@@ -857,8 +864,14 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         if constexpr (kPow2) negz = LT::F::slot_out(j) >= LT::EPT / 2;
         else negz = LT::fout(t, j) > Lz;
         if constexpr (kStage) {
-            const int k = LT::F::slot_out(j);
-            const int kzp = k < LT::EPT / 2 ? t + k * LT::TP : (LT::TP - 1 - t) + P - (k + 1) * LT::TP + 1;
+            int kzp;
+            if constexpr (kPow2) {
+                const int k = LT::F::slot_out(j);
+                kzp = k < LT::EPT / 2 ? t + k * LT::TP : (LT::TP - 1 - t) + P - (k + 1) * LT::TP + 1;
+            } else {
+                const int kz = LT::fout(t, j);
+                kzp = kz <= Lz ? kz : P - kz;
+            }
             typedef T t2 __attribute__((ext_vector_type(2)));
             const t2* e = (const t2*)(tls + kzp * 6);
 #pragma unroll
@@ -1093,6 +1106,12 @@ size_t p2_twiddle_lds_bytes(int P, size_t cbytes) {
     const size_t n = table_entries(P);
     return n * cbytes <= kP2TwLdsMax ? n * cbytes : 0;
 }
+size_t p2_z_lds_bytes(int P, int rows, int lgTx, size_t cbytes) {
+    size_t lds = (size_t)(rows << lgTx) * p2_slab_elems(P) * cbytes + p2_z_twiddle_lds_bytes(P, cbytes);
+    if (p2::is_pow2(P) && 2 * p2_threads_per_pencil(P) <= kP2MaxThreadsZ)  // tensor staging (kz_conv's kStage)
+        lds = ((lds + 15) & ~(size_t)15) + (size_t)(1 << lgTx) * (P / 2 + 1) * 3 * cbytes + 16;
+    return lds;
+}
 size_t p2_z_twiddle_lds_bytes(int P, size_t cbytes) {
     const bool keep = cbytes == sizeof(cx<float>) && p2::is_pow2(P);  // z_keep_twiddles
     return keep ? 0 : p2_twiddle_lds_bytes(P, cbytes);
@@ -1178,8 +1197,7 @@ hipError_t launch_z_conv_p2(int lgTx, int rows, int sched, hipStream_t st, cx<T>
     if (rows != (2 * p2_threads_per_pencil(P) <= kP2MaxThreadsZ ? 2 : 1)) return hipErrorInvalidValue;
     const int G = rows << lgTx;
     dim3 grid((unsigned)(Kx * ((rows == 2 ? Py / 2 + (1 << lgTx) : Py + (1 << lgTx) - 1) >> lgTx) * bio.count));
-    size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
-    if (z_stages_tensor<T>(P)) lds += ((size_t)(1 << lgTx) * (P / 2 + 1) * 6 + 4) * sizeof(T);
+    const size_t lds = p2_z_lds_bytes(P, rows, lgTx, sizeof(cx<T>));
 #define CALLS(PP, SS) \
     if (hipError_t e_ = allow_lds(&kz_conv<T, PP, SS>, lds)) return e_; \
     hipLaunchKernelGGL((kz_conv<T, PP, SS>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, rows, \

@@ -328,9 +328,7 @@ LaunchCfg p2_zconv(int P, int Py, size_t cbytes, int target = 64) {
     const int rows = 2 * TP <= kP2MaxThreadsZ ? 2 : 1;
     int lgTx = std::max(0, ilog2i(std::max(1, target / (rows * TP))));
     lgTx = std::min(lgTx, pow2_ceil_log(Py / 2 + 1));
-    while (lgTx > 0 &&
-           ((size_t)p2_slab_elems(P) * (rows << lgTx)) * cbytes + p2_z_twiddle_lds_bytes(P, cbytes) > g_p2_lds - 256)
-        --lgTx;
+    while (lgTx > 0 && p2_z_lds_bytes(P, rows, lgTx, cbytes) > g_p2_lds - 256) --lgTx;
     while (lgTx > 0 && (rows * TP << lgTx) > kP2MaxThreadsZ) --lgTx;
     c.t0 = lgTx;
     c.t1 = rows;
@@ -348,9 +346,9 @@ bool p2_cfg_ok(const LaunchCfg& c, int P, size_t cbytes, int kind /*0 rows, 1 pe
     long threads = pencils * TP;
     long maxthr = kind == 2 ? kP2MaxThreadsZ : p2_max_threads(P);
     if (kind == 2 && !p2_z_supported(P, cbytes)) return false;
-    const size_t tw = kind == 2 ? p2_z_twiddle_lds_bytes(P, cbytes) : p2_twiddle_lds_bytes(P, cbytes);
-    return threads == c.threads && threads <= maxthr &&
-           (size_t)pencils * p2_slab_elems(P) * cbytes + tw <= g_p2_lds - 256;  // + static reduction scratch
+    const size_t lds = kind == 2 ? p2_z_lds_bytes(P, c.t1, c.t0, cbytes)
+                                 : (size_t)pencils * p2_slab_elems(P) * cbytes + p2_twiddle_lds_bytes(P, cbytes);
+    return threads == c.threads && threads <= maxthr && lds <= g_p2_lds - 256;  // + static reduction scratch
 }
 
 // byte spans the power-of-two Z pass addresses with 32-bit buffer offsets
