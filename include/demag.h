@@ -333,7 +333,9 @@ int demag_autotune(demag_plan_t plan, void* stream);
  * m / H device buffers.  Plans of equal geometry form a group that runs each
  * pass as one launch over all its members (and uses the first member's
  * tensor spectrum and launch shapes); all groups' launches are recorded once
- * into a HIP graph, replayed by demag_batch_launch (asynchronous).  The batch
+ * into a HIP graph, replayed by demag_batch_launch (asynchronous), with the
+ * groups spread over one forked stream per hardware queue ($GPU_MAX_HW_QUEUES,
+ * default 4), largest first onto the least loaded stream.  The batch
  * references (does not own) plans and buffers; all must stay alive and
  * unchanged until demag_batch_destroy.  Plans must be distinct (each owns the
  * scratch its evaluation uses).  demag_batch_create synchronises `stream`. */
@@ -341,7 +343,9 @@ int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans, int count,
                        void* const* H, double Ms, void* stream);
 /* Time the candidate launch shapes of every pass of every group on the
  * group's own buffers (each candidate launch covering all members), keep the
- * fastest per group and re-record the graph.  Synchronous; overwrites the
+ * fastest per group, then spread the groups (by their measured times) over
+ * 1 .. (hardware queues) forked streams, time whole replays of each and keep
+ * the fastest graph.  Synchronous; overwrites the
  * members' H and scratch (the next demag_batch_launch recomputes them); plans'
  * own launch shapes are unchanged.  Groups then may run other kernels than
  * single-plan calls, so members agree with demag_field to rounding only. */

@@ -224,6 +224,7 @@ struct BatchGroup {
     int count = 0;
     void** lists = nullptr;  // device: m[count], H[count], B1[count], B2[count]
     PassCfgs cfg;            // launch shapes of the group's passes (the lead's until tuned)
+    double cost = 0;         // relative run time: modelled (count x padded cells), measured once tuned
 };
 
 struct demag_batch_s {
@@ -234,6 +235,7 @@ struct demag_batch_s {
     double Ms = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int lanes = 0;  // capture streams the groups are spread over (0: one per hardware queue)
 };
 
 namespace {
@@ -1873,6 +1875,15 @@ extern "C" int demag_autotune(demag_plan_t p, void* stream) {
 namespace {
 constexpr int kBranches = 8;
 
+// Hardware queues the runtime gives a process (HIP's GPU_MAX_HW_QUEUES,
+// default 4): capture streams beyond this share a queue, and the groups on a
+// shared queue run one after the other.
+int hw_queues() {
+    const char* e = std::getenv("GPU_MAX_HW_QUEUES");
+    int q = e ? std::atoi(e) : 4;
+    return std::max(1, std::min(q, kBranches));
+}
+
 bool same_geometry(const demag_plan_s* a, const demag_plan_s* b) {
     return a->dtype == b->dtype && a->n[0] == b->n[0] && a->n[1] == b->n[1] && a->n[2] == b->n[2] &&
            a->d[0] == b->d[0] && a->d[1] == b->d[1] && a->d[2] == b->d[2] && a->bands.far_cut == b->bands.far_cut &&
@@ -1906,14 +1917,29 @@ int enqueue_group(const BatchGroup& grp, double Ms, hipStream_t st) {
 }
 
 // Record every group's launches into the batch's graph (replacing an earlier
-// one): groups on up to kBranches forked capture streams, joined at the end.
+// one): the groups are spread over `lanes` forked capture streams, joined at
+// the end, longest first onto the least loaded lane (by group cost), each
+// lane running its groups longest first.
 int record_graph(demag_batch_s* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
     int rc = DEMAG_OK;
-    const int nb = std::min<int>(kBranches, (int)b->groups.size());
+    const int ng = (int)b->groups.size();
+    const int nb = std::min(b->lanes > 0 ? std::min(b->lanes, kBranches) : hw_queues(), ng);
+    std::vector<int> order(ng), lane_of(ng);
+    for (int i = 0; i < ng; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int c) { return b->groups[a].cost > b->groups[c].cost; });
+    {
+        std::vector<double> load(nb, 0.0);
+        for (int gi : order) {
+            const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            lane_of[gi] = l;
+            load[l] += b->groups[gi].cost;
+        }
+    }
     hipStream_t cs[kBranches] = {};
     hipEvent_t ev[kBranches + 1] = {};
     for (int k = 0; k < nb && !rc; ++k)
@@ -1938,10 +1964,10 @@ int record_graph(demag_batch_s* b) {
         chk(hipEventRecord(ev[kBranches], cs[0]), "hipEventRecord (capture fork)");
         for (int k = 1; k < nb; ++k)
             chk(hipStreamWaitEvent(cs[k], ev[kBranches], 0), "hipStreamWaitEvent (capture fork)");
-        for (size_t gi = 0; gi < b->groups.size() && !rc; ++gi) {
-            const BatchGroup& g = b->groups[gi];
-            rc = g.lead->dtype == DEMAG_F32 ? enqueue_group<float>(g, b->Ms, cs[gi % nb])
-                                            : enqueue_group<double>(g, b->Ms, cs[gi % nb]);
+        for (int k = 0; k < ng && !rc; ++k) {
+            const BatchGroup& g = b->groups[order[k]];
+            hipStream_t lst = cs[lane_of[order[k]]];
+            rc = g.lead->dtype == DEMAG_F32 ? enqueue_group<float>(g, b->Ms, lst) : enqueue_group<double>(g, b->Ms, lst);
         }
         for (int k = 1; k < nb; ++k) {
             chk(hipEventRecord(ev[k], cs[k]), "hipEventRecord (capture join)");
@@ -2012,10 +2038,38 @@ int tune_group(BatchGroup& g, hipStream_t st) {
             }
         }
         *slot[w] = bestc;
+        g.cost = best;  // after the last pass: the group's evaluation with every chosen shape
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return hip_fail(err, "batch autotune timing");
+    return DEMAG_OK;
+}
+
+// Average time of one replay of the batch's graph (after warm-up replays).
+int time_replays(demag_batch_s* b, hipStream_t st, float* us) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(DEMAG_EHIP, "hipEventCreate failed");
+    }
+    hipError_t err = hipSuccess;
+    for (int r = 0; r < 3 && err == hipSuccess; ++r) err = hipGraphLaunch(b->exec, st);
+    float best = 1e30f;
+    for (int trial = 0; trial < 3 && err == hipSuccess; ++trial) {
+        err = hipEventRecord(e0, st);
+        for (int r = 0; r < 8 && err == hipSuccess; ++r) err = hipGraphLaunch(b->exec, st);
+        if (err == hipSuccess) err = hipEventRecord(e1, st);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        best = std::min(best, 1e3f * ms / 8);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return hip_fail(err, "batch replay timing");
+    *us = best;
     return DEMAG_OK;
 }
 }  // namespace
@@ -2066,6 +2120,7 @@ extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans,
         g.count = (int)mem.size();
         g.lists = (void**)b->dev_lists + off;
         g.cfg = g.lead->cfg;
+        g.cost = (double)g.count * g.lead->P[0] * g.lead->P[1] * g.lead->P[2];
         off += 4 * (size_t)g.count;
         b->groups.push_back(g);
     }
@@ -2099,6 +2154,21 @@ extern "C" int demag_batch_autotune(demag_batch_t b, void* stream) {
         rc = g.lead->dtype == DEMAG_F32 ? tune_group<float>(g, st) : tune_group<double>(g, st);
         if (rc) break;
     }
+    // then the number of lanes, up to one per hardware queue, by whole replays
+    const int maxl = std::min(hw_queues(), (int)b->groups.size());
+    int best_l = maxl;
+    float best_us = 1e30f;
+    for (int l = 1; l <= maxl && !rc; ++l) {
+        b->lanes = l;
+        rc = record_graph(b);
+        float us = 0;
+        if (!rc) rc = time_replays(b, st, &us);
+        if (!rc && us < best_us) {
+            best_us = us;
+            best_l = l;
+        }
+    }
+    b->lanes = best_l;
     if (!rc) rc = record_graph(b);
     for (auto p : b->plans) {
         int r2 = leave(p, st);
