@@ -110,7 +110,7 @@ def bench_sp(args, torch, np, m_np, dm_value):
     for _ in range(args.warmup):
         step()
     k = args.sp_steps
-    secs = run_steps(step, k, torch)
+    secs = run_steps(step, k, torch, "sp")
     i = plan.info()
     pb = sp_pass_bytes(SHAPE, i["Px"], i["Py"], i["Pz"], i["Kx"], 4)
     nbytes = sum(pb.values())
@@ -145,7 +145,7 @@ def bench_llg(args, torch, np, dm_value):
     for _ in range(3):
         step()
     k = args.llg_steps
-    secs = run_steps(step, k, torch)
+    secs = run_steps(step, k, torch, "llg")
     i = plan.info()
     field = sum(pass_bytes(SHAPE, i["Px"], i["Py"], i["Pz"], i["Kx"], 4).values())
     vec = 3 * SHAPE[0] * SHAPE[1] * SHAPE[2] * 4
@@ -182,7 +182,7 @@ def bench_tg(args, torch, np, m_np, dm_value):
     for _ in range(2):
         step()
     k = args.tg_steps
-    secs = run_steps(step, k, torch)
+    secs = run_steps(step, k, torch, "tg")
     tflops = info["flops_per_eval"] * k / secs / 1e12
     out = {"value": round(k / secs, 2), "unit": "evals/s", "ms_per_eval": round(1e3 * secs / k, 3),
            "sinc_nodes": info["nodes"], "flops_per_eval": info["flops_per_eval"],
@@ -231,9 +231,9 @@ def bench_lowrank(args, torch, np, dm_value):
             compressed()
             dense()
         k = args.lowrank_steps
-        sc = run_steps(compressed, k, torch)
+        sc = run_steps(compressed, k, torch, "lowrank")
         kd = max(1, k // 10)
-        sd = run_steps(dense, kd, torch)
+        sd = run_steps(dense, kd, torch, "lowrank_dense")
         # algorithmic bytes of the compressed evaluation: per axis q the even
         # stack for the two components p != q and the odd one for p = q
         # (R x 2 n_q x n_q each), the factors in, the factor buffer out
@@ -336,13 +336,43 @@ def settle(step, torch, seconds):
         torch.cuda.synchronize()
 
 
-def run_steps(step, k, torch):
+_ROCTX = []
+
+
+def _roctx():
+    """The ROCTx library (host-side profiler ranges), or None if absent."""
+    if not _ROCTX:
+        import ctypes
+        lib = None
+        for name in ("librocprofiler-sdk-roctx.so.1", os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "lib",
+                                                                    "librocprofiler-sdk-roctx.so.1")):
+            try:
+                lib = ctypes.CDLL(name)
+                lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+                break
+            except OSError:
+                lib = None
+        _ROCTX.append(lib)
+    return _ROCTX[0]
+
+
+def run_steps(step, k, torch, name=None):
+    """Time k calls of `step` between two device synchronisations.  With
+    `name`, the region (synchronisations included) is the profiler range
+    "bench:<name>" (rocprofv3 --marker-trace), which --summarize-profile
+    --range selects."""
+    rx = _roctx() if name else None
     torch.cuda.synchronize()
+    if rx:
+        rx.roctxRangePushA(f"bench:{name}".encode())
     t0 = time.perf_counter()
     for _ in range(k):
         step()
     torch.cuda.synchronize()
-    return time.perf_counter() - t0
+    secs = time.perf_counter() - t0
+    if rx:
+        rx.roctxRangePop()
+    return secs
 
 
 def cpu_baseline(m, target_seconds, Href32, Href64):
@@ -416,8 +446,8 @@ def bench_rocfft_reference(args, torch, np, m_np):
     for _ in range(3):
         step()
         plan.field(m, MS, out=H)
-    t_ref = run_steps(step, k, torch)
-    t_dm = run_steps(lambda: plan.field(m, MS, out=H), k, torch)
+    t_ref = run_steps(step, k, torch, "rocfft_reference")
+    t_dm = run_steps(lambda: plan.field(m, MS, out=H), k, torch, "rocfft_reference_dm")
     plan.close()
     del full, mp, out, ref
     torch.cuda.empty_cache()
@@ -507,8 +537,8 @@ def bench_batch(args, torch, np):
     for _ in range(3):
         seq()
         batch.launch()
-    t_seq = run_steps(seq, k, torch)
-    t_graph = run_steps(batch.launch, k, torch)
+    t_seq = run_steps(seq, k, torch, "batch_sequential")
+    t_graph = run_steps(batch.launch, k, torch, "batch_graph")
     # every member of the timed replays against its single-grid call (the
     # group-tuned launch shapes may differ from the plans' own: FP32 rounding)
     batch.launch()
@@ -569,11 +599,11 @@ def bench(args):
             step()
         # the timed region runs without instrumentation; the per-pass times
         # come from a second, separately recorded region of the same length
-        secs = run_steps(step, steps, torch)
+        secs = run_steps(step, steps, torch, "dm_f32" if dtype == torch.float32 else "dm_f64")
         passes, nrec = {}, 0
         if dtype == torch.float32 and not args.no_pass_timing:
             plan.set_option("pass_timing", 2 * steps)
-            run_steps(step, steps, torch)
+            run_steps(step, steps, torch, "dm_f32_pass_timing")
             passes, nrec = plan.pass_times()
             plan.set_option("pass_timing", 0)
         print(f"# {dtype} launch: {plan.describe()}", file=sys.stderr, flush=True)
@@ -689,18 +719,52 @@ def _short(name):
     return name.split("(")[0].replace("void ", "")
 
 
-def summarize_profile(d, out_path, command, match=None):
+def _union_ns(intervals):
+    """Total length of the union of [start, end) intervals."""
+    busy, cur_s, cur_e = 0, None, None
+    for a, b in sorted(intervals):
+        if cur_e is None or a > cur_e:
+            if cur_e is not None:
+                busy += cur_e - cur_s
+            cur_s, cur_e = a, b
+        else:
+            cur_e = max(cur_e, b)
+    return busy + (cur_e - cur_s if cur_e is not None else 0)
+
+
+def summarize_profile(d, out_path, command, match=None, region=None):
     """Per-kernel calls / average / total from a --kernel-trace --stats run
     (only kernels whose name contains one of the comma-separated `match`
-    strings, when given)."""
+    strings, when given).  With `region`, only the kernels that ran inside
+    the bench's profiler range "bench:<region>" (a run with --marker-trace),
+    with the range's length and the fraction of it during which a kernel ran."""
     import sqlite3
     lines = [f"# command: {command}", f"# kernel_source_hash = {kernel_source_hash()}",
              "# per kernel and grid size (work-items), from the trace's dispatch records",
              f"{'kernel':44s} {'grid':>9s} {'calls':>6s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
     for db in _find(d, "*results.db"):
         con = sqlite3.connect(db)
+        where = ""
+        if region:
+            # the range's message is the name (older layouts) or in the JSON extdata
+            ranges = []
+            for a, b, nm, ext in con.execute("select start, end, name, extdata from regions"):
+                try:
+                    msg = json.loads(ext or "{}").get("message")
+                except ValueError:
+                    msg = None
+                if f"bench:{region}" in (nm, msg):
+                    ranges.append((a, b))
+            if not ranges:
+                raise SystemExit(f"no profiler range bench:{region} in {db} (run rocprofv3 with --marker-trace)")
+            where = " where " + " or ".join(f"(start >= {a} and end <= {b})" for a, b in ranges)
+            spans = con.execute(f"select start, end from kernels{where}").fetchall()
+            window = sum(b - a for a, b in ranges)
+            lines.insert(3, f"# range bench:{region}: {len(ranges)} range(s), {window / 1e6:.3f} ms, "
+                            f"{len(spans)} dispatches, a kernel running {100.0 * _union_ns(spans) / window:.1f}% "
+                            "of the time")
         rows = con.execute("select name, grid_x * grid_y * grid_z, count(*), sum(end - start), avg(end - start) "
-                           "from kernels group by name, grid_x, grid_y, grid_z").fetchall()
+                           f"from kernels{where} group by name, grid_x, grid_y, grid_z").fetchall()
         total_ns = sum(r[3] for r in rows) or 1
         if match:
             keys = [k for k in match.split(",") if k]
@@ -792,12 +856,14 @@ def main():
     ap.add_argument("--command", default="", help="command line recorded in the summary")
     ap.add_argument("--match", default=None, help="--summarize-profile: keep kernels whose name contains one of "
                                                   "these comma-separated strings")
+    ap.add_argument("--range", default=None, help="--summarize-profile: only kernels inside the bench's profiler "
+                                                  "range bench:RANGE (e.g. batch_graph, dm_f32)")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(*args.traffic_summary, args.out or "/dev/stdout", args.command)
         return 0
     if args.summarize_profile:
-        summarize_profile(args.summarize_profile, args.out or "/dev/stdout", args.command, args.match)
+        summarize_profile(args.summarize_profile, args.out or "/dev/stdout", args.command, args.match, args.range)
         return 0
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU and measures the one-GPU path only; --gpus {args.gpus} "

@@ -7,6 +7,7 @@
 // enqueues five pass kernels and, for the energy, one reduction.
 #include <hip/hip_runtime.h>
 #include <rocblas/rocblas.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
 #include <chrono>
@@ -27,6 +28,19 @@
 #include "internal.hpp"
 
 using namespace demag;
+
+// ---------------------------------------------------------------------------
+// profiler ranges: every API call that enqueues work, and each pass of a field
+// evaluation, is a named host-side range (rocprofv3 --marker-trace); a range
+// covers the enqueue on the host, the kernels run later on the stream
+namespace {
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // errors
@@ -817,7 +831,9 @@ int run_field(demag_plan_s* p, const PassCfgs& c, const T* m, double Ms, T* H, c
         mark = &p->tev[(size_t)(p->tcount % p->tcap) * kPassMarks];
     double* partials = E_dev ? p->partials : nullptr;
     const T* me = E_dev ? m_energy : nullptr;
+    static const char* const kPassNames[5] = {"x_r2c", "y_fwd", "z_conv", "y_inv", "x_c2r"};
     for (int which = 0; which < 5; ++which) {
+        const Range range_(kPassNames[which]);
         if (mark) HIP_TRY(hipEventRecord(mark[which], st));
         HIP_TRY(launch_pass<T>(p, which, pass_cfg(c, which), st, m, Ms, H, me, partials, accumulate));
     }
@@ -1044,6 +1060,7 @@ const char* demag_last_error(void) { return g_last_error.c_str(); }
 
 int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, double dy, double dz,
                       demag_dtype dtype, void* setup_stream) {
+    const Range range_("demag_plan_create");
     if (!out) return fail(DEMAG_EINVAL, "out is NULL");
     *out = nullptr;
     if (nx < 1 || ny < 1 || nz < 1) return fail(DEMAG_EINVAL, "grid must be at least 1x1x1 (got %d x %d x %d)", nx, ny, nz);
@@ -1221,6 +1238,7 @@ int demag_plan_info(demag_plan_t p, int64_t* info) {
 }
 
 int demag_field(demag_plan_t p, const void* m, double Ms, void* H, void* stream) {
+    const Range range_("demag_field");
     if (!p || !m || !H) return fail(DEMAG_EINVAL, "NULL plan, m or H");
     if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
     hipStream_t st = (hipStream_t)stream;
@@ -1232,6 +1250,7 @@ int demag_field(demag_plan_t p, const void* m, double Ms, void* H, void* stream)
 }
 
 int demag_field_adjoint(demag_plan_t p, const void* gH, double Ms, void* gm, int accumulate, void* stream) {
+    const Range range_("demag_field_adjoint");
     if (!p || !gH || !gm) return fail(DEMAG_EINVAL, "NULL plan, gH or gm");
     if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
     if (accumulate != 0 && accumulate != 1) return fail(DEMAG_EINVAL, "accumulate must be 0 or 1");
@@ -1244,6 +1263,7 @@ int demag_field_adjoint(demag_plan_t p, const void* gH, double Ms, void* gm, int
 }
 
 int demag_field_energy(demag_plan_t p, const void* m, double Ms, void* H, double* E_dev, void* stream) {
+    const Range range_("demag_field_energy");
     if (!p || !m || !E_dev) return fail(DEMAG_EINVAL, "NULL plan, m or E_dev");
     if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
     hipStream_t st = (hipStream_t)stream;
@@ -1255,11 +1275,13 @@ int demag_field_energy(demag_plan_t p, const void* m, double Ms, void* H, double
 }
 
 int demag_energy_async(demag_plan_t p, const void* m, double Ms, double* E_dev, void* stream) {
+    const Range range_("demag_energy_async");
     return demag_field_energy(p, m, Ms, nullptr, E_dev, stream);
 }
 
 int demag_energy_gradient(demag_plan_t p, const void* H, double Ms, const double* gE_dev, void* gm, int accumulate,
                           void* stream) {
+    const Range range_("demag_energy_gradient");
     if (!p || !H || !gm) return fail(DEMAG_EINVAL, "NULL plan, H or gm");
     if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
     if (H == gm) return fail(DEMAG_EINVAL, "H and gm must be distinct buffers");
@@ -1275,6 +1297,7 @@ int demag_energy_gradient(demag_plan_t p, const void* H, double Ms, const double
 }
 
 int demag_energy(demag_plan_t p, const void* m, double Ms, double* E_host, void* stream) {
+    const Range range_("demag_energy");
     if (!E_host) return fail(DEMAG_EINVAL, "E_host is NULL");
     if (!p) return fail(DEMAG_EINVAL, "NULL plan");
     int rc = demag_field_energy(p, m, Ms, nullptr, p->e_dev, stream);
@@ -1315,6 +1338,7 @@ int demag_plan_tensor(demag_plan_t p, double* out) {
 }
 
 int demag_sp_prepare(demag_plan_t p, void* stream) {
+    const Range range_("demag_sp_prepare");
     if (!p) return fail(DEMAG_EINVAL, "NULL plan");
     if (p->shat) return DEMAG_OK;
     const size_t cb = csize(p->dtype), rb = cb / 2;
@@ -1342,6 +1366,7 @@ int demag_sp_prepare(demag_plan_t p, void* stream) {
 }
 
 int demag_sp_field_energy(demag_plan_t p, const void* m, double Ms, void* H, double* E_dev, void* stream) {
+    const Range range_("demag_sp_field_energy");
     if (!p || !m || (!H && !E_dev)) return fail(DEMAG_EINVAL, "NULL plan or m, or neither H nor E_dev");
     if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
     if (!p->shat) return fail(DEMAG_ESTATE, "scalar-potential method not prepared (call demag_sp_prepare)");
@@ -1375,12 +1400,14 @@ int demag_sp_kernel(demag_plan_t p, double* out) {
 
 int demag_llg_heun(demag_plan_t p, void* m, double Ms, double alpha, double gamma, double hx, double hy, double hz,
                    double dt, int nsteps, void* work, void* stream) {
+    const Range range_("demag_llg_heun");
     if (!work) return fail(DEMAG_EINVAL, "NULL work");
     return llg_heun_impl(p, m, Ms, alpha, gamma, hx, hy, hz, dt, nsteps, work, stream);
 }
 
 int demag_llg_heun_static(demag_plan_t p, void* m, double Ms, double alpha, double gamma, double hx, double hy,
                           double hz, double dt, int nsteps, void* stream) {
+    const Range range_("demag_llg_heun_static");
     if (!p) return fail(DEMAG_EINVAL, "NULL plan");
     const size_t N = (size_t)p->n[0] * p->n[1] * p->n[2];
     const size_t need = 9 * N * (p->dtype == DEMAG_F32 ? sizeof(float) : sizeof(double));
@@ -1394,6 +1421,7 @@ int demag_llg_heun_static(demag_plan_t p, void* m, double Ms, double alpha, doub
 }
 
 int demag_tg_prepare(demag_plan_t p, void* stream) {
+    const Range range_("demag_tg_prepare");
     if (!p) return fail(DEMAG_EINVAL, "NULL plan");
     if (p->tg) return DEMAG_OK;
     hipStream_t st = (hipStream_t)stream;
@@ -1410,6 +1438,7 @@ int demag_tg_prepare(demag_plan_t p, void* stream) {
 }
 
 int demag_tg_field_energy(demag_plan_t p, const void* m, double Ms, void* H, double* E_dev, void* stream) {
+    const Range range_("demag_tg_field_energy");
     if (!p || !m || (!H && !E_dev)) return fail(DEMAG_EINVAL, "NULL plan or m, or neither H nor E_dev");
     if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
     if (!p->tg) return fail(DEMAG_ESTATE, "tensor-grid method not prepared (call demag_tg_prepare)");
@@ -1438,6 +1467,7 @@ int demag_tg_info(demag_plan_t p, int64_t* out) {
 }
 
 int demag_tg_lowrank_prepare(demag_plan_t p, void* stream) {
+    const Range range_("demag_tg_lowrank_prepare");
     if (!p) return fail(DEMAG_EINVAL, "NULL plan");
     if (p->lr) return DEMAG_OK;
     hipStream_t st = (hipStream_t)stream;
@@ -1455,6 +1485,7 @@ int demag_tg_lowrank_prepare(demag_plan_t p, void* stream) {
 
 int demag_tg_lowrank_field(demag_plan_t p, int format, int rank, const void* core, const void* U, double Ms, void* FG,
                            void* H, double* E_dev, void* stream) {
+    const Range range_("demag_tg_lowrank_field");
     if (!p || !core || !U || !FG) return fail(DEMAG_EINVAL, "NULL plan, core, U or FG");
     if (format != DEMAG_TUCKER && format != DEMAG_CP) return fail(DEMAG_EINVAL, "format must be DEMAG_TUCKER or DEMAG_CP");
     const int rmax = format == DEMAG_TUCKER ? DEMAG_TUCKER_MAX_RANK : DEMAG_CP_MAX_RANK;
@@ -1528,6 +1559,7 @@ int demag_tg_lowrank_field(demag_plan_t p, int format, int rank, const void* cor
 
 int demag_lowrank_compress(demag_plan_t p, int format, int rank, int sweeps, const void* m, void* core, void* U,
                            double* relerr, void* stream) {
+    const Range range_("demag_lowrank_compress");
     if (!p || !m || !core || !U) return fail(DEMAG_EINVAL, "NULL plan, m, core or U");
     if (format != DEMAG_TUCKER && format != DEMAG_CP) return fail(DEMAG_EINVAL, "format must be DEMAG_TUCKER or DEMAG_CP");
     const int rmax = format == DEMAG_TUCKER ? std::min(DEMAG_TUCKER_MAX_RANK, std::min(p->n[0], std::min(p->n[1], p->n[2])))
@@ -1832,6 +1864,7 @@ int autotune_impl(demag_plan_s* p, hipStream_t st) {
 }  // namespace
 
 extern "C" int demag_autotune(demag_plan_t p, void* stream) {
+    const Range range_("demag_autotune");
     if (!p) return fail(DEMAG_EINVAL, "NULL plan");
     hipStream_t st = (hipStream_t)stream;
     int rc = enter(p, st);
@@ -2076,6 +2109,7 @@ int time_replays(demag_batch_s* b, hipStream_t st, float* us) {
 
 extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans, int count, const void* const* m,
                                   void* const* H, double Ms, void* stream) {
+    const Range range_("demag_batch_create");
     if (!out || !plans || !m || !H || count < 1) return fail(DEMAG_EINVAL, "bad batch arguments");
     *out = nullptr;
     if (!std::isfinite(Ms)) return fail(DEMAG_EINVAL, "Ms must be finite");
@@ -2143,6 +2177,7 @@ extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans,
 }
 
 extern "C" int demag_batch_autotune(demag_batch_t b, void* stream) {
+    const Range range_("demag_batch_autotune");
     if (!b || !b->exec) return fail(DEMAG_EINVAL, "NULL batch");
     hipStream_t st = (hipStream_t)stream;
     for (auto p : b->plans) {
@@ -2180,6 +2215,7 @@ extern "C" int demag_batch_autotune(demag_batch_t b, void* stream) {
 // One event for the whole replay (not one per member: the host cost of the
 // per-member bookkeeping would exceed the replay itself for small grids).
 extern "C" int demag_batch_launch(demag_batch_t b, void* stream) {
+    const Range range_("demag_batch_launch");
     if (!b || !b->exec) return fail(DEMAG_EINVAL, "NULL batch");
     hipStream_t st = (hipStream_t)stream;
     for (auto p : b->plans) {

@@ -26,3 +26,13 @@ def test_mirrored_spectrum_equals_full_half_spectrum(P):
     full = bench.mirrored_spectrum(np, octant, Py, Pz)
     assert full.shape == (6, Pz, Py, Px // 2 + 1)
     assert np.abs(full - F.real).max() < 1e-12
+
+
+def test_union_of_kernel_intervals():
+    """The busy time of a profiled range: overlapping dispatches (concurrent
+    streams) count once, gaps not at all."""
+    assert bench._union_ns([]) == 0
+    assert bench._union_ns([(0, 10)]) == 10
+    assert bench._union_ns([(5, 15), (0, 10), (20, 30)]) == 25
+    assert bench._union_ns([(0, 100), (10, 20), (30, 40)]) == 100
+    assert bench._union_ns([(0, 10), (10, 20)]) == 20
