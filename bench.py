@@ -234,11 +234,14 @@ def bench_lowrank(args, torch, np, dm_value):
         sc = run_steps(compressed, k, torch, "lowrank")
         kd = max(1, k // 10)
         sd = run_steps(dense, kd, torch, "lowrank_dense")
-        # algorithmic bytes of the compressed evaluation: per axis q the even
-        # stack for the two components p != q and the odd one for p = q
-        # (R x 2 n_q x n_q each), the factors in, the factor buffer out
-        gbytes = sum(3 * R * 2 * n * n * 4 for n in SHAPE)
-        fbytes = 4 * (3 * rank * sum(SHAPE) + FG.numel())
+        # algorithmic bytes of the compressed evaluation: per axis q and node
+        # the even and the odd Gaussian matrix (n_q x n_q each, read once for
+        # all three components), the magnetization factors and core in, and
+        # the factor buffer twice (potential factors written, then read by the
+        # difference kernel that writes the field factors; all read by the
+        # Gram matrices)
+        gbytes = sum(2 * R * n * n * 4 for n in SHAPE)
+        fbytes = 4 * (U.numel() + core.numel() + 2 * FG.numel())
         nbytes = gbytes + fbytes
         stored = (core.numel() + U.numel())
         out[name] = {
@@ -791,24 +794,43 @@ def _counter_means(d, counter):
     return {k: (sum(v) / len(v), len(v)) for k, v in agg.items()}
 
 
+# --copy-calibration: a 256 MiB device copy (the runtime's copy kernel) and,
+# as a check, a 1 GiB elementwise copy (torch's kernel, y = 1 * x)
+CALIBRATION = ((256, "copyBuffer"), (1024, "elementwise"))
+
+
 def traffic_summary(fetch_dir, write_dir, out_path, command):
     """HBM bytes per launch of every pass kernel from FETCH_SIZE / WRITE_SIZE
     (KiB per dispatch), each scaled by what the same counter reads for the
-    plain 256 MiB device copy of --copy-calibration (runtime copy kernel)."""
+    plain 256 MiB device copy of --copy-calibration (runtime copy kernel); the
+    1 GiB elementwise copy of the same run is reported beside it as a check
+    that the factor depends neither on the size nor on the copying kernel."""
     fetch, write = _counter_means(fetch_dir, "FETCH_SIZE"), _counter_means(write_dir, "WRITE_SIZE")
-    copy_kib = 256 * 1024.0
 
-    def calib(tab):
-        vals = [v for (k, g), (v, n) in tab.items() if "copyBuffer" in k and v > 0.3 * copy_kib]
-        return vals and max(vals)
+    def calib(mib, kind):
+        # the copy of `mib` MiB: among the dispatches (name, grid) of that kind
+        # of kernel that write about the copied size, the one that reads most
+        # (the fill that initialised the source writes as much but reads nothing)
+        kib = mib * 1024.0
+        keys = [key for key, (v, n) in write.items() if kind in key[0] and 0.5 * kib < v < 2.0 * kib]
+        if not keys:
+            return None, None
+        key = max(keys, key=lambda kk: fetch.get(kk, (0.0, 0))[0])
+        return fetch.get(key, (None, 0))[0], write[key][0]
 
-    fc, wc = calib(fetch), calib(write)
-    f_fetch = copy_kib / fc if fc else None
-    f_write = copy_kib / wc if wc else None
-    lines = [f"# command: {command}", f"kernel_source_hash = {kernel_source_hash()}",
-             f"# calibration: a 256 MiB device copy reads {fc} KiB (FETCH_SIZE) and writes {wc} KiB (WRITE_SIZE)",
-             f"copy_calibration_fetch_factor = {f_fetch}", f"copy_calibration_write_factor = {f_write}",
-             f"# {'kernel':40s} {'grid':>9s} {'FETCH_KiB':>11s} {'WRITE_KiB':>11s} {'scaled_MB':>10s}"]
+    cal = {mib: calib(mib, kind) for mib, kind in CALIBRATION}
+    fc, wc = cal[256]
+    f_fetch = 256 * 1024.0 / fc if fc else None
+    f_write = 256 * 1024.0 / wc if wc else None
+    lines = [f"# command: {command}", f"kernel_source_hash = {kernel_source_hash()}"]
+    for mib, (cf, cw) in cal.items():
+        ff = f"{mib * 1024.0 / cf:.4f}" if cf else "n/a"
+        fw = f"{mib * 1024.0 / cw:.4f}" if cw else "n/a"
+        what = "device copy (runtime copy kernel)" if mib == 256 else "elementwise copy (check)"
+        lines.append(f"# calibration: a {mib} MiB {what} reads {cf} KiB (FETCH_SIZE) and writes {cw} KiB "
+                     f"(WRITE_SIZE): factors {ff} / {fw}")
+    lines += [f"copy_calibration_fetch_factor = {f_fetch}", f"copy_calibration_write_factor = {f_write}",
+              f"# {'kernel':40s} {'grid':>9s} {'FETCH_KiB':>11s} {'WRITE_KiB':>11s} {'scaled_MB':>10s}"]
     zconv = None
     for key in sorted(set(fetch) | set(write)):
         fv, wv = fetch.get(key, (0.0, 0))[0], write.get(key, (0.0, 0))[0]
@@ -871,12 +893,17 @@ def main():
         return 2
     if args.copy_calibration:
         import torch
-        a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print("# copy calibration: 3 x 256 MiB device copies", file=sys.stderr)
+        for mib, kind in CALIBRATION:
+            a = torch.empty(mib * 256 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+            b = torch.empty_like(a)
+            for _ in range(3):
+                if kind == "copyBuffer":
+                    b.copy_(a)
+                else:
+                    torch.mul(a, 1.0, out=b)
+            torch.cuda.synchronize()
+            del a, b
+        print("# copy calibration: 3 x 256 MiB device copies, 3 x 1 GiB elementwise copies", file=sys.stderr)
     bench(args)
     return 0
 

@@ -79,9 +79,10 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
                       demag_dtype dtype, void* setup_stream);
 
 /* Tensor-setup options; the spectrum is recomputed at once (synchronous).
- *  "far_cut": offsets with |o (.) d| / max(d) >= far_cut (cell-size units) use
- *             the moment series of the dipole kernel (default 40; 0 < v).
- *  "fg_cut":  offsets with Chebyshev distance <= fg_cut use the Newell f/g
+ *  "far_cut" (also "far_cutoff"): offsets with |o (.) d| / max(d) >= far_cut
+ *             (cell-size units) use the moment series of the dipole kernel
+ *             (default 40; 0 < v).
+ *  "fg_cut" (also "fg_cutoff"):  offsets with Chebyshev distance <= fg_cut use the Newell f/g
  *             closed form (default 1; integer >= 0); the rest of the near field
  *             uses Gauss-Legendre quadrature of the cell-average integral.
  *  "generic_kernels": 1 runs every pass on the generic (any-length)

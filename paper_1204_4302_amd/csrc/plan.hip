@@ -1171,10 +1171,10 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
 int demag_plan_set_option(demag_plan_t p, const char* key, double value) {
     if (!p || !key) return fail(DEMAG_EINVAL, "NULL plan or key");
     TensorBands b = p->bands;
-    if (!strcmp(key, "far_cut")) {
+    if (!strcmp(key, "far_cut") || !strcmp(key, "far_cutoff")) {
         if (!(value > 0) || std::isnan(value)) return fail(DEMAG_EINVAL, "far_cut must be > 0");
         b.far_cut = value;
-    } else if (!strcmp(key, "fg_cut")) {
+    } else if (!strcmp(key, "fg_cut") || !strcmp(key, "fg_cutoff")) {
         if (!(value >= 0) || value != std::floor(value) || value > 1e9)
             return fail(DEMAG_EINVAL, "fg_cut must be a non-negative integer");
         b.fg_cut = (int)value;

@@ -77,3 +77,19 @@ def test_energy_async_abi_equals_the_other_energy_calls(dtype):
     torch.cuda.synchronize()
     assert float(E_dev) == float(E_fe) == E_host
     plan.close()
+
+
+def test_cutoff_option_aliases_equal_the_short_names():
+    """"far_cutoff" / "fg_cutoff" set the same bands as "far_cut" / "fg_cut":
+    the spectra are bitwise equal."""
+    from paper_1204_4302_amd import Plan
+    shape = (12, 10, 6)
+    a = Plan(shape, CELL, torch.float64, far_cut=6, fg_cut=2)
+    b = Plan(shape, CELL, torch.float64)
+    b.set_option("far_cutoff", 6)
+    b.set_option("fg_cutoff", 2)
+    assert np.array_equal(a.spectrum(), b.spectrum())
+    c = Plan(shape, CELL, torch.float64)
+    assert not np.array_equal(a.spectrum(), c.spectrum())
+    for p in (a, b, c):
+        p.close()
