@@ -717,8 +717,10 @@ __global__ void __launch_bounds__(xy_max_threads<P>()) ky_inv(const cx<T>* __res
 // kP2TwLdsMax).  Power-of-two lengths in the paired form copy the tile's
 // tensor rows into LDS with 16-byte loads issued together with the data loads
 // and read each frequency's six values from LDS right before its product; the
-// split form at 4096 (FP32) loads them into registers up front, and the other
-// lengths load them after the forward transforms.
+// split form at 4096 (FP32) loads them into registers up front, and lengths
+// 3 * 2^a (24 values per component in a thread) load each frequency's six
+// values from memory right before its product, which keeps them within the
+// register file (loaded together after the forward transforms they spilled).
 template <typename T, int P>
 __host__ __device__ constexpr bool z_keep_twiddles() {
     return sizeof(T) == 4 && p2::is_pow2(P);
@@ -851,7 +853,8 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         if constexpr (kKeep) LT::template fft<-1, true>(v[comp], slab, t, tws);
         else run_fft<LT, -1, true>(v[comp], slab, t, twsrc);
     }
-    if constexpr (!kKeep && !kStage) load_tensor();
+    constexpr bool kLazy = !kPow2;  // 3 * 2^a: each frequency's six values loaded right before its product
+    if constexpr (!kKeep && !kStage && !kLazy) load_tensor();
     // H^ = Nhat(kx, ky, kz) M^ (Ms applied at the store).  Octant lookup with
     // parity signs: xy, yz odd in ky (negative for ky > Ly, i.e. s = 1); xz, yz
     // odd in kz, negative for kz > Lz.  For power-of-two lengths that is slot
@@ -863,6 +866,10 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         bool negz;
         if constexpr (kPow2) negz = LT::F::slot_out(j) >= LT::EPT / 2;
         else negz = LT::fout(t, j) > Lz;
+        if constexpr (kLazy && !kStage && !kKeep) {
+            const int kz = LT::fout(t, j);
+            bld6<T>(bt, trow + (kz <= Lz ? kz : P - kz) * FB, nt[j]);
+        }
         if constexpr (kStage) {
             int kzp;
             if constexpr (kPow2) {

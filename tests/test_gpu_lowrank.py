@@ -53,6 +53,9 @@ CASES = [
     ((2, 9, 7), (2e-9, 2e-9, 3e-9), 1, 3),          # two cells along x
     ((33, 17, 9), (2e-9, 2e-9, 3e-9), 0, 5),
     ((20, 20, 20), (1e-9, 1e-9, 1e-9), 1, 12),
+    ((14, 12, 10), (2e-9, 2e-9, 3e-9), 0, 16),      # the largest Tucker rank
+    ((14, 12, 10), (2e-9, 2e-9, 3e-9), 1, 33),      # Gram blocks past the rank
+    ((14, 12, 10), (2e-9, 2e-9, 3e-9), 1, 64),      # the largest CP rank
 ]
 
 
