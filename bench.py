@@ -515,6 +515,54 @@ def cpu_fft_reference(args, np, m_np, plan64, H64):
 BATCH_SIZES = [(32, 32, 32), (64, 64, 16), (96, 48, 8), (128, 128, 4), (48, 48, 48)]
 
 
+XGMI_LINK_GBS, XGMI_LINKS = 153.0, 7  # MI355X: point-to-point xGMI links per GPU
+
+
+def bench_shard_share(args, torch, np):
+    """One GPU's share of the headline grid sharded over G GPUs (the design:
+    z-slabs for the X and Y passes, kx-slabs for the fused Z pass, an
+    all-to-all of B2 before and after the Z pass), its kernels timed here at
+    their real shapes: the X and Y passes of a 256 x 256 x (64/G) slab, and
+    the fused Z pass over ceil(257/G) kx columns x 512 ky x 128 (the Z pass of
+    a 32 x 256 x 64 plan has exactly Kx = 33 such columns for G = 8).  The
+    all-to-alls are a model (bytes over the seven links), not a measurement;
+    no second GPU is used."""
+    from paper_1204_4302_amd import Plan, inputs
+    G = args.shard_share
+    nx, ny, nz = SHAPE
+    Kx = nx + 1  # padded x length 2 nx
+    if nz % G or (Kx + G - 1) // G != 33:
+        return {"note": f"modelled for G = 8 only (got {G})"}
+    times = {}
+    for name, shape in (("slab", (nx, ny, nz // G)), ("kx_slab", (32, ny, nz))):
+        plan = Plan(shape, CELL, torch.float32)
+        if not args.no_autotune:
+            plan.autotune()
+        m = torch.from_numpy(inputs.random_unit(shape, SEED_M)).to("cuda", torch.float32)
+        H = torch.empty_like(m)
+        for _ in range(args.warmup):
+            plan.field(m, MS, out=H)
+        plan.set_option("pass_timing", 200)
+        for _ in range(200):
+            plan.field(m, MS, out=H)
+        torch.cuda.synchronize()
+        times[name], _ = plan.pass_times()
+        plan.close()
+    local_ms = sum(times["slab"][k] for k in ("x_r2c", "y_fwd", "y_inv", "x_c2r")) + times["kx_slab"]["z_conv"]
+    i_b2 = 3 * Kx * (2 * ny) * nz * 8  # B2 bytes of the whole grid (FP32 complex)
+    a2a_bytes = i_b2 / G * (G - 1) / G  # one GPU sends (and receives) this much per exchange
+    a2a_ms = 1e3 * a2a_bytes / (XGMI_LINKS * XGMI_LINK_GBS * 1e9)
+    per_eval_ms = local_ms + 2 * a2a_ms
+    return {"gpus_modelled": G, "slab_passes_ms": {k: round(times["slab"][k], 4) for k in
+                                                   ("x_r2c", "y_fwd", "y_inv", "x_c2r")},
+            "kx_slab_z_conv_ms": round(times["kx_slab"]["z_conv"], 4),
+            "local_ms_per_eval": round(local_ms, 4), "all_to_all_bytes_per_gpu": int(a2a_bytes),
+            "all_to_all_ms_modelled": round(a2a_ms, 4),
+            "evals_per_s_modelled_no_overlap": round(1e3 / per_eval_ms, 1),
+            "note": "kernels measured on this GPU at one GPU's share; the two all-to-alls per evaluation are "
+                    "modelled (bytes / (7 links x 153 GB/s)), not overlapped; no multi-GPU run"}
+
+
 def bench_batch(args, torch, np):
     """96 independent grids of seeded uneven shapes (2 nm cubes, Ms = 8e5, FP32):
     one replay of the recorded batch graph vs 96 single-grid calls."""
@@ -698,6 +746,9 @@ def bench(args):
     if args.batch_steps > 0:
         out["batch"] = bench_batch(args, torch, np)
         print(f"# batch: {out['batch']}", file=sys.stderr, flush=True)
+    if args.shard_share > 0:
+        out["shard_share"] = bench_shard_share(args, torch, np)
+        print(f"# shard_share: {out['shard_share']}", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         H64 = results[torch.float64]["H"] if torch.float64 in results else r32["H"]
         base, err = cpu_baseline(m_np, args.cpu_seconds, r32["H"], H64)
@@ -856,6 +907,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="oracle sample budget")
     ap.add_argument("--batch-steps", type=int, default=50, help="replays of the 96-grid batch (0: skip)")
+    ap.add_argument("--shard-share", type=int, default=8,
+                    help="time one GPU's share of the headline grid sharded over this many GPUs (0: skip)")
     ap.add_argument("--sp-steps", type=int, default=200, help="scalar-potential evaluations (0: skip)")
     ap.add_argument("--tg-steps", type=int, default=10, help="tensor-grid evaluations (0: skip)")
     ap.add_argument("--llg-steps", type=int, default=100, help="LLG Heun steps (0: skip)")
