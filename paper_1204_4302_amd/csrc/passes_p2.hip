@@ -972,6 +972,33 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
     const Buf bt = make_buf(shat, (size_t)Kx * (Ly + 1) * 3 * cs * RB);
     const unsigned trow = ok ? (unsigned)((((size_t)kx * (Ly + 1) + kyp) * 3 * (Lz + 1)) * RB) : 0u;
     T sk[LT::EPT][3];
+    // kStage (as in kz_conv): the tile's kernel rows (kx, r0 .. r0 + Tx - 1)
+    // are one contiguous run, copied into LDS after the slabs with 16-byte
+    // loads; each frequency's three values are read from there before use
+    // (not in FP64 at 2048, where it spilled more registers than it saved)
+    constexpr bool kStage = kPow2 && 2 * LT::TP <= kP2MaxThreadsZ && (sizeof(T) == 4 || P <= 1024);
+    const T* tls = nullptr;
+    if constexpr (kStage) {
+        constexpr unsigned RowB = 3 * (Lz + 1) * RB;  // bytes per octant row
+        const int nthr = blockDim.x;
+        const int G = rows << lgTx;
+        const unsigned tb0 = (unsigned)(((size_t)kx * (Ly + 1) + r0) * RowB);
+        const unsigned tal = tb0 & ~15u;
+        const unsigned tmis = tb0 - tal;
+        const unsigned nbytes = (unsigned)min(Tx, Ly + 1 - r0) * RowB + tmis;
+        constexpr int NCH = ((int)RowB + 16 + 32 * LT::TP - 1) / (32 * LT::TP);
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        u4 ch[NCH];
+#pragma unroll
+        for (int q = 0; q < NCH; ++q) ch[q] = __builtin_amdgcn_raw_buffer_load_b128(bt.r, tal + (unsigned)(tid + q * nthr) * 16u, 0, 0);
+        unsigned char* sbase = (unsigned char*)lds + z_stage_offset<T, P>(G);
+        u4* dstl = (u4*)sbase;
+#pragma unroll
+        for (int q = 0; q < NCH; ++q)
+            if ((unsigned)(tid + q * nthr) * 16u < nbytes) dstl[tid + q * nthr] = ch[q];
+        __syncthreads();
+        tls = (const T*)(sbase + tmis) + (size_t)xi * 3 * (Lz + 1);
+    }
     auto load_kernel = [&]() {
 #pragma unroll
         for (int j = 0; j < LT::EPT; ++j) {
@@ -987,7 +1014,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
             for (int a = 0; a < 3; ++a) sk[j][a] = bldr<T>(bt, off, (unsigned)(a * cs * RB));
         }
     };
-    if constexpr (kKeep) load_kernel();
+    if constexpr (kKeep && !kStage) load_kernel();
     cx<T>* slab = lds + g * LT::PS;
     const cx<T>* twsrc = twt;
     if constexpr (!kKeep) {
@@ -1001,7 +1028,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
         if constexpr (kKeep) LT::template fft<-1, true>(v[comp], slab, t, tws);
         else run_fft<LT, -1, true>(v[comp], slab, t, twsrc);
     }
-    if constexpr (!kKeep) load_kernel();
+    if constexpr (!kKeep && !kStage) load_kernel();
     const T sy = s ? T(-1) : T(1);
     cx<T> w[LT::EPT];
 #pragma unroll
@@ -1009,6 +1036,12 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
         bool negz;
         if constexpr (kPow2) negz = LT::F::slot_out(j) >= LT::EPT / 2;
         else negz = LT::fout(t, j) > Lz;
+        if constexpr (kStage) {
+            const int k = LT::F::slot_out(j);
+            const int kzp = k < LT::EPT / 2 ? t + k * LT::TP : (LT::TP - 1 - t) + P - (k + 1) * LT::TP + 1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) sk[j][a] = tls[a * (Lz + 1) + kzp];
+        }
         const T ax = sk[j][0], ay = sy * sk[j][1], az = negz ? -sk[j][2] : sk[j][2];
         const cx<T> c = mk(ax * v[0][j].re + ay * v[1][j].re + az * v[2][j].re,
                            ax * v[0][j].im + ay * v[1][j].im + az * v[2][j].im);
@@ -1230,7 +1263,8 @@ hipError_t launch_z_sp_p2(int lgTx, int rows, int sched, hipStream_t st, cx<T>* 
     if (!p2_z_supported(P, sizeof(cx<T>)) || (rows != 1 && rows != 2)) return hipErrorInvalidValue;
     const int G = rows << lgTx;
     dim3 grid((unsigned)(Kx * ((rows == 2 ? Py / 2 + (1 << lgTx) : Py + (1 << lgTx) - 1) >> lgTx)));
-    const size_t lds = (size_t)G * p2_slab_elems(P) * sizeof(cx<T>) + p2_z_twiddle_lds_bytes(P, sizeof(cx<T>));
+    // slabs, twiddles and the staged kernel rows (fewer bytes than kz_conv's tensor rows)
+    const size_t lds = p2_z_lds_bytes(P, rows, lgTx, sizeof(cx<T>));
 #define CALLS(PP, SS) \
     if (hipError_t e_ = allow_lds(&kz_sp<T, PP, SS>, lds)) return e_; \
     hipLaunchKernelGGL((kz_sp<T, PP, SS>), grid, dim3(G * tpp<PP>()), lds, st, B2, shat, Ms, nz, Py, Kx, lgTx, rows, \
