@@ -272,13 +272,23 @@ __global__ void __launch_bounds__(256) k_lr_factors_mfma(int n1, int n2, int n3,
             if constexpr (NE > 0) aE[g] = *(const lr_f32x4*)(Esw + off);
             if constexpr (NO > 0) aO[g] = *(const lr_f32x4*)(Osw + off);
         }
-        __syncthreads();
-        for (int idx = tid; idx < kMfChunk * NB * 16; idx += blockDim.x) {
+        // the chunk's factor rows: every load issued before the first LDS store
+        constexpr int kPer = kMfChunk * NB * 16 / 256;
+        float uv[kPer];
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int idx = tid + 256 * e;
             const int kk = idx % kMfChunk, cl = idx / kMfChunk;
             int p = 0;
             const int s = col_of(cl >> 4, cl & 15, p);
             const int k = k0 + kk;
-            Us[kk][cl] = (s >= 0 && k < n) ? U[uoff + (size_t)k + (size_t)n * (p * r + s)] : 0.f;
+            uv[e] = (s >= 0 && k < n) ? U[uoff + (size_t)k + (size_t)n * (p * r + s)] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < kPer; ++e) {
+            const int idx = tid + 256 * e;
+            Us[idx % kMfChunk][idx / kMfChunk] = uv[e];
         }
         __syncthreads();
 #pragma unroll
