@@ -128,6 +128,45 @@ def bench_sp(args, torch, np, m_np, dm_value):
     return out
 
 
+def bench_energy_only(args, torch, np, m_np, dm_value):
+    """The energy alone on the same workload, FP32: X-R2C, Y and the fused Z
+    pass's forward half with the spectral sum of Re(M^H Nhat M) (no inverse
+    passes, no field), against the energy of a field evaluation."""
+    from paper_1204_4302_amd import Plan
+    plan = Plan(SHAPE, CELL, torch.float32)
+    if not args.no_autotune:
+        plan.autotune()
+    m = torch.from_numpy(m_np).to("cuda", torch.float32)
+    E = torch.empty((), dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.field_energy(m, MS, with_field=False, E_out=E)
+
+    for _ in range(args.warmup):
+        step()
+    k = args.energy_steps
+    secs = run_steps(step, k, torch, "energy_only")
+    e_alone = float(E.cpu())
+    _, e_field = plan.field_energy(m, MS)
+    e_field = float(e_field.cpu())
+    i = plan.info()
+    pb = pass_bytes(SHAPE, i["Px"], i["Py"], i["Pz"], i["Kx"], 4)
+    nx, ny, nz = SHAPE
+    B2 = 3 * i["Py"] * i["Kx"] * nz * 8
+    # X-R2C and Y as in a field evaluation; the Z pass reads B2 and the tensor
+    # octant and writes nothing but the partials
+    z_bytes = pb["z_conv"] - B2
+    nbytes = pb["x_r2c"] + pb["y_fwd"] + z_bytes
+    out = {"value": round(k / secs, 2), "unit": "energy evals/s", "ms_per_eval": round(1e3 * secs / k, 4),
+           "modelled_bytes_per_eval": nbytes, "achieved_GBs": round(nbytes * k / secs / 1e9, 1),
+           "roofline": hbm_roofline(nbytes * k, secs, "whole energy evaluation (three passes and the sum)"),
+           "speedup_over_field_evals": round(k / secs / dm_value, 3),
+           "rel_diff_vs_field_energy": abs(e_alone - e_field) / abs(e_field),
+           "step": "energy alone (three passes: X-R2C, Y, Z forward with the spectral quadratic form)"}
+    plan.close()
+    return out
+
+
 def bench_llg(args, torch, np, dm_value):
     """LLG driver on the same grid, FP32: explicit Heun steps with the DM field
     (two field evaluations and two elementwise kernels per step)."""
@@ -728,6 +767,9 @@ def bench(args):
         H64 = r64["H"]
         out["accuracy"] = {"f32_vs_f64_gpu_field": float(np.max(np.abs(r32["H"] - H64)) / np.max(np.abs(H64))),
                            "f32_vs_f64_gpu_energy": abs(r32["E"] - r64["E"]) / abs(r64["E"])}
+    if args.energy_steps > 0:
+        out["energy_only"] = bench_energy_only(args, torch, np, m_np, value)
+        print(f"# energy_only: {out['energy_only']}", file=sys.stderr, flush=True)
     if args.sp_steps > 0:
         out["sp"] = bench_sp(args, torch, np, m_np, value)
         print(f"# sp: {out['sp']}", file=sys.stderr, flush=True)
@@ -910,6 +952,7 @@ def main():
     ap.add_argument("--shard-share", type=int, default=8,
                     help="time one GPU's share of the headline grid sharded over this many GPUs (0: skip)")
     ap.add_argument("--sp-steps", type=int, default=200, help="scalar-potential evaluations (0: skip)")
+    ap.add_argument("--energy-steps", type=int, default=200, help="energy-alone evaluations (0: skip)")
     ap.add_argument("--tg-steps", type=int, default=10, help="tensor-grid evaluations (0: skip)")
     ap.add_argument("--llg-steps", type=int, default=100, help="LLG Heun steps (0: skip)")
     ap.add_argument("--lowrank-steps", type=int, default=200, help="low-rank TG evaluations (0: skip)")

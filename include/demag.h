@@ -91,8 +91,9 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
  *             shapes to their defaults.  DEMAG_EUNSUPPORTED (plan unchanged)
  *             when the generic Z pass cannot hold the padded z length.
  *  "pass_timing": K > 0 records HIP events around every pass of the next
- *             evaluations on their own stream (a ring of K evaluations; 0 turns
- *             it off); read the averages with demag_plan_pass_times.
+ *             field evaluations on their own stream (a ring of K evaluations;
+ *             0 turns it off; evaluations of the energy alone are not
+ *             recorded); read the averages with demag_plan_pass_times.
  *  "radix_schedule": S = 0, 1 or 2 sets the radix schedule of every pass on
  *             the register kernels whose length has schedule S (the others
  *             take 0); launch shapes are kept.  The schedules of a length
@@ -127,7 +128,13 @@ int demag_field_adjoint(demag_plan_t plan, const void* gH, double Ms, void* gm, 
 
 /* Field and energy in one evaluation: H (may be NULL: energy only) and
  * E_dev, a DEVICE double receiving E = -(mu0/2) Ms V sum m.H (Sec. 2).
- * FP32 plans form m.H in FP32 and accumulate in FP64.  Asynchronous. */
+ * FP32 plans form m.H in FP32 and accumulate in FP64.  With H == NULL and the
+ * register kernel on the Z pass (power-of-two padded z up to 4096; 3 * 2^a in
+ * FP32), the field is not formed: after the forward X and Y passes the Z pass
+ * transforms m and sums Re(M^H Nhat M) over the spectrum (Parseval's identity
+ * on the padded grid, where m is zero off the grid equals sum m.H), three
+ * passes instead of five; the result agrees with the field's m.H sum to
+ * rounding (FP32 products, FP64 sums).  Asynchronous. */
 int demag_field_energy(demag_plan_t plan, const void* m, double Ms, void* H, double* E_dev, void* stream);
 
 /* Gradient of the energy of Sec. 2 with respect to m, from the field H that
@@ -140,9 +147,11 @@ int demag_field_energy(demag_plan_t plan, const void* m, double Ms, void* H, dou
 int demag_energy_gradient(demag_plan_t plan, const void* H, double Ms, const double* gE_dev, void* gm, int accumulate,
                           void* stream);
 
-/* Energy only, result to a HOST double; synchronises `stream`. */
+/* Energy only (demag_field_energy with H == NULL), result to a HOST double;
+ * synchronises `stream`. */
 int demag_energy(demag_plan_t plan, const void* m, double Ms, double* E_host, void* stream);
-/* Energy only, result to a DEVICE double; asynchronous. */
+/* Energy only (demag_field_energy with H == NULL), result to a DEVICE double;
+ * asynchronous. */
 int demag_energy_async(demag_plan_t plan, const void* m, double Ms, double* E_dev, void* stream);
 
 /* Copy the stored tensor spectrum (plan precision) to HOST memory `out`,

@@ -133,6 +133,9 @@ hipError_t launch_z_conv_p2(int lgTx, int rows, int sched, hipStream_t, cx<T>* B
 // scalar-potential method: fused Z pass (3 components in, Ms phi out in
 // component 0 of B2), register-kernel lengths only
 template <typename T>
+hipError_t launch_z_energy_p2(int lgTx, int rows, int sched, hipStream_t, cx<T>* B2, const T* nhat, int nz, int Py,
+                              int Kx, int P, const cx<T>* twt, double* epart, int* nparts);
+template <typename T>
 hipError_t launch_z_sp_p2(int lgTx, int rows, int sched, hipStream_t, cx<T>* B2, const T* shat, T Ms, int nz, int Py,
                           int Kx, int P, const cx<T>* twt);
 

@@ -740,10 +740,11 @@ __host__ __device__ constexpr size_t z_stage_offset(int G) {
     return ((size_t)G * p2::Len<P>::PS * sizeof(cx<T>) + tw + 15) & ~(size_t)15;
 }
 
-template <typename T, int P, int S>
+template <typename T, int P, int S, bool EN = false>
 __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2, const T* __restrict__ nhat, T Ms, int nz,
                                                 int Py, int Kx, int lgTx, int rows, int nxcd,
-                                                const cx<T>* __restrict__ twt, BatchIO bio) {
+                                                const cx<T>* __restrict__ twt, BatchIO bio,
+                                                double* __restrict__ epart = nullptr) {
     using LT = p2::Len<P, S>;
     constexpr bool kPow2 = p2::is_pow2(P);
     constexpr bool kKeep = z_keep_twiddles<T, P>();
@@ -861,6 +862,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
     // k >= EPT/2 (a compile-time property) except kz = Lz itself, where the odd
     // components are exactly zero.
     const T sy = s ? T(-1) : T(1);
+    double eacc = 0.0;  // EN: sum over this thread's frequencies of Re(M^H N M)
 #pragma unroll
     for (int j = 0; j < LT::EPT; ++j) {
         bool negz;
@@ -893,9 +895,35 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         const T nxz = negz ? -nt[j][4] : nt[j][4];
         const T nyz = negz ? -(sy * nt[j][5]) : sy * nt[j][5];
         const cx<T> mx = v[0][j], my = v[1][j], mz = v[2][j];
-        v[0][j] = mk(nxx * mx.re + nxy * my.re + nxz * mz.re, nxx * mx.im + nxy * my.im + nxz * mz.im);
-        v[1][j] = mk(nxy * mx.re + nyy * my.re + nyz * mz.re, nxy * mx.im + nyy * my.im + nyz * mz.im);
-        v[2][j] = mk(nxz * mx.re + nyz * my.re + nzz * mz.re, nxz * mx.im + nyz * my.im + nzz * mz.im);
+        const cx<T> hx = mk(nxx * mx.re + nxy * my.re + nxz * mz.re, nxx * mx.im + nxy * my.im + nxz * mz.im);
+        const cx<T> hy = mk(nxy * mx.re + nyy * my.re + nyz * mz.re, nxy * mx.im + nyy * my.im + nyz * mz.im);
+        const cx<T> hz = mk(nxz * mx.re + nyz * my.re + nzz * mz.re, nxz * mx.im + nyz * my.im + nzz * mz.im);
+        if constexpr (EN) {
+            eacc += (double)(mx.re * hx.re + mx.im * hx.im + my.re * hy.re + my.im * hy.im + mz.re * hz.re +
+                             mz.im * hz.im);
+        } else {
+            v[0][j] = hx;
+            v[1][j] = hy;
+            v[2][j] = hz;
+        }
+    }
+    if constexpr (EN) {
+        // Parseval: sum_i m_i . (N * m)_i over the padded grid (m zero off the
+        // grid) = sum over the full spectrum of Re(M^H Nhat M); the stored half
+        // (kx <= Px/2) counts kx = 0 and kx = Px/2 once and the rest twice
+        // (Hermitian symmetry).  Per workgroup one FP64 partial, summed in a
+        // fixed order (a tree over the threads in LDS; the thread count is a
+        // power of two).
+        __syncthreads();  // the slabs are no longer read: reuse them
+        double* red = (double*)lds;
+        red[tid] = ok ? eacc * (kx == 0 || kx == Kx - 1 ? 1.0 : 2.0) : 0.0;
+        __syncthreads();
+        for (int w = (int)blockDim.x >> 1; w > 0; w >>= 1) {
+            if (tid < w) red[tid] += red[tid + w];
+            __syncthreads();
+        }
+        if (tid == 0) epart[blockIdx.x] = red[0];
+        return;
     }
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
@@ -1256,6 +1284,39 @@ hipError_t launch_z_conv_p2(int lgTx, int rows, int sched, hipStream_t st, cx<T>
     return hipGetLastError();
 }
 
+// The fused Z pass's forward half with the energy's quadratic form in place of
+// the product and the inverse transforms: one FP64 partial per workgroup into
+// epart (*nparts of them; B2 is only read).
+template <typename T>
+hipError_t launch_z_energy_p2(int lgTx, int rows, int sched, hipStream_t st, cx<T>* B2, const T* nhat, int nz, int Py,
+                              int Kx, int P, const cx<T>* twt, double* epart, int* nparts) {
+    if (!twt || !epart || !nparts) return hipErrorInvalidValue;
+    if (!p2_z_supported(P, sizeof(cx<T>)) || (rows != 1 && rows != 2)) return hipErrorInvalidValue;
+    if (rows != (2 * p2_threads_per_pencil(P) <= kP2MaxThreadsZ ? 2 : 1)) return hipErrorInvalidValue;
+    const int G = rows << lgTx;
+    dim3 grid((unsigned)(Kx * ((rows == 2 ? Py / 2 + (1 << lgTx) : Py + (1 << lgTx) - 1) >> lgTx)));
+    *nparts = (int)grid.x;
+    // the slabs (P values per pencil) hold the reduction's one double per thread
+    const size_t lds = p2_z_lds_bytes(P, rows, lgTx, sizeof(cx<T>));
+    const BatchIO none;
+#define CALLS(PP, SS) \
+    if (hipError_t e_ = allow_lds(&kz_conv<T, PP, SS, true>, lds)) return e_; \
+    hipLaunchKernelGGL((kz_conv<T, PP, SS, true>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, T(1), nz, Py, Kx, \
+                       lgTx, rows, kXcds, twt, none, epart)
+#define CALL(PP) DEMAG_P2_SCHED(PP, CALLS)
+    if constexpr (sizeof(T) == 4) {
+        DEMAG_P2_SWITCH(P, CALL)
+    } else {
+        switch (P) {
+            DEMAG_P2_CASES_POW2(CALL)
+        default: return hipErrorInvalidValue;
+        }
+    }
+#undef CALL
+#undef CALLS
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_z_sp_p2(int lgTx, int rows, int sched, hipStream_t st, cx<T>* B2, const T* shat, T Ms, int nz,
                           int Py, int Kx, int P, const cx<T>* twt) {
@@ -1324,7 +1385,9 @@ std::vector<cx<T>> p2_thread_twiddles(int P, int sched, const std::vector<cx<T>>
     template hipError_t launch_z_conv_p2<T>(int, int, int, hipStream_t, cx<T>*, const T*, T, int, int, int, int,  \
                                             const cx<T>*, const BatchIO&);                                         \
     template hipError_t launch_z_sp_p2<T>(int, int, int, hipStream_t, cx<T>*, const T*, T, int, int, int, int,    \
-                                          const cx<T>*);
+                                          const cx<T>*);                                                           \
+    template hipError_t launch_z_energy_p2<T>(int, int, int, hipStream_t, cx<T>*, const T*, int, int, int, int,     \
+                                              const cx<T>*, double*, int*);
 
 DEMAG_P2_INSTANTIATE(float)
 DEMAG_P2_INSTANTIATE(double)

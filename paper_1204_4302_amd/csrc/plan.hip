@@ -888,8 +888,41 @@ int run_sp_field(demag_plan_s* p, const T* m, double Ms, T* H, double* E_dev, hi
 }
 
 
+// The energy alone (no field): X-R2C, Y, then the fused Z pass's forward half
+// with the quadratic form of Parseval's identity in place of the product and
+// the inverse passes (sum_i m_i . (N * m)_i = sum_k Re(M^H Nhat M) on the
+// padded grid, m being zero off the grid), partials summed in a fixed order.
+// Three passes instead of five; B2 is only read by the third.
+template <typename T>
+int run_energy_only(demag_plan_s* p, const PassCfgs& c, const T* m, double Ms, double* E_dev, hipStream_t st) {
+    static const char* const kPassNames[3] = {"x_r2c", "y_fwd", "z_energy"};
+    {
+        const Range range_(kPassNames[0]);
+        HIP_TRY(launch_pass<T>(p, 0, c.xf, st, m, Ms, nullptr, nullptr, nullptr, 0));
+    }
+    {
+        const Range range_(kPassNames[1]);
+        HIP_TRY(launch_pass<T>(p, 1, c.yf, st, nullptr, Ms, nullptr, nullptr, nullptr, 0));
+    }
+    const LaunchCfg& z = c.zc;
+    const int sc = z.sched >= 0 && z.sched < 3 ? z.sched : 0;
+    int nparts = 0;
+    {
+        const Range range_(kPassNames[2]);
+        HIP_TRY(launch_z_energy_p2<T>(z.t0, z.t1, sc, st, (cx<T>*)p->B2, (const T*)p->nhat, p->n[2], p->P[1], p->Kx,
+                                      p->P[2], (const cx<T>*)p->twt[2][sc], p->partials, &nparts));
+    }
+    if (nparts > p->npartials) return fail(DEMAG_EHIP, "energy partials exceed their buffer");
+    const double V = p->d[0] * p->d[1] * p->d[2];
+    HIP_TRY(launch_energy_reduce(st, p->partials, nparts, -0.5 * kMu0 * Ms * Ms * V, E_dev));
+    return DEMAG_OK;
+}
+
 int dispatch_field(demag_plan_s* p, const void* m, double Ms, void* H, double* E_dev, int accumulate,
                    hipStream_t st) {
+    if (!H && E_dev && p->cfg.zc.p2 && !accumulate)
+        return p->dtype == DEMAG_F32 ? run_energy_only<float>(p, p->cfg, (const float*)m, Ms, E_dev, st)
+                                     : run_energy_only<double>(p, p->cfg, (const double*)m, Ms, E_dev, st);
     if (p->dtype == DEMAG_F32)
         return run_field<float>(p, p->cfg, (const float*)m, Ms, (float*)H, (const float*)m, E_dev, accumulate, st);
     return run_field<double>(p, p->cfg, (const double*)m, Ms, (double*)H, (const double*)m, E_dev, accumulate, st);
@@ -1140,8 +1173,10 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
     alloc(&p->B1, nB1 * cb, "spectrum scratch B1");
     alloc(&p->B2, nB2 * cb, "spectrum scratch B2");
     alloc(&p->nhat, nH * rb, "tensor spectrum");
-    // upper bound: X-inverse tiles of >= 2 rows; gradient workgroups (SP, TG)
-    p->npartials = (int)std::max<long>(3L * nz * ((ny + 1) / 2), sp_gradient_tiles(nx, ny, nz, 1));
+    // upper bound: X-inverse tiles of >= 2 rows; gradient workgroups (SP, TG);
+    // fused-Z workgroups of the energy alone (at most Kx Py)
+    p->npartials = (int)std::max<long>(std::max<long>(3L * nz * ((ny + 1) / 2), sp_gradient_tiles(nx, ny, nz, 1)),
+                                       (long)Kx * P[1]);
     alloc((void**)&p->partials, (size_t)p->npartials * sizeof(double), "energy partials");
     alloc((void**)&p->e_dev, sizeof(double), "energy scalar");
     p->scratch_bytes = (nB1 + nB2) * cb;

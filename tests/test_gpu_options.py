@@ -65,6 +65,9 @@ def test_pass_timing_counts_and_leaves_results_unchanged():
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
 def test_energy_async_abi_equals_the_other_energy_calls(dtype):
+    """demag_energy_async and demag_energy (the energy alone: the Z pass's
+    spectral sum) agree bit for bit, and with the energy of
+    demag_field_energy (the sum of m.H over the grid) to rounding."""
     from paper_1204_4302_amd import Plan, _lib
     plan = Plan(SHAPE, CELL, dtype)
     m = torch.from_numpy(inputs.random_unit(SHAPE, 6)).to("cuda", dtype)
@@ -75,7 +78,9 @@ def test_energy_async_abi_equals_the_other_energy_calls(dtype):
     _lib.call("demag_energy_async", plan._h, ctypes.c_void_p(m.data_ptr()), float(MS),
               ctypes.c_void_p(E_dev.data_ptr()), stream)
     torch.cuda.synchronize()
-    assert float(E_dev) == float(E_fe) == E_host
+    assert float(E_dev) == E_host
+    tol = 1e-12 if dtype == torch.float64 else 1e-5
+    assert abs(E_host - float(E_fe)) <= tol * abs(float(E_fe))
     plan.close()
 
 
