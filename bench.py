@@ -932,8 +932,9 @@ def traffic_summary(fetch_dir, write_dir, out_path, command):
         scaled = (fv * f_fetch + wv * f_write) * 1024.0 if (f_fetch and f_write) else None
         lines.append(f"  {key[0][:40]:40s} {key[1]:9d} {fv:11.1f} {wv:11.1f} "
                      f"{(scaled or 0) / 1e6:10.1f}")
-        if key[0].startswith("kz_conv<float"):
-            zconv = scaled
+        # the headline's fused Z pass: the largest FP32 field (not energy-alone) launch
+        if key[0].startswith("kz_conv<float") and not key[0].endswith("true>") and scaled is not None:
+            zconv = max(zconv or 0.0, scaled)
     if zconv is not None:
         lines.append(f"traffic_bytes_per_launch = {zconv}")
     with open(out_path, "w") as f:
