@@ -363,6 +363,11 @@ int demag_batch_autotune(demag_batch_t batch, void* stream);
 int demag_batch_launch(demag_batch_t batch, void* stream);
 int demag_batch_destroy(demag_batch_t batch);
 
+/* Test hook (environment): while DEMAG_FAIL_ALLOC_AT=k is set, the k-th
+ * device allocation of the library counted since the value last changed
+ * fails as out of memory (DEMAG_ENOMEM), so that callers can exercise every
+ * failure path of plan creation and set-up; unset, allocations are plain. */
+
 /* Last error message of the calling thread ("" if none). */
 const char* demag_last_error(void);
 

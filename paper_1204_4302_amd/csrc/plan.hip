@@ -43,6 +43,31 @@ struct Range {
 }  // namespace
 
 // ---------------------------------------------------------------------------
+// device allocation with a test hook: while DEMAG_FAIL_ALLOC_AT=k is set, the
+// k-th allocation counted since the variable last changed fails as out of
+// memory (to exercise every failure path of plan creation and set-up)
+namespace {
+template <typename T>
+hipError_t dev_malloc(T** ptr, size_t bytes) {
+    static std::mutex mu;
+    static std::string seen;
+    static long count = 0;
+    if (const char* e = std::getenv("DEMAG_FAIL_ALLOC_AT")) {
+        std::lock_guard<std::mutex> lock(mu);
+        if (seen != e) {
+            seen = e;
+            count = 0;
+        }
+        if (++count == std::atol(e)) {
+            *ptr = nullptr;
+            return hipErrorOutOfMemory;
+        }
+    }
+    return hipMalloc((void**)ptr, bytes);
+}
+}  // namespace
+
+// ---------------------------------------------------------------------------
 // errors
 namespace {
 thread_local std::string g_last_error;
@@ -425,7 +450,7 @@ PassCfgs generic_cfgs(const demag_plan_s* p) {
 
 template <typename T>
 int upload(void** dst, const std::vector<T>& v) {
-    HIP_TRY(hipMalloc(dst, v.size() * sizeof(T)));
+    HIP_TRY(dev_malloc(dst, v.size() * sizeof(T)));
     HIP_TRY(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return DEMAG_OK;
 }
@@ -458,7 +483,7 @@ void reduced_cell(const double d[3], double dt[3]) {
 
 int compute_octant(demag_plan_s* p, hipStream_t st, SetupBufs& sb) {
     const size_t ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
-    HIP_TRY(hipMalloc(&sb.Noct, 6 * ncell * sizeof(double)));
+    HIP_TRY(dev_malloc(&sb.Noct, 6 * ncell * sizeof(double)));
     std::vector<double> gx, gw;
     gauss_legendre(p->bands.gl_q, gx, gw);
     int rc = upload((void**)&sb.glx, gx);
@@ -478,9 +503,9 @@ int setup_spectrum(demag_plan_s* p, hipStream_t st) {
     if (rc) return rc;
     const int Px = p->P[0], Py = p->P[1], Pz = p->P[2], Kx = p->Kx;
     const size_t nA = (size_t)Px * Py * Pz, nS = (size_t)Pz * Kx * Py;
-    HIP_TRY(hipMalloc(&sb.A, nA * sizeof(double)));
-    HIP_TRY(hipMalloc(&sb.B1, nS * sizeof(cx<double>)));
-    HIP_TRY(hipMalloc(&sb.B2, nS * sizeof(cx<double>)));
+    HIP_TRY(dev_malloc(&sb.A, nA * sizeof(double)));
+    HIP_TRY(dev_malloc(&sb.B1, nS * sizeof(cx<double>)));
+    HIP_TRY(dev_malloc(&sb.B2, nS * sizeof(cx<double>)));
     for (int k = 0; k < 3; ++k) {
         rc = upload(&sb.tw[k], twiddles<double>(p->P[k]));
         if (rc) return rc;
@@ -506,7 +531,7 @@ int setup_spectrum(demag_plan_s* p, hipStream_t st) {
 // length: S_physical = h S_reduced, h the largest cell edge).
 int compute_sp_octant(demag_plan_s* p, hipStream_t st, SetupBufs& sb) {
     const size_t ncell = (size_t)p->n[0] * p->n[1] * p->n[2];
-    HIP_TRY(hipMalloc(&sb.Noct, 3 * ncell * sizeof(double)));
+    HIP_TRY(dev_malloc(&sb.Noct, 3 * ncell * sizeof(double)));
     std::vector<double> gx, gw;
     gauss_legendre(p->bands.gl_q, gx, gw);
     int rc = upload((void**)&sb.glx, gx);
@@ -526,9 +551,9 @@ int setup_sp_spectrum(demag_plan_s* p, hipStream_t st) {
     if (rc) return rc;
     const int Px = p->P[0], Py = p->P[1], Pz = p->P[2], Kx = p->Kx;
     const size_t nA = (size_t)Px * Py * Pz, nS = (size_t)Pz * Kx * Py;
-    HIP_TRY(hipMalloc(&sb.A, nA * sizeof(double)));
-    HIP_TRY(hipMalloc(&sb.B1, nS * sizeof(cx<double>)));
-    HIP_TRY(hipMalloc(&sb.B2, nS * sizeof(cx<double>)));
+    HIP_TRY(dev_malloc(&sb.A, nA * sizeof(double)));
+    HIP_TRY(dev_malloc(&sb.B1, nS * sizeof(cx<double>)));
+    HIP_TRY(dev_malloc(&sb.B2, nS * sizeof(cx<double>)));
     for (int k = 0; k < 3; ++k) {
         rc = upload(&sb.tw[k], twiddles<double>(p->P[k]));
         if (rc) return rc;
@@ -597,7 +622,7 @@ int setup_tg(demag_plan_s* p, hipStream_t st, double step) {
     int rc = DEMAG_OK;
     auto alloc = [&](void** ptr, size_t bytes, const char* what) {
         if (rc) return;
-        if (hipMalloc(ptr, bytes) != hipSuccess) {
+        if (dev_malloc(ptr, bytes) != hipSuccess) {
             (void)hipGetLastError();
             *ptr = nullptr;
             rc = fail(DEMAG_ENOMEM, "cannot allocate %zu bytes for the tensor-grid %s", bytes, what);
@@ -716,7 +741,7 @@ int setup_lr(demag_plan_s* p, hipStream_t st, double step) {
     int rc = DEMAG_OK;
     auto alloc = [&](void** ptr, size_t bytes, const char* what) {
         if (rc) return;
-        if (hipMalloc(ptr, bytes) != hipSuccess) {
+        if (dev_malloc(ptr, bytes) != hipSuccess) {
             (void)hipGetLastError();
             *ptr = nullptr;
             rc = fail(DEMAG_ENOMEM, "cannot allocate %zu bytes for the low-rank %s", bytes, what);
@@ -1035,7 +1060,7 @@ int run_compress(demag_plan_s* p, hipStream_t st, int format, int r, int sweeps,
     const size_t dbl = 4 * rr + 1024 + 1 + 6;
     void* buf = nullptr;
     const size_t bytes = elems * sizeof(T) + dbl * sizeof(double) + 64;
-    if (hipMalloc(&buf, bytes) != hipSuccess) {
+    if (dev_malloc(&buf, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return fail(DEMAG_ENOMEM, "cannot allocate %zu bytes of ALS scratch", bytes);
     }
@@ -1164,7 +1189,7 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
     int rc = DEMAG_OK;
     auto alloc = [&](void** ptr, size_t bytes, const char* what) {
         if (rc) return;
-        if (hipMalloc(ptr, bytes) != hipSuccess) {
+        if (dev_malloc(ptr, bytes) != hipSuccess) {
             (void)hipGetLastError();
             *ptr = nullptr;
             rc = fail(DEMAG_ENOMEM, "cannot allocate %zu bytes for %s", bytes, what);
@@ -1385,7 +1410,7 @@ int demag_sp_prepare(demag_plan_t p, void* stream) {
     int rc = enter(p, st);
     if (rc) return rc;
     const size_t bytes = (size_t)(p->P[1] / 2 + 1) * 3 * p->Kx * (p->P[2] / 2 + 1) * rb;
-    if (hipMalloc(&p->shat, bytes) != hipSuccess) {
+    if (dev_malloc(&p->shat, bytes) != hipSuccess) {
         (void)hipGetLastError();
         p->shat = nullptr;
         return fail(DEMAG_ENOMEM, "cannot allocate %zu bytes for the scalar-potential spectrum", bytes);
@@ -1539,7 +1564,7 @@ int demag_tg_lowrank_field(demag_plan_t p, int format, int rank, const void* cor
             g->bytes -= g->w_bytes;
             g->W = nullptr;
             g->w_bytes = 0;
-            if (hipMalloc(&g->W, want) != hipSuccess) {
+            if (dev_malloc(&g->W, want) != hipSuccess) {
                 (void)hipGetLastError();
                 g->W = nullptr;
                 return fail(DEMAG_ENOMEM, "cannot allocate %zu bytes of low-rank expansion scratch", want);
@@ -1557,7 +1582,7 @@ int demag_tg_lowrank_field(demag_plan_t p, int format, int rank, const void* cor
             g->bytes -= g->gram_bytes;
             g->gram = nullptr;
             g->gram_bytes = 0;
-            if (hipMalloc((void**)&g->gram, want) != hipSuccess) {
+            if (dev_malloc((void**)&g->gram, want) != hipSuccess) {
                 (void)hipGetLastError();
                 g->gram = nullptr;
                 return fail(DEMAG_ENOMEM, "cannot allocate %zu bytes for the low-rank Gram matrices", want);
@@ -1862,7 +1887,7 @@ int autotune_impl(demag_plan_s* p, hipStream_t st) {
         (void)hipFree(m);
         (void)hipFree(H);
     };
-    if (hipMalloc(&m, nvec * sizeof(T)) != hipSuccess || hipMalloc(&H, nvec * sizeof(T)) != hipSuccess) {
+    if (dev_malloc(&m, nvec * sizeof(T)) != hipSuccess || dev_malloc(&H, nvec * sizeof(T)) != hipSuccess) {
         (void)hipGetLastError();
         release();
         return fail(DEMAG_ENOMEM, "autotune: cannot allocate %zu bytes of input and output", 2 * nvec * sizeof(T));
@@ -2174,7 +2199,7 @@ extern "C" int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans,
         for (int k = 0; k < n; ++k) host_lists.push_back(plans[mem[k]]->B2);
     }
     int rc = DEMAG_OK;
-    if (hipMalloc(&b->dev_lists, host_lists.size() * sizeof(void*)) != hipSuccess) {
+    if (dev_malloc(&b->dev_lists, host_lists.size() * sizeof(void*)) != hipSuccess) {
         (void)hipGetLastError();
         b->dev_lists = nullptr;
         rc = fail(DEMAG_ENOMEM, "cannot allocate batch pointer lists");
