@@ -2264,7 +2264,10 @@ extern "C" int demag_batch_autotune(demag_batch_t b, void* stream) {
         }
     }
     b->lanes = best_l;
-    if (!rc) rc = record_graph(b);
+    {  // re-record in every case: a failed timing may have left no graph
+        const int r2 = record_graph(b);
+        if (!rc) rc = r2;
+    }
     for (auto p : b->plans) {
         int r2 = leave(p, st);
         if (!rc) rc = r2;
