@@ -62,3 +62,39 @@ def test_field_energy_and_adjoint_in_a_captured_graph(dtype):
     assert torch.equal(H2, -H_ref)
     del graph
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64], ids=["f32", "f64"])
+def test_energy_alone_in_a_captured_graph(dtype):
+    """The energy without a field (X-R2C, Y and the Z pass's spectral sum,
+    then the partials' reduction) captured and replayed: every replay equals
+    the eager energy bit for bit."""
+    from paper_1204_4302_amd import Plan
+    plan = Plan(SHAPE, CELL, dtype)
+    m = torch.from_numpy(inputs.random_unit(SHAPE, 9)).to("cuda", dtype)
+    _, E_ref = plan.field_energy(m, MS, with_field=False)
+    torch.cuda.synchronize()
+    E = torch.empty((), dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.field_energy(m, MS, with_field=False, E_out=E)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.field_energy(m, MS, with_field=False, E_out=E)
+    for rep in range(4):
+        E.zero_()
+        busy = (m * float(rep + 2)).sum()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert float(E) == float(E_ref), f"replay {rep}"
+        del busy
+    m.mul_(2.0)  # quadratic: the next replay sees the new input
+    graph.replay()
+    torch.cuda.synchronize()
+    assert abs(float(E) - 4.0 * float(E_ref)) <= 1e-12 * abs(float(E_ref))
+    del graph
+    plan.close()
