@@ -357,10 +357,12 @@ def test_cell_scale_invariance(dtype):
 
 
 # padded z: 6 (3 * 2^a; FP64 on the generic Z pass), 128, 24, 4096 (split
-# form), 10 (generic); padded x even and odd multiples of the Nyquist weight
+# form), 10 (generic), 2 (one cell along z); one cell, and one cell along x
+# (padded x 2: every kx is 0 or the Nyquist frequency)
 ENERGY_ONLY = [((24, 17, 3), (1.95e-9, 1.95e-9, 0.75e-9)), ((16, 8, 64), (2e-9, 2e-9, 3e-9)),
                ((9, 6, 12), (2e-9, 2e-9, 2e-9)), ((2, 2, 2048), (2e-9, 2e-9, 1e-9)),
-               ((13, 7, 5), (2e-9, 3e-9, 2e-9))]
+               ((13, 7, 5), (2e-9, 3e-9, 2e-9)), ((7, 5, 1), (2e-9, 2e-9, 2e-9)),
+               ((1, 1, 1), (2e-9, 2e-9, 2e-9)), ((1, 6, 4), (2e-9, 2e-9, 2e-9))]
 
 
 @pytest.mark.parametrize("shape,cell", ENERGY_ONLY, ids=lambda v: str(v))
