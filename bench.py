@@ -270,9 +270,9 @@ def bench_lowrank(args, torch, np, dm_value):
             compressed()
             dense()
         k = args.lowrank_steps
-        sc = run_steps(compressed, k, torch, "lowrank")
+        sc = run_steps(compressed, k, torch, f"lowrank_{name}")
         kd = max(1, k // 10)
-        sd = run_steps(dense, kd, torch, "lowrank_dense")
+        sd = run_steps(dense, kd, torch, f"lowrank_dense_{name}")
         # algorithmic bytes of the compressed evaluation: per axis q and node
         # the even and the odd Gaussian matrix (n_q x n_q each, read once for
         # all three components), the magnetization factors and core in, and
