@@ -219,12 +219,21 @@ __device__ __forceinline__ cx<T> bld(Buf b, unsigned off, unsigned soff = 0) {
         return mk(v.x, v.y);
     }
 }
+// Cache policy of the staged (16-byte) loads of the tensor and kernel
+// spectra of a single evaluation: non-temporal (read once per evaluation,
+// they would otherwise displace the spectrum that the next pass reads from
+// the 256 MB memory-side cache; the fused Z pass's TNT instances).  The
+// members of a batch group share one tensor spectrum, which they re-read from
+// the caches: there the loads are plain, and so are the per-frequency loads
+// of the unstaged forms (split form, 3 * 2^a).
+constexpr int kNt = 2;
+
 template <typename T>
-__device__ __forceinline__ T bldr(Buf b, unsigned off, unsigned soff = 0) {
+__device__ __forceinline__ T bldr(Buf b, unsigned off, unsigned soff = 0) {  // (kernel spectrum: streamed)
     if constexpr (sizeof(T) == 4) {
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(b.r, off, soff, 0));
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(b.r, off, soff, kNt));
     } else {
-        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(b.r, off, soff, 0));
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(b.r, off, soff, kNt));
     }
 }
 template <typename T>
@@ -740,7 +749,7 @@ __host__ __device__ constexpr size_t z_stage_offset(int G) {
     return ((size_t)G * p2::Len<P>::PS * sizeof(cx<T>) + tw + 15) & ~(size_t)15;
 }
 
-template <typename T, int P, int S, bool EN = false>
+template <typename T, int P, int S, bool EN = false, bool TNT = false>
 __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2, const T* __restrict__ nhat, T Ms, int nz,
                                                 int Py, int Kx, int lgTx, int rows, int nxcd,
                                                 const cx<T>* __restrict__ twt, BatchIO bio,
@@ -830,7 +839,8 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
         u4 ch[NCH];
 #pragma unroll
-        for (int q = 0; q < NCH; ++q) ch[q] = __builtin_amdgcn_raw_buffer_load_b128(bt.r, tal + (unsigned)(tid + q * nthr) * 16u, 0, 0);
+        for (int q = 0; q < NCH; ++q)
+            ch[q] = __builtin_amdgcn_raw_buffer_load_b128(bt.r, tal + (unsigned)(tid + q * nthr) * 16u, 0, TNT ? kNt : 0);
         unsigned char* sbase = (unsigned char*)lds + z_stage_offset<T, P>(G);
         u4* dstl = (u4*)sbase;
 #pragma unroll
@@ -1018,7 +1028,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
         typedef unsigned u4 __attribute__((ext_vector_type(4)));
         u4 ch[NCH];
 #pragma unroll
-        for (int q = 0; q < NCH; ++q) ch[q] = __builtin_amdgcn_raw_buffer_load_b128(bt.r, tal + (unsigned)(tid + q * nthr) * 16u, 0, 0);
+        for (int q = 0; q < NCH; ++q) ch[q] = __builtin_amdgcn_raw_buffer_load_b128(bt.r, tal + (unsigned)(tid + q * nthr) * 16u, 0, kNt);
         unsigned char* sbase = (unsigned char*)lds + z_stage_offset<T, P>(G);
         u4* dstl = (u4*)sbase;
 #pragma unroll
@@ -1267,9 +1277,15 @@ hipError_t launch_z_conv_p2(int lgTx, int rows, int sched, hipStream_t st, cx<T>
     dim3 grid((unsigned)(Kx * ((rows == 2 ? Py / 2 + (1 << lgTx) : Py + (1 << lgTx) - 1) >> lgTx) * bio.count));
     const size_t lds = p2_z_lds_bytes(P, rows, lgTx, sizeof(cx<T>));
 #define CALLS(PP, SS) \
-    if (hipError_t e_ = allow_lds(&kz_conv<T, PP, SS>, lds)) return e_; \
-    hipLaunchKernelGGL((kz_conv<T, PP, SS>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, rows, \
-                       kXcds, twt, bio)
+    if (bio.in) { /* a batch group: its members re-read one tensor spectrum from the caches */ \
+        if (hipError_t e_ = allow_lds(&kz_conv<T, PP, SS>, lds)) return e_; \
+        hipLaunchKernelGGL((kz_conv<T, PP, SS>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, Kx, lgTx, \
+                           rows, kXcds, twt, bio); \
+    } else { \
+        if (hipError_t e_ = allow_lds(&kz_conv<T, PP, SS, false, true>, lds)) return e_; \
+        hipLaunchKernelGGL((kz_conv<T, PP, SS, false, true>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, Ms, nz, Py, \
+                           Kx, lgTx, rows, kXcds, twt, bio); \
+    }
 #define CALL(PP) DEMAG_P2_SCHED(PP, CALLS)
     if constexpr (sizeof(T) == 4) {
         DEMAG_P2_SWITCH(P, CALL)
@@ -1300,8 +1316,8 @@ hipError_t launch_z_energy_p2(int lgTx, int rows, int sched, hipStream_t st, cx<
     const size_t lds = p2_z_lds_bytes(P, rows, lgTx, sizeof(cx<T>));
     const BatchIO none;
 #define CALLS(PP, SS) \
-    if (hipError_t e_ = allow_lds(&kz_conv<T, PP, SS, true>, lds)) return e_; \
-    hipLaunchKernelGGL((kz_conv<T, PP, SS, true>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, T(1), nz, Py, Kx, \
+    if (hipError_t e_ = allow_lds(&kz_conv<T, PP, SS, true, true>, lds)) return e_; \
+    hipLaunchKernelGGL((kz_conv<T, PP, SS, true, true>), grid, dim3(G * tpp<PP>()), lds, st, B2, nhat, T(1), nz, Py, Kx, \
                        lgTx, rows, kXcds, twt, none, epart)
 #define CALL(PP) DEMAG_P2_SCHED(PP, CALLS)
     if constexpr (sizeof(T) == 4) {
