@@ -933,8 +933,10 @@ def traffic_summary(fetch_dir, write_dir, out_path, command):
         scaled = (fv * f_fetch + wv * f_write) * 1024.0 if (f_fetch and f_write) else None
         lines.append(f"  {key[0][:40]:40s} {key[1]:9d} {fv:11.1f} {wv:11.1f} "
                      f"{(scaled or 0) / 1e6:10.1f}")
-        # the headline's fused Z pass: the largest FP32 field (not energy-alone) launch
-        if key[0].startswith("kz_conv<float") and not key[0].endswith("true>") and scaled is not None:
+        # the headline's fused Z pass: the largest FP32 field launch (template
+        # arguments: type, length, schedule, energy alone, streamed tensor)
+        args_ = key[0][len("kz_conv<"):-1].split(", ") if key[0].startswith("kz_conv<float") else []
+        if len(args_) >= 4 and args_[3] == "false" and scaled is not None:
             zconv = max(zconv or 0.0, scaled)
     if zconv is not None:
         lines.append(f"traffic_bytes_per_launch = {zconv}")
