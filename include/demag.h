@@ -101,7 +101,14 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
  *             1 = 8, r, 8, ..., 8 (k >= 2, r = 2 or 4); 2 = 8, ..., 8, 4, 4
  *             (k >= 2, r = 2).  demag_autotune searches them per pass.
  *  "lowrank_scratch": byte cap of the low-rank dense-expansion scratch
- *             (default 256 MB; at least one z slice is always held). */
+ *             (default 256 MB; at least one z slice is always held).
+ *  "tg_mode12": 0 (default) runs the first two mode products of the dense
+ *             tensor grid as two library GEMMs (rocBLAS); 1 as one fused FP32
+ *             kernel on the matrix cores where it applies (FP32 plans with
+ *             ny <= 512; otherwise the GEMMs): half the scratch (R N values
+ *             instead of 2 R N), about 1.13x the evaluation time at
+ *             256 x 256 x 64.  A prepared tensor grid is rebuilt
+ *             (synchronously) for the chosen path. */
 int demag_plan_set_option(demag_plan_t plan, const char* key, double value);
 int demag_plan_destroy(demag_plan_t plan);
 
@@ -222,16 +229,22 @@ int demag_llg_heun_static(demag_plan_t plan, void* m, double Ms, double alpha, d
  * quadrature of the Gaussian representation of 1/r^3 in t = log(tau) (step
  * 0.25 in FP32, 0.15 in FP64; relative kernel error about 2e-7 and 6e-13 on
  * distances from the smallest cell edge to the body diagonal), closed-form
- * Gaussian matrices per axis and node, mode products as GEMMs (rocBLAS);
- * H = -grad phi with the SP difference stencils.
+ * Gaussian matrices per axis and node; H = -grad phi with the SP difference
+ * stencils.  The mode products are GEMMs (rocBLAS).  With the option
+ * "tg_mode12" 1 (FP32, ny <= 512) the first two mode products of every node
+ * and z-plane, D_1 M(:,:,k) D_2^T, run instead as one fused kernel on the
+ * matrix cores that keeps the intermediate on chip and skips the 16-column
+ * groups of the banded Gaussian matrices that are exactly zero (finite m:
+ * the same sums); the third mode product and the node sum stay one GEMM.
  *
- * demag_tg_prepare builds nodes and matrices and allocates the GEMM scratch
- * (2 R N values; R nodes, about 75 in FP32 and 125 in FP64 at 256 x 256 x 64);
- * in FP32 it also times the rocBLAS solutions of the three GEMM shapes on
- * these buffers and keeps, per shape, the fastest whose result agrees with
- * rocBLAS's default to 1e-5 (preparation takes about 2 s at 256 x 256 x 64; the plan's
- * spectrum scratch is overwritten); synchronous; idempotent; DEMAG_ENOMEM if
- * the scratch does not fit. */
+ * demag_tg_prepare builds nodes and matrices and allocates the scratch (R N
+ * values on the fused path, 2 R N on the library path; R nodes, about 75 in
+ * FP32 and 125 in FP64 at 256 x 256 x 64); in FP32 it also times the rocBLAS
+ * solutions of the library GEMM shapes on these buffers and keeps, per
+ * shape, the fastest whose result agrees with rocBLAS's default to 1e-5
+ * (preparation takes about 2 s at 256 x 256 x 64; the plan's spectrum scratch
+ * is overwritten); synchronous; idempotent; DEMAG_ENOMEM if the scratch does
+ * not fit. */
 int demag_tg_prepare(demag_plan_t plan, void* stream);
 /* H (device, [3][nz][ny][nx]) for m; asynchronous.  DEMAG_ESTATE before
  * demag_tg_prepare. */
@@ -240,6 +253,11 @@ int demag_tg_field(demag_plan_t plan, const void* m, double Ms, void* H, void* s
 int demag_tg_field_energy(demag_plan_t plan, const void* m, double Ms, void* H, double* E_dev, void* stream);
 /* out[0] = R (nodes), out[1] = scratch bytes, out[2] = flops per evaluation. */
 int demag_tg_info(demag_plan_t plan, int64_t* out);
+/* out[0] = 1 when the first two mode products run fused (see above), 0 for
+ * the library GEMMs; out[1] = the mode-product flops one evaluation issues
+ * (out[2] of demag_tg_info less the skipped zero blocks).  DEMAG_ESTATE before
+ * demag_tg_prepare. */
+int demag_tg_path(demag_plan_t plan, int64_t* out);
 /* Host only: the Sinc nodes tau_l and weights w_l (w_l = step tau_l^3 /
  * pi^(3/2), so that 1/r^3 ~ 4 pi sum_l w_l exp(-tau_l^2 r^2)) for
  * distances in [rmin, rmax]; returns R (the count) and fills tau, w when both

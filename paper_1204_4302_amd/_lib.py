@@ -48,6 +48,7 @@ SIGNATURES = {
     "demag_tg_field": (_I, [_P, _P, _D, _P, _P]),
     "demag_tg_field_energy": (_I, [_P, _P, _D, _P, _P, _P]),
     "demag_tg_info": (_I, [_P, _P]),
+    "demag_tg_path": (_I, [_P, _P]),
     "demag_tg_sinc_nodes": (_I, [_D, _D, _D, _P, _P, _I]),
     "demag_tg_lowrank_prepare": (_I, [_P, _P]),
     "demag_tg_lowrank_field": (_I, [_P, _I, _I, _P, _P, _D, _P, _P, _P, _P]),

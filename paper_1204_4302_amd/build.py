@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libdemag.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["passes.hip", "passes_p2.hip", "tensor.hip", "sp.hip", "tg.hip", "lowrank.hip", "als.hip", "llg.hip", "plan.hip"]
+SOURCES = ["passes.hip", "passes_p2.hip", "tensor.hip", "sp.hip", "tg.hip", "tg_fused.hip", "lowrank.hip", "als.hip", "llg.hip", "plan.hip"]
 ARCH = os.environ.get("DEMAG_OFFLOAD_ARCH", "gfx950")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.environ.get("HIPCC", os.path.join(ROCM, "bin", "hipcc"))

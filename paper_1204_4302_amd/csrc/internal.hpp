@@ -178,7 +178,7 @@ hipError_t launch_sp_extract(hipStream_t, int a, int Py, int Pz, int Kx, double 
 // (reduced units), step h; returns R (or -1 for bad arguments).
 int tg_sinc_nodes(double rmin, double rmax, double h, std::vector<double>& tau, std::vector<double>& w);
 template <typename T>
-hipError_t launch_tg_axis(hipStream_t, int n, double d, int R, const double* tau, T* E, T* O);
+hipError_t launch_tg_axis(hipStream_t, int n, double d, int R, const double* tau, T* E, T* O, bool row_major = false);
 template <typename T>
 hipError_t launch_tg_stack3(hipStream_t, int n3, int R, const double* c, const T* D3, T* B3);
 template <typename T>
@@ -188,11 +188,34 @@ int tg_potential(void* handle, hipStream_t st, int n1, int n2, int n3, int R, co
 // rocBLAS solutions for the three GEMMs of tg_potential, chosen by timing on
 // the given buffers (Mp: a mode-1 input; Y1, Y2 (behind Y2k) and phi are
 // overwritten); 0 (the default) for FP64 or when no faster solution agrees
-// with the default's result.
+// with the default's result.  With Y1 NULL only the mode-3 GEMM is tuned.
 template <typename T>
 int tg_tune(void* handle, hipStream_t st, int n1, int n2, int n3, int R, const T* D1, const T* Mp, T* Y1,
             const T* const* Y1k, const T* const* D2k, T* const* Y2k, T* Y2, const T* B3, T* phi, int* sol1, int* sol2,
             int* sol3);
+
+// ---- fused first and second TG mode products, FP32 (tg_fused.hip) -------------
+// Y2[l](:,:,k) = D1[l] M(:,:,k) D2[l]^T for every node and plane in one launch
+// (the intermediate stays in LDS); D1, D2 row-major [R][n][n], M [n3][n2][n1],
+// Y2 [R][n3][n2][n1]; lo/hi per matrix [R][tg_band_blocks(n)] from launch_tg_band.
+constexpr int kTgMode12MaxN2 = 512;  // LDS holds 64 rows of the intermediate
+bool tg_mode12_fits(int n2);
+int tg_band_blocks(int n);
+// allows the launch's dynamic LDS for n2 (once, before the first launch)
+hipError_t tg_mode12_init(int n2);
+// columns [lo, hi] holding the nonzero entries of each block of 64 rows (hi -1: none)
+hipError_t launch_tg_band(hipStream_t st, int n, int R, const float* D, int* lo, int* hi);
+hipError_t launch_tg_mode12(hipStream_t st, int n1, int n2, int n3, int R, const float* D1, const int* lo1,
+                            const int* hi1, const float* M, const float* D2, const int* lo2, const int* hi2, float* Y2);
+// Operands of the fused chain per component p (the odd matrix on axis p).
+struct TGFused {
+    const float* D1[3];
+    const float* D2[3];
+    const int *lo1[3], *hi1[3], *lo2[3], *hi2[3];
+};
+// phi by the fused mode-1/2 kernel and the mode-3 GEMM (rocBLAS solution sol3)
+int tg_potential_fused(void* handle, hipStream_t st, int n1, int n2, int n3, int R, const float* m, const TGFused& f,
+                       const float* const B3[3], float* Y2, float* phi, double alpha, int sol3);
 
 // ---- low-rank tensor grid (lowrank.hip) ---------------------------------------
 // Stacked Gaussian matrices of one axis for every node: [R][2n x n] column-major,

@@ -21,6 +21,7 @@
 #include <sstream>
 #include <string>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/demag.h"
@@ -200,6 +201,11 @@ struct TGState {
     void **Y1k = nullptr, **Y2k = nullptr, **D2kE = nullptr, **D2kO = nullptr;
     size_t bytes = 0;
     int sol1 = 0, sol2 = 0, sol3 = 0;  // rocBLAS solutions of the mode-product GEMMs (0: the default)
+    // FP32 with the fused mode-1/2 kernel: D1E..D2O hold the row-major matrices, Y1 and
+    // the pointer arrays are not used; band: lo/hi of D1E, D1O, D2E, D2O in that order
+    bool fused = false;
+    int* band = nullptr;
+    double flops_issued = 0;  // mode-product flops per evaluation after the skipped zero blocks
 };
 
 // Low-rank tensor-grid state (after demag_tg_lowrank_prepare): nodes,
@@ -233,6 +239,7 @@ struct demag_plan_s {
     TGState* tg = nullptr; // tensor-grid state (after demag_tg_prepare)
     LRState* lr = nullptr; // low-rank tensor-grid state (after demag_tg_lowrank_prepare)
     size_t lr_cap = (size_t)256 << 20;  // byte cap of the low-rank expansion scratch
+    int tg_mode12 = 0;                   // 0: library GEMMs, 1: fused FP32 mode-1/2 kernel where it fits
     void* als_handle = nullptr;          // rocblas_handle of the ALS compression (created on first use)
     LaunchCfg zs;          // launch shape of the scalar-potential Z pass
     void* B1 = nullptr;
@@ -575,6 +582,47 @@ int setup_sp_spectrum(demag_plan_s* p, hipStream_t st) {
     return DEMAG_OK;
 }
 
+// Operands of the fused chain: the odd matrix on axis p for component p.
+TGFused tg_fused_operands(const demag_plan_s* p) {
+    const TGState* g = p->tg;
+    const int R = g->R, b1 = R * tg_band_blocks(p->n[0]), b2 = R * tg_band_blocks(p->n[1]);
+    const int* lo1E = g->band;
+    const int* lo1O = lo1E + 2 * b1;
+    const int* lo2E = lo1O + 2 * b1;
+    const int* lo2O = lo2E + 2 * b2;
+    TGFused f;
+    for (int c = 0; c < 3; ++c) {
+        const bool o1 = c == 0, o2 = c == 1;
+        f.D1[c] = (const float*)(o1 ? g->D1O : g->D1E);
+        f.D2[c] = (const float*)(o2 ? g->D2O : g->D2E);
+        f.lo1[c] = o1 ? lo1O : lo1E;
+        f.hi1[c] = f.lo1[c] + b1;
+        f.lo2[c] = o2 ? lo2O : lo2E;
+        f.hi2[c] = f.lo2[c] + b2;
+    }
+    return f;
+}
+
+// Mode-product flops per evaluation that the fused kernel issues (groups of 16
+// columns outside a row block's band skipped) plus the dense mode-3 GEMMs.
+double tg_fused_flops(const demag_plan_s* p, const std::vector<int>& band) {
+    const int n1 = p->n[0], n2 = p->n[1], n3 = p->n[2], R = p->tg->R;
+    const int nb1 = tg_band_blocks(n1), nb2 = tg_band_blocks(n2), b1 = R * nb1, b2 = R * nb2;
+    auto span = [](int lo, int hi, int n) { return hi < 0 ? 0 : std::min(16 * ((hi >> 4) + 1), n) - 16 * (lo >> 4); };
+    double f = 0;
+    for (int c = 0; c < 3; ++c) {
+        const int* lo1 = band.data() + (c == 0 ? 2 * b1 : 0);
+        const int* lo2 = band.data() + 4 * b1 + (c == 1 ? 2 * b2 : 0);
+        for (int l = 0; l < R; ++l) {
+            for (int b = 0; b < nb1; ++b)
+                f += 2.0 * std::min(64, n1 - 64 * b) * span(lo1[l * nb1 + b], lo1[b1 + l * nb1 + b], n1) * n2 * n3;
+            for (int b = 0; b < nb2; ++b)
+                f += 2.0 * n1 * std::min(64, n2 - 64 * b) * span(lo2[l * nb2 + b], lo2[b2 + l * nb2 + b], n2) * n3;
+        }
+    }
+    return f + 3.0 * 2.0 * R * (double)n1 * n2 * n3 * n3;
+}
+
 // One tensor-grid evaluation: Phi by the GEMM chain into B2's memory, then
 // the finite-difference gradient (and energy) as for SP.
 template <typename T>
@@ -586,9 +634,17 @@ int run_tg_field(demag_plan_s* p, const T* m, double Ms, T* H, double* E_dev, hi
     const T* const* D2p[3] = {(const T* const*)g->D2kE, (const T* const*)g->D2kO, (const T* const*)g->D2kE};
     const T* B3[3] = {(const T*)g->B3E, (const T*)g->B3E, (const T*)g->B3O};
     const double hmax = std::max(p->d[0], std::max(p->d[1], p->d[2]));
-    const int rc = tg_potential<T>(g->handle, st, nx, ny, nz, g->R, m, (const T*)g->D1E, (const T*)g->D1O, D2p,
-                                   (const T* const*)g->Y1k, (T* const*)g->Y2k, B3, (T*)g->Y1, (T*)g->Y2, phi,
-                                   Ms * hmax, g->sol1, g->sol2, g->sol3);
+    int rc = 0;
+    if constexpr (std::is_same<T, float>::value) {
+        if (g->fused) {
+            const TGFused f = tg_fused_operands(p);
+            rc = tg_potential_fused(g->handle, st, nx, ny, nz, g->R, m, f, B3, (float*)g->Y2, phi, Ms * hmax, g->sol3);
+        }
+    }
+    if (!g->fused)
+        rc = tg_potential<T>(g->handle, st, nx, ny, nz, g->R, m, (const T*)g->D1E, (const T*)g->D1O, D2p,
+                             (const T* const*)g->Y1k, (T* const*)g->Y2k, B3, (T*)g->Y1, (T*)g->Y2, phi, Ms * hmax,
+                             g->sol1, g->sol2, g->sol3);
     if (rc) return fail(DEMAG_EHIP, "tensor-grid GEMM failed (%d)", rc);
     int nparts = 0;
     HIP_TRY(launch_sp_gradient<T>(st, nx, ny, nz, p->d, phi, Hout, E_dev ? m : nullptr, E_dev ? p->partials : nullptr,
@@ -615,9 +671,13 @@ int setup_tg(demag_plan_s* p, hipStream_t st, double step) {
     if (R <= 0) return fail(DEMAG_EINVAL, "tensor-grid quadrature");
     g->R = R;
     g->step = step;
+    g->fused = std::is_same<T, float>::value && p->tg_mode12 == 1 && tg_mode12_fits(n2);
     const size_t sz = sizeof(T);
-    const size_t need = sz * ((size_t)R * 2 * ((size_t)n1 * n1 + (size_t)n2 * n2) + 2 * (size_t)R * n3 * n3 + 2 * (size_t)R * N) +
-                        4 * sizeof(void*) * (size_t)R * n3;
+    const size_t nband = (size_t)4 * R * (tg_band_blocks(n1) + tg_band_blocks(n2));  // lo and hi of four matrices
+    const size_t need =
+        sz * ((size_t)R * 2 * ((size_t)n1 * n1 + (size_t)n2 * n2) + 2 * (size_t)R * n3 * n3 +
+              (g->fused ? 1 : 2) * (size_t)R * N) +
+        (g->fused ? nband * sizeof(int) : 4 * sizeof(void*) * (size_t)R * n3);
     g->bytes = need;
     int rc = DEMAG_OK;
     auto alloc = [&](void** ptr, size_t bytes, const char* what) {
@@ -639,18 +699,22 @@ int setup_tg(demag_plan_s* p, hipStream_t st, double step) {
     alloc(&D3O, (size_t)R * n3 * n3 * sz, "matrices");
     alloc(&g->B3E, (size_t)R * n3 * n3 * sz, "mode-3 factors");
     alloc(&g->B3O, (size_t)R * n3 * n3 * sz, "mode-3 factors");
-    alloc(&g->Y1, (size_t)R * N * sz, "scratch");
     alloc(&g->Y2, (size_t)R * N * sz, "scratch");
     const size_t nb = (size_t)R * n3;
-    alloc((void**)&g->Y1k, nb * sizeof(void*), "pointer arrays");
-    alloc((void**)&g->Y2k, nb * sizeof(void*), "pointer arrays");
-    alloc((void**)&g->D2kE, nb * sizeof(void*), "pointer arrays");
-    alloc((void**)&g->D2kO, nb * sizeof(void*), "pointer arrays");
+    if (g->fused) {
+        alloc((void**)&g->band, nband * sizeof(int), "band tables");
+    } else {
+        alloc(&g->Y1, (size_t)R * N * sz, "scratch");
+        alloc((void**)&g->Y1k, nb * sizeof(void*), "pointer arrays");
+        alloc((void**)&g->Y2k, nb * sizeof(void*), "pointer arrays");
+        alloc((void**)&g->D2kE, nb * sizeof(void*), "pointer arrays");
+        alloc((void**)&g->D2kO, nb * sizeof(void*), "pointer arrays");
+    }
     if (!rc && hipMemcpy(g->tau, tau.data(), R * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         rc = fail(DEMAG_EHIP, "upload");
     if (!rc && hipMemcpy(g->c, w.data(), R * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
         rc = fail(DEMAG_EHIP, "upload");
-    if (!rc) {
+    if (!rc && !g->fused) {
         std::vector<void*> y1(nb), y2(nb), de(nb), dO(nb);
         for (int l = 0; l < R; ++l)
             for (int k = 0; k < n3; ++k) {
@@ -667,13 +731,37 @@ int setup_tg(demag_plan_s* p, hipStream_t st, double step) {
             rc = fail(DEMAG_EHIP, "upload");
     }
     if (!rc) {
-        hipError_t e = launch_tg_axis<T>(st, n1, dt[0], R, g->tau, (T*)g->D1E, (T*)g->D1O);
-        if (e == hipSuccess) e = launch_tg_axis<T>(st, n2, dt[1], R, g->tau, (T*)g->D2E, (T*)g->D2O);
+        hipError_t e = launch_tg_axis<T>(st, n1, dt[0], R, g->tau, (T*)g->D1E, (T*)g->D1O, g->fused);
+        if (e == hipSuccess) e = launch_tg_axis<T>(st, n2, dt[1], R, g->tau, (T*)g->D2E, (T*)g->D2O, g->fused);
         if (e == hipSuccess) e = launch_tg_axis<T>(st, n3, dt[2], R, g->tau, (T*)D3E, (T*)D3O);
         if (e == hipSuccess) e = launch_tg_stack3<T>(st, n3, R, g->c, (const T*)D3E, (T*)g->B3E);
         if (e == hipSuccess) e = launch_tg_stack3<T>(st, n3, R, g->c, (const T*)D3O, (T*)g->B3O);
+        if constexpr (std::is_same<T, float>::value) {
+            if (g->fused) {
+                // bands of D1E, D1O, D2E, D2O (lo then hi per matrix)
+                const size_t b1 = (size_t)R * tg_band_blocks(n1), b2 = (size_t)R * tg_band_blocks(n2);
+                int* lo = g->band;
+                const float* mats[4] = {(const float*)g->D1E, (const float*)g->D1O, (const float*)g->D2E,
+                                        (const float*)g->D2O};
+                for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+                    const size_t bi = i < 2 ? b1 : b2;
+                    e = launch_tg_band(st, i < 2 ? n1 : n2, R, mats[i], lo, lo + bi);
+                    lo += 2 * bi;
+                }
+                if (e == hipSuccess) e = tg_mode12_init(n2);
+            }
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) rc = hip_fail(e, "tensor-grid setup");
+    }
+    if (!rc && g->fused) {
+        std::vector<int> band(nband);
+        if (hipMemcpy(band.data(), g->band, nband * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = fail(DEMAG_EHIP, "band tables");
+        else
+            g->flops_issued = tg_fused_flops(p, band);
+    } else if (!rc) {
+        g->flops_issued = 3.0 * 2.0 * R * (double)N * (n1 + n2 + n3);
     }
     (void)hipFree(D3E);
     (void)hipFree(D3O);
@@ -708,7 +796,7 @@ void free_tg(TGState* g) {
     if (!g) return;
     if (g->handle) rocblas_destroy_handle((rocblas_handle)g->handle);
     for (void* q : {(void*)g->tau, (void*)g->c, g->D1E, g->D1O, g->D2E, g->D2O, g->B3E, g->B3O, g->Y1, g->Y2,
-                    (void*)g->Y1k, (void*)g->Y2k, (void*)g->D2kE, (void*)g->D2kO})
+                    (void*)g->Y1k, (void*)g->Y2k, (void*)g->D2kE, (void*)g->D2kO, (void*)g->band})
         (void)hipFree(q);
     delete g;
 }
@@ -1270,6 +1358,16 @@ int demag_plan_set_option(demag_plan_t p, const char* key, double value) {
             if (slot[w]->p2) slot[w]->sched = (int)value < p2_num_schedules(P) ? (int)value : 0;
         }
         return DEMAG_OK;
+    } else if (!strcmp(key, "tg_mode12")) {
+        if (value != 0 && value != 1) return fail(DEMAG_EINVAL, "tg_mode12 must be 0 or 1");
+        if (p->tg_mode12 == (int)value) return DEMAG_OK;
+        p->tg_mode12 = (int)value;
+        if (!p->tg) return DEMAG_OK;
+        // a prepared tensor grid is rebuilt for the other path
+        HIP_TRY(hipDeviceSynchronize());
+        free_tg(p->tg);
+        p->tg = nullptr;
+        return demag_tg_prepare(p, nullptr);
     } else if (!strcmp(key, "lowrank_scratch")) {
         if (!(value >= 0) || value > 1e15) return fail(DEMAG_EINVAL, "lowrank_scratch must be in [0, 1e15] bytes");
         p->lr_cap = (size_t)value;
@@ -1523,6 +1621,14 @@ int demag_tg_info(demag_plan_t p, int64_t* out) {
     out[1] = (int64_t)p->tg->bytes;
     const double n1 = p->n[0], n2 = p->n[1], n3 = p->n[2];
     out[2] = (int64_t)(3.0 * 2.0 * p->tg->R * n1 * n2 * n3 * (n1 + n2 + n3));  // flops per evaluation
+    return DEMAG_OK;
+}
+
+int demag_tg_path(demag_plan_t p, int64_t* out) {
+    if (!p || !out) return fail(DEMAG_EINVAL, "NULL argument");
+    if (!p->tg) return fail(DEMAG_ESTATE, "tensor-grid method not prepared");
+    out[0] = p->tg->fused ? 1 : 0;
+    out[1] = (int64_t)p->tg->flops_issued;
     return DEMAG_OK;
 }
 

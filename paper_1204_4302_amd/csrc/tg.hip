@@ -20,8 +20,10 @@
 //     mode 2: Y2[l](:,:,k) = Y1[l](:,:,k) D_2[l]^T   (pointer-batched over l, k)
 //     mode 3: Phi += [Y2[0] .. Y2[R-1]] [c_l D_3[l]^T stacked]  (one GEMM, K = R n3)
 // In FP32 each of the three runs the rocBLAS solution chosen for its shape
-// when the method is prepared (tg_tune).  The field is the finite-difference
-// gradient of the SP method.
+// when the method is prepared (tg_tune).  Optionally (FP32) modes 1 and 2 run
+// as one hand-written kernel instead (tg_fused.hip, tg_potential_fused), with
+// half the scratch.  The field is the finite-difference gradient of the SP
+// method.
 #define ROCBLAS_BETA_FEATURES_API  // rocblas_gemm_ex_get_solutions: the mode-3 solution is chosen by timing
 #include <rocblas/rocblas.h>
 
@@ -38,16 +40,18 @@ namespace demag {
 namespace {
 
 // Gaussian matrices of one axis (n cells of edge d, reduced units) for every
-// node: E[l][i][i'] and O[l][i][i'] column-major (entry (i', i) at i' + i n).
+// node: E[l] and O[l] column-major (entry (i', i) at i' + i n), or row-major
+// (at i + i' n) when rm is set.
 template <typename T>
 __global__ void __launch_bounds__(256) k_tg_axis(int n, double d, int R, const double* __restrict__ tau,
-                                                 T* __restrict__ E, T* __restrict__ O) {
+                                                 T* __restrict__ E, T* __restrict__ O, int rm) {
     const size_t nn = (size_t)n * n;
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nn * R) return;
     const int l = (int)(t / nn);
     const size_t e = t - (size_t)l * nn;
-    const int ip = (int)(e % n), i = (int)(e / n);
+    const int fast = (int)(e % n), slow = (int)(e / n);
+    const int ip = rm ? slow : fast, i = rm ? fast : slow;
     const double a = (ip + 0.5) * d, c = (i + 0.5) * d, s = tau[l];
     E[t] = (T)gauss_even(a, c, d, s);
     O[t] = (T)gauss_odd(a, c, d, s);
@@ -86,9 +90,10 @@ int tg_sinc_nodes(double rmin, double rmax, double h, std::vector<double>& tau, 
 }
 
 template <typename T>
-hipError_t launch_tg_axis(hipStream_t st, int n, double d, int R, const double* tau, T* E, T* O) {
+hipError_t launch_tg_axis(hipStream_t st, int n, double d, int R, const double* tau, T* E, T* O, bool row_major) {
     const size_t total = (size_t)n * n * R;
-    hipLaunchKernelGGL((k_tg_axis<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, d, R, tau, E, O);
+    hipLaunchKernelGGL((k_tg_axis<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, d, R, tau, E, O,
+                       row_major ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -99,8 +104,8 @@ hipError_t launch_tg_stack3(hipStream_t st, int n3, int R, const double* c, cons
     return hipGetLastError();
 }
 
-template hipError_t launch_tg_axis<float>(hipStream_t, int, double, int, const double*, float*, float*);
-template hipError_t launch_tg_axis<double>(hipStream_t, int, double, int, const double*, double*, double*);
+template hipError_t launch_tg_axis<float>(hipStream_t, int, double, int, const double*, float*, float*, bool);
+template hipError_t launch_tg_axis<double>(hipStream_t, int, double, int, const double*, double*, double*, bool);
 template hipError_t launch_tg_stack3<float>(hipStream_t, int, int, const double*, const float*, float*);
 template hipError_t launch_tg_stack3<double>(hipStream_t, int, int, const double*, const double*, double*);
 
@@ -256,7 +261,7 @@ int tg_tune<float>(void* handle, hipStream_t st, int n1, int n2, int n3, int R, 
             R, rocblas_datatype_f32_r, rocblas_gemm_algo_solution_index, 0, arr, &count);
     };
     int rc = 0;
-    if (list1(nullptr) == rocblas_status_success && count > 0) {
+    if (Y1 && list1(nullptr) == rocblas_status_success && count > 0) {
         sols.assign((size_t)count, 0);
         if (list1(sols.data()) == rocblas_status_success)
             rc = pick_solution(st, sols, [&](int sol) { return mode1(h, n1, nc, R, D1, Mp, Y1, sol); }, Y1,
@@ -272,7 +277,7 @@ int tg_tune<float>(void* handle, hipStream_t st, int n1, int n2, int n3, int R, 
             D2k, rocblas_datatype_f32_r, n2, &zero, Y2k, rocblas_datatype_f32_r, n1, (void*)Y2k, rocblas_datatype_f32_r, n1,
             nb, rocblas_datatype_f32_r, rocblas_gemm_algo_solution_index, 0, arr, &count);
     };
-    if (list2(nullptr) == rocblas_status_success && count > 0) {
+    if (Y1 && list2(nullptr) == rocblas_status_success && count > 0) {
         sols.assign((size_t)count, 0);
         if (list2(sols.data()) == rocblas_status_success)
             rc = pick_solution(st, sols, [&](int sol) { return mode2(h, n1, n2, nb, Y1k, D2k, Y2k, sol); }, Y2,
@@ -324,6 +329,26 @@ int tg_potential(void* handle, hipStream_t st, int n1, int n2, int n3, int R, co
             return -4;
     }
     (void)Y1;
+    return 0;
+}
+
+// The same potential with the first two mode products fused (tg_fused.hip):
+// per component, Y2 = D1 M_p D2^T for every node and plane in one launch,
+// then the mode-3 GEMM and the node sum as in tg_potential.
+int tg_potential_fused(void* handle, hipStream_t st, int n1, int n2, int n3, int R, const float* m, const TGFused& f,
+                       const float* const B3[3], float* Y2, float* phi, double alpha, int sol3) {
+    rocblas_handle h = (rocblas_handle)handle;
+    if (rocblas_set_stream(h, st) != rocblas_status_success) return -1;
+    const size_t N = (size_t)n1 * n2 * n3;
+    const float one = 1, zero = 0, al = (float)alpha;
+    for (int p = 0; p < 3; ++p) {
+        if (launch_tg_mode12(st, n1, n2, n3, R, f.D1[p], f.lo1[p], f.hi1[p], m + (size_t)p * N, f.D2[p], f.lo2[p],
+                             f.hi2[p], Y2) != hipSuccess)
+            return -5;
+        if (mode3(h, n1 * n2, n3, R * n3, &al, Y2, B3[p], p == 0 ? &zero : &one, phi, sol3) !=
+            rocblas_status_success)
+            return -4;
+    }
     return 0;
 }
 

@@ -222,13 +222,19 @@ class Plan:
 
     # -- tensor-grid method (TG, dense) --------------------------------------
     def tg_prepare(self):
-        """Sinc nodes, Gaussian matrices and GEMM scratch (synchronous, once)."""
+        """Sinc nodes, Gaussian matrices and mode-product scratch (synchronous, once)."""
         _lib.call("demag_tg_prepare", self._h, _stream_ptr())
 
     def tg_info(self) -> dict:
         out = (ctypes.c_int64 * 3)()
         _lib.call("demag_tg_info", self._h, out)
         return {"nodes": out[0], "scratch_bytes": out[1], "flops_per_eval": out[2]}
+
+    def tg_path(self) -> dict:
+        """Which mode-product path runs (fused FP32 kernel or library GEMMs) and its flops."""
+        out = (ctypes.c_int64 * 2)()
+        _lib.call("demag_tg_path", self._h, out)
+        return {"fused": bool(out[0]), "flops_issued": out[1]}
 
     def tg_field(self, m: torch.Tensor, Ms: float, out: torch.Tensor | None = None) -> torch.Tensor:
         """H = -grad phi, phi by the block-CP sum of Gaussian mode products."""
