@@ -106,7 +106,7 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
  *             tensor grid as two library GEMMs (rocBLAS); 1 as one fused FP32
  *             kernel on the matrix cores where it applies (FP32 plans with
  *             ny <= 512; otherwise the GEMMs): half the scratch (R N values
- *             instead of 2 R N), about 1.13x the evaluation time at
+ *             instead of 2 R N), about 1.09x the evaluation time at
  *             256 x 256 x 64.  A prepared tensor grid is rebuilt
  *             (synchronously) for the chosen path. */
 int demag_plan_set_option(demag_plan_t plan, const char* key, double value);

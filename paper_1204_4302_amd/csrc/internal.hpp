@@ -178,7 +178,7 @@ hipError_t launch_sp_extract(hipStream_t, int a, int Py, int Pz, int Kx, double 
 // (reduced units), step h; returns R (or -1 for bad arguments).
 int tg_sinc_nodes(double rmin, double rmax, double h, std::vector<double>& tau, std::vector<double>& w);
 template <typename T>
-hipError_t launch_tg_axis(hipStream_t, int n, double d, int R, const double* tau, T* E, T* O, bool row_major = false);
+hipError_t launch_tg_axis(hipStream_t, int n, double d, int R, const double* tau, T* E, T* O);
 template <typename T>
 hipError_t launch_tg_stack3(hipStream_t, int n3, int R, const double* c, const T* D3, T* B3);
 template <typename T>
@@ -196,11 +196,15 @@ int tg_tune(void* handle, hipStream_t st, int n1, int n2, int n3, int R, const T
 
 // ---- fused first and second TG mode products, FP32 (tg_fused.hip) -------------
 // Y2[l](:,:,k) = D1[l] M(:,:,k) D2[l]^T for every node and plane in one launch
-// (the intermediate stays in LDS); D1, D2 row-major [R][n][n], M [n3][n2][n1],
-// Y2 [R][n3][n2][n1]; lo/hi per matrix [R][tg_band_blocks(n)] from launch_tg_band.
+// (the intermediate stays in LDS); D1, D2 [R][tg_tiled_floats(n)] in the tiled
+// operand order of launch_tg_axis_tiled, M [n3][n2][n1], Y2 [R][n3][n2][n1];
+// lo/hi per matrix [R][tg_band_blocks(n)] from launch_tg_band.
 constexpr int kTgMode12MaxN2 = 512;  // LDS holds 64 rows of the intermediate
 bool tg_mode12_fits(int n2);
 int tg_band_blocks(int n);
+size_t tg_tiled_floats(int n);  // per node: ceil(n/16)^2 tiles of 256 values
+// the Gaussian matrices of one axis for every node in the tiled operand order
+hipError_t launch_tg_axis_tiled(hipStream_t st, int n, double d, int R, const double* tau, float* E, float* O);
 // allows the launch's dynamic LDS for n2 (once, before the first launch)
 hipError_t tg_mode12_init(int n2);
 // columns [lo, hi] holding the nonzero entries of each block of 64 rows (hi -1: none)

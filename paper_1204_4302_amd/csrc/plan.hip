@@ -201,7 +201,7 @@ struct TGState {
     void **Y1k = nullptr, **Y2k = nullptr, **D2kE = nullptr, **D2kO = nullptr;
     size_t bytes = 0;
     int sol1 = 0, sol2 = 0, sol3 = 0;  // rocBLAS solutions of the mode-product GEMMs (0: the default)
-    // FP32 with the fused mode-1/2 kernel: D1E..D2O hold the row-major matrices, Y1 and
+    // FP32 with the fused mode-1/2 kernel: D1E..D2O hold the tiled matrices, Y1 and
     // the pointer arrays are not used; band: lo/hi of D1E, D1O, D2E, D2O in that order
     bool fused = false;
     int* band = nullptr;
@@ -674,10 +674,12 @@ int setup_tg(demag_plan_s* p, hipStream_t st, double step) {
     g->fused = std::is_same<T, float>::value && p->tg_mode12 == 1 && tg_mode12_fits(n2);
     const size_t sz = sizeof(T);
     const size_t nband = (size_t)4 * R * (tg_band_blocks(n1) + tg_band_blocks(n2));  // lo and hi of four matrices
-    const size_t need =
-        sz * ((size_t)R * 2 * ((size_t)n1 * n1 + (size_t)n2 * n2) + 2 * (size_t)R * n3 * n3 +
-              (g->fused ? 1 : 2) * (size_t)R * N) +
-        (g->fused ? nband * sizeof(int) : 4 * sizeof(void*) * (size_t)R * n3);
+    // the fused path keeps D1 and D2 in the tiled operand order (zero-padded to 16)
+    const size_t mat1 = g->fused ? tg_tiled_floats(n1) : (size_t)n1 * n1;
+    const size_t mat2 = g->fused ? tg_tiled_floats(n2) : (size_t)n2 * n2;
+    const size_t need = sz * ((size_t)R * 2 * (mat1 + mat2) + 2 * (size_t)R * n3 * n3 +
+                              (g->fused ? 1 : 2) * (size_t)R * N) +
+                        (g->fused ? nband * sizeof(int) : 4 * sizeof(void*) * (size_t)R * n3);
     g->bytes = need;
     int rc = DEMAG_OK;
     auto alloc = [&](void** ptr, size_t bytes, const char* what) {
@@ -691,10 +693,10 @@ int setup_tg(demag_plan_s* p, hipStream_t st, double step) {
     void *D3E = nullptr, *D3O = nullptr;
     alloc((void**)&g->tau, R * sizeof(double), "nodes");
     alloc((void**)&g->c, R * sizeof(double), "weights");
-    alloc(&g->D1E, (size_t)R * n1 * n1 * sz, "matrices");
-    alloc(&g->D1O, (size_t)R * n1 * n1 * sz, "matrices");
-    alloc(&g->D2E, (size_t)R * n2 * n2 * sz, "matrices");
-    alloc(&g->D2O, (size_t)R * n2 * n2 * sz, "matrices");
+    alloc(&g->D1E, (size_t)R * mat1 * sz, "matrices");
+    alloc(&g->D1O, (size_t)R * mat1 * sz, "matrices");
+    alloc(&g->D2E, (size_t)R * mat2 * sz, "matrices");
+    alloc(&g->D2O, (size_t)R * mat2 * sz, "matrices");
     alloc(&D3E, (size_t)R * n3 * n3 * sz, "matrices");
     alloc(&D3O, (size_t)R * n3 * n3 * sz, "matrices");
     alloc(&g->B3E, (size_t)R * n3 * n3 * sz, "mode-3 factors");
@@ -731,8 +733,17 @@ int setup_tg(demag_plan_s* p, hipStream_t st, double step) {
             rc = fail(DEMAG_EHIP, "upload");
     }
     if (!rc) {
-        hipError_t e = launch_tg_axis<T>(st, n1, dt[0], R, g->tau, (T*)g->D1E, (T*)g->D1O, g->fused);
-        if (e == hipSuccess) e = launch_tg_axis<T>(st, n2, dt[1], R, g->tau, (T*)g->D2E, (T*)g->D2O, g->fused);
+        hipError_t e = hipSuccess;
+        if constexpr (std::is_same<T, float>::value) {
+            if (g->fused) {
+                e = launch_tg_axis_tiled(st, n1, dt[0], R, g->tau, (float*)g->D1E, (float*)g->D1O);
+                if (e == hipSuccess) e = launch_tg_axis_tiled(st, n2, dt[1], R, g->tau, (float*)g->D2E, (float*)g->D2O);
+            }
+        }
+        if (!g->fused) {
+            e = launch_tg_axis<T>(st, n1, dt[0], R, g->tau, (T*)g->D1E, (T*)g->D1O);
+            if (e == hipSuccess) e = launch_tg_axis<T>(st, n2, dt[1], R, g->tau, (T*)g->D2E, (T*)g->D2O);
+        }
         if (e == hipSuccess) e = launch_tg_axis<T>(st, n3, dt[2], R, g->tau, (T*)D3E, (T*)D3O);
         if (e == hipSuccess) e = launch_tg_stack3<T>(st, n3, R, g->c, (const T*)D3E, (T*)g->B3E);
         if (e == hipSuccess) e = launch_tg_stack3<T>(st, n3, R, g->c, (const T*)D3O, (T*)g->B3O);

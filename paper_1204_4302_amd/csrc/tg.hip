@@ -40,18 +40,16 @@ namespace demag {
 namespace {
 
 // Gaussian matrices of one axis (n cells of edge d, reduced units) for every
-// node: E[l] and O[l] column-major (entry (i', i) at i' + i n), or row-major
-// (at i + i' n) when rm is set.
+// node: E[l][i][i'] and O[l][i][i'] column-major (entry (i', i) at i' + i n).
 template <typename T>
 __global__ void __launch_bounds__(256) k_tg_axis(int n, double d, int R, const double* __restrict__ tau,
-                                                 T* __restrict__ E, T* __restrict__ O, int rm) {
+                                                 T* __restrict__ E, T* __restrict__ O) {
     const size_t nn = (size_t)n * n;
     const size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nn * R) return;
     const int l = (int)(t / nn);
     const size_t e = t - (size_t)l * nn;
-    const int fast = (int)(e % n), slow = (int)(e / n);
-    const int ip = rm ? slow : fast, i = rm ? fast : slow;
+    const int ip = (int)(e % n), i = (int)(e / n);
     const double a = (ip + 0.5) * d, c = (i + 0.5) * d, s = tau[l];
     E[t] = (T)gauss_even(a, c, d, s);
     O[t] = (T)gauss_odd(a, c, d, s);
@@ -90,10 +88,9 @@ int tg_sinc_nodes(double rmin, double rmax, double h, std::vector<double>& tau, 
 }
 
 template <typename T>
-hipError_t launch_tg_axis(hipStream_t st, int n, double d, int R, const double* tau, T* E, T* O, bool row_major) {
+hipError_t launch_tg_axis(hipStream_t st, int n, double d, int R, const double* tau, T* E, T* O) {
     const size_t total = (size_t)n * n * R;
-    hipLaunchKernelGGL((k_tg_axis<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, d, R, tau, E, O,
-                       row_major ? 1 : 0);
+    hipLaunchKernelGGL((k_tg_axis<T>), dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, d, R, tau, E, O);
     return hipGetLastError();
 }
 
@@ -104,8 +101,8 @@ hipError_t launch_tg_stack3(hipStream_t st, int n3, int R, const double* c, cons
     return hipGetLastError();
 }
 
-template hipError_t launch_tg_axis<float>(hipStream_t, int, double, int, const double*, float*, float*, bool);
-template hipError_t launch_tg_axis<double>(hipStream_t, int, double, int, const double*, double*, double*, bool);
+template hipError_t launch_tg_axis<float>(hipStream_t, int, double, int, const double*, float*, float*);
+template hipError_t launch_tg_axis<double>(hipStream_t, int, double, int, const double*, double*, double*);
 template hipError_t launch_tg_stack3<float>(hipStream_t, int, int, const double*, const float*, float*);
 template hipError_t launch_tg_stack3<double>(hipStream_t, int, int, const double*, const double*, double*);
 
