@@ -207,14 +207,14 @@ __device__ __forceinline__ Buf make_buf(const void* base, size_t bytes) {
     return {__builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)(unsigned)bytes, (int)kBufWord3)};
 }
 
-template <typename T>
+template <typename T, int POL = 0>  // POL: cache policy bits of the load
 __device__ __forceinline__ cx<T> bld(Buf b, unsigned off, unsigned soff = 0) {
     if constexpr (sizeof(T) == 4) {
-        const auto u = __builtin_amdgcn_raw_buffer_load_b64(b.r, off, soff, 0);
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(b.r, off, soff, POL);
         const typename vec2<T>::type v = __builtin_bit_cast(typename vec2<T>::type, u);
         return mk(v.x, v.y);
     } else {
-        const auto u = __builtin_amdgcn_raw_buffer_load_b128(b.r, off, soff, 0);
+        const auto u = __builtin_amdgcn_raw_buffer_load_b128(b.r, off, soff, POL);
         const typename vec2<T>::type v = __builtin_bit_cast(typename vec2<T>::type, u);
         return mk(v.x, v.y);
     }
@@ -788,6 +788,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
                        make_buf(B2 + 2 * cstride, cstride * CB)};
     // byte offset of this lane's first element; zz = t + k TP adds k TP CB
     const unsigned row = (unsigned)((((size_t)kx * Py + ky) * nz + t) * CB);
+    // the energy alone is the spectrum's last reader: its loads are non-temporal
     cx<T> v[3][LT::EPT];
 #pragma unroll
     for (int comp = 0; comp < 3; ++comp) {
@@ -795,7 +796,8 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_conv(cx<T>* __restrict__ B2
         for (int j = 0; j < LT::EPT; ++j) {
             const int k = LT::fin_k(j);
             const int zz = t + k * LT::TP;
-            v[comp][j] = k < LT::EPT / 2 ? bld<T>(bc[comp], boff(ok && zz < nz, row, k * LT::TP * CB)) : czero<T>();
+            v[comp][j] = k < LT::EPT / 2 ? bld<T, EN ? kNt : 0>(bc[comp], boff(ok && zz < nz, row, k * LT::TP * CB))
+                                         : czero<T>();
         }
     }
     // Tensor values of this thread's frequencies kz (forward output slots);
