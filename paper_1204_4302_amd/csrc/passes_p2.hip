@@ -1005,7 +1005,7 @@ __global__ void __launch_bounds__(kP2MaxThreadsZ) kz_sp(cx<T>* __restrict__ B2, 
         for (int j = 0; j < LT::EPT; ++j) {
             const int k = LT::fin_k(j);
             const int zz = t + k * LT::TP;
-            v[comp][j] = k < LT::EPT / 2 ? bld<T>(bc[comp], boff(ok && zz < nz, row, k * LT::TP * CB)) : czero<T>();
+            v[comp][j] = k < LT::EPT / 2 ? bld<T, kNt>(bc[comp], boff(ok && zz < nz, row, k * LT::TP * CB)) : czero<T>();
         }
     }
     const size_t cs = (size_t)(Lz + 1);  // component stride of the spectrum octant
