@@ -127,6 +127,7 @@ FUSED_SHAPES = [
     ((130, 72, 6), (2e-9, 2e-9, 3e-9), 1.4e6),    # three row blocks, ragged, 16-byte loads
     ((67, 45, 4), (2e-9, 2e-9, 2e-9), 8e5),       # lengths not multiples of 4: element loads
     ((40, 300, 2), (2e-9, 2e-9, 3e-9), 1.4e6),    # two passes of column tiles per wave
+    ((16, 512, 1), (2e-9, 2e-9, 2e-9), 8e5),      # the widest ny (132 KB of LDS), one plane
 ]
 
 
