@@ -30,15 +30,21 @@ __device__ __forceinline__ V3<T> unit(V3<T> v) {
     const T r = T(1) / sqrt(v.x * v.x + v.y * v.y + v.z * v.z);
     return {v.x * r, v.y * r, v.z * r};
 }
+// Loads and stores are non-temporal: every array an update touches is read
+// once more at most, after a field evaluation that streams far more than the
+// 256 MB memory-side cache holds (or, for m*, by the field's first pass,
+// whose loads are non-temporal themselves), so caching them only displaces
+// the field passes' data.
 template <typename T>
 __device__ __forceinline__ V3<T> ld(const T* __restrict__ a, size_t N, size_t i) {
-    return {a[i], a[N + i], a[2 * N + i]};
+    return {__builtin_nontemporal_load(a + i), __builtin_nontemporal_load(a + N + i),
+            __builtin_nontemporal_load(a + 2 * N + i)};
 }
 template <typename T>
 __device__ __forceinline__ void st(T* __restrict__ a, size_t N, size_t i, V3<T> v) {
-    a[i] = v.x;
-    a[N + i] = v.y;
-    a[2 * N + i] = v.z;
+    __builtin_nontemporal_store(v.x, a + i);
+    __builtin_nontemporal_store(v.y, a + N + i);
+    __builtin_nontemporal_store(v.z, a + 2 * N + i);
 }
 
 template <typename T>
