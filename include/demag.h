@@ -102,13 +102,13 @@ int demag_plan_create(demag_plan_t* out, int nx, int ny, int nz, double dx, doub
  *             (k >= 2, r = 2).  demag_autotune searches them per pass.
  *  "lowrank_scratch": byte cap of the low-rank dense-expansion scratch
  *             (default 256 MB; at least one z slice is always held).
- *  "tg_mode12": 0 (default) runs the first two mode products of the dense
- *             tensor grid as two library GEMMs (rocBLAS); 1 as one fused FP32
- *             kernel on the matrix cores where it applies (FP32 plans with
- *             ny <= 512; otherwise the GEMMs): half the scratch (R N values
- *             instead of 2 R N), about 1.09x the evaluation time at
- *             256 x 256 x 64.  A prepared tensor grid is rebuilt
- *             (synchronously) for the chosen path. */
+ *  "tg_mode12": 1 (default) runs the first two mode products of the dense
+ *             tensor grid as one fused FP32 kernel on the matrix cores where
+ *             it applies (FP32 plans with ny <= 512; otherwise, and in FP64,
+ *             library GEMMs): half the scratch (R N values instead of 2 R N)
+ *             and about 0.96x the evaluation time of the GEMMs at
+ *             256 x 256 x 64; 0 as two library GEMMs (rocBLAS).  A prepared
+ *             tensor grid is rebuilt (synchronously) for the chosen path. */
 int demag_plan_set_option(demag_plan_t plan, const char* key, double value);
 int demag_plan_destroy(demag_plan_t plan);
 
@@ -230,12 +230,13 @@ int demag_llg_heun_static(demag_plan_t plan, void* m, double Ms, double alpha, d
  * 0.25 in FP32, 0.15 in FP64; relative kernel error about 2e-7 and 6e-13 on
  * distances from the smallest cell edge to the body diagonal), closed-form
  * Gaussian matrices per axis and node; H = -grad phi with the SP difference
- * stencils.  The mode products are GEMMs (rocBLAS).  With the option
- * "tg_mode12" 1 (FP32, ny <= 512) the first two mode products of every node
- * and z-plane, D_1 M(:,:,k) D_2^T, run instead as one fused kernel on the
- * matrix cores that keeps the intermediate on chip and skips the 16-column
- * groups of the banded Gaussian matrices that are exactly zero (finite m:
- * the same sums); the third mode product and the node sum stay one GEMM.
+ * stencils.  In FP32 (ny <= 512, option "tg_mode12" 1, the default) the
+ * first two mode products of every node and z-plane, D_1 M(:,:,k) D_2^T, run
+ * as one fused kernel on the matrix cores that keeps the intermediate on chip
+ * and skips the 16-column groups of the banded Gaussian matrices that are
+ * exactly zero (finite m: the same sums); the third mode product and the node
+ * sum are one GEMM (rocBLAS).  Otherwise all three mode products are GEMMs
+ * (rocBLAS).
  *
  * demag_tg_prepare builds nodes and matrices and allocates the scratch (R N
  * values on the fused path, 2 R N on the library path; R nodes, about 75 in

@@ -239,7 +239,7 @@ struct demag_plan_s {
     TGState* tg = nullptr; // tensor-grid state (after demag_tg_prepare)
     LRState* lr = nullptr; // low-rank tensor-grid state (after demag_tg_lowrank_prepare)
     size_t lr_cap = (size_t)256 << 20;  // byte cap of the low-rank expansion scratch
-    int tg_mode12 = 0;                   // 0: library GEMMs, 1: fused FP32 mode-1/2 kernel where it fits
+    int tg_mode12 = 1;                   // 1: fused FP32 mode-1/2 kernel where it fits, 0: library GEMMs
     void* als_handle = nullptr;          // rocblas_handle of the ALS compression (created on first use)
     LaunchCfg zs;          // launch shape of the scalar-potential Z pass
     void* B1 = nullptr;

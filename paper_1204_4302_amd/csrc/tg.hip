@@ -20,10 +20,10 @@
 //     mode 2: Y2[l](:,:,k) = Y1[l](:,:,k) D_2[l]^T   (pointer-batched over l, k)
 //     mode 3: Phi += [Y2[0] .. Y2[R-1]] [c_l D_3[l]^T stacked]  (one GEMM, K = R n3)
 // In FP32 each of the three runs the rocBLAS solution chosen for its shape
-// when the method is prepared (tg_tune).  Optionally (FP32) modes 1 and 2 run
-// as one hand-written kernel instead (tg_fused.hip, tg_potential_fused), with
-// half the scratch.  The field is the finite-difference gradient of the SP
-// method.
+// when the method is prepared (tg_tune).  By default in FP32 modes 1 and 2 run
+// instead as one hand-written kernel on the matrix cores (tg_fused.hip,
+// tg_potential_fused), with half the scratch.  The field is the
+// finite-difference gradient of the SP method.
 #define ROCBLAS_BETA_FEATURES_API  // rocblas_gemm_ex_get_solutions: the mode-3 solution is chosen by timing
 #include <rocblas/rocblas.h>
 

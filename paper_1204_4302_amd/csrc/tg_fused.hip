@@ -231,16 +231,24 @@ __global__ void __launch_bounds__(256, 2) k_tg_mode12(int n1, int n2, int n3, in
         }
         int g = g0;
         for (; g + 1 < g1; g += 2) {
-            load_tiles(atile, g + 1, a1);
             load_cols<MODE>(bcol, blive, 16 * (g + 1) + 4 * kq, n1, b1);
-            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+            load_tiles(atile, g + 1, a1);
             mfma_group(acc, a0, b0);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+            }
             __builtin_amdgcn_sched_barrier(0);
             const int g2 = g + 2 < g1 ? g + 2 : g1 - 1;
-            load_tiles(atile, g2, a0);
             load_cols<MODE>(bcol, blive, 16 * g2 + 4 * kq, n1, b0);
-            __builtin_amdgcn_sched_barrier(0);
+            load_tiles(atile, g2, a0);
             mfma_group(acc, a1, b1);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
         if (g < g1) mfma_group(acc, a0, b0);
@@ -286,14 +294,26 @@ __global__ void __launch_bounds__(256, 2) k_tg_mode12(int n1, int n2, int n3, in
         for (; g + 1 < f1; g += 2) {
             load_tiles(btile, g + 1, b1);
             read_y1(y1s, ld, lr, 16 * (g + 1) + 4 * kq, a1);
-            __builtin_amdgcn_sched_barrier(0);
             mfma_group(acc, a0, b0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+            }
             __builtin_amdgcn_sched_barrier(0);
             const int g2 = g + 2 < f1 ? g + 2 : f1 - 1;
             load_tiles(btile, g2, b0);
             read_y1(y1s, ld, lr, 16 * g2 + 4 * kq, a0);
-            __builtin_amdgcn_sched_barrier(0);
             mfma_group(acc, a1, b1);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+            }
             __builtin_amdgcn_sched_barrier(0);
         }
         if (g < f1) mfma_group(acc, a0, b0);
