@@ -223,7 +223,10 @@ __global__ void __launch_bounds__(256, 2) k_tg_mode12(int n1, int n2, int n3, in
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = tgf4{0.f, 0.f, 0.f, 0.f};
         // two operand sets in turn: the loads of one group are in flight during the
-        // products of the other (a group past the end is loaded again as the last)
+        // products of the other (a group past the end is loaded again as the last);
+        // the scheduling groups spread those loads through the products, one load
+        // per eight MFMAs, instead of one burst ahead of them (an idle matrix unit
+        // while the burst issues)
         tgf4 a0[4] = {}, b0[4] = {}, a1[4], b1[4];
         if (g0 < g1) {
             load_tiles(atile, g0, a0);
@@ -285,6 +288,8 @@ __global__ void __launch_bounds__(256, 2) k_tg_mode12(int n1, int n2, int n3, in
         for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) acc[rt][ct] = tgf4{0.f, 0.f, 0.f, 0.f};
+        // as in the first product; the global and LDS loads alternate, each ahead of
+        // eight MFMAs
         tgf4 a0[4] = {}, b0[4] = {}, a1[4], b1[4];
         if (f0 < f1) {
             load_tiles(btile, f0, b0);
