@@ -671,6 +671,7 @@ def bench_batch(args, torch, np):
            "modelled_bytes_per_batch": nbytes, "graph_achieved_GBs": round(nbytes * k / t_graph / 1e9, 1),
            "roofline": hbm_roofline(nbytes * k, t_graph, "whole batch replay (96 grids, five passes each)"),
            "launch_shapes": "autotuned per group" if tune_s is not None else "default", "autotune_s": tune_s,
+           "graph": batch.info(),
            "members_max_rel_diff_vs_single_calls": member_err}
     batch.close()
     for p in plans:

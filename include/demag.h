@@ -380,6 +380,9 @@ int demag_batch_create(demag_batch_t* out, const demag_plan_t* plans, int count,
  * single-plan calls, so members agree with demag_field to rounding only. */
 int demag_batch_autotune(demag_batch_t batch, void* stream);
 int demag_batch_launch(demag_batch_t batch, void* stream);
+/* out[0] = members, out[1] = geometry groups (one launch per pass each),
+ * out[2] = streams the recorded graph spreads the groups over (host). */
+int demag_batch_info(demag_batch_t batch, int64_t* out);
 int demag_batch_destroy(demag_batch_t batch);
 
 /* Test hook (environment): while DEMAG_FAIL_ALLOC_AT=k is set, the k-th

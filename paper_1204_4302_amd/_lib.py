@@ -56,6 +56,7 @@ SIGNATURES = {
     "demag_lowrank_compress": (_I, [_P, _I, _I, _I, _P, _P, _P, ctypes.POINTER(_D), _P]),
     "demag_batch_autotune": (_I, [_P, _P]),
     "demag_batch_launch": (_I, [_P, _P]),
+    "demag_batch_info": (_I, [_P, _P]),
     "demag_batch_destroy": (_I, [_P]),
     "demag_last_error": (ctypes.c_char_p, []),
 }

@@ -282,6 +282,7 @@ struct demag_batch_s {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int lanes = 0;  // capture streams the groups are spread over (0: one per hardware queue)
+    int used_lanes = 0;  // streams of the recorded graph
 };
 
 namespace {
@@ -2138,6 +2139,7 @@ int record_graph(demag_batch_s* b) {
     int rc = DEMAG_OK;
     const int ng = (int)b->groups.size();
     const int nb = std::min(b->lanes > 0 ? std::min(b->lanes, kBranches) : hw_queues(), ng);
+    b->used_lanes = nb;
     std::vector<int> order(ng), lane_of(ng);
     for (int i = 0; i < ng; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
@@ -2412,7 +2414,15 @@ extern "C" int demag_batch_launch(demag_batch_t b, void* stream) {
     return DEMAG_OK;
 }
 
-extern "C" int demag_batch_destroy(demag_batch_t b) {
+extern "C" int demag_batch_info(demag_batch_t b, int64_t* out) {
+    if (!b || !out) return fail(DEMAG_EINVAL, "NULL argument");
+    out[0] = (int64_t)b->plans.size();
+    out[1] = (int64_t)b->groups.size();
+    out[2] = b->used_lanes;
+    return DEMAG_OK;
+}
+
+int demag_batch_destroy(demag_batch_t b) {
     if (!b) return fail(DEMAG_EINVAL, "NULL batch");
     (void)hipDeviceSynchronize();
     for (auto p : b->plans)  // the replays are complete: drop the reference to the batch's event

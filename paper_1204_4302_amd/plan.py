@@ -395,6 +395,12 @@ class Batch:
     def launch(self):
         _lib.call("demag_batch_launch", self._h, _stream_ptr())
 
+    def info(self) -> dict:
+        """Members, geometry groups and the streams the recorded graph uses."""
+        out = (ctypes.c_int64 * 3)()
+        _lib.call("demag_batch_info", self._h, out)
+        return {"members": out[0], "groups": out[1], "streams": out[2]}
+
     def close(self):
         if getattr(self, "_h", None):
             _lib.call("demag_batch_destroy", self._h)

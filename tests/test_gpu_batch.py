@@ -38,6 +38,9 @@ def test_batch_equals_single_calls_and_replays_repeat():
     from paper_1204_4302_amd import Batch
     shapes, plans, ms, hs = build(24)
     batch = Batch(plans, ms, hs, MS)
+    info = batch.info()
+    groups = len(set(shapes))
+    assert info["members"] == 24 and info["groups"] == groups and 1 <= info["streams"] <= groups
     batch.launch()
     torch.cuda.synchronize()
     first = [h.clone() for h in hs]
